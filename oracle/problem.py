@@ -1,0 +1,37 @@
+"""Build the oracle's MGRIT hierarchy for a workload configuration.
+
+Level l uses the mesh of the configuration's l-th entry and the step
+dt_l = m**l * dt (coarse propagators are re-discretisations with the coarse
+step, Sec. 2.1).  Spatial transfers between differing meshes are P_s and
+R_s = D^{-1} P_s^T from `transfer.py`; equal meshes use none.
+"""
+
+from workload import hierarchy as mesh_hierarchy
+
+from .fe import MachineFE
+from .mgrit import Hierarchy
+from .stepping import Level
+from . import transfer
+
+
+def build(cfg, restriction="normalized"):
+    meshes = mesh_hierarchy(cfg)
+    fes = {}
+    levels = []
+    for l, mesh in enumerate(meshes):
+        key = (mesh.n_r, mesh.n_theta)
+        if key not in fes:
+            fes[key] = MachineFE(mesh)
+        levels.append(Level(mesh, cfg.level_dt(l), cfg.source, cfg.bh, fe=fes[key],
+                            newton_tol=cfg.newton_tol, newton_maxit=cfg.newton_maxit))
+    R, P = [], []
+    for fine, coarse in zip(meshes, meshes[1:]):
+        if (fine.n_r, fine.n_theta) == (coarse.n_r, coarse.n_theta):
+            R.append(None)
+            P.append(None)
+        else:
+            Ps = transfer.prolongation(fine, coarse)
+            P.append(Ps)
+            R.append(transfer.restriction(Ps, restriction)
+                     if restriction != "injection" else transfer.injection(fine, coarse))
+    return Hierarchy(levels, cfg.m, R=R, P=P, gamma=cfg.gamma), meshes

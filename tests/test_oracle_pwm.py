@@ -1,0 +1,58 @@
+"""Pins of the oracle's PWM excitation (Sec. 3.2, Sec. 3.3 reference/carrier equations)."""
+
+import math
+
+import numpy as np
+import pytest
+
+from workload import Source
+from oracle import pwm
+
+FC = 20.0e3
+
+
+@pytest.mark.parametrize("kind", ["triangle", "sawtooth"])
+@pytest.mark.parametrize("level", [-0.9, -0.35, 0.0, 0.5, 0.8])
+def test_duty_cycle_mean_equals_reference(kind, level):
+    """Over one carrier period, the mean of sgn(r - c) equals r for a constant
+    reference |r| <= 1 (the defining property of PWM: the time average follows
+    the reference)."""
+    n = 400000
+    t = (np.arange(n) + 0.5) / n / FC
+    b = np.sign(level - pwm.carrier(t, FC, kind))
+    assert b.mean() == pytest.approx(level, abs=5e-5)
+
+
+def test_carrier_hand_values():
+    T = 1.0 / FC
+    tri = lambda t: float(pwm.carrier(t, FC, "triangle"))
+    saw = lambda t: float(pwm.carrier(t, FC, "sawtooth"))
+    assert tri(0.0) == 1.0
+    assert tri(T / 4) == pytest.approx(0.0, abs=1e-12)
+    assert tri(T / 2) == pytest.approx(-1.0, abs=1e-12)
+    assert tri(3 * T / 4) == pytest.approx(0.0, abs=1e-12)
+    assert tri(T / 8) == pytest.approx(0.5, abs=1e-12)
+    assert saw(0.0) == -1.0
+    assert saw(T / 2) == pytest.approx(0.0, abs=1e-12)
+    assert saw(T / 4) == pytest.approx(-0.5, abs=1e-12)
+    assert saw(0.999 * T) == pytest.approx(0.998, abs=1e-9)
+
+
+def test_three_phase_values():
+    src = Source()
+    # t = 0: r = (0, sin(-2pi/3), sin(-4pi/3)) = (0, -0.866, +0.866), c = 1 -> all -1
+    assert pwm.phase_signals([0.0], src)[:, 0].tolist() == [-1.0, -1.0, -1.0]
+    # t = T_c/4: c = 0, r_A = sin(2 pi 50 * 12.5us) > 0
+    t = 0.25 / FC
+    assert pwm.phase_signals([t], src)[:, 0].tolist() == [1.0, -1.0, 1.0]
+    # balanced references sum to zero
+    tt = np.linspace(0, 0.02, 101)
+    rs = sum(pwm.reference(tt, src, p) for p in range(3))
+    assert np.abs(rs).max() < 1e-12
+
+
+def test_sign_of_zero_is_zero():
+    # reference crossing the carrier exactly: sgn(0) = 0
+    src = Source(phases=(math.pi / 2, 0.0, 0.0), carrier="triangle")
+    # r_A(0) = sin(pi/2) = 1 = c(0)
+    assert pwm.pwm(0.0, src, 0) == 0.0
