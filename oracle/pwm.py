@@ -10,10 +10,19 @@ Two carriers:
   triangle (the carrier the workload configurations use):
       c(t) = 1 - 4 |f_c t - floor(f_c t + 1/2)|,   c(0) = 1.
 sgn(0) = 0.  One carrier is shared by the three phases.
+
+Ties.  With the reference amplitude equal to the carrier peak, the time
+grids of the workloads hit r(t) = c(t) exactly (t = T/4: r_A = 1 = c), where
+the sign of a difference of two rounded values is decided by the last ulp of
+the sine.  A difference within TIE_BAND = 1e-12 of zero is therefore read as
+a tie (sgn = 0).  Every other decision on the workload grids has a margin
+above 1e-7, so the band changes nothing else.
 """
 
 import math
 import numpy as np
+
+TIE_BAND = 1e-12
 
 
 def carrier(t, f_c, kind):
@@ -34,7 +43,8 @@ def reference(t, src, phase_index):
 
 def pwm(t, src, phase_index):
     """b_p(t) in {-1, 0, +1}."""
-    return np.sign(reference(t, src, phase_index) - carrier(t, src.f_carrier, src.carrier))
+    d = reference(t, src, phase_index) - carrier(t, src.f_carrier, src.carrier)
+    return np.where(np.abs(d) <= TIE_BAND, 0.0, np.sign(d))
 
 
 def phase_signals(t, src):

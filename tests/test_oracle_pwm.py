@@ -56,3 +56,25 @@ def test_sign_of_zero_is_zero():
     src = Source(phases=(math.pi / 2, 0.0, 0.0), carrier="triangle")
     # r_A(0) = sin(pi/2) = 1 = c(0)
     assert pwm.pwm(0.0, src, 0) == 0.0
+
+
+def test_quarter_period_tie_is_zero():
+    """At t = T/4 the phase-A reference peaks at 1 where the triangle carrier
+    also peaks at 1: an exact tie, sgn = 0 regardless of the sine's last ulp."""
+    src = Source()
+    t = 0.25 / src.freq
+    assert pwm.pwm(t, src, 0) == 0.0
+    assert pwm.pwm(np.nextafter(t, 1.0), src, 0) == 0.0
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg4"])
+def test_tie_band_changes_no_other_decision(name):
+    """Outside the exact ties, |r - c| on every level's time grid is far above
+    the tie band, so the band only resolves genuine ties."""
+    from workload import config
+    cfg = config(name)
+    for l in range(cfg.n_levels):
+        t = np.arange(cfg.level_steps(l) + 1) * cfg.level_dt(l)
+        for p in range(3):
+            d = np.abs(pwm.reference(t, cfg.source, p) - pwm.carrier(t, cfg.source.f_carrier, cfg.source.carrier))
+            assert np.all((d <= 1e-14) | (d > 1e-6))
