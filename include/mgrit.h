@@ -1,0 +1,170 @@
+/*
+ * mgrit.h -- C ABI of the MI355X (gfx950) MGRIT library for the 2D eddy-current
+ * problem of an induction machine (arXiv:1912.03106).
+ *
+ * The library solves the space-time system of Sec. 2 (block lower-bidiagonal
+ * system A u = g built from a one-step integrator Phi, eq. 2) for the
+ * backward-Euler discretisation (eq. 8) of the semi-discrete eddy-current
+ * system M u' + K(u) u = f(t) (eq. 7) on P1 triangles, either sequentially
+ * (forward block solve) or with FAS-MGRIT (Algorithm 1) in a V-cycle with
+ * F/FCF relaxation and optional spatial coarsening between nested meshes
+ * (Sec. 2.2).  Every step runs in HIP kernels on one GPU.
+ *
+ * Conventions shared by every entry point
+ *  - Unknowns are the non-Dirichlet nodes of a mesh, in increasing node-id
+ *    order; n_l is their count on level l.
+ *  - Time-major arrays: point t of a trajectory is the contiguous vector
+ *    u[t*n .. t*n+n-1].  Level l has N_l = N_t / m^l steps of size m^l dt.
+ *  - Host pointers unless a field says otherwise.  The library copies what it
+ *    needs during mgrit_setup; the caller keeps ownership of every array it
+ *    passes and may free it after the call returns.
+ *  - Every function returns MGRIT_OK (0) or a negative mgrit_status; no C++
+ *    exception crosses this boundary.  mgrit_last_error() gives the message.
+ *  - A handle is not thread-safe: one handle per host thread.  Work runs on
+ *    the HIP stream given to mgrit_setup; calls that return results to the
+ *    host synchronize that stream before returning.
+ */
+#ifndef MGRIT_H
+#define MGRIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGRIT_ABI_VERSION 1
+#define MGRIT_MAX_LEVELS 8
+#define MGRIT_MAX_HISTORY 128
+
+typedef enum {
+  MGRIT_OK = 0,
+  MGRIT_INVALID_ARGUMENT = -1,
+  MGRIT_NOT_NESTED = -2,          /* spatial coarsening between non-nested meshes */
+  MGRIT_OUT_OF_MEMORY = -3,
+  MGRIT_HIP_ERROR = -4,
+  MGRIT_PCG_NOT_CONVERGED = -5,   /* a linear solve hit pcg_max_iter */
+  MGRIT_NEWTON_NOT_CONVERGED = -6,/* a nonlinear step hit newton_max_iter (Sec. 5.2) */
+  MGRIT_NOT_CONVERGED = -7,       /* MGRIT hit max_iter before tol (Table 2) */
+  MGRIT_NONFINITE = -8,           /* NaN or Inf in an input or an iterate */
+  MGRIT_UNSUPPORTED = -9
+} mgrit_status;
+
+/* One triangulation (Sec. 3.4).  n_r, n_theta > 0 declare the structured
+ * polar numbering node id = i*n_theta + j (i radial, j angular, periodic in j);
+ * spatial coarsening needs it.  Triangles must be counter-clockwise. */
+typedef struct {
+  int32_t n_r, n_theta;
+  int32_t n_nodes, n_tri;
+  const double*  xy;          /* [n_nodes][2] node coordinates, m               */
+  const int32_t* tri;         /* [n_tri][3] node ids                            */
+  const int32_t* cell_mat;    /* [n_tri] index into the material table          */
+  const int32_t* cell_phase;  /* [n_tri] -1 = no source, else phase 0, 1 or 2   */
+  const int32_t* cell_sign;   /* [n_tri] winding direction (+1 / -1 / 0)        */
+  const uint8_t* dirichlet;   /* [n_nodes] 1 = A fixed to 0                     */
+} mgrit_mesh;
+
+/* Materials, source and time grid (Sec. 3.1-3.3).
+ * nu(B^2) = bh_k1 exp(bh_k2 B^2) + bh_k3 in materials with iron[k] = 1 when
+ * nonlinear != 0; otherwise nu = nu[k].  The coil current density of a cell
+ * is sign * J0 * amplitude * b_phase(t), b_p(t) = sgn(sin(2 pi freq t +
+ * phases[p] + phase_offset) - c(t)), carrier c = triangle (0) or sawtooth (1)
+ * of frequency f_carrier; sgn(0) = 0. */
+typedef struct {
+  int32_t n_materials;
+  const double*  nu;          /* [n_materials] reluctivity, A m / Wb */
+  const double*  sigma;       /* [n_materials] conductivity, S / m   */
+  const int32_t* iron;        /* [n_materials] 1 = saturating law applies */
+  int32_t nonlinear;
+  double bh_k1, bh_k2, bh_k3;
+  double J0, amplitude, freq, f_carrier, phase_offset;
+  double phases[3];
+  int32_t carrier;            /* 0 triangle (c(0) = 1), 1 sawtooth */
+  double dt;                  /* finest step; t_i = i * dt */
+  int64_t n_steps;            /* N_t on the finest level */
+} mgrit_physics;
+
+typedef struct {
+  int32_t n_levels;           /* MGRIT levels (>= 1); level 0 is the finest   */
+  const mgrit_mesh* meshes;   /* [n_levels] mesh of every level               */
+  mgrit_physics phys;
+} mgrit_problem;
+
+enum { MGRIT_FP64 = 0, MGRIT_FP32_IR = 1 };
+enum { MGRIT_R_NORMALIZED = 0, MGRIT_R_TRANSPOSE = 1, MGRIT_R_INJECTION = 2 };
+
+typedef struct {
+  int32_t m;                  /* temporal coarsening factor (> 1)               */
+  int32_t gamma;              /* CF relaxations after the first F (1 = FCF)    */
+  int32_t precision;          /* MGRIT_FP64 or MGRIT_FP32_IR                    */
+  int32_t restriction;        /* MGRIT_R_*                                      */
+  double  tol;                /* stop at rho_k <= tol * rho_0 (C-point residual)*/
+  int32_t max_iter;           /* MGRIT iterations (coarse corrections)         */
+  double  pcg_tol;            /* relative residual of every linear solve       */
+  int32_t pcg_max_iter;
+  int32_t pcg_check_every;    /* PCG iterations between host convergence reads */
+  double  ir_inner_tol;       /* FP32 inner PCG tolerance (MGRIT_FP32_IR)       */
+  int32_t ir_max_iter;        /* refinement sweeps                              */
+  double  newton_tol;         /* ||R(u^k)|| <= newton_tol ||R(u^0)||           */
+  int32_t newton_max_iter;
+  int32_t warm_start;         /* 1: linear solves start from the previous iterate */
+  int32_t device_pointers;    /* 1: u_init / u_out of mgrit_solve are device pointers */
+} mgrit_params;
+
+typedef struct {
+  int32_t iterations;         /* coarse corrections performed                   */
+  int32_t converged;
+  int32_t n_history;
+  double  rho[MGRIT_MAX_HISTORY];     /* C-point residual norm per iteration     */
+  int64_t phi_columns[MGRIT_MAX_LEVELS];   /* Phi applications per level        */
+  int64_t pcg_sweeps[MGRIT_MAX_LEVELS];    /* batched PCG iterations per level   */
+  int64_t newton_sweeps[MGRIT_MAX_LEVELS];
+  double  time_relax_s;       /* finest-level F/C relaxation time (device)      */
+  double  time_total_s;
+} mgrit_stats;
+
+/* Fill *par with the defaults (m = 16, FCF, FP64, normalized restriction,
+ * tol 1e-8, pcg_tol 1e-12, ...). */
+void mgrit_default_params(mgrit_params* par);
+
+/* Build the level hierarchy on the device: assembles K, M/dt_l, the Jacobi
+ * diagonal and the phase load vectors on every level (eq. 7, 8), builds the
+ * spatial transfers between consecutive levels whose meshes differ (nodal
+ * interpolation P_s in the logical polar coordinates and R_s from P_s^T,
+ * Sec. 3.4; MGRIT_NOT_NESTED if the meshes are not nested) and allocates the
+ * space-time storage.  hip_stream: a hipStream_t (NULL = default stream).
+ * On success *out owns all device memory until mgrit_destroy. */
+int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par,
+                void* hip_stream, void** out);
+
+/* FAS-MGRIT V-cycles (Algorithm 1, Sec. 2.1) until rho_k <= tol rho_0.
+ * u0:     [n_0] initial value A(t_0) (NULL = 0).
+ * u_init: [(N_t+1)][n_0] initial space-time guess, row 0 ignored (NULL = 0).
+ * u_out:  [(N_t+1)][n_0] result: the relaxed iterate of the last iteration.
+ * Returns MGRIT_NOT_CONVERGED (with u_out and *st filled) if max_iter is hit. */
+int mgrit_solve(void* h, const double* u0, const double* u_init, double* u_out,
+                mgrit_stats* st);
+
+/* Sequential forward block solve (Sec. 2) on the finest level, on the GPU:
+ * u_out [(N_t+1)][n_0] = (u0, Phi_1(u0), ...).  u0 may be NULL (= 0). */
+int mgrit_seq_solve(void* h, const double* u0, double* u_out, mgrit_stats* st);
+
+/* The one-step integrator Phi of level `level` (eq. 2 with eq. 8), batched:
+ * u_next[k] = Phi(u_prev[k]) from t = i_from[k] * dt_level to
+ * (i_from[k] + 1) * dt_level, forcing at the new time included.
+ * u_prev, u_next: [B][n_level] time-major; i_from: [B].  Host pointers. */
+int phi_step(void* h, int32_t level, int32_t B, const int64_t* i_from,
+             const double* u_prev, double* u_next);
+
+/* Sizes: n_level, N_level (steps), nnz of the level operator. */
+int mgrit_level_info(void* h, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz);
+
+void mgrit_destroy(void* h);
+const char* mgrit_strerror(int status);
+const char* mgrit_last_error(void* h);   /* NULL handle: last setup error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGRIT_H */

@@ -1,0 +1,720 @@
+// MGRIT engine and C ABI.
+//
+// Space-time storage of a level with N steps and coarsening factor m
+// (non-coarsest level): m "slabs" [n][ld], slab j holding the points
+// k*m + j (column k), so that one F-relaxation step j (all intervals at once)
+// reads slab j-1 and writes slab j with coalesced column blocks; the
+// C-points are slab 0 (columns 0..N/m).  The coarsest level is one column
+// block [n][ld] with column t = point t.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "setup.h"
+
+namespace mg {
+
+struct LevelState {
+  DevLevel op;
+  ElementData elem;
+  int n = 0;
+  int64_t N = 0;     // steps on this level
+  int64_t NT = 0;    // intervals (N / m) on non-coarsest levels
+  bool coarsest = false;
+  int64_t ld = 0;    // column stride of the storage
+  int64_t ss = 0;    // slab stride
+  double* U = nullptr;
+  double* G = nullptr;
+  double* RES = nullptr;                          // [n][ld] C-point residual
+  double *U2 = nullptr, *G2 = nullptr, *RR = nullptr;  // next level, C-point columns
+  bool has_transfer = false;
+  DevTransfer R, P;
+  PcgWork pcg;       // batched Phi on this level (capacity N + 1 columns)
+  PcgWork user;      // phi_step workspace (grown on demand)
+  double* seq_ws = nullptr;
+  bool relaxed = false;   // F-points hold a previous iterate (warm starts)
+  bool cvalid = false;    // C-points hold a previous iterate
+};
+
+struct Handle {
+  hipStream_t stream = nullptr;
+  mgrit_params par{};
+  mgrit_physics phys{};
+  SourceDev src{};
+  int m = 2;
+  std::vector<LevelState> lv;
+  DeviceArena arena;
+  std::string last_error;
+  double* tm_stage = nullptr;     // time-major staging [(N+1)][n0] (lazy)
+  double* host_sums = nullptr;    // pinned [ld0]
+  double* u0_dev = nullptr;       // [n0]
+  double* seq_U = nullptr;        // sequential trajectory [n0][ld] (lazy)
+  double* seq_ws = nullptr;
+  mgrit_stats* st = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block) {
+  w.n = n;
+  w.cap = cap;
+  w.ld = round_up(cap > 0 ? cap : 1, kWave);
+  w.rows_per_block = rows_per_block;
+  w.nrb = static_cast<int>((n + rows_per_block - 1) / rows_per_block);
+  const size_t vec = static_cast<size_t>(n) * w.ld;
+  w.x = h.arena.alloc<double>(vec);
+  w.r = h.arena.alloc<double>(vec);
+  w.p = h.arena.alloc<double>(vec);
+  w.q = h.arena.alloc<double>(vec);
+  w.part = h.arena.alloc<double>(3 * static_cast<size_t>(w.nrb) * w.ld);
+  w.scal = h.arena.alloc<double>(8 * static_cast<size_t>(w.ld));
+  w.src = h.arena.alloc<double>(3 * static_cast<size_t>(w.ld));
+  w.active = h.arena.alloc<uint8_t>(w.ld);
+  w.flags = h.arena.alloc<int>(4);
+  w.host_flags = static_cast<int*>(h.arena.alloc_host(4 * sizeof(int)));
+  MG_HIP(hipMemsetAsync(w.flags, 0, 4 * sizeof(int), h.stream));
+}
+
+static int rows_per_block_for(int n) {
+  (void)n;
+  return 64;
+}
+
+// ---------------------------------------------------------------------------
+// Batched PCG: solves (M/dt + K) x = (M/dt) u_in + f(t) for every column, x
+// initialised in w.x.  Returns the number of batched sweeps.
+static int pcg_solve(Handle& h, const DevLevel& L, PcgWork& w, int ncols, CView in) {
+  hipStream_t s = h.stream;
+  const double tol2 = h.par.pcg_tol * h.par.pcg_tol;
+  launch_pcg_init(s, L, w, ncols, in);
+  launch_reduce(s, w, ncols, RED_INIT, tol2, 3, nullptr);
+  MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
+  int it = 0;
+  int active = w.host_flags[0];
+  const int chunk = h.par.pcg_check_every > 0 ? h.par.pcg_check_every : 16;
+  while (active > 0) {
+    if (it >= h.par.pcg_max_iter)
+      fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in pcg_max_iter iterations (" +
+                                        std::to_string(active) + " columns left)");
+    const int k = std::min(chunk, h.par.pcg_max_iter - it);
+    for (int t = 0; t < k; ++t) {
+      launch_spmm_dot(s, L, w, ncols);
+      launch_reduce(s, w, ncols, RED_ALPHA, tol2, 1, nullptr);
+      launch_pcg_update(s, L, w, ncols);
+      launch_reduce(s, w, ncols, RED_BETA, tol2, 2, nullptr);
+      launch_pcg_pupdate(s, L, w, ncols);
+    }
+    it += k;
+    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
+    active = w.host_flags[0];
+  }
+  return it;
+}
+
+// One batched application of Phi on level l:
+//   x = Phi(u_in[:, c]) for c < ncols, input time index t_base + c*t_stride
+//   (or t_list[c]), initial guess x0 = ga + sgb * gb,
+//   out = osx * x + oa + osb * ob.
+struct PhiCall {
+  int ncols = 0;
+  CView in;
+  const int64_t* t_list = nullptr;
+  int64_t t_base = 0, t_stride = 1;
+  CView ga, gb;
+  double sgb = 0.0;
+  double* out = nullptr;
+  int64_t ldo = 0;
+  double osx = 1.0;
+  CView oa, ob;
+  double osb = 0.0;
+};
+
+static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
+  if (c.ncols <= 0) return;
+  if (c.ncols > w.cap) fail(MGRIT_INVALID_ARGUMENT, "batched Phi wider than its workspace");
+  LevelState& S = h.lv[l];
+  hipStream_t s = h.stream;
+  launch_source_table(s, h.src, S.op.dt, c.ncols, c.t_list, c.t_base, c.t_stride, w.src, w.ld);
+  launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
+  const int it = pcg_solve(h, S.op, w, c.ncols, c.in);
+  launch_axpby3(s, S.n, c.ncols, c.out, c.ldo, c.osx, CView{w.x, w.ld}, 1.0, c.oa, c.osb, c.ob);
+  if (h.st && l < MGRIT_MAX_LEVELS) {
+    h.st->phi_columns[l] += c.ncols;
+    h.st->pcg_sweeps[l] += it;
+  }
+}
+
+static double* slab(LevelState& S, int j) { return S.U + static_cast<int64_t>(j) * S.ss; }
+static double* gslab(LevelState& S, int j) {
+  return S.G ? S.G + static_cast<int64_t>(j) * S.ss : nullptr;
+}
+
+static void f_relax(Handle& h, int l) {
+  LevelState& S = h.lv[l];
+  const bool warm = S.relaxed && h.par.warm_start;
+  for (int j = 1; j < h.m; ++j) {
+    PhiCall c;
+    c.ncols = static_cast<int>(S.NT);
+    c.in = CView{slab(S, j - 1), S.ld};
+    c.t_base = j - 1;
+    c.t_stride = h.m;
+    if (warm) {
+      c.ga = CView{slab(S, j), S.ld};
+      c.gb = CView{gslab(S, j), S.ld};
+      c.sgb = -1.0;
+    } else {
+      c.ga = c.in;
+    }
+    c.out = slab(S, j);
+    c.ldo = S.ld;
+    c.oa = CView{gslab(S, j), S.ld};
+    phi_batch(h, l, S.pcg, c);
+  }
+  S.relaxed = true;
+}
+
+static void c_relax(Handle& h, int l) {
+  LevelState& S = h.lv[l];
+  PhiCall c;
+  c.ncols = static_cast<int>(S.NT);
+  c.in = CView{slab(S, h.m - 1), S.ld};
+  c.t_base = h.m - 1;
+  c.t_stride = h.m;
+  if (S.cvalid && h.par.warm_start) {
+    c.ga = CView{slab(S, 0) + 1, S.ld};
+    c.gb = CView{S.G ? gslab(S, 0) + 1 : nullptr, S.ld};
+    c.sgb = -1.0;
+  } else {
+    c.ga = c.in;
+  }
+  c.out = slab(S, 0) + 1;
+  c.ldo = S.ld;
+  c.oa = CView{S.G ? gslab(S, 0) + 1 : nullptr, S.ld};
+  phi_batch(h, l, S.pcg, c);
+  S.cvalid = true;
+}
+
+static void relax(Handle& h, int l) {
+  f_relax(h, l);
+  for (int g = 0; g < h.par.gamma; ++g) {
+    c_relax(h, l);
+    f_relax(h, l);
+  }
+}
+
+// RES[:, k] = g_km - u_km + Phi(u_km-1) (k >= 1), RES[:, 0] = g_0 - u_0.
+static void c_residual(Handle& h, int l) {
+  LevelState& S = h.lv[l];
+  hipStream_t s = h.stream;
+  launch_axpby3(s, S.n, 1, S.RES, S.ld, 0.0, CView{}, 1.0, CView{gslab(S, 0), S.ld}, -1.0,
+                CView{slab(S, 0), S.ld});
+  PhiCall c;
+  c.ncols = static_cast<int>(S.NT);
+  c.in = CView{slab(S, h.m - 1), S.ld};
+  c.t_base = h.m - 1;
+  c.t_stride = h.m;
+  c.ga = CView{slab(S, 0) + 1, S.ld};
+  c.gb = CView{S.G ? gslab(S, 0) + 1 : nullptr, S.ld};
+  c.sgb = -1.0;
+  c.out = S.RES + 1;
+  c.ldo = S.ld;
+  c.osx = 1.0;
+  c.oa = c.gb;
+  c.ob = CView{slab(S, 0) + 1, S.ld};
+  c.osb = -1.0;
+  phi_batch(h, l, S.pcg, c);
+}
+
+static double residual_norm(Handle& h, int l) {
+  LevelState& S = h.lv[l];
+  hipStream_t s = h.stream;
+  const int ncols = static_cast<int>(S.NT + 1);
+  launch_colsq(s, S.pcg, S.n, ncols, CView{S.RES, S.ld});
+  double* sums = S.pcg.scal + 5 * S.pcg.ld;
+  launch_reduce(s, S.pcg, ncols, RED_SUM, 0.0, 1, sums);
+  MG_HIP(hipMemcpyAsync(h.host_sums, sums, sizeof(double) * ncols, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  double t = 0.0;
+  for (int c = 0; c < ncols; ++c) t += h.host_sums[c];
+  if (!std::isfinite(t)) fail(MGRIT_NONFINITE, "non-finite MGRIT residual");
+  return std::sqrt(t);
+}
+
+static void coarsest_solve(Handle& h, int l) {
+  LevelState& S = h.lv[l];
+  hipStream_t s = h.stream;
+  // u_0 = g_0
+  launch_axpby3(s, S.n, 1, S.U, S.ld, 0.0, CView{}, 1.0, CView{S.G, S.ld}, 0.0, CView{});
+  MG_HIP(hipMemsetAsync(S.pcg.flags, 0, 4 * sizeof(int), s));
+  launch_seq_small(s, S.op, h.src, static_cast<int>(S.N), 0, S.U, S.ld, S.G, S.ld, S.seq_ws,
+                   h.par.pcg_tol, h.par.pcg_max_iter, 1, S.pcg.flags);
+  MG_HIP(hipMemcpyAsync(S.pcg.host_flags, S.pcg.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  if (S.pcg.host_flags[1] & 1) fail(MGRIT_NONFINITE, "non-finite value in the coarsest solve");
+  if (S.pcg.host_flags[1] & 2) fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge on the coarsest level");
+  if (h.st && l < MGRIT_MAX_LEVELS) {
+    h.st->phi_columns[l] += S.N;
+    h.st->pcg_sweeps[l] += S.pcg.host_flags[2];
+  }
+}
+
+static void cycle(Handle& h, int l);
+
+// Algorithm 1, steps 4-9: restrict, FAS right-hand side, coarse solve, correct.
+static void coarse_correct(Handle& h, int l) {
+  LevelState& S = h.lv[l];
+  LevelState& C = h.lv[l + 1];
+  hipStream_t s = h.stream;
+  const int np = static_cast<int>(S.NT + 1);  // points of level l+1
+  if (S.has_transfer) {
+    launch_transfer(s, S.R, np, CView{slab(S, 0), S.ld}, 1.0, S.U2, S.ld, 0.0);
+    launch_transfer(s, S.R, np, CView{S.RES, S.ld}, 1.0, S.RR, S.ld, 0.0);
+  } else {
+    launch_axpby3(s, C.n, np, S.U2, S.ld, 1.0, CView{slab(S, 0), S.ld}, 0.0, CView{}, 0.0, CView{});
+    launch_axpby3(s, C.n, np, S.RR, S.ld, 1.0, CView{S.RES, S.ld}, 0.0, CView{}, 0.0, CView{});
+  }
+  // g2_0 = u2_0 + rr_0 ; g2_k = u2_k - Phi_{l+1}(u2_{k-1}) + rr_k
+  launch_axpby3(s, C.n, 1, S.G2, S.ld, 1.0, CView{S.U2, S.ld}, 1.0, CView{S.RR, S.ld}, 0.0, CView{});
+  PhiCall c;
+  c.ncols = np - 1;
+  c.in = CView{S.U2, S.ld};
+  c.t_base = 0;
+  c.t_stride = 1;
+  c.ga = CView{S.U2 + 1, S.ld};
+  c.out = S.G2 + 1;
+  c.ldo = S.ld;
+  c.osx = -1.0;
+  c.oa = CView{S.U2 + 1, S.ld};
+  c.ob = CView{S.RR + 1, S.ld};
+  c.osb = 1.0;
+  phi_batch(h, l + 1, C.pcg, c);
+  // v = u2, load the coarse problem
+  if (C.coarsest) {
+    launch_axpby3(s, C.n, np, C.U, C.ld, 1.0, CView{S.U2, S.ld}, 0.0, CView{}, 0.0, CView{});
+    launch_axpby3(s, C.n, np, C.G, C.ld, 1.0, CView{S.G2, S.ld}, 0.0, CView{}, 0.0, CView{});
+  } else {
+    launch_cols_to_slabs(s, C.n, np, h.m, S.U2, S.ld, C.U, C.ld, C.ss);
+    launch_cols_to_slabs(s, C.n, np, h.m, S.G2, S.ld, C.G, C.ld, C.ss);
+  }
+  C.cvalid = true;
+  cycle(h, l + 1);
+  // e = v - u2 (into RR), u_C += P_s e
+  if (C.coarsest) {
+    launch_axpby3(s, C.n, np, S.RR, S.ld, 1.0, CView{C.U, C.ld}, -1.0, CView{S.U2, S.ld}, 0.0, CView{});
+  } else {
+    launch_slabs_to_cols(s, C.n, np, h.m, C.U, C.ld, C.ss, S.RR, S.ld);
+    launch_axpby3(s, C.n, np, S.RR, S.ld, 1.0, CView{S.RR, S.ld}, -1.0, CView{S.U2, S.ld}, 0.0, CView{});
+  }
+  if (S.has_transfer) {
+    launch_transfer(s, S.P, np, CView{S.RR, S.ld}, 1.0, slab(S, 0), S.ld, 1.0);
+  } else {
+    launch_axpby3(s, S.n, np, slab(S, 0), S.ld, 1.0, CView{slab(S, 0), S.ld}, 1.0, CView{S.RR, S.ld},
+                  0.0, CView{});
+  }
+}
+
+static void cycle(Handle& h, int l) {
+  LevelState& S = h.lv[l];
+  if (S.coarsest) {
+    coarsest_solve(h, l);
+    return;
+  }
+  relax(h, l);
+  c_residual(h, l);
+  coarse_correct(h, l);
+  f_relax(h, l);
+}
+
+// ---------------------------------------------------------------------------
+// Setup.
+
+static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params* par) {
+  if (!prob || !par) fail(MGRIT_INVALID_ARGUMENT, "null problem or params");
+  h.par = *par;
+  h.phys = prob->phys;
+  const mgrit_physics& ph = prob->phys;
+  const int L = prob->n_levels;
+  if (L < 1 || L > MGRIT_MAX_LEVELS || !prob->meshes) fail(MGRIT_INVALID_ARGUMENT, "n_levels out of range");
+  if (par->m < 2) fail(MGRIT_INVALID_ARGUMENT, "m must be > 1");
+  if (par->gamma < 0) fail(MGRIT_INVALID_ARGUMENT, "gamma must be >= 0");
+  if (!(par->pcg_tol > 0.0) || par->pcg_max_iter < 1) fail(MGRIT_INVALID_ARGUMENT, "bad PCG settings");
+  if (par->precision != MGRIT_FP64) fail(MGRIT_UNSUPPORTED, "only MGRIT_FP64 is available in this build");
+  if (ph.nonlinear) fail(MGRIT_UNSUPPORTED, "the nonlinear model is not available in this build");
+  if (ph.n_materials <= 0 || !ph.nu || !ph.sigma) fail(MGRIT_INVALID_ARGUMENT, "material table");
+  if (!(ph.dt > 0.0) || ph.n_steps < 1) fail(MGRIT_INVALID_ARGUMENT, "time grid");
+  if (ph.carrier != 0 && ph.carrier != 1) fail(MGRIT_INVALID_ARGUMENT, "carrier");
+  h.m = par->m;
+  int64_t mpow = 1;
+  for (int l = 0; l + 1 < L; ++l) {
+    mpow *= par->m;
+    if (ph.n_steps % mpow != 0) fail(MGRIT_INVALID_ARGUMENT, "n_steps must be divisible by m^(levels-1)");
+  }
+  h.src.scale = ph.J0 * ph.amplitude;
+  h.src.freq = ph.freq;
+  h.src.f_carrier = ph.f_carrier;
+  for (int p = 0; p < 3; ++p) h.src.phi[p] = ph.phases[p] + ph.phase_offset;
+  h.src.carrier = ph.carrier;
+
+  // host phase: validate every mesh, build patterns and transfers (no HIP call)
+  std::vector<HostPattern> pats(L);
+  for (int l = 0; l < L; ++l) {
+    validate_mesh(prob->meshes[l], ph.n_materials);
+    pats[l] = build_pattern(prob->meshes[l]);
+  }
+  std::vector<HostSparse> Ps(L), Rs(L);
+  std::vector<bool> sc(L, false);
+  for (int l = 0; l + 1 < L; ++l) {
+    if (same_mesh(prob->meshes[l], prob->meshes[l + 1])) continue;
+    Ps[l] = build_prolongation(prob->meshes[l], prob->meshes[l + 1], pats[l], pats[l + 1]);
+    Rs[l] = build_restriction(Ps[l], par->restriction, prob->meshes[l], prob->meshes[l + 1],
+                              pats[l], pats[l + 1]);
+    sc[l] = true;
+  }
+  // device phase
+  hipStream_t s = h.stream;
+  h.lv.resize(L);
+  double dt = ph.dt;
+  int64_t N = ph.n_steps;
+  for (int l = 0; l < L; ++l) {
+    LevelState& S = h.lv[l];
+    S.n = pats[l].n;
+    S.N = N;
+    S.coarsest = (l == L - 1);
+    S.op = assemble_level(h.arena, s, prob->meshes[l], pats[l], ph, dt, &S.elem);
+    dt *= par->m;
+    N /= par->m;
+  }
+  for (int l = 0; l < L; ++l) {
+    LevelState& S = h.lv[l];
+    const int rpb = rows_per_block_for(S.n);
+    if (S.coarsest) {
+      S.ld = round_up(S.N + 1, kWave);
+      S.ss = static_cast<int64_t>(S.n) * S.ld;
+      S.U = h.arena.alloc<double>(S.ss);
+      S.G = h.arena.alloc<double>(S.ss);
+      S.seq_ws = h.arena.alloc<double>(4 * static_cast<size_t>(S.n));
+      MG_HIP(hipMemsetAsync(S.U, 0, sizeof(double) * S.ss, s));
+      MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss, s));
+    } else {
+      S.NT = S.N / par->m;
+      S.ld = round_up(S.NT + 1, kWave);
+      S.ss = static_cast<int64_t>(S.n) * S.ld;
+      S.U = h.arena.alloc<double>(static_cast<size_t>(S.ss) * par->m);
+      MG_HIP(hipMemsetAsync(S.U, 0, sizeof(double) * S.ss * par->m, s));
+      if (l > 0) {
+        S.G = h.arena.alloc<double>(static_cast<size_t>(S.ss) * par->m);
+        MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss * par->m, s));
+      }
+      S.RES = h.arena.alloc<double>(S.ss);
+      const int nc = pats[l + 1].n;
+      const size_t cs = static_cast<size_t>(nc) * S.ld;
+      S.U2 = h.arena.alloc<double>(cs);
+      S.G2 = h.arena.alloc<double>(cs);
+      S.RR = h.arena.alloc<double>(cs);
+      if (sc[l]) {
+        S.P = upload_transfer(h.arena, s, Ps[l]);
+        S.R = upload_transfer(h.arena, s, Rs[l]);
+        S.has_transfer = true;
+      }
+    }
+    // level l's batched Phi serves its own sweeps (NT columns) and, on
+    // coarse levels, the FAS right-hand side (N columns)
+    const int cap = static_cast<int>((l == 0 ? S.NT : S.N) + 1);
+    alloc_pcg(h, S.pcg, S.n, cap, rpb);
+  }
+  const int64_t ld0 = h.lv[0].pcg.ld > h.lv[0].ld ? h.lv[0].pcg.ld : h.lv[0].ld;
+  h.host_sums = static_cast<double*>(h.arena.alloc_host(sizeof(double) * (ld0 + 64)));
+  h.u0_dev = h.arena.alloc<double>(h.lv[0].n);
+  MG_HIP(hipEventCreate(&h.ev0));
+  MG_HIP(hipEventCreate(&h.ev1));
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+static double* stage(Handle& h) {
+  if (!h.tm_stage) {
+    const LevelState& S = h.lv[0];
+    h.tm_stage = h.arena.alloc<double>(static_cast<size_t>(S.N + 1) * S.n);
+  }
+  return h.tm_stage;
+}
+
+static void load_u0(Handle& h, const double* u0) {
+  LevelState& S = h.lv[0];
+  if (u0) {
+    MG_HIP(hipMemcpyAsync(h.u0_dev, u0, sizeof(double) * S.n,
+                          h.par.device_pointers ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          h.stream));
+  } else {
+    MG_HIP(hipMemsetAsync(h.u0_dev, 0, sizeof(double) * S.n, h.stream));
+  }
+}
+
+static void solve_impl(Handle& h, const double* u0, const double* u_init, double* u_out,
+                       mgrit_stats* st) {
+  hipStream_t s = h.stream;
+  LevelState& S0 = h.lv[0];
+  if (h.lv.size() < 2) fail(MGRIT_INVALID_ARGUMENT, "mgrit_solve needs at least two levels");
+  if (!u_out) fail(MGRIT_INVALID_ARGUMENT, "u_out is null");
+  for (auto& S : h.lv) S.relaxed = S.cvalid = false;
+  const size_t tm_elems = static_cast<size_t>(S0.N + 1) * S0.n;
+  const hipMemcpyKind h2d = h.par.device_pointers ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const hipMemcpyKind d2h = h.par.device_pointers ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  load_u0(h, u0);
+  if (u_init) {
+    double* tm = stage(h);
+    MG_HIP(hipMemcpyAsync(tm, u_init, sizeof(double) * tm_elems, h2d, s));
+    launch_tm_to_slabs(s, S0.n, S0.N + 1, h.m, tm, S0.U, S0.ld, S0.ss);
+  } else {
+    MG_HIP(hipMemsetAsync(S0.U, 0, sizeof(double) * S0.ss * h.m, s));
+  }
+  launch_axpby3(s, S0.n, 1, S0.U, S0.ld, 1.0, CView{h.u0_dev, 1}, 0.0, CView{}, 0.0, CView{});
+  auto t0 = std::chrono::steady_clock::now();
+  double rho0 = 0.0;
+  int status = MGRIT_OK;
+  for (int it = 0;; ++it) {
+    relax(h, 0);
+    c_residual(h, 0);
+    const double rho = residual_norm(h, 0);
+    if (st->n_history < MGRIT_MAX_HISTORY) st->rho[st->n_history++] = rho;
+    if (it == 0) rho0 = rho;
+    if (rho == 0.0 || rho <= h.par.tol * rho0) {
+      st->converged = 1;
+      break;
+    }
+    if (it >= h.par.max_iter) {
+      status = MGRIT_NOT_CONVERGED;
+      break;
+    }
+    coarse_correct(h, 0);
+    st->iterations = it + 1;
+  }
+  double* tm = h.par.device_pointers ? u_out : stage(h);
+  launch_slabs_to_tm(s, S0.n, S0.N + 1, h.m, S0.U, S0.ld, S0.ss, tm);
+  if (!h.par.device_pointers)
+    MG_HIP(hipMemcpyAsync(u_out, tm, sizeof(double) * tm_elems, d2h, s));
+  MG_HIP(hipStreamSynchronize(s));
+  st->time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (status != MGRIT_OK) fail(status, "MGRIT did not reach tol within max_iter iterations");
+}
+
+static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st) {
+  hipStream_t s = h.stream;
+  LevelState& S0 = h.lv[0];
+  if (!u_out) fail(MGRIT_INVALID_ARGUMENT, "u_out is null");
+  load_u0(h, u0);
+  // trajectory as a column block [n][N+1] (column t = point t)
+  const int64_t ld = round_up(S0.N + 1, kWave);
+  if (!h.seq_U) {
+    h.seq_U = h.arena.alloc<double>(static_cast<size_t>(S0.n) * ld);
+    h.seq_ws = h.arena.alloc<double>(4 * static_cast<size_t>(S0.n));
+  }
+  double* U = h.seq_U;
+  double* ws = h.seq_ws;
+  MG_HIP(hipMemsetAsync(U, 0, sizeof(double) * S0.n * ld, s));
+  launch_axpby3(s, S0.n, 1, U, ld, 1.0, CView{h.u0_dev, 1}, 0.0, CView{}, 0.0, CView{});
+  int* flags = S0.pcg.flags;
+  MG_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), s));
+  auto t0 = std::chrono::steady_clock::now();
+  launch_seq_small(s, S0.op, h.src, static_cast<int>(S0.N), 0, U, ld, nullptr, 0, ws,
+                   h.par.pcg_tol, h.par.pcg_max_iter, 0, flags);
+  MG_HIP(hipMemcpyAsync(S0.pcg.host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  st->time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  st->phi_columns[0] += S0.N;
+  st->pcg_sweeps[0] += S0.pcg.host_flags[2];
+  if (S0.pcg.host_flags[1] & 1) fail(MGRIT_NONFINITE, "non-finite value in sequential stepping");
+  if (S0.pcg.host_flags[1] & 2) fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in sequential stepping");
+  const size_t tm_elems = static_cast<size_t>(S0.N + 1) * S0.n;
+  double* tm = h.par.device_pointers ? u_out : stage(h);
+  launch_slabs_to_tm(s, S0.n, S0.N + 1, 1, U, ld, 0, tm);
+  if (!h.par.device_pointers)
+    MG_HIP(hipMemcpyAsync(u_out, tm, sizeof(double) * tm_elems, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, const double* u_prev,
+                          double* u_next) {
+  if (level < 0 || level >= static_cast<int>(h.lv.size())) fail(MGRIT_INVALID_ARGUMENT, "level");
+  if (B < 0 || (B > 0 && (!i_from || !u_prev || !u_next))) fail(MGRIT_INVALID_ARGUMENT, "phi_step arguments");
+  if (B == 0) return;
+  LevelState& S = h.lv[level];
+  hipStream_t s = h.stream;
+  if (S.user.cap < B) alloc_pcg(h, S.user, S.n, static_cast<int>(round_up(B, kWave)), rows_per_block_for(S.n));
+  PcgWork& w = S.user;
+  // staging: time-major input/output and the column-block copy of u_prev
+  double* tm = h.arena.alloc<double>(static_cast<size_t>(B) * S.n);
+  double* cols = h.arena.alloc<double>(static_cast<size_t>(S.n) * w.ld);
+  double* outc = h.arena.alloc<double>(static_cast<size_t>(S.n) * w.ld);
+  int64_t* tl = h.arena.alloc<int64_t>(B);
+  MG_HIP(hipMemcpyAsync(tm, u_prev, sizeof(double) * B * S.n, hipMemcpyHostToDevice, s));
+  MG_HIP(hipMemcpyAsync(tl, i_from, sizeof(int64_t) * B, hipMemcpyHostToDevice, s));
+  launch_tm_to_slabs(s, S.n, B, 1, tm, cols, w.ld, 0);
+  PhiCall c;
+  c.ncols = B;
+  c.in = CView{cols, w.ld};
+  c.t_list = tl;
+  c.ga = c.in;
+  c.out = outc;
+  c.ldo = w.ld;
+  phi_batch(h, level, w, c);
+  launch_slabs_to_tm(s, S.n, B, 1, outc, w.ld, 0, tm);
+  MG_HIP(hipMemcpyAsync(u_next, tm, sizeof(double) * B * S.n, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  // release the staging buffers of this call
+  for (void* p : {static_cast<void*>(tm), static_cast<void*>(cols), static_cast<void*>(outc),
+                  static_cast<void*>(tl)}) {
+    for (size_t k = 0; k < h.arena.ptrs.size(); ++k)
+      if (h.arena.ptrs[k] == p) {
+        (void)hipFree(p);
+        h.arena.ptrs.erase(h.arena.ptrs.begin() + k);
+        break;
+      }
+  }
+}
+
+}  // namespace mg
+
+// ---------------------------------------------------------------------------
+// C ABI.
+
+namespace {
+thread_local std::string g_setup_error;
+
+template <class F>
+int guarded(mg::Handle* h, F&& f) {
+  try {
+    f();
+    return MGRIT_OK;
+  } catch (const mg::Fail& e) {
+    if (h) h->last_error = e.msg;
+    else g_setup_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (h) h->last_error = "host allocation failed";
+    else g_setup_error = "host allocation failed";
+    return MGRIT_OUT_OF_MEMORY;
+  } catch (...) {
+    if (h) h->last_error = "unexpected error";
+    else g_setup_error = "unexpected error";
+    return MGRIT_HIP_ERROR;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+void mgrit_default_params(mgrit_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->m = 16;
+  p->gamma = 1;
+  p->precision = MGRIT_FP64;
+  p->restriction = MGRIT_R_NORMALIZED;
+  p->tol = 1e-8;
+  p->max_iter = 64;
+  p->pcg_tol = 1e-12;
+  p->pcg_max_iter = 5000;
+  p->pcg_check_every = 16;
+  p->ir_inner_tol = 1e-5;
+  p->ir_max_iter = 20;
+  p->newton_tol = 1e-10;
+  p->newton_max_iter = 8;
+  p->warm_start = 1;
+  p->device_pointers = 0;
+}
+
+int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
+  if (!out) return MGRIT_INVALID_ARGUMENT;
+  *out = nullptr;
+  auto h = std::make_unique<mg::Handle>();
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  const int rc = guarded(nullptr, [&] { mg::setup_impl(*h, prob, par); });
+  if (rc != MGRIT_OK) return rc;
+  *out = h.release();
+  return MGRIT_OK;
+}
+
+int mgrit_solve(void* hp, const double* u0, const double* u_init, double* u_out, mgrit_stats* st) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  mgrit_stats local;
+  mgrit_stats* s = st ? st : &local;
+  std::memset(s, 0, sizeof(*s));
+  h->st = s;
+  const int rc = guarded(h, [&] { mg::solve_impl(*h, u0, u_init, u_out, s); });
+  h->st = nullptr;
+  return rc;
+}
+
+int mgrit_seq_solve(void* hp, const double* u0, double* u_out, mgrit_stats* st) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  mgrit_stats local;
+  mgrit_stats* s = st ? st : &local;
+  std::memset(s, 0, sizeof(*s));
+  h->st = s;
+  const int rc = guarded(h, [&] { mg::seq_impl(*h, u0, u_out, s); });
+  h->st = nullptr;
+  return rc;
+}
+
+int phi_step(void* hp, int32_t level, int32_t B, const int64_t* i_from, const double* u_prev,
+             double* u_next) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] { mg::phi_step_impl(*h, level, B, i_from, u_prev, u_next); });
+}
+
+int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h || level < 0 || level >= static_cast<int>(h->lv.size())) return MGRIT_INVALID_ARGUMENT;
+  const auto& S = h->lv[level];
+  if (n) *n = S.n;
+  if (n_steps) *n_steps = S.N;
+  if (nnz) *nnz = static_cast<int64_t>(S.n) * S.op.W;
+  return MGRIT_OK;
+}
+
+void mgrit_destroy(void* hp) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete h;
+}
+
+const char* mgrit_strerror(int status) {
+  switch (status) {
+    case MGRIT_OK: return "ok";
+    case MGRIT_INVALID_ARGUMENT: return "invalid argument";
+    case MGRIT_NOT_NESTED: return "meshes are not nested";
+    case MGRIT_OUT_OF_MEMORY: return "out of memory";
+    case MGRIT_HIP_ERROR: return "HIP runtime error";
+    case MGRIT_PCG_NOT_CONVERGED: return "PCG did not converge";
+    case MGRIT_NEWTON_NOT_CONVERGED: return "Newton did not converge";
+    case MGRIT_NOT_CONVERGED: return "MGRIT did not converge";
+    case MGRIT_NONFINITE: return "non-finite value";
+    case MGRIT_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* mgrit_last_error(void* hp) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  return h ? h->last_error.c_str() : g_setup_error.c_str();
+}
+
+}  // extern "C"

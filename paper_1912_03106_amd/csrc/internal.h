@@ -1,0 +1,129 @@
+// Internal declarations of the MGRIT library: device data structures and the
+// launch wrappers of every kernel.  Not part of the public ABI (see mgrit.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mgrit.h"
+
+namespace mg {
+
+// ---------------------------------------------------------------------------
+// Errors: thrown inside the library, turned into mgrit_status at the C ABI.
+struct Fail {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define MG_HIP(x) ::mg::hip_check((x), #x)
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;        // threads of the batched kernels (4 waves)
+constexpr int kSeqThreads = 1024;  // threads of the single-workgroup stepper
+
+// Source parameters evaluated on the device (PWM, Sec. 3.2-3.3).
+struct SourceDev {
+  double scale;        // J0 * amplitude
+  double freq, f_carrier;
+  double phi[3];       // phases[p] + phase_offset
+  int carrier;         // 0 triangle, 1 sawtooth
+};
+
+// Column-block view: entry (row i, column c) at p[i * ld + c].
+struct CView {
+  const double* p = nullptr;
+  int64_t ld = 0;
+};
+
+// Operators of one level on the device.  The sparsity pattern is stored with a
+// fixed row width W (rows padded with a zero entry pointing at the row itself).
+struct DevLevel {
+  int n = 0, W = 0;
+  double dt = 0.0;
+  int* col = nullptr;          // [n*W]
+  double* a64 = nullptr;       // [n*W] A = M/dt + K (linear model)
+  float* a32 = nullptr;        // [n*W]
+  double* m64 = nullptr;       // [n*W] M/dt
+  uint8_t* has_mass = nullptr; // [n] row of M/dt is not identically zero
+  double* dinv64 = nullptr;    // [n] 1 / diag(A)
+  float* dinv32 = nullptr;
+  double* F = nullptr;         // [3][n] phase load vectors (unit current density x sign)
+};
+
+// Spatial transfer (rows = output nodes), fixed row width.
+struct DevTransfer {
+  int n_out = 0, n_in = 0, W = 0;
+  int* col = nullptr;
+  double* val = nullptr;
+};
+
+// Batched-PCG workspace for up to `cap` columns of an n-row level.
+struct PcgWork {
+  int n = 0, cap = 0, nrb = 0, rows_per_block = 0;
+  int64_t ld = 0;
+  double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  double* part = nullptr;       // [3][nrb][ld] per-row-block partial sums
+  double* scal = nullptr;       // [8][ld]: rz, rr, bb, alpha, beta, (spare)
+  double* src = nullptr;        // [3][ld] source value per phase and column
+  uint8_t* active = nullptr;    // [ld]
+  int* flags = nullptr;         // [4]: 0 active count, 1 error flag, 2.. spare
+  int* host_flags = nullptr;    // pinned copy of flags
+};
+
+enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3 };
+
+// --- setup kernels ---------------------------------------------------------
+void launch_elem_geometry(hipStream_t s, int n_tri, const double* xy, const int* tri,
+                          double* area, double* grad);
+void launch_assemble_linear(hipStream_t s, const DevLevel& L, const int* cptr, const int* contrib,
+                            const double* area, const double* grad, const double* nu_e,
+                            const double* sigma_e);
+void launch_diag_inverse(hipStream_t s, const DevLevel& L, const int* diag_slot);
+void launch_load_vectors(hipStream_t s, const DevLevel& L, const int* cptr, const int* contrib,
+                         const int* diag_slot, const double* area, const int* cell_phase,
+                         const int* cell_sign);
+
+// --- batched Phi / PCG kernels (FP64) ---------------------------------------
+void launch_source_table(hipStream_t s, const SourceDev& src, double dt, int ncols,
+                         const int64_t* t_list, int64_t t_base, int64_t t_stride,
+                         double* table, int64_t ld);
+void launch_axpby3(hipStream_t s, int n, int ncols, double* out, int64_t ldo, double sx,
+                   CView x, double sa, CView a, double sb, CView b);
+void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in);
+void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
+                   double* sums_out);
+void launch_spmm_dot(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
+void launch_pcg_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
+void launch_pcg_pupdate(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
+
+// Y = alpha * T X + beta * Y for a transfer operator (beta = 0: overwrite).
+void launch_transfer(hipStream_t s, const DevTransfer& T, int ncols, CView X, double alpha,
+                     double* Y, int64_t ldy, double beta);
+// Sum of squares of every column: per-column partials into w.part, reduced into sums.
+void launch_colsq(hipStream_t s, PcgWork& w, int n, int ncols, CView X);
+
+// Layout conversions.
+// time-major [npts][n] <-> slabs: point t -> slab t % m, column t / m.
+void launch_tm_to_slabs(hipStream_t s, int n, int64_t npts, int m, const double* tm,
+                        double* slabs, int64_t ld, int64_t slab_stride);
+void launch_slabs_to_tm(hipStream_t s, int n, int64_t npts, int m, const double* slabs,
+                        int64_t ld, int64_t slab_stride, double* tm);
+// column block [n][lds] (column t = point t) <-> slabs.
+void launch_cols_to_slabs(hipStream_t s, int n, int64_t npts, int m, const double* src,
+                          int64_t lds, double* slabs, int64_t ld, int64_t slab_stride);
+void launch_slabs_to_cols(hipStream_t s, int n, int64_t npts, int m, const double* slabs,
+                          int64_t ld, int64_t slab_stride, double* dst, int64_t ldd);
+
+// Single-workgroup sequential stepper for small levels: for s = 1..nsteps,
+// U[:, s] = Phi(U[:, s-1]) + G[:, s] (G may be null) by Jacobi-PCG.
+void launch_seq_small(hipStream_t s, const DevLevel& L, const SourceDev& src, int nsteps,
+                      int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
+                      double* ws, double tol, int maxit, int warm, int* flags);
+
+}  // namespace mg

@@ -1,0 +1,821 @@
+// HIP kernels of the MGRIT library (gfx950).
+//
+// Data layout of every batched kernel: a "column block" [n][ld] holds one
+// state vector per column (node-major, columns contiguous).  The columns are
+// the coarse time intervals of an F/C sweep (or the points of a coarse level),
+// so every column shares the sparsity pattern and the matrix values of the
+// level.  A wave owns 64 consecutive columns of one row at a time: the row's
+// pattern and values are wave-uniform (scalar loads), each lane streams its
+// own column, and the loads of a row's neighbours are 512-byte coalesced
+// segments.  A workgroup (4 waves) covers `rpb` consecutive rows of one
+// 64-column chunk; the chunk -> XCD mapping keeps the rows a chunk re-reads
+// (neighbours at +-1 and +-n_theta) inside one XCD's L2.
+//
+// Reductions (dot products, norms) are deterministic: per-workgroup partial
+// sums in a fixed order, then a fixed-order reduction per column.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace mg {
+
+namespace {
+
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+}
+
+// Work-group -> (row block, 64-column chunk).  Work-groups are dispatched
+// round-robin over the 8 XCDs (XCD = id % 8); when the chunk count is a
+// multiple of 8 each XCD owns a fixed set of chunks and walks their rows in
+// order, so the +-n_theta neighbour rows are L2 hits on the same XCD.
+__device__ __forceinline__ void tile_decode(int w, int nrb, int ncc, int& rb, int& cc) {
+  if ((ncc & 7) == 0) {
+    const int xcd = w & 7, local = w >> 3, per = ncc >> 3;
+    cc = xcd + 8 * (local % per);
+    rb = local / per;
+  } else {
+    cc = w % ncc;
+    rb = w / ncc;
+  }
+  (void)nrb;
+}
+
+// PWM signal b_p(t) = sgn(sin(2 pi f t + phi_p) - c(t)) (Sec. 3.2, 3.3).
+// A difference within 1e-12 of zero is a tie (sgn = 0): the time grids hit
+// r = c exactly (reference and carrier both at their peak 1 at t = T/4), and
+// the last ulp of the sine must not decide the sign there.
+__device__ __forceinline__ double pwm(double t, const SourceDev& s, int p) {
+  const double two_pi = 6.283185307179586;  // 2*pi rounded to double
+  const double ref = sin(two_pi * s.freq * t + s.phi[p]);
+  const double x = s.f_carrier * t;
+  const double c = (s.carrier == 0) ? 1.0 - 4.0 * fabs(x - floor(x + 0.5))
+                                    : 2.0 * (x - floor(x)) - 1.0;
+  const double d = ref - c;
+  return d > 1e-12 ? 1.0 : (d < -1e-12 ? -1.0 : 0.0);
+}
+
+// Sum the per-lane values v[0..NQ) of the 4 waves of a work-group in a fixed
+// order and store them, for every lane's column, at out[q * qstride + c].
+template <int NQ>
+__device__ __forceinline__ void block_partials(const double (&v)[NQ], double* out,
+                                               int64_t qstride, int c, bool on) {
+  __shared__ double red[NQ][4][kWave];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) red[q][wv][lane] = v[q];
+  __syncthreads();
+  if (wv == 0 && on) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      out[q * qstride + c] = ((red[q][0][lane] + red[q][1][lane]) + red[q][2][lane]) + red[q][3][lane];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Setup: element geometry and assembly (P1 Galerkin, eq. 7).
+
+__global__ void k_elem_geometry(int n_tri, const double* __restrict__ xy,
+                                const int* __restrict__ tri, double* __restrict__ area,
+                                double* __restrict__ grad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_tri) return;
+  const int v0 = tri[3 * e], v1 = tri[3 * e + 1], v2 = tri[3 * e + 2];
+  const double x0 = xy[2 * v0], y0 = xy[2 * v0 + 1];
+  const double x1 = xy[2 * v1], y1 = xy[2 * v1 + 1];
+  const double x2 = xy[2 * v2], y2 = xy[2 * v2 + 1];
+  const double det = (x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0);
+  area[e] = 0.5 * det;
+  // grad(phi_a) = (y_{a+1} - y_{a+2}, x_{a+2} - x_{a+1}) / det
+  const double inv = 1.0 / det;
+  double* g = grad + 6 * e;
+  g[0] = (y1 - y2) * inv; g[1] = (x2 - x1) * inv;
+  g[2] = (y2 - y0) * inv; g[3] = (x0 - x2) * inv;
+  g[4] = (y0 - y1) * inv; g[5] = (x1 - x0) * inv;
+}
+
+// One thread per stored entry (row i, slot k): K and M/dt are sums over the
+// (element, a, b) contributions listed for that entry, in a fixed order.
+__global__ void k_assemble_linear(int n, int W, double inv_dt, const int* __restrict__ cptr,
+                                  const int* __restrict__ contrib, const double* __restrict__ area,
+                                  const double* __restrict__ grad, const double* __restrict__ nu_e,
+                                  const double* __restrict__ sigma_e, double* __restrict__ a64,
+                                  float* __restrict__ a32, double* __restrict__ m64) {
+  const int64_t slot = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (slot >= static_cast<int64_t>(n) * W) return;
+  double kv = 0.0, mv = 0.0;
+  for (int t = cptr[slot]; t < cptr[slot + 1]; ++t) {
+    const int code = contrib[t];
+    const int e = code / 9, a = (code % 9) / 3, b = code % 3;
+    const double* g = grad + 6 * e;
+    kv += nu_e[e] * area[e] * (g[2 * a] * g[2 * b] + g[2 * a + 1] * g[2 * b + 1]);
+    mv += sigma_e[e] * area[e] * ((a == b) ? 2.0 : 1.0) / 12.0;
+  }
+  const double md = mv * inv_dt;
+  m64[slot] = md;
+  a64[slot] = md + kv;
+  a32[slot] = static_cast<float>(md + kv);
+}
+
+__global__ void k_diag_inverse(int n, int W, const int* __restrict__ diag_slot,
+                               const double* __restrict__ a64, const double* __restrict__ m64,
+                               double* __restrict__ dinv64, float* __restrict__ dinv32,
+                               uint8_t* __restrict__ has_mass) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = a64[static_cast<int64_t>(i) * W + diag_slot[i]];
+  dinv64[i] = 1.0 / d;
+  dinv32[i] = static_cast<float>(1.0 / d);
+  uint8_t hm = 0;
+  for (int k = 0; k < W; ++k) hm |= (m64[static_cast<int64_t>(i) * W + k] != 0.0);
+  has_mass[i] = hm;
+}
+
+// F_p[i] = sum over the elements touching node i with phase p of sign*area/3
+// (the diagonal entry's contribution list is exactly those elements).
+__global__ void k_load_vectors(int n, int W, const int* __restrict__ cptr,
+                               const int* __restrict__ contrib, const int* __restrict__ diag_slot,
+                               const double* __restrict__ area, const int* __restrict__ cell_phase,
+                               const int* __restrict__ cell_sign, double* __restrict__ F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t slot = static_cast<int64_t>(i) * W + diag_slot[i];
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int t = cptr[slot]; t < cptr[slot + 1]; ++t) {
+    const int e = contrib[t] / 9;
+    const int p = cell_phase[e];
+    if (p >= 0 && p < 3) f[p] += cell_sign[e] * area[e] / 3.0;
+  }
+  F[i] = f[0];
+  F[n + i] = f[1];
+  F[2 * n + i] = f[2];
+}
+
+// ----------------------------------------------------------------------------
+// Batched Phi / PCG.
+
+// table[p][c] = J0*amp * b_p(t) at the new time t = (i_from(c) + 1) * dt.
+__global__ void k_source_table(SourceDev s, double dt, int ncols, const int64_t* __restrict__ t_list,
+                               int64_t t_base, int64_t t_stride, double* __restrict__ table,
+                               int64_t ld) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const int64_t i_from = t_list ? t_list[c] : t_base + static_cast<int64_t>(c) * t_stride;
+  const double t = static_cast<double>(i_from + 1) * dt;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) table[p * ld + c] = s.scale * pwm(t, s, p);
+}
+
+__global__ void k_axpby3(int n, int ncols, double* __restrict__ out, int64_t ldo, double sx,
+                         const double* __restrict__ x, int64_t ldx, double sa,
+                         const double* __restrict__ a, int64_t lda, double sb,
+                         const double* __restrict__ b, int64_t ldb) {
+  const int c = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (c >= ncols || i >= n) return;
+  double v = 0.0;
+  if (x) v += sx * x[i * ldx + c];
+  if (a) v += sa * a[i * lda + c];
+  if (b) v += sb * b[i * ldb + c];
+  out[i * ldo + c] = v;
+}
+
+// r = b - A x0 with b = (M/dt) u_in + f(t), p = D^{-1} r; partials of
+// r.z, r.r, b.b.  Block 0 clears the active-column counter for the reduce
+// that follows.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(
+    int n, const int* __restrict__ col, const double* __restrict__ a,
+    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+    const double* __restrict__ dinv, const double* __restrict__ F, int ncols, int nrb, int ncc,
+    int rpb, const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src,
+    int64_t ld, const double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+    double* __restrict__ part, int* __restrict__ flags) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (on) { s0 = src[c]; s1 = src[ld + c]; s2 = src[2 * ld + c]; }
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      double bv = 0.0;
+      if (has_mass[i]) {
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+#pragma unroll
+        for (int t = 0; t < W; ++t) bv += mi[t] * uin[ci[t] * ldu + c];
+      }
+      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      const double* ai = a + static_cast<int64_t>(i) * W;
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t] * ld + c];
+      const double rv = bv - ax;
+      const double z = dinv[i] * rv;
+      r[i * ld + c] = rv;
+      p[i * ld + c] = z;
+      acc[0] += rv * z;
+      acc[1] += rv * rv;
+      acc[2] += bv * bv;
+    }
+  }
+  block_partials<3>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// q = A p and partials of p.q (active columns only).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_spmm_dot(
+    int n, const int* __restrict__ col, const double* __restrict__ a, int ncols, int nrb,
+    int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
+    const double* __restrict__ p, double* __restrict__ q, double* __restrict__ part) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && active[c];
+  double acc[1] = {0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      const double* ai = a + static_cast<int64_t>(i) * W;
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) s += ai[t] * p[ci[t] * ld + c];
+      q[i * ld + c] = s;
+      acc[0] += p[i * ld + c] * s;
+    }
+  }
+  block_partials<1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// x += alpha p, r -= alpha q, partials of r.z and r.r with z = D^{-1} r.
+__global__ __launch_bounds__(kBlock) void k_pcg_update(
+    int n, const double* __restrict__ dinv, int ncols, int nrb, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ active, const double* __restrict__ alpha,
+    double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+    const double* __restrict__ q, double* __restrict__ part) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && active[c];
+  double acc[2] = {0.0, 0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    const double al = alpha[c];
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int64_t o = i * ld + c;
+      x[o] += al * p[o];
+      const double rv = r[o] - al * q[o];
+      r[o] = rv;
+      acc[0] += rv * (dinv[i] * rv);
+      acc[1] += rv * rv;
+    }
+  }
+  block_partials<2>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// p = D^{-1} r + beta p (active columns only).
+__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(
+    int n, const double* __restrict__ dinv, int ncols, int nrb, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ active, const double* __restrict__ beta,
+    const double* __restrict__ r, double* __restrict__ p) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && active[c])) return;
+  const double be = beta[c];
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+    const int64_t o = i * ld + c;
+    p[o] = dinv[i] * r[o] + be * p[o];
+  }
+}
+
+// Sum of squares of every column over a row block.
+__global__ __launch_bounds__(kBlock) void k_colsq(int n, int ncols, int nrb, int ncc, int rpb,
+                                                  const double* __restrict__ X, int64_t ldx,
+                                                  double* __restrict__ part, int64_t ldp) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols;
+  double acc[1] = {0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const double v = X[i * ldx + c];
+      acc[0] += v * v;
+    }
+  }
+  block_partials<1>(acc, part + rb * ldp, static_cast<int64_t>(nrb) * ldp, c, on);
+}
+
+// Per-column reduction of the row-block partials, in a fixed order, followed
+// by the PCG scalar updates.  16 columns per work-group, 16 threads per column.
+__global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t ld, int mode,
+                                                   int nq, double tol2,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ scal,
+                                                   uint8_t* __restrict__ active,
+                                                   int* __restrict__ flags,
+                                                   double* __restrict__ sums_out) {
+  __shared__ double red[3][16][16];
+  __shared__ int cnt;
+  const int cl = threadIdx.x & 15, seg = threadIdx.x >> 4;
+  const int c = blockIdx.x * 16 + cl;
+  if (threadIdx.x == 0) cnt = 0;
+  if (mode == RED_ALPHA && blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
+  bool on = c < ncols;
+  if (on && (mode == RED_ALPHA || mode == RED_BETA)) on = active[c] != 0;
+  double S[3] = {0.0, 0.0, 0.0};
+  if (on) {
+    const int64_t qs = static_cast<int64_t>(nrb) * ld;
+    for (int rb = seg; rb < nrb; rb += 16) {
+      for (int q = 0; q < nq; ++q) S[q] += part[q * qs + rb * ld + c];
+    }
+  }
+  for (int q = 0; q < 3; ++q) red[q][seg][cl] = S[q];
+  __syncthreads();
+  if (seg == 0 && c < ncols) {
+    double T[3];
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+      for (int s = 0; s < 16; ++s) t += red[q][s][cl];
+      T[q] = t;
+    }
+    double* rz = scal;
+    double* rr = scal + ld;
+    double* bb = scal + 2 * ld;
+    double* al = scal + 3 * ld;
+    double* be = scal + 4 * ld;
+    int act = 0;
+    bool bad = false;
+    if (mode == RED_INIT) {
+      double b2 = T[2];
+      if (b2 == 0.0) b2 = T[1];
+      rz[c] = T[0];
+      rr[c] = T[1];
+      bb[c] = b2;
+      act = T[1] > tol2 * b2;
+      active[c] = static_cast<uint8_t>(act);
+      bad = !isfinite(T[0]) || !isfinite(T[1]) || !isfinite(T[2]);
+    } else if (mode == RED_ALPHA) {
+      if (on) {
+        const double a = rz[c] / T[0];
+        bad = !isfinite(a);
+        al[c] = bad ? 0.0 : a;
+      }
+    } else if (mode == RED_BETA) {
+      if (on) {
+        const double b = T[0] / rz[c];
+        rz[c] = T[0];
+        rr[c] = T[1];
+        be[c] = b;
+        act = T[1] > tol2 * bb[c];
+        active[c] = static_cast<uint8_t>(act);
+        bad = !isfinite(b) || !isfinite(T[1]);
+      }
+    } else {
+      sums_out[c] = T[0];
+      bad = !isfinite(T[0]);
+    }
+    if (bad) atomicOr(flags + 1, 1);
+    if (act) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt > 0 && (mode == RED_INIT || mode == RED_BETA)) atomicAdd(flags, cnt);
+}
+
+// Y = alpha * T X + beta * Y for a fixed-width transfer operator.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_transfer(int n_out, const int* __restrict__ col,
+                                                     const double* __restrict__ val, int ncols,
+                                                     const double* __restrict__ X, int64_t ldx,
+                                                     double alpha, double* __restrict__ Y,
+                                                     int64_t ldy, double beta) {
+  const int c = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + wave_index();
+  if (c >= ncols || i >= n_out) return;
+  const int* ci = col + static_cast<int64_t>(i) * W;
+  const double* vi = val + static_cast<int64_t>(i) * W;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < W; ++t) s += vi[t] * X[ci[t] * ldx + c];
+  const int64_t o = i * ldy + c;
+  Y[o] = (beta == 0.0) ? alpha * s : alpha * s + beta * Y[o];
+}
+
+// Tiled transposes between time-major trajectories and slabs.
+// Tile: 64 nodes x 64 slab columns of one slab (blockIdx.z = slab).
+__global__ __launch_bounds__(kBlock) void k_tm_to_slabs(int n, int64_t npts, int m,
+                                                        const double* __restrict__ tm,
+                                                        double* __restrict__ slabs, int64_t ld,
+                                                        int64_t ss) {
+  __shared__ double tile[64][65];
+  const int j = blockIdx.z;
+  const int64_t k0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int i0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int q = ty; q < 64; q += 4) {
+    const int64_t t = (k0 + q) * m + j;
+    const int i = i0 + tx;
+    tile[q][tx] = (t < npts && i < n) ? tm[t * n + i] : 0.0;
+  }
+  __syncthreads();
+  for (int q = ty; q < 64; q += 4) {
+    const int i = i0 + q;
+    const int64_t k = k0 + tx;
+    const int64_t t = k * m + j;
+    if (i < n && t < npts) slabs[j * ss + i * ld + k] = tile[tx][q];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_slabs_to_tm(int n, int64_t npts, int m,
+                                                        const double* __restrict__ slabs,
+                                                        int64_t ld, int64_t ss,
+                                                        double* __restrict__ tm) {
+  __shared__ double tile[64][65];
+  const int j = blockIdx.z;
+  const int64_t k0 = static_cast<int64_t>(blockIdx.x) * 64;
+  const int i0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int q = ty; q < 64; q += 4) {
+    const int i = i0 + q;
+    const int64_t k = k0 + tx;
+    const int64_t t = k * m + j;
+    tile[q][tx] = (i < n && t < npts) ? slabs[j * ss + i * ld + k] : 0.0;
+  }
+  __syncthreads();
+  for (int q = ty; q < 64; q += 4) {
+    const int64_t t = (k0 + q) * m + j;
+    const int i = i0 + tx;
+    if (t < npts && i < n) tm[t * n + i] = tile[tx][q];
+  }
+}
+
+__global__ void k_cols_to_slabs(int n, int64_t npts, int m, const double* __restrict__ src,
+                                int64_t lds, double* __restrict__ slabs, int64_t ld, int64_t ss) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= npts) return;
+  for (int i = blockIdx.y; i < n; i += gridDim.y)
+    slabs[(t % m) * ss + static_cast<int64_t>(i) * ld + t / m] = src[static_cast<int64_t>(i) * lds + t];
+}
+
+__global__ void k_slabs_to_cols(int n, int64_t npts, int m, const double* __restrict__ slabs,
+                                int64_t ld, int64_t ss, double* __restrict__ dst, int64_t ldd) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= npts) return;
+  for (int i = blockIdx.y; i < n; i += gridDim.y)
+    dst[static_cast<int64_t>(i) * ldd + t] = slabs[(t % m) * ss + static_cast<int64_t>(i) * ld + t / m];
+}
+
+// ----------------------------------------------------------------------------
+// Single-work-group sequential stepper (coarsest level, small sequential
+// baselines).  Vectors in global memory (L2-resident at these sizes); block
+// reductions in a fixed order.
+
+__device__ double block_sum(double v, double* sh) {
+  // wave reduction (fixed butterfly), then the 16 wave sums in order
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) t += sh[k];
+  return t;
+}
+
+template <int W>
+__global__ __launch_bounds__(kSeqThreads) void k_seq_small(
+    int n, const int* __restrict__ col, const double* __restrict__ a,
+    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+    const double* __restrict__ dinv, const double* __restrict__ F, SourceDev src, double dt,
+    int nsteps, int64_t t0, double* __restrict__ U, int64_t ldu, const double* __restrict__ G,
+    int64_t ldg, double* __restrict__ ws, double tol, int maxit, int warm,
+    int* __restrict__ flags) {
+  __shared__ double sh[32];
+  __shared__ double sgn[3];
+  __shared__ int stop;
+  if (threadIdx.x == 0) stop = 0;
+  double* x = ws;
+  double* r = ws + n;
+  double* p = ws + 2 * n;
+  double* q = ws + 3 * n;
+  const double tol2 = tol * tol;
+  int total_iters = 0;
+  for (int s = 1; s <= nsteps; ++s) {
+    if (threadIdx.x == 0) {
+      const double t = static_cast<double>(t0 + s) * dt;
+      for (int k = 0; k < 3; ++k) sgn[k] = src.scale * pwm(t, src, k);
+    }
+    __syncthreads();
+    const double s0 = sgn[0], s1 = sgn[1], s2 = sgn[2];
+    // initial guess
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double g = warm ? U[i * ldu + s] : U[i * ldu + s - 1];
+      if (warm && G) g -= G[i * ldg + s];
+      x[i] = g;
+    }
+    __syncthreads();
+    double lrz = 0.0, lrr = 0.0, lbb = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      double bv = 0.0;
+      if (has_mass[i]) {
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+        for (int t = 0; t < W; ++t) bv += mi[t] * U[ci[t] * ldu + s - 1];
+      }
+      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      const double* ai = a + static_cast<int64_t>(i) * W;
+      double ax = 0.0;
+      for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t]];
+      const double rv = bv - ax;
+      const double z = dinv[i] * rv;
+      r[i] = rv;
+      p[i] = z;
+      lrz += rv * z;
+      lrr += rv * rv;
+      lbb += bv * bv;
+    }
+    double rz = block_sum(lrz, sh);
+    double rr = block_sum(lrr, sh + 16);
+    double bb = block_sum(lbb, sh);
+    if (bb == 0.0) bb = rr;
+    int it = 0;
+    while (rr > tol2 * bb) {
+      if (it >= maxit) {
+        if (threadIdx.x == 0) {
+          atomicOr(flags + 1, 2);
+          stop = 1;
+        }
+        break;
+      }
+      __syncthreads();
+      double lpq = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int* ci = col + static_cast<int64_t>(i) * W;
+        const double* ai = a + static_cast<int64_t>(i) * W;
+        double sq = 0.0;
+        for (int t = 0; t < W; ++t) sq += ai[t] * p[ci[t]];
+        q[i] = sq;
+        lpq += p[i] * sq;
+      }
+      const double pq = block_sum(lpq, sh);
+      const double al = rz / pq;
+      double lz = 0.0;
+      lrr = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        x[i] += al * p[i];
+        const double rv = r[i] - al * q[i];
+        r[i] = rv;
+        lz += rv * (dinv[i] * rv);
+        lrr += rv * rv;
+      }
+      const double rzn = block_sum(lz, sh + 16);
+      rr = block_sum(lrr, sh);
+      const double be = rzn / rz;
+      rz = rzn;
+      if (!isfinite(rr)) {
+        if (threadIdx.x == 0) {
+          atomicOr(flags + 1, 1);
+          stop = 1;
+        }
+        break;
+      }
+      for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = dinv[i] * r[i] + be * p[i];
+      __syncthreads();
+      ++it;
+    }
+    total_iters += it;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double v = x[i];
+      if (G) v += G[i * ldg + s];
+      U[i * ldu + s] = v;
+    }
+    __syncthreads();
+    if (stop) break;
+  }
+  if (threadIdx.x == 0) atomicAdd(flags + 2, total_iters);
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Launch wrappers.
+
+void launch_elem_geometry(hipStream_t s, int n_tri, const double* xy, const int* tri,
+                          double* area, double* grad) {
+  hipLaunchKernelGGL(k_elem_geometry, dim3(ceil_div(n_tri, 256)), dim3(256), 0, s, n_tri, xy, tri,
+                     area, grad);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_assemble_linear(hipStream_t s, const DevLevel& L, const int* cptr, const int* contrib,
+                            const double* area, const double* grad, const double* nu_e,
+                            const double* sigma_e) {
+  const int64_t slots = static_cast<int64_t>(L.n) * L.W;
+  hipLaunchKernelGGL(k_assemble_linear, dim3(ceil_div(slots, 256)), dim3(256), 0, s, L.n, L.W,
+                     1.0 / L.dt, cptr, contrib, area, grad, nu_e, sigma_e, L.a64, L.a32, L.m64);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_diag_inverse(hipStream_t s, const DevLevel& L, const int* diag_slot) {
+  hipLaunchKernelGGL(k_diag_inverse, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, L.W,
+                     diag_slot, L.a64, L.m64, L.dinv64, L.dinv32, L.has_mass);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_load_vectors(hipStream_t s, const DevLevel& L, const int* cptr, const int* contrib,
+                         const int* diag_slot, const double* area, const int* cell_phase,
+                         const int* cell_sign) {
+  hipLaunchKernelGGL(k_load_vectors, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, L.W, cptr,
+                     contrib, diag_slot, area, cell_phase, cell_sign, L.F);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_source_table(hipStream_t s, const SourceDev& src, double dt, int ncols,
+                         const int64_t* t_list, int64_t t_base, int64_t t_stride, double* table,
+                         int64_t ld) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_source_table, dim3(ceil_div(ncols, 256)), dim3(256), 0, s, src, dt, ncols,
+                     t_list, t_base, t_stride, table, ld);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_axpby3(hipStream_t s, int n, int ncols, double* out, int64_t ldo, double sx, CView x,
+                   double sa, CView a, double sb, CView b) {
+  if (n <= 0 || ncols <= 0) return;
+  dim3 grid(ceil_div(ncols, kWave), ceil_div(n, 4));
+  hipLaunchKernelGGL(k_axpby3, grid, dim3(kBlock), 0, s, n, ncols, out, ldo, sx, x.p, x.ld, sa, a.p,
+                     a.ld, sb, b.p, b.ld);
+  MG_HIP(hipGetLastError());
+}
+
+static int grid_tiles(const PcgWork& w, int ncols, int& ncc) {
+  ncc = ceil_div(ncols, kWave);
+  return w.nrb * ncc;
+}
+
+void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  if (L.W == 8) {
+    hipLaunchKernelGGL(k_pcg_init<8>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
+                       L.has_mass, L.dinv64, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
+                       u_in.ld, w.src, w.ld, w.x, w.r, w.p, w.part, w.flags);
+  } else {
+    hipLaunchKernelGGL(k_pcg_init<16>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
+                       L.has_mass, L.dinv64, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
+                       u_in.ld, w.src, w.ld, w.x, w.r, w.p, w.part, w.flags);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
+                   double* sums_out) {
+  hipLaunchKernelGGL(k_reduce, dim3(ceil_div(ncols, 16)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
+                     mode, nq, tol2, w.part, w.scal, w.active, w.flags, sums_out);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_spmm_dot(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  if (L.W == 8) {
+    hipLaunchKernelGGL(k_spmm_dot<8>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, ncols, w.nrb,
+                       ncc, w.rows_per_block, w.ld, w.active, w.p, w.q, w.part);
+  } else {
+    hipLaunchKernelGGL(k_spmm_dot<16>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, ncols,
+                       w.nrb, ncc, w.rows_per_block, w.ld, w.active, w.p, w.q, w.part);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_pcg_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(kBlock), 0, s, L.n, L.dinv64, ncols, w.nrb, ncc,
+                     w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, w.x, w.r, w.p, w.q,
+                     w.part);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_pcg_pupdate(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  hipLaunchKernelGGL(k_pcg_pupdate, dim3(nb), dim3(kBlock), 0, s, L.n, L.dinv64, ncols, w.nrb,
+                     ncc, w.rows_per_block, w.ld, w.active, w.scal + 4 * w.ld, w.r, w.p);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_colsq(hipStream_t s, PcgWork& w, int n, int ncols, CView X) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  hipLaunchKernelGGL(k_colsq, dim3(nb), dim3(kBlock), 0, s, n, ncols, w.nrb, ncc, w.rows_per_block,
+                     X.p, X.ld, w.part, w.ld);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_transfer(hipStream_t s, const DevTransfer& T, int ncols, CView X, double alpha,
+                     double* Y, int64_t ldy, double beta) {
+  if (ncols <= 0) return;
+  dim3 grid(ceil_div(ncols, kWave), ceil_div(T.n_out, 4));
+  switch (T.W) {
+    case 2:
+      hipLaunchKernelGGL(k_transfer<2>, grid, dim3(kBlock), 0, s, T.n_out, T.col, T.val, ncols, X.p,
+                         X.ld, alpha, Y, ldy, beta);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_transfer<4>, grid, dim3(kBlock), 0, s, T.n_out, T.col, T.val, ncols, X.p,
+                         X.ld, alpha, Y, ldy, beta);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_transfer<8>, grid, dim3(kBlock), 0, s, T.n_out, T.col, T.val, ncols, X.p,
+                         X.ld, alpha, Y, ldy, beta);
+      break;
+    default:
+      hipLaunchKernelGGL(k_transfer<16>, grid, dim3(kBlock), 0, s, T.n_out, T.col, T.val, ncols,
+                         X.p, X.ld, alpha, Y, ldy, beta);
+      break;
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_tm_to_slabs(hipStream_t s, int n, int64_t npts, int m, const double* tm, double* slabs,
+                        int64_t ld, int64_t ss) {
+  const int64_t cols = (npts + m - 1) / m;
+  dim3 grid(ceil_div(cols, 64), ceil_div(n, 64), m);
+  hipLaunchKernelGGL(k_tm_to_slabs, grid, dim3(kBlock), 0, s, n, npts, m, tm, slabs, ld, ss);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_slabs_to_tm(hipStream_t s, int n, int64_t npts, int m, const double* slabs, int64_t ld,
+                        int64_t ss, double* tm) {
+  const int64_t cols = (npts + m - 1) / m;
+  dim3 grid(ceil_div(cols, 64), ceil_div(n, 64), m);
+  hipLaunchKernelGGL(k_slabs_to_tm, grid, dim3(kBlock), 0, s, n, npts, m, slabs, ld, ss, tm);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_cols_to_slabs(hipStream_t s, int n, int64_t npts, int m, const double* src,
+                          int64_t lds, double* slabs, int64_t ld, int64_t ss) {
+  dim3 grid(ceil_div(npts, 256), n < 4096 ? n : 4096);
+  hipLaunchKernelGGL(k_cols_to_slabs, grid, dim3(256), 0, s, n, npts, m, src, lds, slabs, ld, ss);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_slabs_to_cols(hipStream_t s, int n, int64_t npts, int m, const double* slabs,
+                          int64_t ld, int64_t ss, double* dst, int64_t ldd) {
+  dim3 grid(ceil_div(npts, 256), n < 4096 ? n : 4096);
+  hipLaunchKernelGGL(k_slabs_to_cols, grid, dim3(256), 0, s, n, npts, m, slabs, ld, ss, dst, ldd);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_seq_small(hipStream_t s, const DevLevel& L, const SourceDev& src, int nsteps,
+                      int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg, double* ws,
+                      double tol, int maxit, int warm, int* flags) {
+  if (nsteps <= 0) return;
+  if (L.W == 8) {
+    hipLaunchKernelGGL(k_seq_small<8>, dim3(1), dim3(kSeqThreads), 0, s, L.n, L.col, L.a64, L.m64,
+                       L.has_mass, L.dinv64, L.F, src, L.dt, nsteps, t0, U, ldu, G, ldg, ws, tol,
+                       maxit, warm, flags);
+  } else {
+    hipLaunchKernelGGL(k_seq_small<16>, dim3(1), dim3(kSeqThreads), 0, s, L.n, L.col, L.a64,
+                       L.m64, L.has_mass, L.dinv64, L.F, src, L.dt, nsteps, t0, U, ldu, G, ldg, ws,
+                       tol, maxit, warm, flags);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+}  // namespace mg

@@ -1,0 +1,185 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+`Solver(cfg)` builds the mgrit_problem / mgrit_params structs from a workload
+configuration and calls mgrit_setup; every computation then runs inside
+libmgrit.so on the GPU:
+
+    s = Solver(config("cfg1"))
+    U, stats = s.solve()          # FAS-MGRIT, time-major [(N_t+1), n0]
+    U_seq, _ = s.seq_solve()      # sequential stepping on the GPU
+    u1 = s.phi(0, U[:4], [0, 1, 2, 3])   # batched Phi (eq. 2)
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from workload import hierarchy
+from workload.machine import material_arrays
+
+from . import _abi
+from ._abi import MgritError
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _check(L, h, rc):
+    if rc != 0:
+        msg = L.mgrit_last_error(h)
+        raise MgritError(rc, msg.decode() if msg else "")
+
+
+class Solver:
+    """One mgrit_setup handle for a workload configuration."""
+
+    def __init__(self, cfg, meshes=None, stream=None, device_io=False, **overrides):
+        self._L = _abi.lib()
+        self.cfg = cfg
+        self.meshes = meshes if meshes is not None else hierarchy(cfg)
+        self.device_io = bool(device_io)
+        self._keep = []
+        mesh_arr = (_abi.Mesh * len(self.meshes))()
+        for k, m in enumerate(self.meshes):
+            arrs = dict(
+                xy=np.ascontiguousarray(m.xy, dtype=np.float64),
+                tri=np.ascontiguousarray(m.tri, dtype=np.int32),
+                cell_mat=np.ascontiguousarray(m.cell_mat, dtype=np.int32),
+                cell_phase=np.ascontiguousarray(m.cell_phase, dtype=np.int32),
+                cell_sign=np.ascontiguousarray(m.cell_sign, dtype=np.int32),
+                dirichlet=np.ascontiguousarray(m.dirichlet, dtype=np.uint8),
+            )
+            self._keep.append(arrs)
+            mesh_arr[k] = _abi.Mesh(
+                m.n_r, m.n_theta, m.n_nodes, m.n_tri,
+                _ptr(arrs["xy"], C.c_double), _ptr(arrs["tri"], C.c_int32),
+                _ptr(arrs["cell_mat"], C.c_int32), _ptr(arrs["cell_phase"], C.c_int32),
+                _ptr(arrs["cell_sign"], C.c_int32), _ptr(arrs["dirichlet"], C.c_uint8))
+        nu, sigma, iron = material_arrays()
+        mats = dict(nu=np.ascontiguousarray(nu), sigma=np.ascontiguousarray(sigma),
+                    iron=np.ascontiguousarray(iron, dtype=np.int32))
+        self._keep.append(mats)
+        src, bh = cfg.source, cfg.bh
+        phys = _abi.Physics(
+            len(nu), _ptr(mats["nu"], C.c_double), _ptr(mats["sigma"], C.c_double),
+            _ptr(mats["iron"], C.c_int32), int(bh.nonlinear), bh.k1, bh.k2, bh.k3,
+            src.J0, src.amplitude, src.freq, src.f_carrier, src.phase_offset,
+            (C.c_double * 3)(*src.phases), src.carrier_code, cfg.dt, cfg.n_steps)
+        self._mesh_arr = mesh_arr
+        self._prob = _abi.Problem(len(self.meshes), mesh_arr, phys)
+        par = _abi.Params()
+        self._L.mgrit_default_params(C.byref(par))
+        par.m = cfg.m
+        par.gamma = cfg.gamma
+        par.precision = {"fp64": _abi.FP64, "fp32_ir": _abi.FP32_IR}[cfg.precision]
+        par.tol = cfg.mgrit_tol
+        par.pcg_tol = cfg.pcg_tol
+        par.newton_tol = cfg.newton_tol
+        par.newton_max_iter = cfg.newton_maxit
+        par.device_pointers = int(self.device_io)
+        for k, v in overrides.items():
+            if not hasattr(par, k):
+                raise AttributeError(f"mgrit_params has no field {k}")
+            setattr(par, k, v)
+        self.params = par
+        h = C.c_void_p()
+        rc = self._L.mgrit_setup(C.byref(self._prob), C.byref(par),
+                                 C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc != 0:
+            msg = self._L.mgrit_last_error(None)
+            raise MgritError(rc, msg.decode() if msg else "")
+        self._h = h
+
+    # -- sizes -----------------------------------------------------------
+    def level_info(self, level):
+        n, N, nnz = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(self._L, self._h, self._L.mgrit_level_info(self._h, level, C.byref(n), C.byref(N),
+                                                          C.byref(nnz)))
+        return n.value, N.value, nnz.value
+
+    @property
+    def n0(self):
+        return self.level_info(0)[0]
+
+    # -- entry points ----------------------------------------------------
+    def _io(self, arr, shape, zero_ok=True):
+        if arr is None:
+            return None, None
+        if self.device_io:
+            return arr, C.c_void_p(arr.data_ptr())
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        if a.shape != shape:
+            raise ValueError(f"expected shape {shape}, got {a.shape}")
+        return a, a.ctypes.data_as(C.c_void_p)
+
+    def _out(self, out, shape):
+        if self.device_io:
+            if out is None:
+                raise ValueError("device_io solvers need a preallocated device output")
+            return out, C.c_void_p(out.data_ptr())
+        if out is None:
+            out = np.empty(shape)
+        return out, out.ctypes.data_as(C.c_void_p)
+
+    def solve(self, u0=None, u_init=None, out=None, raise_on_stall=True):
+        n0, N = self.n0, self.cfg.n_steps
+        u0a, u0p = self._io(u0, (n0,))
+        uia, uip = self._io(u_init, (N + 1, n0))
+        out, outp = self._out(out, (N + 1, n0))
+        st = _abi.Stats()
+        rc = self._L.mgrit_solve(self._h, u0p, uip, outp, C.byref(st))
+        if rc != 0 and not (rc == -7 and not raise_on_stall):
+            _check(self._L, self._h, rc)
+        return out, stats_dict(st)
+
+    def seq_solve(self, u0=None, out=None):
+        n0, N = self.n0, self.cfg.n_steps
+        u0a, u0p = self._io(u0, (n0,))
+        out, outp = self._out(out, (N + 1, n0))
+        st = _abi.Stats()
+        _check(self._L, self._h, self._L.mgrit_seq_solve(self._h, u0p, outp, C.byref(st)))
+        return out, stats_dict(st)
+
+    def phi(self, level, u_prev, i_from):
+        """Batched Phi of a level: u_prev [B, n_level], i_from [B] (host arrays)."""
+        u = np.ascontiguousarray(np.atleast_2d(u_prev), dtype=np.float64)
+        t = np.ascontiguousarray(np.atleast_1d(i_from), dtype=np.int64)
+        if t.shape[0] != u.shape[0]:
+            raise ValueError("i_from and u_prev disagree on B")
+        n = self.level_info(level)[0]
+        if u.shape[1] != n:
+            raise ValueError(f"u_prev must have {n} columns")
+        out = np.empty_like(u)
+        _check(self._L, self._h, self._L.phi_step(self._h, level, u.shape[0],
+                                                  t.ctypes.data_as(C.c_void_p),
+                                                  u.ctypes.data_as(C.c_void_p),
+                                                  out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mgrit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def stats_dict(st):
+    k = st.n_history
+    return dict(
+        iterations=st.iterations, converged=bool(st.converged), rho=list(st.rho[:k]),
+        phi_columns=list(st.phi_columns), pcg_sweeps=list(st.pcg_sweeps),
+        newton_sweeps=list(st.newton_sweeps), time_total_s=st.time_total_s,
+        time_relax_s=st.time_relax_s,
+    )

@@ -1,0 +1,115 @@
+"""GPU FAS-MGRIT and GPU sequential stepping against the oracle (Algorithm 1,
+Sec. 2.1, Sec. 2.2), through the C ABI."""
+
+import numpy as np
+import pytest
+
+from workload import config
+from workload.configs import LevelSpec
+from oracle.problem import build
+from oracle import mgrit, stepping
+
+pytestmark = pytest.mark.gpu
+
+SEQ_TOL = 1e-10     # GPU sequential stepping vs the direct-solve oracle
+MGRIT_GATE = 1e-7   # ||U - U_seq|| / ||U_seq|| after MGRIT stops at rho <= 1e-8 rho_0
+
+
+def _solver(cfg, **kw):
+    from paper_1912_03106_amd.solver import Solver
+    return Solver(cfg, **kw)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def cfg1_oracle():
+    cfg = config("cfg1")
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    U_mg, hist, conv = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=40)
+    assert conv
+    return cfg, U_seq, U_mg, hist
+
+
+def test_seq_solve_matches_oracle(cfg1_oracle):
+    print("seq cfg1", flush=True)
+    cfg, U_seq, _, _ = cfg1_oracle
+    s = _solver(cfg, pcg_tol=1e-13)
+    U, st = s.seq_solve()
+    assert U.shape == U_seq.shape
+    err = np.linalg.norm(U - U_seq, axis=1)[1:] / np.linalg.norm(U_seq, axis=1)[1:]
+    assert err.max() <= SEQ_TOL, err.max()
+
+
+def test_mgrit_two_level_matches_oracle(cfg1_oracle):
+    """Linear 16x128 machine, 1024 steps, two-level FCF, m = 16, no spatial coarsening."""
+    print("mgrit cfg1", flush=True)
+    cfg, U_seq, U_mg, hist = cfg1_oracle
+    s = _solver(cfg, pcg_tol=1e-12)
+    U, st = s.solve()
+    assert st["converged"]
+    # same iteration count as the textbook oracle (round-off may move the last one)
+    assert abs(len(st["rho"]) - len(hist)) <= 1, (st["rho"], hist)
+    # residual histories agree while rho is well above the linear-solve tolerance
+    for a, b in zip(st["rho"][:5], hist[:5]):
+        assert a == pytest.approx(b, rel=1e-6)
+    assert _rel(U, U_seq) <= MGRIT_GATE
+    assert _rel(U, U_mg) <= MGRIT_GATE
+    assert st["rho"][-1] <= cfg.mgrit_tol * st["rho"][0]
+
+
+def test_mgrit_exact_after_nt_over_2m_fcf(cfg1_oracle):
+    """FCF reaches the sequential solution after N_t/(2m) iterations (Sec. 2.1)."""
+    cfg, U_seq, _, _ = cfg1_oracle
+    s = _solver(cfg, pcg_tol=1e-13, tol=0.0, max_iter=32)
+    U, st = s.solve(raise_on_stall=False)
+    assert st["iterations"] == 32
+    assert _rel(U, U_seq) <= 1e-10
+
+
+def _sc_cfg():
+    cfg = config("cfg1")
+    cfg.meshes = [LevelSpec(32, 256), LevelSpec(16, 128), LevelSpec(8, 64)]
+    cfg.n_steps, cfg.m = 1024, 16
+    return cfg
+
+
+def test_mgrit_three_level_spatial_coarsening_matches_oracle():
+    """Three-level V-cycle, direct spatial coarsening 32x256 -> 16x128 -> 8x64."""
+    print("mgrit 3-level SC", flush=True)
+    cfg = _sc_cfg()
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    s = _solver(cfg, pcg_tol=1e-12)
+    U, st = s.solve()
+    assert st["converged"]
+    assert _rel(U, U_seq) <= MGRIT_GATE
+    # iteration count of the textbook algorithm on this problem (oracle: 11)
+    _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=3)
+    for a, b in zip(st["rho"][:4], hist[:4]):
+        assert a == pytest.approx(b, rel=1e-6)
+    assert abs(len(st["rho"]) - 11) <= 1
+
+
+def test_mgrit_failure_modes(cfg1_oracle):
+    cfg, _, _, _ = cfg1_oracle
+    from paper_1912_03106_amd import MgritError
+    s = _solver(cfg, pcg_max_iter=1)
+    with pytest.raises(MgritError) as e:
+        s.solve()
+    assert e.value.name == "PCG_NOT_CONVERGED"
+    s = _solver(cfg, max_iter=1)
+    with pytest.raises(MgritError) as e:
+        s.solve()
+    assert e.value.name == "NOT_CONVERGED"
+    s = _solver(cfg)
+    guess = np.zeros((cfg.n_steps + 1, s.n0))
+    guess[5, 3] = np.nan
+    with pytest.raises(MgritError) as e:
+        s.solve(u_init=guess)
+    assert e.value.name == "NONFINITE"

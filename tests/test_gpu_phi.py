@@ -1,0 +1,96 @@
+"""GPU parity of the batched propagator Phi (eq. 2, eq. 8) against the oracle's
+direct sparse solve, through the C ABI (phi_step)."""
+
+import numpy as np
+import pytest
+
+from workload import config, polar_mesh
+from workload.configs import LevelSpec
+from oracle.stepping import Level, sequential
+
+pytestmark = pytest.mark.gpu
+
+PHI_TOL = 1e-10          # relative 2-norm error per column (FP64 Phi)
+
+
+def _solver(cfg, **kw):
+    from paper_1912_03106_amd.solver import Solver
+    return Solver(cfg, **kw)
+
+
+def _col_err(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+@pytest.fixture(scope="module")
+def cfg1_pair():
+    cfg = config("cfg1")
+    s = _solver(cfg, pcg_tol=1e-13)
+    lev = Level(polar_mesh(16, 128), cfg.dt, cfg.source)
+    U = sequential(lev, np.zeros(lev.n), 200)
+    return cfg, s, lev, U
+
+
+@pytest.mark.parametrize("B", [1, 63, 64, 65, 200])
+def test_phi_matches_direct_solve(cfg1_pair, B):
+    cfg, s, lev, U = cfg1_pair
+    print(f"phi parity 16x128 B={B}", flush=True)
+    rng = np.random.default_rng(B)
+    i_from = rng.integers(0, cfg.n_steps - 1, size=B)
+    # realistic states (a trajectory) plus a perturbation
+    u_prev = U[rng.integers(1, U.shape[0], size=B)] + 1e-4 * rng.standard_normal((B, lev.n))
+    got = s.phi(0, u_prev, i_from)
+    ref = lev.phi(u_prev, i_from)
+    err = _col_err(got, ref)
+    assert err.max() <= PHI_TOL, err.max()
+
+
+def test_phi_coarse_level_step(cfg1_pair):
+    """Level 1 of the two-level hierarchy uses dt_1 = m dt (re-discretisation)."""
+    cfg, s, _, U = cfg1_pair
+    lev1 = Level(polar_mesh(16, 128), cfg.level_dt(1), cfg.source)
+    rng = np.random.default_rng(7)
+    u_prev = U[rng.integers(1, U.shape[0], size=10)]
+    i_from = rng.integers(0, cfg.level_steps(1) - 1, size=10)
+    err = _col_err(s.phi(1, u_prev, i_from), lev1.phi(u_prev, i_from))
+    assert err.max() <= PHI_TOL, err.max()
+
+
+def test_phi_is_deterministic(cfg1_pair):
+    cfg, s, lev, U = cfg1_pair
+    rng = np.random.default_rng(3)
+    u_prev = U[rng.integers(1, U.shape[0], size=70)]
+    i_from = rng.integers(0, 1000, size=70)
+    a = s.phi(0, u_prev, i_from)
+    b = s.phi(0, u_prev, i_from)
+    assert np.array_equal(a, b)
+
+
+def test_phi_edge_cases(cfg1_pair):
+    cfg, s, lev, U = cfg1_pair
+    from paper_1912_03106_amd import MgritError
+    # zero state at a time where every source is active equals the magnetostatic-with-mass solve
+    out = s.phi(0, np.zeros((2, lev.n)), [0, 511])
+    ref = lev.phi(np.zeros((2, lev.n)), [0, 511])
+    assert _col_err(out, ref).max() <= PHI_TOL
+    with pytest.raises(MgritError) as e:
+        s.phi(5, np.zeros((1, lev.n)), [0])
+    assert e.value.name == "INVALID_ARGUMENT"
+
+
+def test_phi_full_size_sampled_columns():
+    """The 64 x 512 level of the large linear workload (n = 32,256, dt = 0.02/16384),
+    on sampled columns the oracle solves one by one."""
+    print("phi parity 64x512 sampled", flush=True)
+    cfg = config("cfg2")
+    cfg.meshes = [LevelSpec(64, 512), LevelSpec(32, 256)]
+    s = _solver(cfg, pcg_tol=1e-13, m=16)
+    lev = Level(polar_mesh(64, 512), cfg.dt, cfg.source)
+    U = sequential(lev, np.zeros(lev.n), 24)
+    rng = np.random.default_rng(11)
+    i_from = np.array([3, 100, 2047, 5000, 9999, 16382, 12, 777])
+    u_prev = U[rng.integers(5, 25, size=8)]
+    got = s.phi(0, u_prev, i_from)
+    ref = lev.phi(u_prev, i_from)
+    err = _col_err(got, ref)
+    assert err.max() <= PHI_TOL, err
