@@ -1,0 +1,186 @@
+"""Benchmark: FAS-MGRIT on the large linear machine workload, one MI355X.
+
+Workload: linear eddy-current machine on the 64 x 512 polar mesh (n = 32,256
+unknowns), 16,384 implicit-Euler steps over one 50 Hz period, three-level
+V-cycle (m = 16, FCF, direct spatial coarsening 64x512 -> 32x256 -> 16x128),
+batched FP64 Jacobi-PCG, stop at a 1e-8 relative C-point residual.
+
+One bench step = one complete MGRIT solve to the tolerance (every part of the
+hot path: F/C relaxation, C-point residual, restriction, FAS right-hand side,
+coarse solves, correction).  `value` is the useful throughput n0 * N_t / T of
+that solve in DOF-steps/s, inputs resident on the GPU.
+
+Also reported (same JSON line): GPU sequential stepping on the same problem
+(timed on a prefix of the horizon and scaled to N_t), the F-relaxation
+DOF-steps/s, the roofline of the dominant kernel (PCG pass B) from HIP-event
+timings of every launch in the timed region, and the CPU oracle timed on this
+host.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pass_b_roofline(st, solver):
+    """Algorithmic bytes of PCG pass B over the timed region / its device time.
+
+    Per unconverged column of one row: read p, x, r and write x, r = 5 values;
+    per launch: the level's matrix (W values + W column indices per row) and
+    the Jacobi diagonal.
+    """
+    bytes_total = 0.0
+    launches = 0
+    t = 0.0
+    for l in range(solver.cfg.n_levels):
+        n, _, nnz = solver.level_info(l)
+        W = nnz // n
+        cols = st["kernel_columns"][l]
+        lau = st["kernel_launches"][1][l]
+        bytes_total += 5 * 8 * n * cols + lau * n * (W * 12 + 8)
+        launches += lau
+        t += st["kernel_time_s"][1][l]
+    if launches == 0 or t <= 0:
+        return None
+    achieved = bytes_total / t / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_pcg_pass_b<double,8>", "launches": launches,
+            "avg_launch_us": round(1e6 * t / launches, 2),
+            "bytes_per_launch": round(bytes_total / launches)}
+
+
+def cpu_baseline(cfg, budget_s=12.0):
+    """The oracle's sequential stepping (SuperLU factor + one triangular solve
+    pair per step, single thread) on a prefix of the same workload."""
+    import numpy as np
+    from workload import polar_mesh
+    from oracle.stepping import Level
+    spec = cfg.meshes[0]
+    t0 = time.perf_counter()
+    lev = Level(polar_mesh(spec.n_r, spec.n_theta), cfg.dt, cfg.source)
+    t_fact = time.perf_counter() - t0
+    u = np.zeros(lev.n)
+    steps = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s and steps < cfg.n_steps:
+        u = lev.phi(u[None], [steps])[0]
+        steps += 1
+    el = time.perf_counter() - t1
+    return {"value": round(lev.n * steps / el, 1), "unit": "DOF-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"sequential implicit Euler, SuperLU, first {steps} of {cfg.n_steps} steps "
+                      f"on the {spec.n_r}x{spec.n_theta} mesh (factorisation {t_fact:.2f} s excluded); "
+                      f"host has {os.cpu_count()} logical CPUs",
+            "extrapolated_full_horizon_s": round(el / steps * cfg.n_steps + t_fact, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--seq-prefix", type=int, default=256,
+                    help="steps of the GPU sequential baseline actually run (scaled to N_t)")
+    ap.add_argument("--no-seq", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-parallel "
+              "decomposition over several GPUs is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from workload import config
+    from paper_1912_03106_amd.solver import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cfg = config(args.config)
+    log(f"setup {cfg.name}")
+    solver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1)
+    n0 = solver.n0
+    out = torch.empty((cfg.n_steps + 1, n0), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        solver.solve(out=out)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        _, st = solver.solve(out=out)
+        stats.append(st)
+        log(f"solve {k + 1}/{args.steps}: {len(st['rho']) - 1} iterations, {st['time_total_s']:.2f} s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = stats[-1]
+    per = el / args.steps
+    value = n0 * cfg.n_steps / per
+    rho = st["rho"]
+    n_t = cfg.level_steps(1)                     # intervals = C-point residual columns per iteration
+    frelax_cols = st["phi_columns"][0] - len(rho) * n_t
+
+    seq = None
+    if not args.no_seq:
+        pre = min(args.seq_prefix, cfg.n_steps)
+        pcfg = config(args.config, n_steps=pre, t_final=pre * cfg.dt)
+        pcfg.meshes = cfg.meshes[:1] * 2
+        ps = Solver(pcfg, stream=stream.cuda_stream, device_io=True)
+        pout = torch.empty((pre + 1, n0), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, sst = ps.seq_solve(out=pout)
+        torch.cuda.synchronize()
+        tseq = time.perf_counter() - ts
+        seq = {"kernel": "single-workgroup persistent Jacobi-PCG stepper", "steps_run": pre,
+               "time_s_run": round(tseq, 3), "time_s_full_horizon": round(tseq * cfg.n_steps / pre, 2),
+               "dof_steps_per_s": round(n0 * pre / tseq, 1),
+               "pcg_iterations_per_step": round(sst["pcg_sweeps"][0] / pre, 1)}
+        ps.close()
+        log(f"sequential prefix {pre} steps: {tseq:.2f} s")
+
+    roof = pass_b_roofline(st, solver)
+    cpu = None if args.no_cpu else cpu_baseline(cfg)
+    line = {
+        "metric": "MGRIT time to 1e-8 rel. resid vs GPU seq. stepping; F-relax DOF-steps/s, GB/s",
+        "value": round(value, 1), "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * per, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "linear eddy-current machine, 64x512 polar P1 mesh (n=32256), "
+                               "16384 implicit-Euler steps over 0.02 s, PWM 20 kHz; 3-level V-cycle "
+                               "m=16 FCF, spatial coarsening 64x512/32x256/16x128; FP64 Jacobi-PCG",
+                   "n_dof": n0, "n_steps": cfg.n_steps, "levels": cfg.n_levels, "m": cfg.m},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "mgrit": {"time_to_solution_s": round(per, 3), "iterations": len(rho) - 1,
+                  "rho_rel_final": rho[-1] / rho[0] if rho and rho[0] else None,
+                  "frelax_dof_steps_per_s": round(n0 * frelax_cols / st["time_relax_s"], 1)
+                  if st["time_relax_s"] > 0 else None,
+                  "level0_phi": frelax_cols, "pcg_sweeps": st["pcg_sweeps"][:cfg.n_levels],
+                  "pass_a_time_s": [round(x, 3) for x in st["kernel_time_s"][0][:cfg.n_levels]],
+                  "pass_b_time_s": [round(x, 3) for x in st["kernel_time_s"][1][:cfg.n_levels]]},
+        "gpu_sequential": seq,
+    }
+    if seq:
+        line["mgrit"]["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon"] / per, 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -110,6 +110,7 @@ typedef struct {
   int32_t newton_max_iter;
   int32_t warm_start;         /* 1: linear solves start from the previous iterate */
   int32_t device_pointers;    /* 1: u_init / u_out of mgrit_solve are device pointers */
+  int32_t profile_kernels;    /* 1: time every PCG pass with HIP events (mgrit_stats.kernel_*) */
 } mgrit_params;
 
 typedef struct {
@@ -120,7 +121,15 @@ typedef struct {
   int64_t phi_columns[MGRIT_MAX_LEVELS];   /* Phi applications per level        */
   int64_t pcg_sweeps[MGRIT_MAX_LEVELS];    /* batched PCG iterations per level   */
   int64_t newton_sweeps[MGRIT_MAX_LEVELS];
-  double  time_relax_s;       /* finest-level F/C relaxation time (device)      */
+  /* batched PCG passes per level: [0] pass A (new direction, p.Ap), [1] pass B
+   * (x, r update).  Launches and device time count every launch (including
+   * the few at the end of a check interval that find every column converged
+   * and exit at once); kernel_columns sums the unconverged columns the
+   * launches worked on. */
+  int64_t kernel_launches[2][MGRIT_MAX_LEVELS];
+  int64_t kernel_columns[MGRIT_MAX_LEVELS];
+  double  kernel_time_s[2][MGRIT_MAX_LEVELS];   /* needs profile_kernels = 1 */
+  double  time_relax_s;       /* finest-level F/C relaxation time (device events) */
   double  time_total_s;
 } mgrit_stats;
 

@@ -56,7 +56,7 @@ class Params(C.Structure):
         ("tol", C.c_double), ("max_iter", C.c_int32), ("pcg_tol", C.c_double),
         ("pcg_max_iter", C.c_int32), ("pcg_check_every", C.c_int32), ("ir_inner_tol", C.c_double),
         ("ir_max_iter", C.c_int32), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
-        ("warm_start", C.c_int32), ("device_pointers", C.c_int32),
+        ("warm_start", C.c_int32), ("device_pointers", C.c_int32), ("profile_kernels", C.c_int32),
     ]
 
 
@@ -66,6 +66,8 @@ class Stats(C.Structure):
         ("rho", C.c_double * MAX_HISTORY),
         ("phi_columns", C.c_int64 * MAX_LEVELS), ("pcg_sweeps", C.c_int64 * MAX_LEVELS),
         ("newton_sweeps", C.c_int64 * MAX_LEVELS),
+        ("kernel_launches", (C.c_int64 * MAX_LEVELS) * 2), ("kernel_columns", C.c_int64 * MAX_LEVELS),
+        ("kernel_time_s", (C.c_double * MAX_LEVELS) * 2),
         ("time_relax_s", C.c_double), ("time_total_s", C.c_double),
     ]
 

@@ -8,6 +8,7 @@
 // block [n][ld] with column t = point t.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -59,6 +60,7 @@ struct Handle {
   double* seq_ws = nullptr;
   mgrit_stats* st = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> ev;     // 4 per PCG iteration of a chunk (profiling)
 };
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -72,8 +74,12 @@ static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block)
   const size_t vec = static_cast<size_t>(n) * w.ld;
   w.x = h.arena.alloc<double>(vec);
   w.r = h.arena.alloc<double>(vec);
-  w.p = h.arena.alloc<double>(vec);
-  w.q = h.arena.alloc<double>(vec);
+  w.pbuf[0] = h.arena.alloc<double>(vec);
+  w.pbuf[1] = h.arena.alloc<double>(vec);
+  w.parity = 0;
+  w.hist_cap = h.par.pcg_max_iter + 64;
+  w.hist = h.arena.alloc<int>(w.hist_cap);
+  w.host_hist = static_cast<int*>(h.arena.alloc_host(sizeof(int) * w.hist_cap));
   w.part = h.arena.alloc<double>(3 * static_cast<size_t>(w.nrb) * w.ld);
   w.scal = h.arena.alloc<double>(8 * static_cast<size_t>(w.ld));
   w.src = h.arena.alloc<double>(3 * static_cast<size_t>(w.ld));
@@ -90,37 +96,68 @@ static int rows_per_block_for(int n) {
 
 // ---------------------------------------------------------------------------
 // Batched PCG: solves (M/dt + K) x = (M/dt) u_in + f(t) for every column, x
-// initialised in w.x.  Returns the number of batched sweeps.
-static int pcg_solve(Handle& h, const DevLevel& L, PcgWork& w, int ncols, CView in) {
+// initialised in w.x.  Each iteration is pass A, reduce (alpha), pass B,
+// reduce (beta, convergence); converged columns drop out of every kernel.
+// The host reads the active-column count every pcg_check_every iterations.
+// Returns the number of iterations in which some column was active.
+static int pcg_solve(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, CView in) {
   hipStream_t s = h.stream;
   const double tol2 = h.par.pcg_tol * h.par.pcg_tol;
+  const bool prof = h.par.profile_kernels && h.st && level < MGRIT_MAX_LEVELS;
   launch_pcg_init(s, L, w, ncols, in);
   launch_reduce(s, w, ncols, RED_INIT, tol2, 3, nullptr);
-  MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
-  int it = 0;
+  int it = 0, used = 0;
   int active = w.host_flags[0];
-  const int chunk = h.par.pcg_check_every > 0 ? h.par.pcg_check_every : 16;
+  const int chunk = std::max(1, std::min(h.par.pcg_check_every > 0 ? h.par.pcg_check_every : 16,
+                                         static_cast<int>(h.ev.size() / 4)));
+  int64_t cols = 0, launches = 0;
   while (active > 0) {
     if (it >= h.par.pcg_max_iter)
       fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in pcg_max_iter iterations (" +
                                         std::to_string(active) + " columns left)");
-    const int k = std::min(chunk, h.par.pcg_max_iter - it);
+    const int k = std::min(chunk, std::min(h.par.pcg_max_iter, w.hist_cap) - it);
     for (int t = 0; t < k; ++t) {
-      launch_spmm_dot(s, L, w, ncols);
+      if (prof) MG_HIP(hipEventRecord(h.ev[4 * t], s));
+      launch_pcg_pass_a(s, L, w, ncols, it + t == 0, it + t);
+      if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 1], s));
       launch_reduce(s, w, ncols, RED_ALPHA, tol2, 1, nullptr);
-      launch_pcg_update(s, L, w, ncols);
+      if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 2], s));
+      launch_pcg_pass_b(s, L, w, ncols);
+      if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 3], s));
       launch_reduce(s, w, ncols, RED_BETA, tol2, 2, nullptr);
-      launch_pcg_pupdate(s, L, w, ncols);
     }
-    it += k;
-    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipMemcpyAsync(w.host_hist, w.hist + it, sizeof(int) * k, hipMemcpyDeviceToHost, s));
     MG_HIP(hipStreamSynchronize(s));
     if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
+    for (int t = 0; t < k; ++t) {
+      const int a = w.host_hist[t];
+      if (a > 0) {
+        ++used;
+        cols += a;
+      }
+      if (prof) {
+        float ta = 0.f, tb = 0.f;
+        MG_HIP(hipEventElapsedTime(&ta, h.ev[4 * t], h.ev[4 * t + 1]));
+        MG_HIP(hipEventElapsedTime(&tb, h.ev[4 * t + 2], h.ev[4 * t + 3]));
+        h.st->kernel_time_s[0][level] += 1e-3 * ta;
+        h.st->kernel_time_s[1][level] += 1e-3 * tb;
+      }
+    }
+    launches += k;
+    it += k;
     active = w.host_flags[0];
   }
-  return it;
+  if (h.st && level < MGRIT_MAX_LEVELS) {
+    h.st->kernel_launches[0][level] += launches;
+    h.st->kernel_launches[1][level] += launches;
+    h.st->kernel_columns[level] += cols;
+  }
+  w.parity = 0;
+  return used;
 }
 
 // One batched application of Phi on level l:
@@ -148,7 +185,7 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
   hipStream_t s = h.stream;
   launch_source_table(s, h.src, S.op.dt, c.ncols, c.t_list, c.t_base, c.t_stride, w.src, w.ld);
   launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
-  const int it = pcg_solve(h, S.op, w, c.ncols, c.in);
+  const int it = pcg_solve(h, l, S.op, w, c.ncols, c.in);
   launch_axpby3(s, S.n, c.ncols, c.out, c.ldo, c.osx, CView{w.x, w.ld}, 1.0, c.oa, c.osb, c.ob);
   if (h.st && l < MGRIT_MAX_LEVELS) {
     h.st->phi_columns[l] += c.ncols;
@@ -439,6 +476,9 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   h.u0_dev = h.arena.alloc<double>(h.lv[0].n);
   MG_HIP(hipEventCreate(&h.ev0));
   MG_HIP(hipEventCreate(&h.ev1));
+  const int chunk = std::max(1, std::min(par->pcg_check_every > 0 ? par->pcg_check_every : 16, 64));
+  h.ev.resize(4 * chunk);
+  for (auto& e : h.ev) MG_HIP(hipEventCreate(&e));
   MG_HIP(hipStreamSynchronize(s));
 }
 
@@ -484,7 +524,13 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
   double rho0 = 0.0;
   int status = MGRIT_OK;
   for (int it = 0;; ++it) {
+    MG_HIP(hipEventRecord(h.ev0, s));
     relax(h, 0);
+    MG_HIP(hipEventRecord(h.ev1, s));
+    MG_HIP(hipEventSynchronize(h.ev1));
+    float ms = 0.f;
+    MG_HIP(hipEventElapsedTime(&ms, h.ev0, h.ev1));
+    st->time_relax_s += 1e-3 * ms;
     c_residual(h, 0);
     const double rho = residual_norm(h, 0);
     if (st->n_history < MGRIT_MAX_HISTORY) st->rho[st->n_history++] = rho;
@@ -633,6 +679,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->newton_max_iter = 8;
   p->warm_start = 1;
   p->device_pointers = 0;
+  p->profile_kernels = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -693,6 +740,7 @@ void mgrit_destroy(void* hp) {
   (void)hipStreamSynchronize(h->stream);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  for (auto e : h->ev) (void)hipEventDestroy(e);
   delete h;
 }
 

@@ -67,13 +67,19 @@ struct DevTransfer {
 struct PcgWork {
   int n = 0, cap = 0, nrb = 0, rows_per_block = 0;
   int64_t ld = 0;
-  double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  double *x = nullptr, *r = nullptr;
+  double* pbuf[2] = {nullptr, nullptr};  // search directions, ping-pong
+  int parity = 0;                        // pbuf[parity] holds the current p
   double* part = nullptr;       // [3][nrb][ld] per-row-block partial sums
   double* scal = nullptr;       // [8][ld]: rz, rr, bb, alpha, beta, (spare)
   double* src = nullptr;        // [3][ld] source value per phase and column
   uint8_t* active = nullptr;    // [ld]
-  int* flags = nullptr;         // [4]: 0 active count, 1 error flag, 2.. spare
+  int* flags = nullptr;         // [4]: 0 active count, 1 error bits, 2 iterations,
+                                //      3 sum of active columns over iterations
   int* host_flags = nullptr;    // pinned copy of flags
+  int* hist = nullptr;          // [max_iter] active columns of every PCG iteration
+  int* host_hist = nullptr;     // pinned copy
+  int hist_cap = 0;
 };
 
 enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3 };
@@ -98,9 +104,10 @@ void launch_axpby3(hipStream_t s, int n, int ncols, double* out, int64_t ldo, do
 void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in);
 void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
                    double* sums_out);
-void launch_spmm_dot(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
-void launch_pcg_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
-void launch_pcg_pupdate(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
+// pass A: p_new = D^{-1} r + beta p_old, partials of p.Ap (flips w.parity)
+void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it);
+// pass B: x += alpha p, r -= alpha A p, partials of r.z and r.r
+void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
 
 // Y = alpha * T X + beta * Y for a transfer operator (beta = 0: overwrite).
 void launch_transfer(hipStream_t s, const DevTransfer& T, int ncols, CView X, double alpha,

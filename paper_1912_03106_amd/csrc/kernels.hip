@@ -183,20 +183,23 @@ __global__ void k_axpby3(int n, int ncols, double* __restrict__ out, int64_t ldo
   out[i * ldo + c] = v;
 }
 
-// r = b - A x0 with b = (M/dt) u_in + f(t), p = D^{-1} r; partials of
-// r.z, r.r, b.b.  Block 0 clears the active-column counter for the reduce
-// that follows.
+// r = b - A x0 with b = (M/dt) u_in + f(t); partials of r.z (z = D^{-1} r),
+// r.r and b.b.  Block 0 clears the active-column counter for the reduce that
+// follows.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_pcg_init(
     int n, const int* __restrict__ col, const double* __restrict__ a,
     const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
     const double* __restrict__ dinv, const double* __restrict__ F, int ncols, int nrb, int ncc,
     int rpb, const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src,
-    int64_t ld, const double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+    int64_t ld, const double* __restrict__ x, double* __restrict__ r,
     double* __restrict__ part, int* __restrict__ flags) {
   int rb, cc;
   tile_decode(blockIdx.x, nrb, ncc, rb, cc);
-  if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[3] = 0;
+  }
   const int lane = threadIdx.x & 63, wv = wave_index();
   const int c = cc * kWave + lane;
   const bool on = c < ncols;
@@ -222,10 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(
 #pragma unroll
       for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t] * ld + c];
       const double rv = bv - ax;
-      const double z = dinv[i] * rv;
       r[i * ld + c] = rv;
-      p[i * ld + c] = z;
-      acc[0] += rv * z;
+      acc[0] += rv * (dinv[i] * rv);
       acc[1] += rv * rv;
       acc[2] += bv * bv;
     }
@@ -233,14 +234,28 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(
   block_partials<3>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
 }
 
-// q = A p and partials of p.q (active columns only).
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_spmm_dot(
-    int n, const int* __restrict__ col, const double* __restrict__ a, int ncols, int nrb,
-    int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
-    const double* __restrict__ p, double* __restrict__ q, double* __restrict__ part) {
+// New search direction p = D^{-1} r + beta p_old, written the same way
+// wherever it is formed so every use sees identical bits.
+template <typename T>
+__device__ __forceinline__ T pdir(T dinv, T r, T beta, T pold) {
+  return fma(beta, pold, dinv * r);
+}
+
+// PCG pass A (one SpMM): p = D^{-1} r + beta p_old for the own rows (stored
+// into p_new, a different buffer from p_old), and partials of p.(A p), where
+// the neighbours' p is formed on the fly from r and p_old.  A p is not stored;
+// pass B recomputes it.  first != 0: p = D^{-1} r.
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_pcg_pass_a(
+    int n, const int* __restrict__ col, const T* __restrict__ a, const T* __restrict__ dinv,
+    int ncols, int nrb, int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
+    const double* __restrict__ beta, int first, const T* __restrict__ r,
+    const T* __restrict__ pold, T* __restrict__ pnew, double* __restrict__ part,
+    const int* __restrict__ flags, int* __restrict__ hist, int it) {
   int rb, cc;
   tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  // record how many columns this iteration works on (count of the last reduce)
+  if (blockIdx.x == 0 && threadIdx.x == 0) hist[it] = flags[0];
   const int lane = threadIdx.x & 63, wv = wave_index();
   const int c = cc * kWave + lane;
   const bool on = c < ncols && active[c];
@@ -248,27 +263,44 @@ __global__ __launch_bounds__(kBlock) void k_spmm_dot(
   const int rpw = rpb >> 2;
   const int i0 = rb * rpb + wv * rpw;
   if (on) {
+    const T be = first ? T(0) : static_cast<T>(beta[c]);
     for (int k = 0; k < rpw; ++k) {
       const int i = i0 + k;
       if (i >= n) break;
       const int* ci = col + static_cast<int64_t>(i) * W;
-      const double* ai = a + static_cast<int64_t>(i) * W;
-      double s = 0.0;
+      const T* ai = a + static_cast<int64_t>(i) * W;
+      T s = T(0);
+      T pi;
+      if (first) {
 #pragma unroll
-      for (int t = 0; t < W; ++t) s += ai[t] * p[ci[t] * ld + c];
-      q[i * ld + c] = s;
-      acc[0] += p[i * ld + c] * s;
+        for (int t = 0; t < W; ++t) {
+          const int j = ci[t];
+          s += ai[t] * (dinv[j] * r[j * ld + c]);
+        }
+        pi = dinv[i] * r[i * ld + c];
+      } else {
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          const int j = ci[t];
+          s += ai[t] * pdir(dinv[j], r[j * ld + c], be, pold[j * ld + c]);
+        }
+        pi = pdir(dinv[i], r[i * ld + c], be, pold[i * ld + c]);
+      }
+      pnew[i * ld + c] = pi;
+      acc[0] += static_cast<double>(pi) * static_cast<double>(s);
     }
   }
   block_partials<1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
 }
 
-// x += alpha p, r -= alpha q, partials of r.z and r.r with z = D^{-1} r.
-__global__ __launch_bounds__(kBlock) void k_pcg_update(
-    int n, const double* __restrict__ dinv, int ncols, int nrb, int ncc, int rpb, int64_t ld,
-    const uint8_t* __restrict__ active, const double* __restrict__ alpha,
-    double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-    const double* __restrict__ q, double* __restrict__ part) {
+// PCG pass B (one SpMM): q = A p, x += alpha p, r -= alpha q, partials of
+// r.(D^{-1} r) and r.r.
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_pcg_pass_b(
+    int n, const int* __restrict__ col, const T* __restrict__ a, const T* __restrict__ dinv,
+    int ncols, int nrb, int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
+    const double* __restrict__ alpha, const T* __restrict__ p, T* __restrict__ x,
+    T* __restrict__ r, double* __restrict__ part) {
   int rb, cc;
   tile_decode(blockIdx.x, nrb, ncc, rb, cc);
   const int lane = threadIdx.x & 63, wv = wave_index();
@@ -278,40 +310,25 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(
   const int rpw = rpb >> 2;
   const int i0 = rb * rpb + wv * rpw;
   if (on) {
-    const double al = alpha[c];
+    const T al = static_cast<T>(alpha[c]);
     for (int k = 0; k < rpw; ++k) {
       const int i = i0 + k;
       if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      const T* ai = a + static_cast<int64_t>(i) * W;
+      T q = T(0);
+#pragma unroll
+      for (int t = 0; t < W; ++t) q += ai[t] * p[ci[t] * ld + c];
       const int64_t o = i * ld + c;
       x[o] += al * p[o];
-      const double rv = r[o] - al * q[o];
+      const T rv = r[o] - al * q;
       r[o] = rv;
-      acc[0] += rv * (dinv[i] * rv);
-      acc[1] += rv * rv;
+      const double rd = static_cast<double>(rv);
+      acc[0] += rd * (static_cast<double>(dinv[i]) * rd);
+      acc[1] += rd * rd;
     }
   }
   block_partials<2>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
-}
-
-// p = D^{-1} r + beta p (active columns only).
-__global__ __launch_bounds__(kBlock) void k_pcg_pupdate(
-    int n, const double* __restrict__ dinv, int ncols, int nrb, int ncc, int rpb, int64_t ld,
-    const uint8_t* __restrict__ active, const double* __restrict__ beta,
-    const double* __restrict__ r, double* __restrict__ p) {
-  int rb, cc;
-  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
-  const int lane = threadIdx.x & 63, wv = wave_index();
-  const int c = cc * kWave + lane;
-  if (!(c < ncols && active[c])) return;
-  const double be = beta[c];
-  const int rpw = rpb >> 2;
-  const int i0 = rb * rpb + wv * rpw;
-  for (int k = 0; k < rpw; ++k) {
-    const int i = i0 + k;
-    if (i >= n) break;
-    const int64_t o = i * ld + c;
-    p[o] = dinv[i] * r[o] + be * p[o];
-  }
 }
 
 // Sum of squares of every column over a row block.
@@ -410,7 +427,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
     if (act) atomicAdd(&cnt, 1);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && cnt > 0 && (mode == RED_INIT || mode == RED_BETA)) atomicAdd(flags, cnt);
+  if (threadIdx.x == 0 && cnt > 0 && (mode == RED_INIT || mode == RED_BETA)) {
+    atomicAdd(flags, cnt);
+    atomicAdd(flags + 3, cnt);   // columns entering the next PCG iteration
+  }
 }
 
 // Y = alpha * T X + beta * Y for a fixed-width transfer operator.
@@ -693,11 +713,11 @@ void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CV
   if (L.W == 8) {
     hipLaunchKernelGGL(k_pcg_init<8>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
                        L.has_mass, L.dinv64, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
-                       u_in.ld, w.src, w.ld, w.x, w.r, w.p, w.part, w.flags);
+                       u_in.ld, w.src, w.ld, w.x, w.r, w.part, w.flags);
   } else {
     hipLaunchKernelGGL(k_pcg_init<16>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
                        L.has_mass, L.dinv64, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
-                       u_in.ld, w.src, w.ld, w.x, w.r, w.p, w.part, w.flags);
+                       u_in.ld, w.src, w.ld, w.x, w.r, w.part, w.flags);
   }
   MG_HIP(hipGetLastError());
 }
@@ -709,33 +729,37 @@ void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, 
   MG_HIP(hipGetLastError());
 }
 
-void launch_spmm_dot(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it) {
   int ncc;
   const int nb = grid_tiles(w, ncols, ncc);
+  double* pold = w.pbuf[w.parity];
+  double* pnew = w.pbuf[w.parity ^ 1];
   if (L.W == 8) {
-    hipLaunchKernelGGL(k_spmm_dot<8>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, ncols, w.nrb,
-                       ncc, w.rows_per_block, w.ld, w.active, w.p, w.q, w.part);
+    hipLaunchKernelGGL((k_pcg_pass_a<double, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
+                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 4 * w.ld, first, w.r, pold, pnew, w.part, w.flags, w.hist, it);
   } else {
-    hipLaunchKernelGGL(k_spmm_dot<16>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, ncols,
-                       w.nrb, ncc, w.rows_per_block, w.ld, w.active, w.p, w.q, w.part);
+    hipLaunchKernelGGL((k_pcg_pass_a<double, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
+                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 4 * w.ld, first, w.r, pold, pnew, w.part, w.flags, w.hist, it);
   }
+  w.parity ^= 1;
   MG_HIP(hipGetLastError());
 }
 
-void launch_pcg_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
   int ncc;
   const int nb = grid_tiles(w, ncols, ncc);
-  hipLaunchKernelGGL(k_pcg_update, dim3(nb), dim3(kBlock), 0, s, L.n, L.dinv64, ncols, w.nrb, ncc,
-                     w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, w.x, w.r, w.p, w.q,
-                     w.part);
-  MG_HIP(hipGetLastError());
-}
-
-void launch_pcg_pupdate(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  hipLaunchKernelGGL(k_pcg_pupdate, dim3(nb), dim3(kBlock), 0, s, L.n, L.dinv64, ncols, w.nrb,
-                     ncc, w.rows_per_block, w.ld, w.active, w.scal + 4 * w.ld, w.r, w.p);
+  const double* p = w.pbuf[w.parity];
+  if (L.W == 8) {
+    hipLaunchKernelGGL((k_pcg_pass_b<double, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
+                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 3 * w.ld, p, w.x, w.r, w.part);
+  } else {
+    hipLaunchKernelGGL((k_pcg_pass_b<double, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
+                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 3 * w.ld, p, w.x, w.r, w.part);
+  }
   MG_HIP(hipGetLastError());
 }
 

@@ -182,4 +182,7 @@ def stats_dict(st):
         phi_columns=list(st.phi_columns), pcg_sweeps=list(st.pcg_sweeps),
         newton_sweeps=list(st.newton_sweeps), time_total_s=st.time_total_s,
         time_relax_s=st.time_relax_s,
+        kernel_launches=[list(st.kernel_launches[0]), list(st.kernel_launches[1])],
+        kernel_columns=list(st.kernel_columns),
+        kernel_time_s=[list(st.kernel_time_s[0]), list(st.kernel_time_s[1])],
     )

@@ -54,9 +54,9 @@ def test_mgrit_two_level_matches_oracle(cfg1_oracle):
     assert st["converged"]
     # same iteration count as the textbook oracle (round-off may move the last one)
     assert abs(len(st["rho"]) - len(hist)) <= 1, (st["rho"], hist)
-    # residual histories agree while rho is well above the linear-solve tolerance
-    for a, b in zip(st["rho"][:5], hist[:5]):
-        assert a == pytest.approx(b, rel=1e-6)
+    # residual histories agree, on the scale of rho_0, down to the MGRIT tolerance
+    for a, b in zip(st["rho"], hist):
+        assert abs(a - b) <= 1e-9 * hist[0], (a, b)
     assert _rel(U, U_seq) <= MGRIT_GATE
     assert _rel(U, U_mg) <= MGRIT_GATE
     assert st["rho"][-1] <= cfg.mgrit_tol * st["rho"][0]
@@ -67,7 +67,9 @@ def test_mgrit_exact_after_nt_over_2m_fcf(cfg1_oracle):
     cfg, U_seq, _, _ = cfg1_oracle
     s = _solver(cfg, pcg_tol=1e-13, tol=0.0, max_iter=32)
     U, st = s.solve(raise_on_stall=False)
-    assert st["iterations"] == 32
+    # it may stop earlier: once every C-point satisfies Phi to the solver
+    # tolerance, the warm-started residual solve returns rho = 0 exactly
+    assert st["iterations"] <= 32
     assert _rel(U, U_seq) <= 1e-10
 
 
@@ -92,7 +94,7 @@ def test_mgrit_three_level_spatial_coarsening_matches_oracle():
     # iteration count of the textbook algorithm on this problem (oracle: 11)
     _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=3)
     for a, b in zip(st["rho"][:4], hist[:4]):
-        assert a == pytest.approx(b, rel=1e-6)
+        assert abs(a - b) <= 1e-9 * hist[0], (a, b)
     assert abs(len(st["rho"]) - 11) <= 1
 
 
@@ -109,7 +111,10 @@ def test_mgrit_failure_modes(cfg1_oracle):
     assert e.value.name == "NOT_CONVERGED"
     s = _solver(cfg)
     guess = np.zeros((cfg.n_steps + 1, s.n0))
-    guess[5, 3] = np.nan
+    guess[5, 3] = np.nan          # an F-point: F-relaxation overwrites it, harmless
+    U, st = s.solve(u_init=guess)
+    assert st["converged"] and np.isfinite(U).all()
+    guess[5 * cfg.m, 3] = np.nan  # a C-point feeds the first F-relaxation
     with pytest.raises(MgritError) as e:
         s.solve(u_init=guess)
     assert e.value.name == "NONFINITE"
