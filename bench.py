@@ -176,6 +176,7 @@ def main():
                   "pass_a_time_s": [round(x, 3) for x in st["kernel_time_s"][0][:cfg.n_levels]],
                   "pass_b_time_s": [round(x, 3) for x in st["kernel_time_s"][1][:cfg.n_levels]]},
         "gpu_sequential": seq,
+        "autotuned_rows_per_block": [solver.rows_per_block(l) for l in range(cfg.n_levels)],
     }
     if seq:
         line["mgrit"]["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon"] / per, 3)

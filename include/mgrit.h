@@ -111,6 +111,7 @@ typedef struct {
   int32_t warm_start;         /* 1: linear solves start from the previous iterate */
   int32_t device_pointers;    /* 1: u_init / u_out of mgrit_solve are device pointers */
   int32_t profile_kernels;    /* 1: time every PCG pass with HIP events (mgrit_stats.kernel_*) */
+  int32_t autotune;           /* 1: time the batched-PCG tile shapes at setup and keep the fastest */
 } mgrit_params;
 
 typedef struct {
@@ -166,8 +167,11 @@ int mgrit_seq_solve(void* h, const double* u0, double* u_out, mgrit_stats* st);
 int phi_step(void* h, int32_t level, int32_t B, const int64_t* i_from,
              const double* u_prev, double* u_next);
 
-/* Sizes: n_level, N_level (steps), nnz of the level operator. */
-int mgrit_level_info(void* h, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz);
+/* Sizes of a level: unknowns, steps, stored entries of the operator (fixed
+ * row width times n), and the rows per work-group of its batched PCG kernels
+ * (chosen by the autotuner).  Any output pointer may be NULL. */
+int mgrit_level_info(void* h, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
+                     int32_t* rows_per_block);
 
 void mgrit_destroy(void* h);
 const char* mgrit_strerror(int status);

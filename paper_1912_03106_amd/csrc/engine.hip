@@ -10,6 +10,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -40,6 +43,7 @@ struct LevelState {
   PcgWork pcg;       // batched Phi on this level (capacity N + 1 columns)
   PcgWork user;      // phi_step workspace (grown on demand)
   double* seq_ws = nullptr;
+  int* nat = nullptr;     // internal unknown -> user-facing index
   bool relaxed = false;   // F-points hold a previous iterate (warm starts)
   bool cvalid = false;    // C-points hold a previous iterate
 };
@@ -65,12 +69,16 @@ struct Handle {
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+constexpr int kMinRowsPerBlock = 16;
+static const int kRowsPerBlockCandidates[] = {16, 32, 64, 128, 256};
+
 static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block) {
   w.n = n;
   w.cap = cap;
   w.ld = round_up(cap > 0 ? cap : 1, kWave);
   w.rows_per_block = rows_per_block;
   w.nrb = static_cast<int>((n + rows_per_block - 1) / rows_per_block);
+  const int nrb_max = static_cast<int>((n + kMinRowsPerBlock - 1) / kMinRowsPerBlock);
   const size_t vec = static_cast<size_t>(n) * w.ld;
   w.x = h.arena.alloc<double>(vec);
   w.r = h.arena.alloc<double>(vec);
@@ -80,52 +88,141 @@ static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block)
   w.hist_cap = h.par.pcg_max_iter + 64;
   w.hist = h.arena.alloc<int>(w.hist_cap);
   w.host_hist = static_cast<int*>(h.arena.alloc_host(sizeof(int) * w.hist_cap));
-  w.part = h.arena.alloc<double>(3 * static_cast<size_t>(w.nrb) * w.ld);
+  w.part = h.arena.alloc<double>(3 * static_cast<size_t>(std::max(w.nrb, nrb_max)) * w.ld);
   w.scal = h.arena.alloc<double>(8 * static_cast<size_t>(w.ld));
   w.src = h.arena.alloc<double>(3 * static_cast<size_t>(w.ld));
   w.active = h.arena.alloc<uint8_t>(w.ld);
+  w.outer = h.arena.alloc<uint8_t>(w.ld);
+  if (h.par.precision == MGRIT_FP32_IR) {
+    w.r32 = h.arena.alloc<float>(vec);
+    w.x32 = h.arena.alloc<float>(vec);
+    w.p32[0] = h.arena.alloc<float>(vec);
+    w.p32[1] = h.arena.alloc<float>(vec);
+  }
   w.flags = h.arena.alloc<int>(4);
   w.host_flags = static_cast<int*>(h.arena.alloc_host(4 * sizeof(int)));
   MG_HIP(hipMemsetAsync(w.flags, 0, 4 * sizeof(int), h.stream));
 }
+
 
 static int rows_per_block_for(int n) {
   (void)n;
   return 64;
 }
 
-// ---------------------------------------------------------------------------
-// Batched PCG: solves (M/dt + K) x = (M/dt) u_in + f(t) for every column, x
-// initialised in w.x.  Each iteration is pass A, reduce (alpha), pass B,
-// reduce (beta, convergence); converged columns drop out of every kernel.
-// The host reads the active-column count every pcg_check_every iterations.
-// Returns the number of iterations in which some column was active.
-static int pcg_solve(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, CView in) {
+static void set_rows_per_block(PcgWork& w, int rpb) {
+  w.rows_per_block = rpb;
+  w.nrb = (w.n + rpb - 1) / rpb;
+}
+
+// Autotuner: time pass A + pass B of the batched PCG on the level's own
+// matrix with every column active, for each candidate rows-per-work-group,
+// and keep the fastest.  Results are cached per (n, W, columns, precision)
+// for the life of the process.
+struct TuneKey {
+  int n, W, cols, prec;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(n, W, cols, prec) < std::tie(o.n, o.W, o.cols, o.prec);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune_cache;
+
+static void autotune(Handle& h, LevelState& S) {
+  PcgWork& w = S.pcg;
+  const int ncols = w.cap;
+  if (S.n < 4096 || ncols < kWave) return;
+  const bool fp32 = h.par.precision == MGRIT_FP32_IR;
+  const TuneKey key{S.n, S.op.W, ncols, h.par.precision};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      set_rows_per_block(w, it->second);
+      return;
+    }
+  }
   hipStream_t s = h.stream;
-  const double tol2 = h.par.pcg_tol * h.par.pcg_tol;
+  const size_t vec = static_cast<size_t>(S.n) * w.ld;
+  if (fp32) {
+    MG_HIP(hipMemsetAsync(w.r32, 0, sizeof(float) * vec, s));
+    MG_HIP(hipMemsetAsync(w.x32, 0, sizeof(float) * vec, s));
+    MG_HIP(hipMemsetAsync(w.p32[0], 0, sizeof(float) * vec, s));
+    MG_HIP(hipMemsetAsync(w.p32[1], 0, sizeof(float) * vec, s));
+  } else {
+    MG_HIP(hipMemsetAsync(w.r, 0, sizeof(double) * vec, s));
+    MG_HIP(hipMemsetAsync(w.x, 0, sizeof(double) * vec, s));
+    MG_HIP(hipMemsetAsync(w.pbuf[0], 0, sizeof(double) * vec, s));
+    MG_HIP(hipMemsetAsync(w.pbuf[1], 0, sizeof(double) * vec, s));
+  }
+  MG_HIP(hipMemsetAsync(w.scal, 0, sizeof(double) * 8 * w.ld, s));
+  launch_fill_u8(s, w.active, ncols, 1);
+  const int reps = 4;
+  float best = 1e30f;
+  int best_rpb = w.rows_per_block;
+  for (int rpb : kRowsPerBlockCandidates) {
+    set_rows_per_block(w, rpb);
+    for (int warm = 0; warm < 2; ++warm) {
+      if (warm) MG_HIP(hipEventRecord(h.ev0, s));
+      for (int r = 0; r < reps; ++r) {
+        if (fp32) {
+          launch_pcg_pass_a32(s, S.op, w, ncols, 0, 0);
+          launch_pcg_pass_b32(s, S.op, w, ncols);
+        } else {
+          launch_pcg_pass_a(s, S.op, w, ncols, 0, 0);
+          launch_pcg_pass_b(s, S.op, w, ncols);
+        }
+      }
+    }
+    MG_HIP(hipEventRecord(h.ev1, s));
+    MG_HIP(hipEventSynchronize(h.ev1));
+    float ms = 0.f;
+    MG_HIP(hipEventElapsedTime(&ms, h.ev0, h.ev1));
+    if (ms < best) {
+      best = ms;
+      best_rpb = rpb;
+    }
+  }
+  w.parity = 0;
+  set_rows_per_block(w, best_rpb);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune_cache[key] = best_rpb;
+}
+
+// ---------------------------------------------------------------------------
+// Batched PCG iterations on an initialised state (after a reduce that set
+// rz, the reference norms and the active flags; `active` columns remain).
+// Each iteration is pass A, reduce (alpha), pass B, reduce (beta,
+// convergence); converged columns drop out of every kernel.  The host reads
+// the active-column count every pcg_check_every iterations.  Returns the
+// number of iterations in which some column was active.
+static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, double tol2,
+                       bool fp32, int active, bool fail_at_cap) {
+  hipStream_t s = h.stream;
   const bool prof = h.par.profile_kernels && h.st && level < MGRIT_MAX_LEVELS;
-  launch_pcg_init(s, L, w, ncols, in);
-  launch_reduce(s, w, ncols, RED_INIT, tol2, 3, nullptr);
-  MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-  MG_HIP(hipStreamSynchronize(s));
-  if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
   int it = 0, used = 0;
-  int active = w.host_flags[0];
   const int chunk = std::max(1, std::min(h.par.pcg_check_every > 0 ? h.par.pcg_check_every : 16,
                                          static_cast<int>(h.ev.size() / 4)));
+  const int cap = std::min(h.par.pcg_max_iter, w.hist_cap);
   int64_t cols = 0, launches = 0;
+  w.parity = 0;
   while (active > 0) {
-    if (it >= h.par.pcg_max_iter)
-      fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in pcg_max_iter iterations (" +
-                                        std::to_string(active) + " columns left)");
-    const int k = std::min(chunk, std::min(h.par.pcg_max_iter, w.hist_cap) - it);
+    if (it >= cap) {
+      if (fail_at_cap)
+        fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in pcg_max_iter iterations (" +
+                                          std::to_string(active) + " columns left)");
+      break;
+    }
+    const int k = std::min(chunk, cap - it);
     for (int t = 0; t < k; ++t) {
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t], s));
-      launch_pcg_pass_a(s, L, w, ncols, it + t == 0, it + t);
+      if (fp32) launch_pcg_pass_a32(s, L, w, ncols, it + t == 0, it + t);
+      else launch_pcg_pass_a(s, L, w, ncols, it + t == 0, it + t);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 1], s));
       launch_reduce(s, w, ncols, RED_ALPHA, tol2, 1, nullptr);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 2], s));
-      launch_pcg_pass_b(s, L, w, ncols);
+      if (fp32) launch_pcg_pass_b32(s, L, w, ncols);
+      else launch_pcg_pass_b(s, L, w, ncols);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 3], s));
       launch_reduce(s, w, ncols, RED_BETA, tol2, 2, nullptr);
     }
@@ -156,8 +253,43 @@ static int pcg_solve(Handle& h, int level, const DevLevel& L, PcgWork& w, int nc
     h.st->kernel_launches[1][level] += launches;
     h.st->kernel_columns[level] += cols;
   }
-  w.parity = 0;
   return used;
+}
+
+// Solves (M/dt + K) x = (M/dt) u_in + f(t) for every column, x initialised in
+// w.x, to ||b - A x|| <= pcg_tol ||b||.
+//  FP64:     Jacobi-PCG in FP64.
+//  FP32_IR:  refinement sweeps: r = b - A x in FP64; if not converged, solve
+//            A d = r by FP32 Jacobi-PCG to ir_inner_tol (relative), x += d.
+static int pcg_solve(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, CView in) {
+  hipStream_t s = h.stream;
+  const double tol2 = h.par.pcg_tol * h.par.pcg_tol;
+  if (h.par.precision == MGRIT_FP64) {
+    launch_pcg_init(s, L, w, ncols, in);
+    launch_reduce(s, w, ncols, RED_INIT, tol2, 3, nullptr);
+    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
+    return pcg_iterate(h, level, L, w, ncols, tol2, false, w.host_flags[0], true);
+  }
+  const double tin2 = h.par.ir_inner_tol * h.par.ir_inner_tol;
+  launch_fill_u8(s, w.outer, ncols, 1);
+  int total = 0;
+  for (int sweep = 0;; ++sweep) {
+    launch_ir_residual(s, L, w, ncols, in);
+    launch_reduce(s, w, ncols, RED_IR_INIT, tol2, 3, nullptr);
+    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
+    const int active = w.host_flags[0];
+    if (active == 0) break;
+    if (sweep >= h.par.ir_max_iter)
+      fail(MGRIT_PCG_NOT_CONVERGED, "iterative refinement did not converge in ir_max_iter sweeps (" +
+                                        std::to_string(active) + " columns left)");
+    total += pcg_iterate(h, level, L, w, ncols, tin2, true, active, false);
+    launch_ir_update(s, L, w, ncols);
+  }
+  return total;
 }
 
 // One batched application of Phi on level l:
@@ -387,7 +519,10 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (par->m < 2) fail(MGRIT_INVALID_ARGUMENT, "m must be > 1");
   if (par->gamma < 0) fail(MGRIT_INVALID_ARGUMENT, "gamma must be >= 0");
   if (!(par->pcg_tol > 0.0) || par->pcg_max_iter < 1) fail(MGRIT_INVALID_ARGUMENT, "bad PCG settings");
-  if (par->precision != MGRIT_FP64) fail(MGRIT_UNSUPPORTED, "only MGRIT_FP64 is available in this build");
+  if (par->precision != MGRIT_FP64 && par->precision != MGRIT_FP32_IR)
+    fail(MGRIT_INVALID_ARGUMENT, "precision must be MGRIT_FP64 or MGRIT_FP32_IR");
+  if (par->precision == MGRIT_FP32_IR && (!(par->ir_inner_tol > 0.0) || par->ir_max_iter < 1))
+    fail(MGRIT_INVALID_ARGUMENT, "bad refinement settings");
   if (ph.nonlinear) fail(MGRIT_UNSUPPORTED, "the nonlinear model is not available in this build");
   if (ph.n_materials <= 0 || !ph.nu || !ph.sigma) fail(MGRIT_INVALID_ARGUMENT, "material table");
   if (!(ph.dt > 0.0) || ph.n_steps < 1) fail(MGRIT_INVALID_ARGUMENT, "time grid");
@@ -430,6 +565,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     S.N = N;
     S.coarsest = (l == L - 1);
     S.op = assemble_level(h.arena, s, prob->meshes[l], pats[l], ph, dt, &S.elem);
+    S.nat = upload_vec(h.arena, s, pats[l].nat);
     dt *= par->m;
     N /= par->m;
   }
@@ -479,6 +615,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   const int chunk = std::max(1, std::min(par->pcg_check_every > 0 ? par->pcg_check_every : 16, 64));
   h.ev.resize(4 * chunk);
   for (auto& e : h.ev) MG_HIP(hipEventCreate(&e));
+  if (par->autotune)
+    for (auto& S : h.lv) autotune(h, S);
   MG_HIP(hipStreamSynchronize(s));
 }
 
@@ -515,11 +653,11 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
   if (u_init) {
     double* tm = stage(h);
     MG_HIP(hipMemcpyAsync(tm, u_init, sizeof(double) * tm_elems, h2d, s));
-    launch_tm_to_slabs(s, S0.n, S0.N + 1, h.m, tm, S0.U, S0.ld, S0.ss);
+    launch_tm_to_slabs(s, S0.n, S0.N + 1, h.m, tm, S0.U, S0.ld, S0.ss, S0.nat);
   } else {
     MG_HIP(hipMemsetAsync(S0.U, 0, sizeof(double) * S0.ss * h.m, s));
   }
-  launch_axpby3(s, S0.n, 1, S0.U, S0.ld, 1.0, CView{h.u0_dev, 1}, 0.0, CView{}, 0.0, CView{});
+  launch_tm_to_slabs(s, S0.n, 1, 1, h.u0_dev, S0.U, S0.ld, 0, S0.nat);
   auto t0 = std::chrono::steady_clock::now();
   double rho0 = 0.0;
   int status = MGRIT_OK;
@@ -547,7 +685,7 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
     st->iterations = it + 1;
   }
   double* tm = h.par.device_pointers ? u_out : stage(h);
-  launch_slabs_to_tm(s, S0.n, S0.N + 1, h.m, S0.U, S0.ld, S0.ss, tm);
+  launch_slabs_to_tm(s, S0.n, S0.N + 1, h.m, S0.U, S0.ld, S0.ss, tm, S0.nat);
   if (!h.par.device_pointers)
     MG_HIP(hipMemcpyAsync(u_out, tm, sizeof(double) * tm_elems, d2h, s));
   MG_HIP(hipStreamSynchronize(s));
@@ -569,7 +707,7 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   double* U = h.seq_U;
   double* ws = h.seq_ws;
   MG_HIP(hipMemsetAsync(U, 0, sizeof(double) * S0.n * ld, s));
-  launch_axpby3(s, S0.n, 1, U, ld, 1.0, CView{h.u0_dev, 1}, 0.0, CView{}, 0.0, CView{});
+  launch_tm_to_slabs(s, S0.n, 1, 1, h.u0_dev, U, ld, 0, S0.nat);
   int* flags = S0.pcg.flags;
   MG_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), s));
   auto t0 = std::chrono::steady_clock::now();
@@ -584,7 +722,7 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   if (S0.pcg.host_flags[1] & 2) fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in sequential stepping");
   const size_t tm_elems = static_cast<size_t>(S0.N + 1) * S0.n;
   double* tm = h.par.device_pointers ? u_out : stage(h);
-  launch_slabs_to_tm(s, S0.n, S0.N + 1, 1, U, ld, 0, tm);
+  launch_slabs_to_tm(s, S0.n, S0.N + 1, 1, U, ld, 0, tm, S0.nat);
   if (!h.par.device_pointers)
     MG_HIP(hipMemcpyAsync(u_out, tm, sizeof(double) * tm_elems, hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
@@ -606,7 +744,7 @@ static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, co
   int64_t* tl = h.arena.alloc<int64_t>(B);
   MG_HIP(hipMemcpyAsync(tm, u_prev, sizeof(double) * B * S.n, hipMemcpyHostToDevice, s));
   MG_HIP(hipMemcpyAsync(tl, i_from, sizeof(int64_t) * B, hipMemcpyHostToDevice, s));
-  launch_tm_to_slabs(s, S.n, B, 1, tm, cols, w.ld, 0);
+  launch_tm_to_slabs(s, S.n, B, 1, tm, cols, w.ld, 0, S.nat);
   PhiCall c;
   c.ncols = B;
   c.in = CView{cols, w.ld};
@@ -615,7 +753,7 @@ static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, co
   c.out = outc;
   c.ldo = w.ld;
   phi_batch(h, level, w, c);
-  launch_slabs_to_tm(s, S.n, B, 1, outc, w.ld, 0, tm);
+  launch_slabs_to_tm(s, S.n, B, 1, outc, w.ld, 0, tm, S.nat);
   MG_HIP(hipMemcpyAsync(u_next, tm, sizeof(double) * B * S.n, hipMemcpyDeviceToHost, s));
   MG_HIP(hipStreamSynchronize(s));
   // release the staging buffers of this call
@@ -680,6 +818,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->warm_start = 1;
   p->device_pointers = 0;
   p->profile_kernels = 0;
+  p->autotune = 1;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -724,13 +863,15 @@ int phi_step(void* hp, int32_t level, int32_t B, const int64_t* i_from, const do
   return guarded(h, [&] { mg::phi_step_impl(*h, level, B, i_from, u_prev, u_next); });
 }
 
-int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz) {
+int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
+                     int32_t* rows_per_block) {
   auto* h = static_cast<mg::Handle*>(hp);
   if (!h || level < 0 || level >= static_cast<int>(h->lv.size())) return MGRIT_INVALID_ARGUMENT;
   const auto& S = h->lv[level];
   if (n) *n = S.n;
   if (n_steps) *n_steps = S.N;
   if (nnz) *nnz = static_cast<int64_t>(S.n) * S.op.W;
+  if (rows_per_block) *rows_per_block = S.pcg.rows_per_block;
   return MGRIT_OK;
 }
 

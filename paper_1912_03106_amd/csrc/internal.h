@@ -73,7 +73,10 @@ struct PcgWork {
   double* part = nullptr;       // [3][nrb][ld] per-row-block partial sums
   double* scal = nullptr;       // [8][ld]: rz, rr, bb, alpha, beta, (spare)
   double* src = nullptr;        // [3][ld] source value per phase and column
-  uint8_t* active = nullptr;    // [ld]
+  uint8_t* active = nullptr;    // [ld] column still iterating (inner solve)
+  uint8_t* outer = nullptr;     // [ld] column still refining (FP32 + FP64 refinement)
+  float *r32 = nullptr, *x32 = nullptr;  // FP32 inner solve (residual, correction)
+  float* p32[2] = {nullptr, nullptr};
   int* flags = nullptr;         // [4]: 0 active count, 1 error bits, 2 iterations,
                                 //      3 sum of active columns over iterations
   int* host_flags = nullptr;    // pinned copy of flags
@@ -82,7 +85,7 @@ struct PcgWork {
   int hist_cap = 0;
 };
 
-enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3 };
+enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3, RED_IR_INIT = 4 };
 
 // --- setup kernels ---------------------------------------------------------
 void launch_elem_geometry(hipStream_t s, int n_tri, const double* xy, const int* tri,
@@ -109,6 +112,14 @@ void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, 
 // pass B: x += alpha p, r -= alpha A p, partials of r.z and r.r
 void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
 
+// FP32 inner solve of the refinement: the same two passes on r32/p32/x32.
+void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it);
+void launch_pcg_pass_b32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
+// FP64 residual of a refinement sweep (and FP32 inner start), FP64 update.
+void launch_ir_residual(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in);
+void launch_ir_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
+void launch_fill_u8(hipStream_t s, uint8_t* p, int n, uint8_t v);
+
 // Y = alpha * T X + beta * Y for a transfer operator (beta = 0: overwrite).
 void launch_transfer(hipStream_t s, const DevTransfer& T, int ncols, CView X, double alpha,
                      double* Y, int64_t ldy, double beta);
@@ -116,11 +127,12 @@ void launch_transfer(hipStream_t s, const DevTransfer& T, int ncols, CView X, do
 void launch_colsq(hipStream_t s, PcgWork& w, int n, int ncols, CView X);
 
 // Layout conversions.
-// time-major [npts][n] <-> slabs: point t -> slab t % m, column t / m.
+// time-major [npts][n] (user order) <-> slabs (internal order): point t ->
+// slab t % m, column t / m; internal row i is user row nat[i] (nat may be null).
 void launch_tm_to_slabs(hipStream_t s, int n, int64_t npts, int m, const double* tm,
-                        double* slabs, int64_t ld, int64_t slab_stride);
+                        double* slabs, int64_t ld, int64_t slab_stride, const int* nat);
 void launch_slabs_to_tm(hipStream_t s, int n, int64_t npts, int m, const double* slabs,
-                        int64_t ld, int64_t slab_stride, double* tm);
+                        int64_t ld, int64_t slab_stride, double* tm, const int* nat);
 // column block [n][lds] (column t = point t) <-> slabs.
 void launch_cols_to_slabs(hipStream_t s, int n, int64_t npts, int m, const double* src,
                           int64_t lds, double* slabs, int64_t ld, int64_t slab_stride);

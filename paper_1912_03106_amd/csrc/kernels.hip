@@ -331,6 +331,78 @@ __global__ __launch_bounds__(kBlock) void k_pcg_pass_b(
   block_partials<2>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
 }
 
+// Refinement sweep, FP64 part: r = b - A x (x, A, b in FP64) for the
+// columns that have not reached the outer tolerance; the FP32 inner solve
+// starts from r32 = float(r), d = 0.  Partials: r32.(D^{-1} r32) (inner
+// start), r.r and b.b (outer test).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_ir_residual(
+    int n, const int* __restrict__ col, const double* __restrict__ a,
+    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+    const float* __restrict__ dinv32, const double* __restrict__ F, int ncols, int nrb, int ncc,
+    int rpb, const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src,
+    int64_t ld, const uint8_t* __restrict__ outer, const double* __restrict__ x,
+    float* __restrict__ r32, float* __restrict__ d32, double* __restrict__ part,
+    int* __restrict__ flags) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && outer[c];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (on) { s0 = src[c]; s1 = src[ld + c]; s2 = src[2 * ld + c]; }
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      double bv = 0.0;
+      if (has_mass[i]) {
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+#pragma unroll
+        for (int t = 0; t < W; ++t) bv += mi[t] * uin[ci[t] * ldu + c];
+      }
+      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      const double* ai = a + static_cast<int64_t>(i) * W;
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t] * ld + c];
+      const double rv = bv - ax;
+      const float rf = static_cast<float>(rv);
+      r32[i * ld + c] = rf;
+      d32[i * ld + c] = 0.0f;
+      const double rd = static_cast<double>(rf);
+      acc[0] += rd * (static_cast<double>(dinv32[i]) * rd);
+      acc[1] += rv * rv;
+      acc[2] += bv * bv;
+    }
+  }
+  block_partials<3>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// Refinement sweep, FP64 update: x += d for the columns of the sweep.
+__global__ __launch_bounds__(kBlock) void k_ir_update(int n, int ncols, int nrb, int ncc, int rpb,
+                                                      int64_t ld, const uint8_t* __restrict__ outer,
+                                                      const float* __restrict__ d32,
+                                                      double* __restrict__ x) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && outer[c])) return;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+    x[i * ld + c] += static_cast<double>(d32[i * ld + c]);
+  }
+}
+
 // Sum of squares of every column over a row block.
 __global__ __launch_bounds__(kBlock) void k_colsq(int n, int ncols, int nrb, int ncc, int rpb,
                                                   const double* __restrict__ X, int64_t ldx,
@@ -362,7 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
                                                    double* __restrict__ scal,
                                                    uint8_t* __restrict__ active,
                                                    int* __restrict__ flags,
-                                                   double* __restrict__ sums_out) {
+                                                   double* __restrict__ sums_out,
+                                                   uint8_t* __restrict__ outer) {
   __shared__ double red[3][16][16];
   __shared__ int cnt;
   const int cl = threadIdx.x & 15, seg = threadIdx.x >> 4;
@@ -371,6 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
   if (mode == RED_ALPHA && blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
   bool on = c < ncols;
   if (on && (mode == RED_ALPHA || mode == RED_BETA)) on = active[c] != 0;
+  if (on && mode == RED_IR_INIT) on = outer[c] != 0;
   double S[3] = {0.0, 0.0, 0.0};
   if (on) {
     const int64_t qs = static_cast<int64_t>(nrb) * ld;
@@ -419,6 +493,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
         active[c] = static_cast<uint8_t>(act);
         bad = !isfinite(b) || !isfinite(T[1]);
       }
+    } else if (mode == RED_IR_INIT) {
+      // refinement sweep: T = (inner r.z, ||r||^2, ||b||^2) of the FP64 residual
+      if (on) {
+        double b2 = T[2];
+        if (b2 == 0.0) b2 = T[1];
+        act = T[1] > tol2 * b2;        // outer (FP64) convergence test
+        outer[c] = static_cast<uint8_t>(act);
+        rz[c] = T[0];
+        rr[c] = T[1];
+        bb[c] = T[1];                  // inner tolerance is relative to this residual
+        bad = !isfinite(T[0]) || !isfinite(T[1]) || !isfinite(T[2]);
+      }
+      active[c] = static_cast<uint8_t>(act);
     } else {
       sums_out[c] = T[0];
       bad = !isfinite(T[0]);
@@ -427,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
     if (act) atomicAdd(&cnt, 1);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && cnt > 0 && (mode == RED_INIT || mode == RED_BETA)) {
+  if (threadIdx.x == 0 && cnt > 0 && (mode == RED_INIT || mode == RED_BETA || mode == RED_IR_INIT)) {
     atomicAdd(flags, cnt);
     atomicAdd(flags + 3, cnt);   // columns entering the next PCG iteration
   }
@@ -457,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_transfer(int n_out, const int* __res
 __global__ __launch_bounds__(kBlock) void k_tm_to_slabs(int n, int64_t npts, int m,
                                                         const double* __restrict__ tm,
                                                         double* __restrict__ slabs, int64_t ld,
-                                                        int64_t ss) {
+                                                        int64_t ss, const int* __restrict__ nat) {
   __shared__ double tile[64][65];
   const int j = blockIdx.z;
   const int64_t k0 = static_cast<int64_t>(blockIdx.x) * 64;
@@ -466,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_tm_to_slabs(int n, int64_t npts, int
   for (int q = ty; q < 64; q += 4) {
     const int64_t t = (k0 + q) * m + j;
     const int i = i0 + tx;
-    tile[q][tx] = (t < npts && i < n) ? tm[t * n + i] : 0.0;
+    tile[q][tx] = (t < npts && i < n) ? tm[t * n + (nat ? nat[i] : i)] : 0.0;
   }
   __syncthreads();
   for (int q = ty; q < 64; q += 4) {
@@ -480,7 +567,8 @@ __global__ __launch_bounds__(kBlock) void k_tm_to_slabs(int n, int64_t npts, int
 __global__ __launch_bounds__(kBlock) void k_slabs_to_tm(int n, int64_t npts, int m,
                                                         const double* __restrict__ slabs,
                                                         int64_t ld, int64_t ss,
-                                                        double* __restrict__ tm) {
+                                                        double* __restrict__ tm,
+                                                        const int* __restrict__ nat) {
   __shared__ double tile[64][65];
   const int j = blockIdx.z;
   const int64_t k0 = static_cast<int64_t>(blockIdx.x) * 64;
@@ -496,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_slabs_to_tm(int n, int64_t npts, int
   for (int q = ty; q < 64; q += 4) {
     const int64_t t = (k0 + q) * m + j;
     const int i = i0 + tx;
-    if (t < npts && i < n) tm[t * n + i] = tile[tx][q];
+    if (t < npts && i < n) tm[t * n + (nat ? nat[i] : i)] = tile[tx][q];
   }
 }
 
@@ -725,7 +813,7 @@ void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CV
 void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
                    double* sums_out) {
   hipLaunchKernelGGL(k_reduce, dim3(ceil_div(ncols, 16)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
-                     mode, nq, tol2, w.part, w.scal, w.active, w.flags, sums_out);
+                     mode, nq, tol2, w.part, w.scal, w.active, w.flags, sums_out, w.outer);
   MG_HIP(hipGetLastError());
 }
 
@@ -763,6 +851,73 @@ void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) 
   MG_HIP(hipGetLastError());
 }
 
+void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  float* pold = w.p32[w.parity];
+  float* pnew = w.p32[w.parity ^ 1];
+  if (L.W == 8) {
+    hipLaunchKernelGGL((k_pcg_pass_a<float, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
+                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 4 * w.ld, first, w.r32, pold, pnew, w.part, w.flags, w.hist, it);
+  } else {
+    hipLaunchKernelGGL((k_pcg_pass_a<float, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
+                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 4 * w.ld, first, w.r32, pold, pnew, w.part, w.flags, w.hist, it);
+  }
+  w.parity ^= 1;
+  MG_HIP(hipGetLastError());
+}
+
+void launch_pcg_pass_b32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  const float* p = w.p32[w.parity];
+  if (L.W == 8) {
+    hipLaunchKernelGGL((k_pcg_pass_b<float, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
+                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 3 * w.ld, p, w.x32, w.r32, w.part);
+  } else {
+    hipLaunchKernelGGL((k_pcg_pass_b<float, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
+                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
+                       w.scal + 3 * w.ld, p, w.x32, w.r32, w.part);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_ir_residual(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  if (L.W == 8) {
+    hipLaunchKernelGGL(k_ir_residual<8>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
+                       L.has_mass, L.dinv32, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
+                       u_in.ld, w.src, w.ld, w.outer, w.x, w.r32, w.x32, w.part, w.flags);
+  } else {
+    hipLaunchKernelGGL(k_ir_residual<16>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
+                       L.has_mass, L.dinv32, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
+                       u_in.ld, w.src, w.ld, w.outer, w.x, w.r32, w.x32, w.part, w.flags);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_ir_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  hipLaunchKernelGGL(k_ir_update, dim3(nb), dim3(kBlock), 0, s, L.n, ncols, w.nrb, ncc,
+                     w.rows_per_block, w.ld, w.outer, w.x32, w.x);
+  MG_HIP(hipGetLastError());
+}
+
+__global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_u8(hipStream_t s, uint8_t* p, int n, uint8_t v) {
+  hipLaunchKernelGGL(k_fill_u8, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
+  MG_HIP(hipGetLastError());
+}
+
 void launch_colsq(hipStream_t s, PcgWork& w, int n, int ncols, CView X) {
   int ncc;
   const int nb = grid_tiles(w, ncols, ncc);
@@ -797,18 +952,18 @@ void launch_transfer(hipStream_t s, const DevTransfer& T, int ncols, CView X, do
 }
 
 void launch_tm_to_slabs(hipStream_t s, int n, int64_t npts, int m, const double* tm, double* slabs,
-                        int64_t ld, int64_t ss) {
+                        int64_t ld, int64_t ss, const int* nat) {
   const int64_t cols = (npts + m - 1) / m;
   dim3 grid(ceil_div(cols, 64), ceil_div(n, 64), m);
-  hipLaunchKernelGGL(k_tm_to_slabs, grid, dim3(kBlock), 0, s, n, npts, m, tm, slabs, ld, ss);
+  hipLaunchKernelGGL(k_tm_to_slabs, grid, dim3(kBlock), 0, s, n, npts, m, tm, slabs, ld, ss, nat);
   MG_HIP(hipGetLastError());
 }
 
 void launch_slabs_to_tm(hipStream_t s, int n, int64_t npts, int m, const double* slabs, int64_t ld,
-                        int64_t ss, double* tm) {
+                        int64_t ss, double* tm, const int* nat) {
   const int64_t cols = (npts + m - 1) / m;
   dim3 grid(ceil_div(cols, 64), ceil_div(n, 64), m);
-  hipLaunchKernelGGL(k_slabs_to_tm, grid, dim3(kBlock), 0, s, n, npts, m, slabs, ld, ss, tm);
+  hipLaunchKernelGGL(k_slabs_to_tm, grid, dim3(kBlock), 0, s, n, npts, m, slabs, ld, ss, tm, nat);
   MG_HIP(hipGetLastError());
 }
 

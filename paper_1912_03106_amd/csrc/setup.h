@@ -23,7 +23,8 @@ struct DeviceArena {
 // Interior-node operator pattern with fixed row width W.
 struct HostPattern {
   int n = 0, W = 0;
-  std::vector<int> index;    // node -> unknown or -1 (Dirichlet)
+  std::vector<int> index;    // node -> internal unknown index or -1 (Dirichlet)
+  std::vector<int> nat;      // internal unknown -> user-facing (node-id order) index
   std::vector<int> col;      // [n*W]
   std::vector<int> cptr;     // [n*W + 1] contribution list per stored entry
   std::vector<int> contrib;  // element*9 + a*3 + b
@@ -35,6 +36,9 @@ struct HostSparse {
   std::vector<int> col;
   std::vector<double> val;
 };
+
+template <class T>
+T* upload_vec(DeviceArena& A, hipStream_t s, const std::vector<T>& v);
 
 // Per-element device data kept for the nonlinear model.
 struct ElementData {

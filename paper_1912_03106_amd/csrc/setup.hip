@@ -75,10 +75,25 @@ HostPattern build_pattern(const mgrit_mesh& m) {
   HostPattern P;
   P.index.assign(m.n_nodes, -1);
   int n = 0;
-  for (int v = 0; v < m.n_nodes; ++v)
-    if (!m.dirichlet[v]) P.index[v] = n++;
+  if (m.n_r > 0 && m.n_theta > 0) {
+    // Polar mesh: number the unknowns angle-major (radial index fastest), so
+    // a row's neighbours lie within about n_r rows of it instead of n_theta;
+    // the batched kernels then find them in L2 (see the layout note in
+    // kernels.hip).  The user-facing order stays the node-id order.
+    for (int j = 0; j < m.n_theta; ++j)
+      for (int i = 0; i <= m.n_r; ++i) {
+        const int v = i * m.n_theta + j;
+        if (!m.dirichlet[v]) P.index[v] = n++;
+      }
+  } else {
+    for (int v = 0; v < m.n_nodes; ++v)
+      if (!m.dirichlet[v]) P.index[v] = n++;
+  }
   if (n == 0) fail(MGRIT_INVALID_ARGUMENT, "mesh: no unknowns");
   P.n = n;
+  P.nat.assign(n, 0);
+  for (int v = 0, k = 0; v < m.n_nodes; ++v)
+    if (!m.dirichlet[v]) P.nat[P.index[v]] = k++;
   // node -> incident (element, local index)
   std::vector<int> start(m.n_nodes + 1, 0);
   for (int64_t k = 0; k < 3LL * m.n_tri; ++k) start[m.tri[k] + 1]++;
@@ -261,6 +276,12 @@ static T* upload_raw(DeviceArena& A, hipStream_t s, const T* p, size_t n) {
   MG_HIP(hipMemcpyAsync(d, p, sizeof(T) * n, hipMemcpyHostToDevice, s));
   return d;
 }
+
+template <class T>
+T* upload_vec(DeviceArena& A, hipStream_t s, const std::vector<T>& v) {
+  return upload(A, s, v);
+}
+template int* upload_vec<int>(DeviceArena&, hipStream_t, const std::vector<int>&);
 
 DevTransfer upload_transfer(DeviceArena& A, hipStream_t s, const HostSparse& T) {
   DevTransfer d;

@@ -93,10 +93,18 @@ class Solver:
 
     # -- sizes -----------------------------------------------------------
     def level_info(self, level):
-        n, N, nnz = C.c_int64(), C.c_int64(), C.c_int64()
+        """(unknowns, steps, stored operator entries) of a level."""
+        n, N, nnz, rpb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
         _check(self._L, self._h, self._L.mgrit_level_info(self._h, level, C.byref(n), C.byref(N),
-                                                          C.byref(nnz)))
+                                                          C.byref(nnz), C.byref(rpb)))
         return n.value, N.value, nnz.value
+
+    def rows_per_block(self, level):
+        """Rows per work-group of the level's batched PCG kernels (autotuned)."""
+        rpb = C.c_int32()
+        _check(self._L, self._h, self._L.mgrit_level_info(self._h, level, None, None, None,
+                                                          C.byref(rpb)))
+        return rpb.value
 
     @property
     def n0(self):

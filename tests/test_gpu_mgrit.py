@@ -118,3 +118,18 @@ def test_mgrit_failure_modes(cfg1_oracle):
     with pytest.raises(MgritError) as e:
         s.solve(u_init=guess)
     assert e.value.name == "NONFINITE"
+
+
+def test_mgrit_fp32_refinement_random_guess_matches_oracle(cfg1_oracle):
+    """FP32 inner solves + FP64 refinement, seeded U(-1e-3, 1e-3) initial guess:
+    the same gate against the FP64 sequential solution."""
+    print("mgrit cfg1 FP32+IR random guess", flush=True)
+    cfg, U_seq, _, _ = cfg1_oracle
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, pcg_tol=1e-12, precision=_abi.FP32_IR, ir_inner_tol=1e-4)
+    rng = np.random.default_rng(3)
+    guess = np.zeros((cfg.n_steps + 1, s.n0))
+    guess[1:] = rng.uniform(-1e-3, 1e-3, size=(cfg.n_steps, s.n0))
+    U, st = s.solve(u_init=guess)
+    assert st["converged"]
+    assert _rel(U, U_seq) <= MGRIT_GATE

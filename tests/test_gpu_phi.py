@@ -94,3 +94,31 @@ def test_phi_full_size_sampled_columns():
     ref = lev.phi(u_prev, i_from)
     err = _col_err(got, ref)
     assert err.max() <= PHI_TOL, err
+
+
+def test_phi_fp32_refinement_matches_direct_solve(cfg1_pair):
+    """FP32 inner PCG with FP64 iterative refinement reaches the FP64 accuracy."""
+    cfg, _, lev, U = cfg1_pair
+    print("phi parity FP32+IR 16x128", flush=True)
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, pcg_tol=1e-13, precision=_abi.FP32_IR, ir_inner_tol=1e-4)
+    rng = np.random.default_rng(21)
+    B = 97
+    i_from = rng.integers(0, cfg.n_steps - 1, size=B)
+    u_prev = U[rng.integers(1, U.shape[0], size=B)] + 1e-4 * rng.standard_normal((B, lev.n))
+    err = _col_err(s.phi(0, u_prev, i_from), lev.phi(u_prev, i_from))
+    assert err.max() <= PHI_TOL, err.max()
+
+
+def test_phi_fp32_refinement_full_size():
+    print("phi parity FP32+IR 64x512 sampled", flush=True)
+    from paper_1912_03106_amd import _abi
+    cfg = config("cfg3")
+    cfg.meshes = [LevelSpec(64, 512), LevelSpec(32, 256)]
+    s = _solver(cfg, pcg_tol=1e-13, precision=_abi.FP32_IR, ir_inner_tol=1e-4)
+    lev = Level(polar_mesh(64, 512), cfg.dt, cfg.source)
+    U = sequential(lev, np.zeros(lev.n), 12)
+    i_from = np.array([3, 4095, 8191, 16000])
+    u_prev = U[[4, 7, 9, 12]]
+    err = _col_err(s.phi(0, u_prev, i_from), lev.phi(u_prev, i_from))
+    assert err.max() <= PHI_TOL, err
