@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -99,9 +101,9 @@ static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block)
     w.p32[0] = h.arena.alloc<float>(vec);
     w.p32[1] = h.arena.alloc<float>(vec);
   }
-  w.flags = h.arena.alloc<int>(4);
-  w.host_flags = static_cast<int*>(h.arena.alloc_host(4 * sizeof(int)));
-  MG_HIP(hipMemsetAsync(w.flags, 0, 4 * sizeof(int), h.stream));
+  w.flags = h.arena.alloc<int>(8);
+  w.host_flags = static_cast<int*>(h.arena.alloc_host(8 * sizeof(int)));
+  MG_HIP(hipMemsetAsync(w.flags, 0, 8 * sizeof(int), h.stream));
 }
 
 
@@ -126,7 +128,7 @@ struct TuneKey {
   }
 };
 static std::mutex g_tune_mu;
-static std::map<TuneKey, int> g_tune_cache;
+static std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 
 static void autotune(Handle& h, LevelState& S) {
   PcgWork& w = S.pcg;
@@ -138,7 +140,8 @@ static void autotune(Handle& h, LevelState& S) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      set_rows_per_block(w, it->second);
+      set_rows_per_block(w, it->second.first);
+      w.cpl = it->second.second;
       return;
     }
   }
@@ -159,17 +162,21 @@ static void autotune(Handle& h, LevelState& S) {
   launch_fill_u8(s, w.active, ncols, 1);
   const int reps = 4;
   float best = 1e30f;
-  int best_rpb = w.rows_per_block;
-  for (int rpb : kRowsPerBlockCandidates) {
+  int best_rpb = w.rows_per_block, best_cpl = 1;
+  for (int cand = 0; cand < 2 * static_cast<int>(sizeof(kRowsPerBlockCandidates) / sizeof(int)); ++cand) {
+    const int rpb = kRowsPerBlockCandidates[cand >> 1];
+    const int cpl = 1 + (cand & 1);
+    if (cpl == 2 && S.op.W != 8) continue;
     set_rows_per_block(w, rpb);
+    w.cpl = cpl;
     for (int warm = 0; warm < 2; ++warm) {
       if (warm) MG_HIP(hipEventRecord(h.ev0, s));
       for (int r = 0; r < reps; ++r) {
         if (fp32) {
-          launch_pcg_pass_a32(s, S.op, w, ncols, 0, 0);
+          launch_pcg_pass_a32(s, S.op, w, ncols, 0);
           launch_pcg_pass_b32(s, S.op, w, ncols);
         } else {
-          launch_pcg_pass_a(s, S.op, w, ncols, 0, 0);
+          launch_pcg_pass_a(s, S.op, w, ncols, 0);
           launch_pcg_pass_b(s, S.op, w, ncols);
         }
       }
@@ -181,12 +188,21 @@ static void autotune(Handle& h, LevelState& S) {
     if (ms < best) {
       best = ms;
       best_rpb = rpb;
+      best_cpl = cpl;
+    }
+    if (std::getenv("MGRIT_TUNE_LOG")) {
+      const double unit = fp32 ? 4.0 : 8.0;
+      const double bytes = 8.0 * unit * S.n * static_cast<double>(ncols);  // A + B vector passes
+      std::fprintf(stderr, "[mgrit tune] n=%d cols=%d %s rpb=%d cpl=%d: A+B %.1f us, %.0f GB/s\n",
+                   S.n, ncols, fp32 ? "fp32" : "fp64", rpb, cpl, 1e3 * ms / reps,
+                   bytes / (1e-3 * ms / reps) / 1e9);
     }
   }
   w.parity = 0;
   set_rows_per_block(w, best_rpb);
+  w.cpl = best_cpl;
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune_cache[key] = best_rpb;
+  g_tune_cache[key] = {best_rpb, best_cpl};
 }
 
 // ---------------------------------------------------------------------------
@@ -216,8 +232,8 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     const int k = std::min(chunk, cap - it);
     for (int t = 0; t < k; ++t) {
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t], s));
-      if (fp32) launch_pcg_pass_a32(s, L, w, ncols, it + t == 0, it + t);
-      else launch_pcg_pass_a(s, L, w, ncols, it + t == 0, it + t);
+      if (fp32) launch_pcg_pass_a32(s, L, w, ncols, it + t == 0);
+      else launch_pcg_pass_a(s, L, w, ncols, it + t == 0);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 1], s));
       launch_reduce(s, w, ncols, RED_ALPHA, tol2, 1, nullptr);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 2], s));

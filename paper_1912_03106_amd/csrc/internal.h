@@ -54,6 +54,12 @@ struct DevLevel {
   double* dinv64 = nullptr;    // [n] 1 / diag(A)
   float* dinv32 = nullptr;
   double* F = nullptr;         // [3][n] phase load vectors (unit current density x sign)
+  // symmetric Jacobi scaling used by the batched CG: A^ = S A S, S = diag(A)^{-1/2}
+  double* s64 = nullptr;       // [n] S
+  float* s32 = nullptr;
+  double* d64 = nullptr;       // [n] diag(A)
+  double* ah64 = nullptr;      // [n*W] A^
+  float* ah32 = nullptr;
 };
 
 // Spatial transfer (rows = output nodes), fixed row width.
@@ -66,6 +72,7 @@ struct DevTransfer {
 // Batched-PCG workspace for up to `cap` columns of an n-row level.
 struct PcgWork {
   int n = 0, cap = 0, nrb = 0, rows_per_block = 0;
+  int cpl = 1;                  // columns per lane of the CG passes (1 or 2)
   int64_t ld = 0;
   double *x = nullptr, *r = nullptr;
   double* pbuf[2] = {nullptr, nullptr};  // search directions, ping-pong
@@ -77,8 +84,8 @@ struct PcgWork {
   uint8_t* outer = nullptr;     // [ld] column still refining (FP32 + FP64 refinement)
   float *r32 = nullptr, *x32 = nullptr;  // FP32 inner solve (residual, correction)
   float* p32[2] = {nullptr, nullptr};
-  int* flags = nullptr;         // [4]: 0 active count, 1 error bits, 2 iterations,
-                                //      3 sum of active columns over iterations
+  int* flags = nullptr;         // [8]: 0 active count, 1 error bits, 2 iterations of the
+                                //      sequential stepper, 4 pass-A launches of this solve
   int* host_flags = nullptr;    // pinned copy of flags
   int* hist = nullptr;          // [max_iter] active columns of every PCG iteration
   int* host_hist = nullptr;     // pinned copy
@@ -107,13 +114,15 @@ void launch_axpby3(hipStream_t s, int n, int ncols, double* out, int64_t ldo, do
 void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in);
 void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
                    double* sums_out);
-// pass A: p_new = D^{-1} r + beta p_old, partials of p.Ap (flips w.parity)
-void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it);
-// pass B: x += alpha p, r -= alpha A p, partials of r.z and r.r
+// CG on the scaled system (pcg.hip).
+// pass A: p^ = r^ + beta p^_old, partials of p^.A^p^ (flips w.parity)
+void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first);
+// pass B: x += alpha S p^, r^ -= alpha A^ p^, partials of r^.r^ and ||r||^2
 void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
+void launch_scale_matrix(hipStream_t s, DevLevel& L, const int* diag_slot);
 
 // FP32 inner solve of the refinement: the same two passes on r32/p32/x32.
-void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it);
+void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first);
 void launch_pcg_pass_b32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
 // FP64 residual of a refinement sweep (and FP32 inner start), FP64 update.
 void launch_ir_residual(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in);

@@ -183,226 +183,6 @@ __global__ void k_axpby3(int n, int ncols, double* __restrict__ out, int64_t ldo
   out[i * ldo + c] = v;
 }
 
-// r = b - A x0 with b = (M/dt) u_in + f(t); partials of r.z (z = D^{-1} r),
-// r.r and b.b.  Block 0 clears the active-column counter for the reduce that
-// follows.
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(
-    int n, const int* __restrict__ col, const double* __restrict__ a,
-    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
-    const double* __restrict__ dinv, const double* __restrict__ F, int ncols, int nrb, int ncc,
-    int rpb, const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src,
-    int64_t ld, const double* __restrict__ x, double* __restrict__ r,
-    double* __restrict__ part, int* __restrict__ flags) {
-  int rb, cc;
-  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    flags[0] = 0;
-    flags[3] = 0;
-  }
-  const int lane = threadIdx.x & 63, wv = wave_index();
-  const int c = cc * kWave + lane;
-  const bool on = c < ncols;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (on) { s0 = src[c]; s1 = src[ld + c]; s2 = src[2 * ld + c]; }
-  double acc[3] = {0.0, 0.0, 0.0};
-  const int rpw = rpb >> 2;
-  const int i0 = rb * rpb + wv * rpw;
-  if (on) {
-    for (int k = 0; k < rpw; ++k) {
-      const int i = i0 + k;
-      if (i >= n) break;
-      const int* ci = col + static_cast<int64_t>(i) * W;
-      double bv = 0.0;
-      if (has_mass[i]) {
-        const double* mi = mm + static_cast<int64_t>(i) * W;
-#pragma unroll
-        for (int t = 0; t < W; ++t) bv += mi[t] * uin[ci[t] * ldu + c];
-      }
-      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
-      const double* ai = a + static_cast<int64_t>(i) * W;
-      double ax = 0.0;
-#pragma unroll
-      for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t] * ld + c];
-      const double rv = bv - ax;
-      r[i * ld + c] = rv;
-      acc[0] += rv * (dinv[i] * rv);
-      acc[1] += rv * rv;
-      acc[2] += bv * bv;
-    }
-  }
-  block_partials<3>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
-}
-
-// New search direction p = D^{-1} r + beta p_old, written the same way
-// wherever it is formed so every use sees identical bits.
-template <typename T>
-__device__ __forceinline__ T pdir(T dinv, T r, T beta, T pold) {
-  return fma(beta, pold, dinv * r);
-}
-
-// PCG pass A (one SpMM): p = D^{-1} r + beta p_old for the own rows (stored
-// into p_new, a different buffer from p_old), and partials of p.(A p), where
-// the neighbours' p is formed on the fly from r and p_old.  A p is not stored;
-// pass B recomputes it.  first != 0: p = D^{-1} r.
-template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_pcg_pass_a(
-    int n, const int* __restrict__ col, const T* __restrict__ a, const T* __restrict__ dinv,
-    int ncols, int nrb, int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
-    const double* __restrict__ beta, int first, const T* __restrict__ r,
-    const T* __restrict__ pold, T* __restrict__ pnew, double* __restrict__ part,
-    const int* __restrict__ flags, int* __restrict__ hist, int it) {
-  int rb, cc;
-  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
-  // record how many columns this iteration works on (count of the last reduce)
-  if (blockIdx.x == 0 && threadIdx.x == 0) hist[it] = flags[0];
-  const int lane = threadIdx.x & 63, wv = wave_index();
-  const int c = cc * kWave + lane;
-  const bool on = c < ncols && active[c];
-  double acc[1] = {0.0};
-  const int rpw = rpb >> 2;
-  const int i0 = rb * rpb + wv * rpw;
-  if (on) {
-    const T be = first ? T(0) : static_cast<T>(beta[c]);
-    for (int k = 0; k < rpw; ++k) {
-      const int i = i0 + k;
-      if (i >= n) break;
-      const int* ci = col + static_cast<int64_t>(i) * W;
-      const T* ai = a + static_cast<int64_t>(i) * W;
-      T s = T(0);
-      T pi;
-      if (first) {
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          const int j = ci[t];
-          s += ai[t] * (dinv[j] * r[j * ld + c]);
-        }
-        pi = dinv[i] * r[i * ld + c];
-      } else {
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          const int j = ci[t];
-          s += ai[t] * pdir(dinv[j], r[j * ld + c], be, pold[j * ld + c]);
-        }
-        pi = pdir(dinv[i], r[i * ld + c], be, pold[i * ld + c]);
-      }
-      pnew[i * ld + c] = pi;
-      acc[0] += static_cast<double>(pi) * static_cast<double>(s);
-    }
-  }
-  block_partials<1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
-}
-
-// PCG pass B (one SpMM): q = A p, x += alpha p, r -= alpha q, partials of
-// r.(D^{-1} r) and r.r.
-template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_pcg_pass_b(
-    int n, const int* __restrict__ col, const T* __restrict__ a, const T* __restrict__ dinv,
-    int ncols, int nrb, int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
-    const double* __restrict__ alpha, const T* __restrict__ p, T* __restrict__ x,
-    T* __restrict__ r, double* __restrict__ part) {
-  int rb, cc;
-  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
-  const int lane = threadIdx.x & 63, wv = wave_index();
-  const int c = cc * kWave + lane;
-  const bool on = c < ncols && active[c];
-  double acc[2] = {0.0, 0.0};
-  const int rpw = rpb >> 2;
-  const int i0 = rb * rpb + wv * rpw;
-  if (on) {
-    const T al = static_cast<T>(alpha[c]);
-    for (int k = 0; k < rpw; ++k) {
-      const int i = i0 + k;
-      if (i >= n) break;
-      const int* ci = col + static_cast<int64_t>(i) * W;
-      const T* ai = a + static_cast<int64_t>(i) * W;
-      T q = T(0);
-#pragma unroll
-      for (int t = 0; t < W; ++t) q += ai[t] * p[ci[t] * ld + c];
-      const int64_t o = i * ld + c;
-      x[o] += al * p[o];
-      const T rv = r[o] - al * q;
-      r[o] = rv;
-      const double rd = static_cast<double>(rv);
-      acc[0] += rd * (static_cast<double>(dinv[i]) * rd);
-      acc[1] += rd * rd;
-    }
-  }
-  block_partials<2>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
-}
-
-// Refinement sweep, FP64 part: r = b - A x (x, A, b in FP64) for the
-// columns that have not reached the outer tolerance; the FP32 inner solve
-// starts from r32 = float(r), d = 0.  Partials: r32.(D^{-1} r32) (inner
-// start), r.r and b.b (outer test).
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_ir_residual(
-    int n, const int* __restrict__ col, const double* __restrict__ a,
-    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
-    const float* __restrict__ dinv32, const double* __restrict__ F, int ncols, int nrb, int ncc,
-    int rpb, const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src,
-    int64_t ld, const uint8_t* __restrict__ outer, const double* __restrict__ x,
-    float* __restrict__ r32, float* __restrict__ d32, double* __restrict__ part,
-    int* __restrict__ flags) {
-  int rb, cc;
-  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
-  if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
-  const int lane = threadIdx.x & 63, wv = wave_index();
-  const int c = cc * kWave + lane;
-  const bool on = c < ncols && outer[c];
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (on) { s0 = src[c]; s1 = src[ld + c]; s2 = src[2 * ld + c]; }
-  double acc[3] = {0.0, 0.0, 0.0};
-  const int rpw = rpb >> 2;
-  const int i0 = rb * rpb + wv * rpw;
-  if (on) {
-    for (int k = 0; k < rpw; ++k) {
-      const int i = i0 + k;
-      if (i >= n) break;
-      const int* ci = col + static_cast<int64_t>(i) * W;
-      double bv = 0.0;
-      if (has_mass[i]) {
-        const double* mi = mm + static_cast<int64_t>(i) * W;
-#pragma unroll
-        for (int t = 0; t < W; ++t) bv += mi[t] * uin[ci[t] * ldu + c];
-      }
-      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
-      const double* ai = a + static_cast<int64_t>(i) * W;
-      double ax = 0.0;
-#pragma unroll
-      for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t] * ld + c];
-      const double rv = bv - ax;
-      const float rf = static_cast<float>(rv);
-      r32[i * ld + c] = rf;
-      d32[i * ld + c] = 0.0f;
-      const double rd = static_cast<double>(rf);
-      acc[0] += rd * (static_cast<double>(dinv32[i]) * rd);
-      acc[1] += rv * rv;
-      acc[2] += bv * bv;
-    }
-  }
-  block_partials<3>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
-}
-
-// Refinement sweep, FP64 update: x += d for the columns of the sweep.
-__global__ __launch_bounds__(kBlock) void k_ir_update(int n, int ncols, int nrb, int ncc, int rpb,
-                                                      int64_t ld, const uint8_t* __restrict__ outer,
-                                                      const float* __restrict__ d32,
-                                                      double* __restrict__ x) {
-  int rb, cc;
-  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
-  const int lane = threadIdx.x & 63, wv = wave_index();
-  const int c = cc * kWave + lane;
-  if (!(c < ncols && outer[c])) return;
-  const int rpw = rpb >> 2;
-  const int i0 = rb * rpb + wv * rpw;
-  for (int k = 0; k < rpw; ++k) {
-    const int i = i0 + k;
-    if (i >= n) break;
-    x[i * ld + c] += static_cast<double>(d32[i * ld + c]);
-  }
-}
-
 // Sum of squares of every column over a row block.
 __global__ __launch_bounds__(kBlock) void k_colsq(int n, int ncols, int nrb, int ncc, int rpb,
                                                   const double* __restrict__ X, int64_t ldx,
@@ -424,100 +204,6 @@ __global__ __launch_bounds__(kBlock) void k_colsq(int n, int ncols, int nrb, int
     }
   }
   block_partials<1>(acc, part + rb * ldp, static_cast<int64_t>(nrb) * ldp, c, on);
-}
-
-// Per-column reduction of the row-block partials, in a fixed order, followed
-// by the PCG scalar updates.  16 columns per work-group, 16 threads per column.
-__global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t ld, int mode,
-                                                   int nq, double tol2,
-                                                   const double* __restrict__ part,
-                                                   double* __restrict__ scal,
-                                                   uint8_t* __restrict__ active,
-                                                   int* __restrict__ flags,
-                                                   double* __restrict__ sums_out,
-                                                   uint8_t* __restrict__ outer) {
-  __shared__ double red[3][16][16];
-  __shared__ int cnt;
-  const int cl = threadIdx.x & 15, seg = threadIdx.x >> 4;
-  const int c = blockIdx.x * 16 + cl;
-  if (threadIdx.x == 0) cnt = 0;
-  if (mode == RED_ALPHA && blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
-  bool on = c < ncols;
-  if (on && (mode == RED_ALPHA || mode == RED_BETA)) on = active[c] != 0;
-  if (on && mode == RED_IR_INIT) on = outer[c] != 0;
-  double S[3] = {0.0, 0.0, 0.0};
-  if (on) {
-    const int64_t qs = static_cast<int64_t>(nrb) * ld;
-    for (int rb = seg; rb < nrb; rb += 16) {
-      for (int q = 0; q < nq; ++q) S[q] += part[q * qs + rb * ld + c];
-    }
-  }
-  for (int q = 0; q < 3; ++q) red[q][seg][cl] = S[q];
-  __syncthreads();
-  if (seg == 0 && c < ncols) {
-    double T[3];
-    for (int q = 0; q < 3; ++q) {
-      double t = 0.0;
-      for (int s = 0; s < 16; ++s) t += red[q][s][cl];
-      T[q] = t;
-    }
-    double* rz = scal;
-    double* rr = scal + ld;
-    double* bb = scal + 2 * ld;
-    double* al = scal + 3 * ld;
-    double* be = scal + 4 * ld;
-    int act = 0;
-    bool bad = false;
-    if (mode == RED_INIT) {
-      double b2 = T[2];
-      if (b2 == 0.0) b2 = T[1];
-      rz[c] = T[0];
-      rr[c] = T[1];
-      bb[c] = b2;
-      act = T[1] > tol2 * b2;
-      active[c] = static_cast<uint8_t>(act);
-      bad = !isfinite(T[0]) || !isfinite(T[1]) || !isfinite(T[2]);
-    } else if (mode == RED_ALPHA) {
-      if (on) {
-        const double a = rz[c] / T[0];
-        bad = !isfinite(a);
-        al[c] = bad ? 0.0 : a;
-      }
-    } else if (mode == RED_BETA) {
-      if (on) {
-        const double b = T[0] / rz[c];
-        rz[c] = T[0];
-        rr[c] = T[1];
-        be[c] = b;
-        act = T[1] > tol2 * bb[c];
-        active[c] = static_cast<uint8_t>(act);
-        bad = !isfinite(b) || !isfinite(T[1]);
-      }
-    } else if (mode == RED_IR_INIT) {
-      // refinement sweep: T = (inner r.z, ||r||^2, ||b||^2) of the FP64 residual
-      if (on) {
-        double b2 = T[2];
-        if (b2 == 0.0) b2 = T[1];
-        act = T[1] > tol2 * b2;        // outer (FP64) convergence test
-        outer[c] = static_cast<uint8_t>(act);
-        rz[c] = T[0];
-        rr[c] = T[1];
-        bb[c] = T[1];                  // inner tolerance is relative to this residual
-        bad = !isfinite(T[0]) || !isfinite(T[1]) || !isfinite(T[2]);
-      }
-      active[c] = static_cast<uint8_t>(act);
-    } else {
-      sums_out[c] = T[0];
-      bad = !isfinite(T[0]);
-    }
-    if (bad) atomicOr(flags + 1, 1);
-    if (act) atomicAdd(&cnt, 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && cnt > 0 && (mode == RED_INIT || mode == RED_BETA || mode == RED_IR_INIT)) {
-    atomicAdd(flags, cnt);
-    atomicAdd(flags + 3, cnt);   // columns entering the next PCG iteration
-  }
 }
 
 // Y = alpha * T X + beta * Y for a fixed-width transfer operator.
@@ -793,129 +479,6 @@ void launch_axpby3(hipStream_t s, int n, int ncols, double* out, int64_t ldo, do
 static int grid_tiles(const PcgWork& w, int ncols, int& ncc) {
   ncc = ceil_div(ncols, kWave);
   return w.nrb * ncc;
-}
-
-void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  if (L.W == 8) {
-    hipLaunchKernelGGL(k_pcg_init<8>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
-                       L.has_mass, L.dinv64, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
-                       u_in.ld, w.src, w.ld, w.x, w.r, w.part, w.flags);
-  } else {
-    hipLaunchKernelGGL(k_pcg_init<16>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
-                       L.has_mass, L.dinv64, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
-                       u_in.ld, w.src, w.ld, w.x, w.r, w.part, w.flags);
-  }
-  MG_HIP(hipGetLastError());
-}
-
-void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
-                   double* sums_out) {
-  hipLaunchKernelGGL(k_reduce, dim3(ceil_div(ncols, 16)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
-                     mode, nq, tol2, w.part, w.scal, w.active, w.flags, sums_out, w.outer);
-  MG_HIP(hipGetLastError());
-}
-
-void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  double* pold = w.pbuf[w.parity];
-  double* pnew = w.pbuf[w.parity ^ 1];
-  if (L.W == 8) {
-    hipLaunchKernelGGL((k_pcg_pass_a<double, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
-                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 4 * w.ld, first, w.r, pold, pnew, w.part, w.flags, w.hist, it);
-  } else {
-    hipLaunchKernelGGL((k_pcg_pass_a<double, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
-                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 4 * w.ld, first, w.r, pold, pnew, w.part, w.flags, w.hist, it);
-  }
-  w.parity ^= 1;
-  MG_HIP(hipGetLastError());
-}
-
-void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  const double* p = w.pbuf[w.parity];
-  if (L.W == 8) {
-    hipLaunchKernelGGL((k_pcg_pass_b<double, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
-                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 3 * w.ld, p, w.x, w.r, w.part);
-  } else {
-    hipLaunchKernelGGL((k_pcg_pass_b<double, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64,
-                       L.dinv64, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 3 * w.ld, p, w.x, w.r, w.part);
-  }
-  MG_HIP(hipGetLastError());
-}
-
-void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, int it) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  float* pold = w.p32[w.parity];
-  float* pnew = w.p32[w.parity ^ 1];
-  if (L.W == 8) {
-    hipLaunchKernelGGL((k_pcg_pass_a<float, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
-                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 4 * w.ld, first, w.r32, pold, pnew, w.part, w.flags, w.hist, it);
-  } else {
-    hipLaunchKernelGGL((k_pcg_pass_a<float, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
-                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 4 * w.ld, first, w.r32, pold, pnew, w.part, w.flags, w.hist, it);
-  }
-  w.parity ^= 1;
-  MG_HIP(hipGetLastError());
-}
-
-void launch_pcg_pass_b32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  const float* p = w.p32[w.parity];
-  if (L.W == 8) {
-    hipLaunchKernelGGL((k_pcg_pass_b<float, 8>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
-                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 3 * w.ld, p, w.x32, w.r32, w.part);
-  } else {
-    hipLaunchKernelGGL((k_pcg_pass_b<float, 16>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a32,
-                       L.dinv32, ncols, w.nrb, ncc, w.rows_per_block, w.ld, w.active,
-                       w.scal + 3 * w.ld, p, w.x32, w.r32, w.part);
-  }
-  MG_HIP(hipGetLastError());
-}
-
-void launch_ir_residual(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  if (L.W == 8) {
-    hipLaunchKernelGGL(k_ir_residual<8>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
-                       L.has_mass, L.dinv32, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
-                       u_in.ld, w.src, w.ld, w.outer, w.x, w.r32, w.x32, w.part, w.flags);
-  } else {
-    hipLaunchKernelGGL(k_ir_residual<16>, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64,
-                       L.has_mass, L.dinv32, L.F, ncols, w.nrb, ncc, w.rows_per_block, u_in.p,
-                       u_in.ld, w.src, w.ld, w.outer, w.x, w.r32, w.x32, w.part, w.flags);
-  }
-  MG_HIP(hipGetLastError());
-}
-
-void launch_ir_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
-  int ncc;
-  const int nb = grid_tiles(w, ncols, ncc);
-  hipLaunchKernelGGL(k_ir_update, dim3(nb), dim3(kBlock), 0, s, L.n, ncols, w.nrb, ncc,
-                     w.rows_per_block, w.ld, w.outer, w.x32, w.x);
-  MG_HIP(hipGetLastError());
-}
-
-__global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-void launch_fill_u8(hipStream_t s, uint8_t* p, int n, uint8_t v) {
-  hipLaunchKernelGGL(k_fill_u8, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
-  MG_HIP(hipGetLastError());
 }
 
 void launch_colsq(hipStream_t s, PcgWork& w, int n, int ncols, CView X) {

@@ -1,0 +1,638 @@
+// Batched Jacobi-preconditioned CG for the one-step propagator Phi.
+//
+// Every column of a column block [n][ld] is an independent linear system
+// (M/dt + K) x = (M/dt) u_prev + f(t) with the same matrix: the columns are
+// the time intervals of an F- or C-relaxation sweep.  CG runs on the
+// symmetrically scaled system  A^ = S A S,  S = diag(A)^{-1/2}, whose
+// iterates are those of Jacobi-PCG on A (same Krylov space, same stopping
+// residual); the scaling removes the preconditioner from the inner loop.
+// Vectors r^ (scaled residual) and p^ (scaled direction) live in the scaled
+// space, x stays in the original one (x += alpha S p^).
+//
+// One iteration = two passes over the column block, each containing one
+// product with A^, plus two small per-column reductions:
+//   pass A: p^ = r^ + beta p^_old (own rows stored into a second buffer),
+//           partials of p^.(A^ p^), the neighbours' p^ formed on the fly;
+//   pass B: q^ = A^ p^ (recomputed), x += alpha S p^, r^ -= alpha q^,
+//           partials of r^.r^ and ||r||^2 = sum_i diag_i r^_i^2.
+// 8 vector passes per iteration (r, p_old read + p written; p, x, r read +
+// x, r written) instead of 11 for the textbook split.
+//
+// Mapping: a wave owns CPL x 64 consecutive columns of one row at a time
+// (CPL = columns per lane, 1 or 2); the row's pattern and values are
+// wave-uniform scalar loads.  A work-group (4 waves) covers `rpb` rows of one
+// column chunk; chunks are pinned to XCDs when their count allows.  Both
+// knobs are chosen per level by the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace mg {
+namespace {
+
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+}
+
+// Work-group -> (row block, column chunk); see kernels.hip for the XCD note.
+__device__ __forceinline__ void tile_decode(int w, int ncc, int& rb, int& cc) {
+  if ((ncc & 7) == 0) {
+    const int xcd = w & 7, local = w >> 3, per = ncc >> 3;
+    cc = xcd + 8 * (local % per);
+    rb = local / per;
+  } else {
+    cc = w % ncc;
+    rb = w / ncc;
+  }
+}
+
+template <typename T, int CPL>
+struct Vec;
+template <typename T>
+struct Vec<T, 1> {
+  T v[1];
+  __device__ __forceinline__ static Vec load(const T* p) { return Vec{{p[0]}}; }
+  __device__ __forceinline__ void store(T* p) const { p[0] = v[0]; }
+};
+template <>
+struct Vec<double, 2> {
+  double v[2];
+  __device__ __forceinline__ static Vec load(const double* p) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    return Vec{{t.x, t.y}};
+  }
+  __device__ __forceinline__ void store(double* p) const {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  }
+};
+template <>
+struct Vec<float, 2> {
+  float v[2];
+  __device__ __forceinline__ static Vec load(const float* p) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    return Vec{{t.x, t.y}};
+  }
+  __device__ __forceinline__ void store(float* p) const {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  }
+};
+
+// Sum the per-column values of the 4 waves in a fixed order and store them
+// at out[q * qstride + c] for the columns of this work-group's chunk.
+template <int NQ, int CPL>
+__device__ __forceinline__ void block_partials(const double (&v)[NQ][CPL], double* out,
+                                               int64_t qstride, int c0, const bool (&on)[CPL]) {
+  __shared__ double red[NQ][4][kWave * CPL];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) red[q][wv][lane * CPL + k] = v[q][k];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      if (!on[k]) continue;
+      const int l = lane * CPL + k;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        out[q * qstride + c0 + k] = ((red[q][0][l] + red[q][1][l]) + red[q][2][l]) + red[q][3][l];
+    }
+  }
+}
+
+// r = b - A x with b = (M/dt) u_in + f(t) (original scaling, FP64);
+// stores r^ = S r; partials r^.r^, r.r, b.b.  Block 0 clears the
+// active-column counter for the reduce that follows.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_cg_init(
+    int n, const int* __restrict__ col, const double* __restrict__ a,
+    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+    const double* __restrict__ sc, const double* __restrict__ F, int ncols, int ncc, int rpb,
+    const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src, int64_t ld,
+    const double* __restrict__ x, double* __restrict__ r, double* __restrict__ part,
+    int nrb, int* __restrict__ flags) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[4] = 0;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  bool on[1] = {c < ncols};
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (on[0]) { s0 = src[c]; s1 = src[ld + c]; s2 = src[2 * ld + c]; }
+  double acc[3][1] = {{0.0}, {0.0}, {0.0}};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on[0]) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      double bv = 0.0;
+      if (has_mass[i]) {
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+#pragma unroll
+        for (int t = 0; t < W; ++t) bv += mi[t] * uin[ci[t] * ldu + c];
+      }
+      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      const double* ai = a + static_cast<int64_t>(i) * W;
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t] * ld + c];
+      const double rv = bv - ax;
+      const double rh = sc[i] * rv;
+      r[i * ld + c] = rh;
+      acc[0][0] += rh * rh;
+      acc[1][0] += rv * rv;
+      acc[2][0] += bv * bv;
+    }
+  }
+  block_partials<3, 1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// Pass A.  first != 0: p^ = r^ (beta and p_old unused).  Block 0 records the
+// number of columns this iteration works on (the count left by the previous
+// reduce) in hist[flags[4]] and advances flags[4].
+template <typename T, int W, int CPL>
+__global__ __launch_bounds__(kBlock) void k_cg_pass_a(
+    int n, const int* __restrict__ col, const T* __restrict__ ah, int ncols, int ncc, int rpb,
+    int64_t ld, const uint8_t* __restrict__ active, const double* __restrict__ beta, int first,
+    const T* __restrict__ r, const T* __restrict__ pold, T* __restrict__ pnew,
+    double* __restrict__ part, int nrb, int* __restrict__ flags, int* __restrict__ hist) {
+  using V = Vec<T, CPL>;
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int it = flags[4];
+    hist[it] = flags[0];
+    flags[4] = it + 1;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c0 = (cc * kWave + lane) * CPL;
+  bool on[CPL];
+  bool any = false;
+  T be[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    on[k] = (c0 + k < ncols) && active[c0 + k];
+    any |= on[k];
+    be[k] = (first || !on[k]) ? T(0) : static_cast<T>(beta[c0 + k]);
+  }
+  double acc[1][CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) acc[0][k] = 0.0;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (any) {
+    for (int kk = 0; kk < rpw; ++kk) {
+      const int i = i0 + kk;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      const T* ai = ah + static_cast<int64_t>(i) * W;
+      T s[CPL];
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) s[k] = T(0);
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const int64_t o = ci[t] * ld + c0;
+        const V rv = V::load(r + o);
+        if (first) {
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) s[k] += ai[t] * rv.v[k];
+        } else {
+          const V pv = V::load(pold + o);
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) s[k] += ai[t] * fma(be[k], pv.v[k], rv.v[k]);
+        }
+      }
+      const int64_t o = i * ld + c0;
+      V pi = V::load(r + o);
+      if (!first) {
+        const V pv = V::load(pold + o);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) pi.v[k] = fma(be[k], pv.v[k], pi.v[k]);
+      }
+      pi.store(pnew + o);
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) acc[0][k] += static_cast<double>(pi.v[k]) * static_cast<double>(s[k]);
+    }
+  }
+  block_partials<1, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
+}
+
+// Pass B: q^ = A^ p^, x += alpha S p^, r^ -= alpha q^ (columns that are not
+// active are left untouched), partials r^.r^ and sum diag_i r^_i^2.
+template <typename T, int W, int CPL>
+__global__ __launch_bounds__(kBlock) void k_cg_pass_b(
+    int n, const int* __restrict__ col, const T* __restrict__ ah, const T* __restrict__ sc,
+    const double* __restrict__ dg, int ncols, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ active, const double* __restrict__ alpha, const T* __restrict__ p,
+    T* __restrict__ x, T* __restrict__ r, double* __restrict__ part, int nrb) {
+  using V = Vec<T, CPL>;
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c0 = (cc * kWave + lane) * CPL;
+  bool on[CPL];
+  bool any = false, all = true;
+  T al[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    on[k] = (c0 + k < ncols) && active[c0 + k];
+    any |= on[k];
+    all &= on[k];
+    al[k] = on[k] ? static_cast<T>(alpha[c0 + k]) : T(0);
+  }
+  double acc[2][CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) acc[0][k] = acc[1][k] = 0.0;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (any) {
+    for (int kk = 0; kk < rpw; ++kk) {
+      const int i = i0 + kk;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      const T* ai = ah + static_cast<int64_t>(i) * W;
+      T q[CPL];
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) q[k] = T(0);
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const V pv = V::load(p + ci[t] * ld + c0);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) q[k] += ai[t] * pv.v[k];
+      }
+      const int64_t o = i * ld + c0;
+      const T si = sc[i];
+      const double di = dg[i];
+      const V pi = V::load(p + o);
+      V xi = V::load(x + o);
+      V ri = V::load(r + o);
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        xi.v[k] = fma(al[k] * si, pi.v[k], xi.v[k]);
+        ri.v[k] = ri.v[k] - al[k] * q[k];
+        const double rd = static_cast<double>(ri.v[k]);
+        acc[0][k] += rd * rd;
+        acc[1][k] += di * (rd * rd);
+      }
+      if (all) {
+        xi.store(x + o);
+        ri.store(r + o);
+      } else {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+          if (on[k]) {
+            x[o + k] = xi.v[k];
+            r[o + k] = ri.v[k];
+          }
+      }
+    }
+  }
+  block_partials<2, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
+}
+
+// Refinement sweep, FP64 part: r = b - A x (FP64) for the columns that have
+// not reached the outer tolerance; the FP32 inner solve starts from
+// r^32 = float(S r) with correction d = 0.  Partials: r^32.r^32 (inner
+// start), r.r and b.b (outer test).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_ir_residual(
+    int n, const int* __restrict__ col, const double* __restrict__ a,
+    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+    const double* __restrict__ sc, const double* __restrict__ F, int ncols, int ncc, int rpb,
+    const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src, int64_t ld,
+    const uint8_t* __restrict__ outer, const double* __restrict__ x, float* __restrict__ r32,
+    float* __restrict__ d32, double* __restrict__ part, int nrb, int* __restrict__ flags) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[4] = 0;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  bool on[1] = {c < ncols && outer[c]};
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (on[0]) { s0 = src[c]; s1 = src[ld + c]; s2 = src[2 * ld + c]; }
+  double acc[3][1] = {{0.0}, {0.0}, {0.0}};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on[0]) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      double bv = 0.0;
+      if (has_mass[i]) {
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+#pragma unroll
+        for (int t = 0; t < W; ++t) bv += mi[t] * uin[ci[t] * ldu + c];
+      }
+      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      const double* ai = a + static_cast<int64_t>(i) * W;
+      double ax = 0.0;
+#pragma unroll
+      for (int t = 0; t < W; ++t) ax += ai[t] * x[ci[t] * ld + c];
+      const double rv = bv - ax;
+      const float rf = static_cast<float>(sc[i] * rv);
+      r32[i * ld + c] = rf;
+      d32[i * ld + c] = 0.0f;
+      const double rd = static_cast<double>(rf);
+      acc[0][0] += rd * rd;
+      acc[1][0] += rv * rv;
+      acc[2][0] += bv * bv;
+    }
+  }
+  block_partials<3, 1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// Refinement sweep, FP64 update: x += d for the columns of the sweep.
+__global__ __launch_bounds__(kBlock) void k_ir_update(int n, int ncols, int ncc, int rpb, int64_t ld,
+                                                      const uint8_t* __restrict__ outer,
+                                                      const float* __restrict__ d32,
+                                                      double* __restrict__ x) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && outer[c])) return;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+    x[i * ld + c] += static_cast<double>(d32[i * ld + c]);
+  }
+}
+
+// Per-column reduction of the row-block partials, in a fixed order, followed
+// by the CG scalar updates.  16 columns per work-group, 16 threads per column.
+//   INIT:    rz, rr, bb; active = rr > tol2 bb (bb = 0: relative to rr)
+//   ALPHA:   alpha = rz / p.Ap (0 for columns that are not active)
+//   BETA:    beta = rz_new / rz, convergence test (beta = 0 once converged)
+//   SUM:     plain sums into sums_out
+//   IR_INIT: outer test on the FP64 residual; inner start (rz, reference rr)
+__global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t ld, int mode,
+                                                   int nq, double tol2,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ scal,
+                                                   uint8_t* __restrict__ active,
+                                                   int* __restrict__ flags,
+                                                   double* __restrict__ sums_out,
+                                                   uint8_t* __restrict__ outer) {
+  __shared__ double red[3][16][16];
+  __shared__ int cnt;
+  const int cl = threadIdx.x & 15, seg = threadIdx.x >> 4;
+  const int c = blockIdx.x * 16 + cl;
+  if (threadIdx.x == 0) cnt = 0;
+  if (mode == RED_ALPHA && blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
+  bool on = c < ncols;
+  if (on && (mode == RED_ALPHA || mode == RED_BETA)) on = active[c] != 0;
+  if (on && mode == RED_IR_INIT) on = outer[c] != 0;
+  double S[3] = {0.0, 0.0, 0.0};
+  if (on) {
+    const int64_t qs = static_cast<int64_t>(nrb) * ld;
+    for (int rb = seg; rb < nrb; rb += 16) {
+      for (int q = 0; q < nq; ++q) S[q] += part[q * qs + rb * ld + c];
+    }
+  }
+  for (int q = 0; q < 3; ++q) red[q][seg][cl] = S[q];
+  __syncthreads();
+  if (seg == 0 && c < ncols) {
+    double T[3];
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+      for (int s = 0; s < 16; ++s) t += red[q][s][cl];
+      T[q] = t;
+    }
+    double* rz = scal;
+    double* rr = scal + ld;
+    double* bb = scal + 2 * ld;
+    double* al = scal + 3 * ld;
+    double* be = scal + 4 * ld;
+    int act = 0;
+    bool bad = false;
+    if (mode == RED_INIT) {
+      double b2 = T[2];
+      if (b2 == 0.0) b2 = T[1];
+      rz[c] = T[0];
+      rr[c] = T[1];
+      bb[c] = b2;
+      al[c] = 0.0;
+      be[c] = 0.0;
+      act = T[1] > tol2 * b2;
+      active[c] = static_cast<uint8_t>(act);
+      bad = !isfinite(T[0]) || !isfinite(T[1]) || !isfinite(T[2]);
+    } else if (mode == RED_ALPHA) {
+      double a = 0.0;
+      if (on) {
+        a = rz[c] / T[0];
+        bad = !isfinite(a);
+        if (bad) a = 0.0;
+      }
+      al[c] = a;
+    } else if (mode == RED_BETA) {
+      double b = 0.0;
+      if (on) {
+        b = T[0] / rz[c];
+        rz[c] = T[0];
+        rr[c] = T[1];
+        act = T[1] > tol2 * bb[c];
+        active[c] = static_cast<uint8_t>(act);
+        bad = !isfinite(b) || !isfinite(T[1]);
+        if (!act || bad) b = 0.0;
+      }
+      be[c] = b;
+    } else if (mode == RED_IR_INIT) {
+      if (on) {
+        double b2 = T[2];
+        if (b2 == 0.0) b2 = T[1];
+        act = T[1] > tol2 * b2;        // outer (FP64) convergence test
+        outer[c] = static_cast<uint8_t>(act);
+        rz[c] = T[0];
+        rr[c] = T[1];
+        bb[c] = T[1];                  // inner tolerance is relative to this residual
+        bad = !isfinite(T[0]) || !isfinite(T[1]) || !isfinite(T[2]);
+      }
+      al[c] = 0.0;
+      be[c] = 0.0;
+      active[c] = static_cast<uint8_t>(act);
+    } else {
+      sums_out[c] = T[0];
+      bad = !isfinite(T[0]);
+    }
+    if (bad) atomicOr(flags + 1, 1);
+    if (act) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt > 0 &&
+      (mode == RED_INIT || mode == RED_BETA || mode == RED_IR_INIT))
+    atomicAdd(flags, cnt);
+}
+
+// A^ = S A S, S = diag(A)^{-1/2}, and the diagonal itself.
+__global__ void k_scale_matrix(int n, int W, const int* __restrict__ col,
+                               const double* __restrict__ a, const int* __restrict__ diag_slot,
+                               double* __restrict__ s64, float* __restrict__ s32,
+                               double* __restrict__ d64) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = a[static_cast<int64_t>(i) * W + diag_slot[i]];
+  d64[i] = d;
+  s64[i] = 1.0 / sqrt(d);
+  s32[i] = static_cast<float>(1.0 / sqrt(d));
+}
+
+__global__ void k_scale_entries(int n, int W, const int* __restrict__ col,
+                                const double* __restrict__ a, const double* __restrict__ s64,
+                                double* __restrict__ ah64, float* __restrict__ ah32) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * W) return;
+  const int i = static_cast<int>(e / W);
+  const double v = s64[i] * a[e] * s64[col[e]];
+  ah64[e] = v;
+  ah32[e] = static_cast<float>(v);
+}
+
+__global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Launch wrappers.
+
+static int grid_tiles(const PcgWork& w, int ncols, int cpl, int& ncc) {
+  ncc = ceil_div(ncols, kWave * cpl);
+  return w.nrb * ncc;
+}
+
+void launch_scale_matrix(hipStream_t s, DevLevel& L, const int* diag_slot) {
+  hipLaunchKernelGGL(k_scale_matrix, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, L.W, L.col,
+                     L.a64, diag_slot, L.s64, L.s32, L.d64);
+  const int64_t e = static_cast<int64_t>(L.n) * L.W;
+  hipLaunchKernelGGL(k_scale_entries, dim3(ceil_div(e, 256)), dim3(256), 0, s, L.n, L.W, L.col,
+                     L.a64, L.s64, L.ah64, L.ah32);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_fill_u8(hipStream_t s, uint8_t* p, int n, uint8_t v) {
+  hipLaunchKernelGGL(k_fill_u8, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, 1, ncc);
+  auto k = (L.W == 8) ? k_cg_init<8> : k_cg_init<16>;
+  hipLaunchKernelGGL(k, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64, L.has_mass, L.s64,
+                     L.F, ncols, ncc, w.rows_per_block, u_in.p, u_in.ld, w.src, w.ld, w.x, w.r,
+                     w.part, w.nrb, w.flags);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
+                   double* sums_out) {
+  hipLaunchKernelGGL(k_reduce, dim3(ceil_div(ncols, 16)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
+                     mode, nq, tol2, w.part, w.scal, w.active, w.flags, sums_out, w.outer);
+  MG_HIP(hipGetLastError());
+}
+
+template <typename T, int W, int CPL>
+static void pass_a_impl(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first,
+                        const T* ah, const T* r, T* pold, T* pnew) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, CPL, ncc);
+  hipLaunchKernelGGL((k_cg_pass_a<T, W, CPL>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, ah, ncols,
+                     ncc, w.rows_per_block, w.ld, w.active, w.scal + 4 * w.ld, first, r, pold, pnew,
+                     w.part, w.nrb, w.flags, w.hist);
+}
+
+template <typename T, int W, int CPL>
+static void pass_b_impl(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, const T* ah,
+                        const T* sc, const T* p, T* x, T* r) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, CPL, ncc);
+  hipLaunchKernelGGL((k_cg_pass_b<T, W, CPL>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, ah, sc,
+                     L.d64, ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, p, x,
+                     r, w.part, w.nrb);
+}
+
+void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first) {
+  double* pold = w.pbuf[w.parity];
+  double* pnew = w.pbuf[w.parity ^ 1];
+  if (L.W == 8) {
+    if (w.cpl == 2) pass_a_impl<double, 8, 2>(s, L, w, ncols, first, L.ah64, w.r, pold, pnew);
+    else pass_a_impl<double, 8, 1>(s, L, w, ncols, first, L.ah64, w.r, pold, pnew);
+  } else {
+    pass_a_impl<double, 16, 1>(s, L, w, ncols, first, L.ah64, w.r, pold, pnew);
+  }
+  w.parity ^= 1;
+  MG_HIP(hipGetLastError());
+}
+
+void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  const double* p = w.pbuf[w.parity];
+  if (L.W == 8) {
+    if (w.cpl == 2) pass_b_impl<double, 8, 2>(s, L, w, ncols, L.ah64, L.s64, p, w.x, w.r);
+    else pass_b_impl<double, 8, 1>(s, L, w, ncols, L.ah64, L.s64, p, w.x, w.r);
+  } else {
+    pass_b_impl<double, 16, 1>(s, L, w, ncols, L.ah64, L.s64, p, w.x, w.r);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first) {
+  float* pold = w.p32[w.parity];
+  float* pnew = w.p32[w.parity ^ 1];
+  if (L.W == 8) {
+    if (w.cpl == 2) pass_a_impl<float, 8, 2>(s, L, w, ncols, first, L.ah32, w.r32, pold, pnew);
+    else pass_a_impl<float, 8, 1>(s, L, w, ncols, first, L.ah32, w.r32, pold, pnew);
+  } else {
+    pass_a_impl<float, 16, 1>(s, L, w, ncols, first, L.ah32, w.r32, pold, pnew);
+  }
+  w.parity ^= 1;
+  MG_HIP(hipGetLastError());
+}
+
+void launch_pcg_pass_b32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  const float* p = w.p32[w.parity];
+  if (L.W == 8) {
+    if (w.cpl == 2) pass_b_impl<float, 8, 2>(s, L, w, ncols, L.ah32, L.s32, p, w.x32, w.r32);
+    else pass_b_impl<float, 8, 1>(s, L, w, ncols, L.ah32, L.s32, p, w.x32, w.r32);
+  } else {
+    pass_b_impl<float, 16, 1>(s, L, w, ncols, L.ah32, L.s32, p, w.x32, w.r32);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_ir_residual(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, 1, ncc);
+  auto k = (L.W == 8) ? k_ir_residual<8> : k_ir_residual<16>;
+  hipLaunchKernelGGL(k, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64, L.has_mass, L.s64,
+                     L.F, ncols, ncc, w.rows_per_block, u_in.p, u_in.ld, w.src, w.ld, w.outer, w.x,
+                     w.r32, w.x32, w.part, w.nrb, w.flags);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_ir_update(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, 1, ncc);
+  hipLaunchKernelGGL(k_ir_update, dim3(nb), dim3(kBlock), 0, s, L.n, ncols, ncc, w.rows_per_block,
+                     w.ld, w.outer, w.x32, w.x);
+  MG_HIP(hipGetLastError());
+}
+
+}  // namespace mg

@@ -311,6 +311,11 @@ DevLevel assemble_level(DeviceArena& A, hipStream_t s, const mgrit_mesh& m, cons
   L.dinv64 = A.alloc<double>(P.n);
   L.dinv32 = A.alloc<float>(P.n);
   L.F = A.alloc<double>(3 * static_cast<size_t>(P.n));
+  L.s64 = A.alloc<double>(P.n);
+  L.s32 = A.alloc<float>(P.n);
+  L.d64 = A.alloc<double>(P.n);
+  L.ah64 = A.alloc<double>(slots);
+  L.ah32 = A.alloc<float>(slots);
   int* cptr = upload(A, s, P.cptr);
   int* contrib = upload(A, s, P.contrib);
   int* diag = upload(A, s, P.diag);
@@ -333,6 +338,7 @@ DevLevel assemble_level(DeviceArena& A, hipStream_t s, const mgrit_mesh& m, cons
   launch_assemble_linear(s, L, cptr, contrib, area, grad, dnu, dsig);
   launch_diag_inverse(s, L, diag);
   launch_load_vectors(s, L, cptr, contrib, diag, area, phase, sign);
+  launch_scale_matrix(s, L, diag);
   if (keep) {
     keep->n_tri = m.n_tri;
     keep->area = area;
