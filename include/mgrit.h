@@ -112,6 +112,8 @@ typedef struct {
   int32_t device_pointers;    /* 1: u_init / u_out of mgrit_solve are device pointers */
   int32_t profile_kernels;    /* 1: time every PCG pass with HIP events (mgrit_stats.kernel_*) */
   int32_t autotune;           /* 1: time the batched-PCG tile shapes at setup and keep the fastest */
+  int32_t pcg_kernel;         /* batched-PCG kernels: 0 choose (autotuner), 1 general sparse rows,
+                               * 2 diagonal window (periodic polar stencil only, else UNSUPPORTED) */
 } mgrit_params;
 
 typedef struct {

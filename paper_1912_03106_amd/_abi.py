@@ -57,7 +57,7 @@ class Params(C.Structure):
         ("pcg_max_iter", C.c_int32), ("pcg_check_every", C.c_int32), ("ir_inner_tol", C.c_double),
         ("ir_max_iter", C.c_int32), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
         ("warm_start", C.c_int32), ("device_pointers", C.c_int32), ("profile_kernels", C.c_int32),
-        ("autotune", C.c_int32),
+        ("autotune", C.c_int32), ("pcg_kernel", C.c_int32),
     ]
 
 

@@ -122,26 +122,32 @@ static void set_rows_per_block(PcgWork& w, int rpb) {
 // and keep the fastest.  Results are cached per (n, W, columns, precision)
 // for the life of the process.
 struct TuneKey {
-  int n, W, cols, prec;
+  int n, W, cols, prec, dia;
   bool operator<(const TuneKey& o) const {
-    return std::tie(n, W, cols, prec) < std::tie(o.n, o.W, o.cols, o.prec);
+    return std::tie(n, W, cols, prec, dia) < std::tie(o.n, o.W, o.cols, o.prec, o.dia);
   }
 };
+struct TuneChoice {
+  int rpb, cpl;
+  bool dia;
+};
 static std::mutex g_tune_mu;
-static std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+static std::map<TuneKey, TuneChoice> g_tune_cache;
 
 static void autotune(Handle& h, LevelState& S) {
   PcgWork& w = S.pcg;
   const int ncols = w.cap;
-  if (S.n < 4096 || ncols < kWave) return;
+  w.dia = (h.par.pcg_kernel == 2);
+  if (!h.par.autotune || S.n < 4096 || ncols < kWave) return;
   const bool fp32 = h.par.precision == MGRIT_FP32_IR;
-  const TuneKey key{S.n, S.op.W, ncols, h.par.precision};
+  const TuneKey key{S.n, S.op.W, ncols, h.par.precision, S.op.dia_R * 4 + h.par.pcg_kernel};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      set_rows_per_block(w, it->second.first);
-      w.cpl = it->second.second;
+      set_rows_per_block(w, it->second.rpb);
+      w.cpl = it->second.cpl;
+      w.dia = it->second.dia;
       return;
     }
   }
@@ -163,12 +169,18 @@ static void autotune(Handle& h, LevelState& S) {
   const int reps = 4;
   float best = 1e30f;
   int best_rpb = w.rows_per_block, best_cpl = 1;
-  for (int cand = 0; cand < 2 * static_cast<int>(sizeof(kRowsPerBlockCandidates) / sizeof(int)); ++cand) {
-    const int rpb = kRowsPerBlockCandidates[cand >> 1];
-    const int cpl = 1 + (cand & 1);
-    if (cpl == 2 && S.op.W != 8) continue;
+  bool best_dia = false;
+  const int nr = static_cast<int>(sizeof(kRowsPerBlockCandidates) / sizeof(int));
+  for (int cand = 0; cand < 4 * nr; ++cand) {
+    const int rpb = kRowsPerBlockCandidates[cand % nr];
+    const int cpl = 1 + ((cand / nr) & 1);
+    const bool dia = (cand / (2 * nr)) != 0;
+    if (dia && S.op.dia_R == 0) continue;
+    if ((dia && h.par.pcg_kernel == 1) || (!dia && h.par.pcg_kernel == 2)) continue;
+    if (!dia && cpl == 2 && S.op.W != 8) continue;
     set_rows_per_block(w, rpb);
     w.cpl = cpl;
+    w.dia = dia;
     for (int warm = 0; warm < 2; ++warm) {
       if (warm) MG_HIP(hipEventRecord(h.ev0, s));
       for (int r = 0; r < reps; ++r) {
@@ -189,20 +201,22 @@ static void autotune(Handle& h, LevelState& S) {
       best = ms;
       best_rpb = rpb;
       best_cpl = cpl;
+      best_dia = dia;
     }
     if (std::getenv("MGRIT_TUNE_LOG")) {
       const double unit = fp32 ? 4.0 : 8.0;
       const double bytes = 8.0 * unit * S.n * static_cast<double>(ncols);  // A + B vector passes
-      std::fprintf(stderr, "[mgrit tune] n=%d cols=%d %s rpb=%d cpl=%d: A+B %.1f us, %.0f GB/s\n",
-                   S.n, ncols, fp32 ? "fp32" : "fp64", rpb, cpl, 1e3 * ms / reps,
-                   bytes / (1e-3 * ms / reps) / 1e9);
+      std::fprintf(stderr, "[mgrit tune] n=%d cols=%d %s %s rpb=%d cpl=%d: A+B %.1f us, %.0f GB/s\n",
+                   S.n, ncols, fp32 ? "fp32" : "fp64", dia ? "diag" : "ell", rpb, cpl,
+                   1e3 * ms / reps, bytes / (1e-3 * ms / reps) / 1e9);
     }
   }
   w.parity = 0;
   set_rows_per_block(w, best_rpb);
   w.cpl = best_cpl;
+  w.dia = best_dia;
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune_cache[key] = {best_rpb, best_cpl};
+  g_tune_cache[key] = {best_rpb, best_cpl, best_dia};
 }
 
 // ---------------------------------------------------------------------------
@@ -537,6 +551,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (!(par->pcg_tol > 0.0) || par->pcg_max_iter < 1) fail(MGRIT_INVALID_ARGUMENT, "bad PCG settings");
   if (par->precision != MGRIT_FP64 && par->precision != MGRIT_FP32_IR)
     fail(MGRIT_INVALID_ARGUMENT, "precision must be MGRIT_FP64 or MGRIT_FP32_IR");
+  if (par->pcg_kernel < 0 || par->pcg_kernel > 2) fail(MGRIT_INVALID_ARGUMENT, "pcg_kernel");
   if (par->precision == MGRIT_FP32_IR && (!(par->ir_inner_tol > 0.0) || par->ir_max_iter < 1))
     fail(MGRIT_INVALID_ARGUMENT, "bad refinement settings");
   if (ph.nonlinear) fail(MGRIT_UNSUPPORTED, "the nonlinear model is not available in this build");
@@ -631,8 +646,11 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   const int chunk = std::max(1, std::min(par->pcg_check_every > 0 ? par->pcg_check_every : 16, 64));
   h.ev.resize(4 * chunk);
   for (auto& e : h.ev) MG_HIP(hipEventCreate(&e));
-  if (par->autotune)
-    for (auto& S : h.lv) autotune(h, S);
+  for (auto& S : h.lv) {
+    if (par->pcg_kernel == 2 && S.op.dia_R == 0)
+      fail(MGRIT_UNSUPPORTED, "diagonal-window kernels need the periodic polar stencil");
+    autotune(h, S);
+  }
   MG_HIP(hipStreamSynchronize(s));
 }
 
@@ -753,6 +771,10 @@ static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, co
   hipStream_t s = h.stream;
   if (S.user.cap < B) alloc_pcg(h, S.user, S.n, static_cast<int>(round_up(B, kWave)), rows_per_block_for(S.n));
   PcgWork& w = S.user;
+  // same kernel family and tile shape as the level's own sweeps
+  set_rows_per_block(w, S.pcg.rows_per_block);
+  w.cpl = S.pcg.cpl;
+  w.dia = S.pcg.dia;
   // staging: time-major input/output and the column-block copy of u_prev
   double* tm = h.arena.alloc<double>(static_cast<size_t>(B) * S.n);
   double* cols = h.arena.alloc<double>(static_cast<size_t>(S.n) * w.ld);
@@ -835,6 +857,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->device_pointers = 0;
   p->profile_kernels = 0;
   p->autotune = 1;
+  p->pcg_kernel = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {

@@ -60,6 +60,11 @@ struct DevLevel {
   double* d64 = nullptr;       // [n] diag(A)
   double* ah64 = nullptr;      // [n*W] A^
   float* ah32 = nullptr;
+  // A^ by offset when the pattern is the periodic 7-diagonal polar stencil
+  // (offsets 0, +-1, +-R, +-(R+1) mod n); dia_R = 0 when it is not
+  int dia_R = 0;
+  double* dv64 = nullptr;      // [n][8]
+  float* dv32 = nullptr;
 };
 
 // Spatial transfer (rows = output nodes), fixed row width.
@@ -73,6 +78,7 @@ struct DevTransfer {
 struct PcgWork {
   int n = 0, cap = 0, nrb = 0, rows_per_block = 0;
   int cpl = 1;                  // columns per lane of the CG passes (1 or 2)
+  bool dia = false;             // use the diagonal-window CG passes
   int64_t ld = 0;
   double *x = nullptr, *r = nullptr;
   double* pbuf[2] = {nullptr, nullptr};  // search directions, ping-pong
@@ -120,6 +126,8 @@ void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, 
 // pass B: x += alpha S p^, r^ -= alpha A^ p^, partials of r^.r^ and ||r||^2
 void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols);
 void launch_scale_matrix(hipStream_t s, DevLevel& L, const int* diag_slot);
+// per-offset copy of A^ (L.dia_R set); *bad (device) counts entries off the stencil
+void launch_build_dia(hipStream_t s, DevLevel& L, int* bad);
 
 // FP32 inner solve of the refinement: the same two passes on r32/p32/x32.
 void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first);

@@ -298,6 +298,203 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_b(
   block_partials<2, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
 }
 
+// ---------------------------------------------------------------------------
+// Diagonal-window variants.  When every row's entries sit at the offsets
+// {-(R+1), -R, -1, 0, +1, +R, +R+1} (mod n) -- the P1 operator of a periodic
+// polar mesh numbered angle-major, R = radial unknowns per ray -- the
+// values are stored per offset (dv[i][8], slot order as listed, slot 7 = 0)
+// and a wave walking consecutive rows keeps three sliding windows in
+// registers: (i-R-1, i-R), (i-1, i, i+1), (i+R, i+R+1).  Moving to the next
+// row loads three new rows instead of seven.
+
+__device__ __forceinline__ int wrap_index(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
+
+template <typename T, int CPL>
+struct PDir {
+  // p^ = r^ + beta p^_old formed while loading (first: p^ = r^)
+  const T* r;
+  const T* pold;
+  int64_t ld;
+  int c0;
+  bool first;
+  T be[CPL];
+  __device__ __forceinline__ Vec<T, CPL> load(int row) const {
+    const int64_t o = row * ld + c0;
+    Vec<T, CPL> v = Vec<T, CPL>::load(r + o);
+    if (!first) {
+      const Vec<T, CPL> q = Vec<T, CPL>::load(pold + o);
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) v.v[k] = fma(be[k], q.v[k], v.v[k]);
+    }
+    return v;
+  }
+};
+
+template <typename T, int CPL>
+__global__ __launch_bounds__(kBlock) void k_cg_pass_a_dia(
+    int n, int R, const T* __restrict__ dv, int ncols, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ active, const double* __restrict__ beta, int first,
+    const T* __restrict__ r, const T* __restrict__ pold, T* __restrict__ pnew,
+    double* __restrict__ part, int nrb, int* __restrict__ flags, int* __restrict__ hist) {
+  using V = Vec<T, CPL>;
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int it = flags[4];
+    hist[it] = flags[0];
+    flags[4] = it + 1;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c0 = (cc * kWave + lane) * CPL;
+  bool on[CPL];
+  bool any = false;
+  PDir<T, CPL> P{r, pold, ld, c0, first != 0, {}};
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    on[k] = (c0 + k < ncols) && active[c0 + k];
+    any |= on[k];
+    P.be[k] = (first || !on[k]) ? T(0) : static_cast<T>(beta[c0 + k]);
+  }
+  double acc[1][CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) acc[0][k] = 0.0;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (any && i0 < n) {
+    V lo0 = P.load(wrap_index(i0 - R - 1, n)), lo1 = P.load(wrap_index(i0 - R, n));
+    V m0 = P.load(wrap_index(i0 - 1, n)), m1 = P.load(i0), m2 = P.load(wrap_index(i0 + 1, n));
+    V hi0 = P.load(wrap_index(i0 + R, n)), hi1 = P.load(wrap_index(i0 + R + 1, n));
+    for (int kk = 0; kk < rpw; ++kk) {
+      const int i = i0 + kk;
+      if (i >= n) break;
+      const T* a = dv + static_cast<int64_t>(i) * 8;
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        const T s = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
+                    a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
+        acc[0][k] += static_cast<double>(m1.v[k]) * static_cast<double>(s);
+      }
+      m1.store(pnew + i * ld + c0);
+      lo0 = lo1;
+      lo1 = P.load(wrap_index(i + 1 - R, n));
+      m0 = m1;
+      m1 = m2;
+      m2 = P.load(wrap_index(i + 2, n));
+      hi0 = hi1;
+      hi1 = P.load(wrap_index(i + R + 2, n));
+    }
+  }
+  block_partials<1, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
+}
+
+template <typename T, int CPL>
+__global__ __launch_bounds__(kBlock) void k_cg_pass_b_dia(
+    int n, int R, const T* __restrict__ dv, const T* __restrict__ sc, const double* __restrict__ dg,
+    int ncols, int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
+    const double* __restrict__ alpha, const T* __restrict__ p, T* __restrict__ x,
+    T* __restrict__ r, double* __restrict__ part, int nrb) {
+  using V = Vec<T, CPL>;
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c0 = (cc * kWave + lane) * CPL;
+  bool on[CPL];
+  bool any = false, all = true;
+  T al[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    on[k] = (c0 + k < ncols) && active[c0 + k];
+    any |= on[k];
+    all &= on[k];
+    al[k] = on[k] ? static_cast<T>(alpha[c0 + k]) : T(0);
+  }
+  double acc[2][CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) acc[0][k] = acc[1][k] = 0.0;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  auto ld_p = [&](int row) { return V::load(p + row * ld + c0); };
+  if (any && i0 < n) {
+    V lo0 = ld_p(wrap_index(i0 - R - 1, n)), lo1 = ld_p(wrap_index(i0 - R, n));
+    V m0 = ld_p(wrap_index(i0 - 1, n)), m1 = ld_p(i0), m2 = ld_p(wrap_index(i0 + 1, n));
+    V hi0 = ld_p(wrap_index(i0 + R, n)), hi1 = ld_p(wrap_index(i0 + R + 1, n));
+    for (int kk = 0; kk < rpw; ++kk) {
+      const int i = i0 + kk;
+      if (i >= n) break;
+      const T* a = dv + static_cast<int64_t>(i) * 8;
+      const int64_t o = i * ld + c0;
+      const T si = sc[i];
+      const double di = dg[i];
+      V xi = V::load(x + o);
+      V ri = V::load(r + o);
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        const T q = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
+                    a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
+        xi.v[k] = fma(al[k] * si, m1.v[k], xi.v[k]);
+        ri.v[k] = ri.v[k] - al[k] * q;
+        const double rd = static_cast<double>(ri.v[k]);
+        acc[0][k] += rd * rd;
+        acc[1][k] += di * (rd * rd);
+      }
+      if (all) {
+        xi.store(x + o);
+        ri.store(r + o);
+      } else {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+          if (on[k]) {
+            x[o + k] = xi.v[k];
+            r[o + k] = ri.v[k];
+          }
+      }
+      lo0 = lo1;
+      lo1 = ld_p(wrap_index(i + 1 - R, n));
+      m0 = m1;
+      m1 = m2;
+      m2 = ld_p(wrap_index(i + 2, n));
+      hi0 = hi1;
+      hi1 = ld_p(wrap_index(i + R + 2, n));
+    }
+  }
+  block_partials<2, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
+}
+
+// Scatter the scaled operator into the per-offset layout; flags[0] counts
+// entries whose offset is not one of the seven (then the layout is unusable).
+__global__ void k_build_dia(int n, int W, int R, const int* __restrict__ col,
+                            const double* __restrict__ ah, double* __restrict__ dv64,
+                            float* __restrict__ dv32, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int nbad = 0;
+  for (int t = 0; t < W; ++t) {
+    const double a = ah[static_cast<int64_t>(i) * W + t];
+    int off = col[static_cast<int64_t>(i) * W + t] - i;
+    if (off > n / 2) off -= n;
+    if (off < -(n / 2)) off += n;
+    int slot = -1;
+    if (off == -R - 1) slot = 0;
+    else if (off == -R) slot = 1;
+    else if (off == -1) slot = 2;
+    else if (off == 0) slot = 3;
+    else if (off == 1) slot = 4;
+    else if (off == R) slot = 5;
+    else if (off == R + 1) slot = 6;
+    if (slot < 0) {
+      if (a != 0.0) ++nbad;
+      continue;
+    }
+    v[slot] += a;
+  }
+  for (int t = 0; t < 8; ++t) {
+    dv64[static_cast<int64_t>(i) * 8 + t] = v[t];
+    dv32[static_cast<int64_t>(i) * 8 + t] = static_cast<float>(v[t]);
+  }
+  if (nbad) atomicAdd(bad, nbad);
+}
+
 // Refinement sweep, FP64 part: r = b - A x (FP64) for the columns that have
 // not reached the outer tolerance; the FP32 inner solve starts from
 // r^32 = float(S r) with correction d = 0.  Partials: r^32.r^32 (inner
@@ -569,10 +766,39 @@ static void pass_b_impl(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols,
                      r, w.part, w.nrb);
 }
 
+template <typename T, int CPL>
+static void pass_a_dia(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first,
+                       const T* dv, const T* r, T* pold, T* pnew) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, CPL, ncc);
+  hipLaunchKernelGGL((k_cg_pass_a_dia<T, CPL>), dim3(nb), dim3(kBlock), 0, s, L.n, L.dia_R, dv,
+                     ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 4 * w.ld, first, r, pold,
+                     pnew, w.part, w.nrb, w.flags, w.hist);
+}
+
+template <typename T, int CPL>
+static void pass_b_dia(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, const T* dv,
+                       const T* sc, const T* p, T* x, T* r) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, CPL, ncc);
+  hipLaunchKernelGGL((k_cg_pass_b_dia<T, CPL>), dim3(nb), dim3(kBlock), 0, s, L.n, L.dia_R, dv, sc,
+                     L.d64, ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, p, x,
+                     r, w.part, w.nrb);
+}
+
+void launch_build_dia(hipStream_t s, DevLevel& L, int* bad) {
+  hipLaunchKernelGGL(k_build_dia, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, L.W, L.dia_R,
+                     L.col, L.ah64, L.dv64, L.dv32, bad);
+  MG_HIP(hipGetLastError());
+}
+
 void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first) {
   double* pold = w.pbuf[w.parity];
   double* pnew = w.pbuf[w.parity ^ 1];
-  if (L.W == 8) {
+  if (w.dia) {
+    if (w.cpl == 2) pass_a_dia<double, 2>(s, L, w, ncols, first, L.dv64, w.r, pold, pnew);
+    else pass_a_dia<double, 1>(s, L, w, ncols, first, L.dv64, w.r, pold, pnew);
+  } else if (L.W == 8) {
     if (w.cpl == 2) pass_a_impl<double, 8, 2>(s, L, w, ncols, first, L.ah64, w.r, pold, pnew);
     else pass_a_impl<double, 8, 1>(s, L, w, ncols, first, L.ah64, w.r, pold, pnew);
   } else {
@@ -584,7 +810,10 @@ void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, 
 
 void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
   const double* p = w.pbuf[w.parity];
-  if (L.W == 8) {
+  if (w.dia) {
+    if (w.cpl == 2) pass_b_dia<double, 2>(s, L, w, ncols, L.dv64, L.s64, p, w.x, w.r);
+    else pass_b_dia<double, 1>(s, L, w, ncols, L.dv64, L.s64, p, w.x, w.r);
+  } else if (L.W == 8) {
     if (w.cpl == 2) pass_b_impl<double, 8, 2>(s, L, w, ncols, L.ah64, L.s64, p, w.x, w.r);
     else pass_b_impl<double, 8, 1>(s, L, w, ncols, L.ah64, L.s64, p, w.x, w.r);
   } else {
@@ -596,7 +825,10 @@ void launch_pcg_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) 
 void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first) {
   float* pold = w.p32[w.parity];
   float* pnew = w.p32[w.parity ^ 1];
-  if (L.W == 8) {
+  if (w.dia) {
+    if (w.cpl == 2) pass_a_dia<float, 2>(s, L, w, ncols, first, L.dv32, w.r32, pold, pnew);
+    else pass_a_dia<float, 1>(s, L, w, ncols, first, L.dv32, w.r32, pold, pnew);
+  } else if (L.W == 8) {
     if (w.cpl == 2) pass_a_impl<float, 8, 2>(s, L, w, ncols, first, L.ah32, w.r32, pold, pnew);
     else pass_a_impl<float, 8, 1>(s, L, w, ncols, first, L.ah32, w.r32, pold, pnew);
   } else {
@@ -608,7 +840,10 @@ void launch_pcg_pass_a32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols
 
 void launch_pcg_pass_b32(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols) {
   const float* p = w.p32[w.parity];
-  if (L.W == 8) {
+  if (w.dia) {
+    if (w.cpl == 2) pass_b_dia<float, 2>(s, L, w, ncols, L.dv32, L.s32, p, w.x32, w.r32);
+    else pass_b_dia<float, 1>(s, L, w, ncols, L.dv32, L.s32, p, w.x32, w.r32);
+  } else if (L.W == 8) {
     if (w.cpl == 2) pass_b_impl<float, 8, 2>(s, L, w, ncols, L.ah32, L.s32, p, w.x32, w.r32);
     else pass_b_impl<float, 8, 1>(s, L, w, ncols, L.ah32, L.s32, p, w.x32, w.r32);
   } else {

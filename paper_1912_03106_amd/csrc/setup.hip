@@ -339,6 +339,21 @@ DevLevel assemble_level(DeviceArena& A, hipStream_t s, const mgrit_mesh& m, cons
   launch_diag_inverse(s, L, diag);
   launch_load_vectors(s, L, cptr, contrib, diag, area, phase, sign);
   launch_scale_matrix(s, L, diag);
+  // Polar mesh numbered angle-major with both radii Dirichlet: the operator
+  // is the periodic 7-diagonal stencil with R = n_r - 1 unknowns per ray.
+  if (m.n_r > 2 && m.n_theta > 2 && P.n == (m.n_r - 1) * m.n_theta &&
+      2 * (m.n_r - 1) + 2 < P.n) {
+    L.dia_R = m.n_r - 1;
+    L.dv64 = A.alloc<double>(static_cast<size_t>(P.n) * 8);
+    L.dv32 = A.alloc<float>(static_cast<size_t>(P.n) * 8);
+    int* bad = A.alloc<int>(1);
+    MG_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    launch_build_dia(s, L, bad);
+    int hbad = 0;
+    MG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (hbad != 0) L.dia_R = 0;
+  }
   if (keep) {
     keep->n_tri = m.n_tri;
     keep->area = area;

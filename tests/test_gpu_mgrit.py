@@ -133,3 +133,26 @@ def test_mgrit_fp32_refinement_random_guess_matches_oracle(cfg1_oracle):
     U, st = s.solve(u_init=guess)
     assert st["converged"]
     assert _rel(U, U_seq) <= MGRIT_GATE
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_mgrit_kernel_families_agree(cfg1_oracle, kernel):
+    """The two batched-CG kernel families give the same MGRIT run."""
+    cfg, U_seq, _, hist = cfg1_oracle
+    s = _solver(cfg, pcg_tol=1e-12, pcg_kernel=kernel)
+    U, st = s.solve()
+    assert st["converged"] and abs(len(st["rho"]) - len(hist)) <= 1
+    assert _rel(U, U_seq) <= MGRIT_GATE
+
+
+def test_diagonal_window_rejects_non_polar_mesh():
+    from paper_1912_03106_amd import MgritError
+    from workload import polar_mesh
+    cfg = config("cfg1")
+    meshes = [polar_mesh(16, 128), polar_mesh(16, 128)]
+    for m in meshes:
+        m.n_r = 0
+        m.n_theta = 0
+    with pytest.raises(MgritError) as e:
+        _solver(cfg, meshes=meshes, pcg_kernel=2)
+    assert e.value.name == "UNSUPPORTED"

@@ -31,10 +31,20 @@ def cfg1_pair():
     return cfg, s, lev, U
 
 
+@pytest.fixture(scope="module")
+def solvers_by_kernel(cfg1_pair):
+    """phi_step with each batched-CG kernel family forced: general sparse
+    rows (1) and the diagonal window of the periodic polar stencil (2)."""
+    cfg = cfg1_pair[0]
+    return {k: _solver(cfg, pcg_tol=1e-13, pcg_kernel=k) for k in (1, 2)}
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("B", [1, 63, 64, 65, 200])
-def test_phi_matches_direct_solve(cfg1_pair, B):
-    cfg, s, lev, U = cfg1_pair
-    print(f"phi parity 16x128 B={B}", flush=True)
+def test_phi_matches_direct_solve(cfg1_pair, solvers_by_kernel, B, kernel):
+    cfg, _, lev, U = cfg1_pair
+    s = solvers_by_kernel[kernel]
+    print(f"phi parity 16x128 B={B} kernel={kernel}", flush=True)
     rng = np.random.default_rng(B)
     i_from = rng.integers(0, cfg.n_steps - 1, size=B)
     # realistic states (a trajectory) plus a perturbation
