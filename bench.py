@@ -34,30 +34,35 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def pass_b_roofline(st, solver):
-    """Algorithmic bytes of PCG pass B over the timed region / its device time.
+def pass_b_bytes(n, W, family, unit, cols, launches):
+    """Algorithmic bytes of CG pass B: per unconverged column of one row, read
+    p, x, r and write x, r (5 values); per launch, the level's operator
+    (family 2: 8 values per row; family 1: W values + W column indices) and
+    the two per-row scalings (S and diag A)."""
+    matrix = n * 8 * unit if family == 2 else n * W * (unit + 4)
+    return 5 * unit * n * cols + launches * (matrix + n * (unit + 8))
 
-    Per unconverged column of one row: read p, x, r and write x, r = 5 values;
-    per launch: the level's matrix (W values + W column indices per row) and
-    the Jacobi diagonal.
-    """
-    bytes_total = 0.0
-    launches = 0
-    t = 0.0
+
+def pass_b_roofline(st, solver, unit):
+    """Pass B over the whole timed region: algorithmic bytes / device time
+    (HIP events around every launch, every level)."""
+    bytes_total, launches, t = 0.0, 0, 0.0
+    names = set()
     for l in range(solver.cfg.n_levels):
         n, _, nnz = solver.level_info(l)
-        W = nnz // n
-        cols = st["kernel_columns"][l]
+        rpb, cpl, fam = solver.kernel_shape(l)
         lau = st["kernel_launches"][1][l]
-        bytes_total += 5 * 8 * n * cols + lau * n * (W * 12 + 8)
+        bytes_total += pass_b_bytes(n, nnz // n, fam, unit, st["kernel_columns"][l], lau)
         launches += lau
         t += st["kernel_time_s"][1][l]
+        T = "double" if unit == 8 else "float"
+        names.add(f"k_cg_pass_b_dia<{T}, {cpl}>" if fam == 2 else f"k_cg_pass_b<{T}, {nnz // n}, {cpl}>")
     if launches == 0 or t <= 0:
         return None
     achieved = bytes_total / t / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_pcg_pass_b<double,8>", "launches": launches,
+            "kernel": " + ".join(sorted(names)), "launches": launches,
             "avg_launch_us": round(1e6 * t / launches, 2),
             "bytes_per_launch": round(bytes_total / launches)}
 
@@ -155,7 +160,7 @@ def main():
         ps.close()
         log(f"sequential prefix {pre} steps: {tseq:.2f} s")
 
-    roof = pass_b_roofline(st, solver)
+    roof = pass_b_roofline(st, solver, 8 if cfg.precision == "fp64" else 4)
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     line = {
         "metric": "MGRIT time to 1e-8 rel. resid vs GPU seq. stepping; F-relax DOF-steps/s, GB/s",
@@ -176,7 +181,8 @@ def main():
                   "pass_a_time_s": [round(x, 3) for x in st["kernel_time_s"][0][:cfg.n_levels]],
                   "pass_b_time_s": [round(x, 3) for x in st["kernel_time_s"][1][:cfg.n_levels]]},
         "gpu_sequential": seq,
-        "autotuned_rows_per_block": [solver.rows_per_block(l) for l in range(cfg.n_levels)],
+        "autotuned_kernels": [dict(zip(("rows_per_block", "cols_per_lane", "family"),
+                                       solver.kernel_shape(l))) for l in range(cfg.n_levels)],
     }
     if seq:
         line["mgrit"]["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon"] / per, 3)

@@ -114,6 +114,8 @@ typedef struct {
   int32_t autotune;           /* 1: time the batched-PCG tile shapes at setup and keep the fastest */
   int32_t pcg_kernel;         /* batched-PCG kernels: 0 choose (autotuner), 1 general sparse rows,
                                * 2 diagonal window (periodic polar stencil only, else UNSUPPORTED) */
+  int32_t coarse_inverse;     /* 1: linear model, coarsest level <= 8192 unknowns: step with a
+                               * stored A^{-1} (exact implicit Euler) instead of PCG */
 } mgrit_params;
 
 typedef struct {
@@ -170,10 +172,11 @@ int phi_step(void* h, int32_t level, int32_t B, const int64_t* i_from,
              const double* u_prev, double* u_next);
 
 /* Sizes of a level: unknowns, steps, stored entries of the operator (fixed
- * row width times n), and the rows per work-group of its batched PCG kernels
- * (chosen by the autotuner).  Any output pointer may be NULL. */
+ * row width times n), and kernel_shape[3] of its batched PCG kernels as the
+ * autotuner chose them: rows per work-group, columns per lane, kernel family
+ * (1 general sparse rows, 2 diagonal window).  Any output pointer may be NULL. */
 int mgrit_level_info(void* h, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
-                     int32_t* rows_per_block);
+                     int32_t* kernel_shape);
 
 void mgrit_destroy(void* h);
 const char* mgrit_strerror(int status);

@@ -57,7 +57,7 @@ class Params(C.Structure):
         ("pcg_max_iter", C.c_int32), ("pcg_check_every", C.c_int32), ("ir_inner_tol", C.c_double),
         ("ir_max_iter", C.c_int32), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
         ("warm_start", C.c_int32), ("device_pointers", C.c_int32), ("profile_kernels", C.c_int32),
-        ("autotune", C.c_int32), ("pcg_kernel", C.c_int32),
+        ("autotune", C.c_int32), ("pcg_kernel", C.c_int32), ("coarse_inverse", C.c_int32),
     ]
 
 
@@ -100,7 +100,7 @@ def lib():
     L.phi_step.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.phi_step.restype = C.c_int
     L.mgrit_level_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
-                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32 * 3)]
     L.mgrit_level_info.restype = C.c_int
     L.mgrit_destroy.argtypes = [vp]
     L.mgrit_destroy.restype = None

@@ -46,6 +46,9 @@ struct LevelState {
   PcgWork user;      // phi_step workspace (grown on demand)
   double* seq_ws = nullptr;
   int* nat = nullptr;     // internal unknown -> user-facing index
+  double* Ainv = nullptr; // coarsest level, linear model: A^{-1} [n][ld_inv]
+  int64_t ld_inv = 0;
+  double* bvec = nullptr; // [n] right-hand side of one coarse step
   bool relaxed = false;   // F-points hold a previous iterate (warm starts)
   bool cvalid = false;    // C-points hold a previous iterate
 };
@@ -72,6 +75,7 @@ struct Handle {
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 constexpr int kMinRowsPerBlock = 16;
+constexpr int kMaxInverseN = 8192;   // largest coarsest level given a stored inverse
 static const int kRowsPerBlockCandidates[] = {16, 32, 64, 128, 256};
 
 static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block) {
@@ -184,13 +188,14 @@ static void autotune(Handle& h, LevelState& S) {
     for (int warm = 0; warm < 2; ++warm) {
       if (warm) MG_HIP(hipEventRecord(h.ev0, s));
       for (int r = 0; r < reps; ++r) {
-        if (fp32) {
-          launch_pcg_pass_a32(s, S.op, w, ncols, 0);
-          launch_pcg_pass_b32(s, S.op, w, ncols);
-        } else {
-          launch_pcg_pass_a(s, S.op, w, ncols, 0);
-          launch_pcg_pass_b(s, S.op, w, ncols);
-        }
+        // one CG iteration as the solver runs it (the reduces only sum
+        // partials here: every column stays active with alpha = beta = 0)
+        if (fp32) launch_pcg_pass_a32(s, S.op, w, ncols, 0);
+        else launch_pcg_pass_a(s, S.op, w, ncols, 0);
+        launch_reduce(s, w, ncols, RED_SUM, 0.0, 1, w.scal + 6 * w.ld);
+        if (fp32) launch_pcg_pass_b32(s, S.op, w, ncols);
+        else launch_pcg_pass_b(s, S.op, w, ncols);
+        launch_reduce(s, w, ncols, RED_SUM, 0.0, 2, w.scal + 6 * w.ld);
       }
     }
     MG_HIP(hipEventRecord(h.ev1, s));
@@ -206,7 +211,7 @@ static void autotune(Handle& h, LevelState& S) {
     if (std::getenv("MGRIT_TUNE_LOG")) {
       const double unit = fp32 ? 4.0 : 8.0;
       const double bytes = 8.0 * unit * S.n * static_cast<double>(ncols);  // A + B vector passes
-      std::fprintf(stderr, "[mgrit tune] n=%d cols=%d %s %s rpb=%d cpl=%d: A+B %.1f us, %.0f GB/s\n",
+      std::fprintf(stderr, "[mgrit tune] n=%d cols=%d %s %s rpb=%d cpl=%d: iteration %.1f us, %.0f GB/s\n",
                    S.n, ncols, fp32 ? "fp32" : "fp64", dia ? "diag" : "ell", rpb, cpl,
                    1e3 * ms / reps, bytes / (1e-3 * ms / reps) / 1e9);
     }
@@ -227,13 +232,13 @@ static void autotune(Handle& h, LevelState& S) {
 // the active-column count every pcg_check_every iterations.  Returns the
 // number of iterations in which some column was active.
 static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, double tol2,
-                       bool fp32, int active, bool fail_at_cap) {
+                       bool fp32, int active, bool fail_at_cap, int max_iter = -1) {
   hipStream_t s = h.stream;
   const bool prof = h.par.profile_kernels && h.st && level < MGRIT_MAX_LEVELS;
   int it = 0, used = 0;
   const int chunk = std::max(1, std::min(h.par.pcg_check_every > 0 ? h.par.pcg_check_every : 16,
                                          static_cast<int>(h.ev.size() / 4)));
-  const int cap = std::min(h.par.pcg_max_iter, w.hist_cap);
+  const int cap = std::min(max_iter > 0 ? max_iter : h.par.pcg_max_iter, w.hist_cap);
   int64_t cols = 0, launches = 0;
   w.parity = 0;
   while (active > 0) {
@@ -456,6 +461,14 @@ static void coarsest_solve(Handle& h, int l) {
   hipStream_t s = h.stream;
   // u_0 = g_0
   launch_axpby3(s, S.n, 1, S.U, S.ld, 0.0, CView{}, 1.0, CView{S.G, S.ld}, 0.0, CView{});
+  if (S.Ainv) {
+    // implicit Euler with the stored inverse: u_s = A^{-1} ((M/dt) u_{s-1} + f(t_s)) + g_s
+    for (int64_t st = 1; st <= S.N; ++st)
+      launch_coarse_step(s, S.op, h.src, static_cast<double>(st) * S.op.dt, S.U, S.ld,
+                         static_cast<int>(st), S.G, S.ld, S.Ainv, S.ld_inv, S.bvec);
+    if (h.st && l < MGRIT_MAX_LEVELS) h.st->phi_columns[l] += S.N;
+    return;
+  }
   MG_HIP(hipMemsetAsync(S.pcg.flags, 0, 4 * sizeof(int), s));
   launch_seq_small(s, S.op, h.src, static_cast<int>(S.N), 0, S.U, S.ld, S.G, S.ld, S.seq_ws,
                    h.par.pcg_tol, h.par.pcg_max_iter, 1, S.pcg.flags);
@@ -534,6 +547,37 @@ static void cycle(Handle& h, int l) {
   c_residual(h, l);
   coarse_correct(h, l);
   f_relax(h, l);
+}
+
+// A^{-1} of the coarsest level (linear model), by batched CG on the columns
+// of the identity to a relative residual of 1e-14.
+static void build_coarse_inverse(Handle& h, LevelState& S) {
+  hipStream_t s = h.stream;
+  PcgWork w;
+  const int chunk = std::min(S.n, 2048);
+  const int keep_max = h.par.pcg_max_iter;
+  h.par.pcg_max_iter = std::max(keep_max, 20000);   // history buffer size for this solve
+  alloc_pcg(h, w, S.n, chunk, rows_per_block_for(S.n));
+  h.par.pcg_max_iter = keep_max;
+  S.ld_inv = round_up(S.n, kWave);
+  S.Ainv = h.arena.alloc<double>(static_cast<size_t>(S.n) * S.ld_inv);
+  S.bvec = h.arena.alloc<double>(S.n);
+  const double tol2 = 1e-28;
+  for (int j0 = 0; j0 < S.n; j0 += chunk) {
+    const int nc = std::min(chunk, S.n - j0);
+    launch_cg_init_identity(s, S.op, w, j0, nc);
+    launch_reduce(s, w, nc, RED_INIT, tol2, 3, nullptr);
+    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    mgrit_stats* keep = h.st;
+    h.st = nullptr;
+    pcg_iterate(h, 0, S.op, w, nc, tol2, false, w.host_flags[0], true, w.hist_cap);
+    h.st = keep;
+    // columns j0.. of the inverse (symmetric: rows j0.. as well)
+    launch_axpby3(s, S.n, nc, S.Ainv + j0, S.ld_inv, 1.0, CView{w.x, w.ld}, 0.0, CView{}, 0.0,
+                  CView{});
+  }
+  MG_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------------------
@@ -651,6 +695,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
       fail(MGRIT_UNSUPPORTED, "diagonal-window kernels need the periodic polar stencil");
     autotune(h, S);
   }
+  if (L > 1 && !ph.nonlinear && par->coarse_inverse && h.lv.back().n <= kMaxInverseN)
+    build_coarse_inverse(h, h.lv.back());
   MG_HIP(hipStreamSynchronize(s));
 }
 
@@ -858,6 +904,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->profile_kernels = 0;
   p->autotune = 1;
   p->pcg_kernel = 0;
+  p->coarse_inverse = 1;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -903,14 +950,18 @@ int phi_step(void* hp, int32_t level, int32_t B, const int64_t* i_from, const do
 }
 
 int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
-                     int32_t* rows_per_block) {
+                     int32_t* kernel_shape) {
   auto* h = static_cast<mg::Handle*>(hp);
   if (!h || level < 0 || level >= static_cast<int>(h->lv.size())) return MGRIT_INVALID_ARGUMENT;
   const auto& S = h->lv[level];
   if (n) *n = S.n;
   if (n_steps) *n_steps = S.N;
   if (nnz) *nnz = static_cast<int64_t>(S.n) * S.op.W;
-  if (rows_per_block) *rows_per_block = S.pcg.rows_per_block;
+  if (kernel_shape) {
+    kernel_shape[0] = S.pcg.rows_per_block;
+    kernel_shape[1] = S.pcg.cpl;
+    kernel_shape[2] = S.pcg.dia ? 2 : 1;
+  }
   return MGRIT_OK;
 }
 

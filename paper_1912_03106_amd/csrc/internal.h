@@ -156,6 +156,13 @@ void launch_cols_to_slabs(hipStream_t s, int n, int64_t npts, int m, const doubl
 void launch_slabs_to_cols(hipStream_t s, int n, int64_t npts, int m, const double* slabs,
                           int64_t ld, int64_t slab_stride, double* dst, int64_t ldd);
 
+// Columns j0 .. j0+ncols-1 of the identity as CG right-hand sides (x = 0).
+void launch_cg_init_identity(hipStream_t s, const DevLevel& L, PcgWork& w, int j0, int ncols);
+// One coarse step with a stored inverse: U[:, step] = Ainv ((M/dt) U[:, step-1] + f(t)) + G[:, step].
+void launch_coarse_step(hipStream_t s, const DevLevel& L, const SourceDev& src, double t,
+                        double* U, int64_t ldu, int step, const double* G, int64_t ldg,
+                        const double* Ainv, int64_t lda, double* b);
+
 // Single-workgroup sequential stepper for small levels: for s = 1..nsteps,
 // U[:, s] = Phi(U[:, s-1]) + G[:, s] (G may be null) by Jacobi-PCG.
 void launch_seq_small(hipStream_t s, const DevLevel& L, const SourceDev& src, int nsteps,

@@ -421,6 +421,48 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_small(
   if (threadIdx.x == 0) atomicAdd(flags + 2, total_iters);
 }
 
+// Coarsest level with a stored inverse (linear model).  One step:
+//   b = (M/dt) U[:, s-1] + f(t_s);   U[:, s] = A^{-1} b + G[:, s].
+__global__ void k_coarse_rhs(int n, int W, const int* __restrict__ col,
+                             const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+                             const double* __restrict__ F, SourceDev src, double t,
+                             const double* __restrict__ U, int64_t ldu, int s,
+                             double* __restrict__ b) {
+  __shared__ double sg[3];
+  if (threadIdx.x == 0)
+    for (int p = 0; p < 3; ++p) sg[p] = src.scale * pwm(t, src, p);
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double bv = 0.0;
+  if (has_mass[i]) {
+    for (int k = 0; k < W; ++k)
+      bv += mm[static_cast<int64_t>(i) * W + k] * U[col[static_cast<int64_t>(i) * W + k] * ldu + s - 1];
+  }
+  bv += (sg[0] * F[i] + sg[1] * F[n + i]) + sg[2] * F[2 * n + i];
+  b[i] = bv;
+}
+
+// y_i = sum_j Ainv[i][j] b_j (+ g_i): one wave per row, lanes stride over j,
+// fixed butterfly.  Ainv is symmetric, stored [n][lda].
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(int n, const double* __restrict__ Ainv,
+                                                        int64_t lda, const double* __restrict__ b,
+                                                        double* __restrict__ U, int64_t ldu, int s,
+                                                        const double* __restrict__ G, int64_t ldg) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wave_index();
+  if (i >= n) return;
+  const double* row = Ainv + static_cast<int64_t>(i) * lda;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += kWave) acc += row[j] * b[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    double v = acc;
+    if (G) v += G[i * ldg + s];
+    U[i * ldu + s] = v;
+  }
+}
+
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 }  // namespace
@@ -541,6 +583,16 @@ void launch_slabs_to_cols(hipStream_t s, int n, int64_t npts, int m, const doubl
                           int64_t ld, int64_t ss, double* dst, int64_t ldd) {
   dim3 grid(ceil_div(npts, 256), n < 4096 ? n : 4096);
   hipLaunchKernelGGL(k_slabs_to_cols, grid, dim3(256), 0, s, n, npts, m, slabs, ld, ss, dst, ldd);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_coarse_step(hipStream_t s, const DevLevel& L, const SourceDev& src, double t,
+                        double* U, int64_t ldu, int step, const double* G, int64_t ldg,
+                        const double* Ainv, int64_t lda, double* b) {
+  hipLaunchKernelGGL(k_coarse_rhs, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, L.W, L.col,
+                     L.m64, L.has_mass, L.F, src, t, U, ldu, step, b);
+  hipLaunchKernelGGL(k_coarse_gemv, dim3(ceil_div(L.n, 4)), dim3(kBlock), 0, s, L.n, Ainv, lda, b,
+                     U, ldu, step, G, ldg);
   MG_HIP(hipGetLastError());
 }
 

@@ -495,6 +495,40 @@ __global__ void k_build_dia(int n, int W, int R, const int* __restrict__ col,
   if (nbad) atomicAdd(bad, nbad);
 }
 
+// CG start for A x = e_(j0 + c) (columns of the inverse), x = 0:
+// r^ = S e, partials r^.r^, r.r = 1, b.b = 1.
+__global__ __launch_bounds__(kBlock) void k_cg_init_identity(
+    int n, int j0, const double* __restrict__ sc, int ncols, int ncc, int rpb, int64_t ld,
+    double* __restrict__ x, double* __restrict__ r, double* __restrict__ part, int nrb,
+    int* __restrict__ flags) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[4] = 0;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  bool on[1] = {c < ncols};
+  double acc[3][1] = {{0.0}, {0.0}, {0.0}};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on[0]) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const double rv = (i == j0 + c) ? 1.0 : 0.0;
+      const double rh = sc[i] * rv;
+      x[i * ld + c] = 0.0;
+      r[i * ld + c] = rh;
+      acc[0][0] += rh * rh;
+      acc[1][0] += rv * rv;
+      acc[2][0] += rv * rv;
+    }
+  }
+  block_partials<3, 1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
 // Refinement sweep, FP64 part: r = b - A x (FP64) for the columns that have
 // not reached the outer tolerance; the FP32 inner solve starts from
 // r^32 = float(S r) with correction d = 0.  Partials: r^32.r^32 (inner
@@ -570,7 +604,8 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(int n, int ncols, int ncc,
 }
 
 // Per-column reduction of the row-block partials, in a fixed order, followed
-// by the CG scalar updates.  16 columns per work-group, 16 threads per column.
+// by the CG scalar updates.  One wave per column (4 columns per work-group):
+// lane l sums row blocks l, l+64, ... in order, then a fixed butterfly.
 //   INIT:    rz, rr, bb; active = rr > tol2 bb (bb = 0: relative to rr)
 //   ALPHA:   alpha = rz / p.Ap (0 for columns that are not active)
 //   BETA:    beta = rz_new / rz, convergence test (beta = 0 once converged)
@@ -584,31 +619,24 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
                                                    int* __restrict__ flags,
                                                    double* __restrict__ sums_out,
                                                    uint8_t* __restrict__ outer) {
-  __shared__ double red[3][16][16];
   __shared__ int cnt;
-  const int cl = threadIdx.x & 15, seg = threadIdx.x >> 4;
-  const int c = blockIdx.x * 16 + cl;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + wv;
   if (threadIdx.x == 0) cnt = 0;
   if (mode == RED_ALPHA && blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
+  __syncthreads();
   bool on = c < ncols;
   if (on && (mode == RED_ALPHA || mode == RED_BETA)) on = active[c] != 0;
   if (on && mode == RED_IR_INIT) on = outer[c] != 0;
-  double S[3] = {0.0, 0.0, 0.0};
+  double T[3] = {0.0, 0.0, 0.0};
   if (on) {
     const int64_t qs = static_cast<int64_t>(nrb) * ld;
-    for (int rb = seg; rb < nrb; rb += 16) {
-      for (int q = 0; q < nq; ++q) S[q] += part[q * qs + rb * ld + c];
-    }
+    for (int rb = lane; rb < nrb; rb += kWave)
+      for (int q = 0; q < nq; ++q) T[q] += part[q * qs + rb * ld + c];
+    for (int q = 0; q < nq; ++q)
+      for (int off = 32; off > 0; off >>= 1) T[q] += __shfl_xor(T[q], off, 64);
   }
-  for (int q = 0; q < 3; ++q) red[q][seg][cl] = S[q];
-  __syncthreads();
-  if (seg == 0 && c < ncols) {
-    double T[3];
-    for (int q = 0; q < 3; ++q) {
-      double t = 0.0;
-      for (int s = 0; s < 16; ++s) t += red[q][s][cl];
-      T[q] = t;
-    }
+  if (lane == 0 && c < ncols) {
     double* rz = scal;
     double* rr = scal + ld;
     double* bb = scal + 2 * ld;
@@ -739,9 +767,17 @@ void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CV
   MG_HIP(hipGetLastError());
 }
 
+void launch_cg_init_identity(hipStream_t s, const DevLevel& L, PcgWork& w, int j0, int ncols) {
+  int ncc;
+  const int nb = grid_tiles(w, ncols, 1, ncc);
+  hipLaunchKernelGGL(k_cg_init_identity, dim3(nb), dim3(kBlock), 0, s, L.n, j0, L.s64, ncols, ncc,
+                     w.rows_per_block, w.ld, w.x, w.r, w.part, w.nrb, w.flags);
+  MG_HIP(hipGetLastError());
+}
+
 void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
                    double* sums_out) {
-  hipLaunchKernelGGL(k_reduce, dim3(ceil_div(ncols, 16)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
+  hipLaunchKernelGGL(k_reduce, dim3(ceil_div(ncols, 4)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
                      mode, nq, tol2, w.part, w.scal, w.active, w.flags, sums_out, w.outer);
   MG_HIP(hipGetLastError());
 }

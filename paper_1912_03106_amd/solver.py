@@ -94,17 +94,19 @@ class Solver:
     # -- sizes -----------------------------------------------------------
     def level_info(self, level):
         """(unknowns, steps, stored operator entries) of a level."""
-        n, N, nnz, rpb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        n, N, nnz = C.c_int64(), C.c_int64(), C.c_int64()
         _check(self._L, self._h, self._L.mgrit_level_info(self._h, level, C.byref(n), C.byref(N),
-                                                          C.byref(nnz), C.byref(rpb)))
+                                                          C.byref(nnz), None))
         return n.value, N.value, nnz.value
 
-    def rows_per_block(self, level):
-        """Rows per work-group of the level's batched PCG kernels (autotuned)."""
-        rpb = C.c_int32()
+    def kernel_shape(self, level):
+        """(rows per work-group, columns per lane, family) of the level's batched
+        PCG kernels as the autotuner chose them; family 1 = general sparse rows,
+        2 = diagonal window."""
+        shape = (C.c_int32 * 3)()
         _check(self._L, self._h, self._L.mgrit_level_info(self._h, level, None, None, None,
-                                                          C.byref(rpb)))
-        return rpb.value
+                                                          C.byref(shape)))
+        return tuple(shape)
 
     @property
     def n0(self):

@@ -156,3 +156,15 @@ def test_diagonal_window_rejects_non_polar_mesh():
     with pytest.raises(MgritError) as e:
         _solver(cfg, meshes=meshes, pcg_kernel=2)
     assert e.value.name == "UNSUPPORTED"
+
+
+@pytest.mark.parametrize("coarse_inverse", [0, 1])
+def test_mgrit_coarsest_solver_variants_agree(cfg1_oracle, coarse_inverse):
+    """Coarsest level stepped by PCG or by the stored inverse: same iterates."""
+    cfg, U_seq, _, hist = cfg1_oracle
+    s = _solver(cfg, pcg_tol=1e-12, coarse_inverse=coarse_inverse)
+    U, st = s.solve()
+    assert st["converged"] and abs(len(st["rho"]) - len(hist)) <= 1
+    for a, b in zip(st["rho"], hist):
+        assert abs(a - b) <= 1e-9 * hist[0]
+    assert _rel(U, U_seq) <= MGRIT_GATE
