@@ -98,8 +98,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--config", default="cfg2")
-    ap.add_argument("--seq-prefix", type=int, default=256,
-                    help="steps of the GPU sequential baseline actually run (scaled to N_t)")
+    ap.add_argument("--seq-prefix", type=int, default=0,
+                    help="run only this many steps of the GPU sequential baseline and scale "
+                         "to N_t (0 = the whole horizon)")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -143,7 +144,7 @@ def main():
 
     seq = None
     if not args.no_seq:
-        pre = min(args.seq_prefix, cfg.n_steps)
+        pre = min(args.seq_prefix, cfg.n_steps) if args.seq_prefix > 0 else cfg.n_steps
         pcfg = config(args.config, n_steps=pre, t_final=pre * cfg.dt)
         pcfg.meshes = cfg.meshes[:1] * 2
         ps = Solver(pcfg, stream=stream.cuda_stream, device_io=True)
@@ -153,7 +154,8 @@ def main():
         _, sst = ps.seq_solve(out=pout)
         torch.cuda.synchronize()
         tseq = time.perf_counter() - ts
-        seq = {"kernel": "single-workgroup persistent Jacobi-PCG stepper", "steps_run": pre,
+        seq = {"kernel": "cooperative multi-work-group Jacobi-PCG stepper (warm start u_{i-1})",
+               "steps_run": pre,
                "time_s_run": round(tseq, 3), "time_s_full_horizon": round(tseq * cfg.n_steps / pre, 2),
                "dof_steps_per_s": round(n0 * pre / tseq, 1),
                "pcg_iterations_per_step": round(sst["pcg_sweeps"][0] / pre, 1)}

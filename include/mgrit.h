@@ -116,6 +116,7 @@ typedef struct {
                                * 2 diagonal window (periodic polar stencil only, else UNSUPPORTED) */
   int32_t coarse_inverse;     /* 1: linear model, coarsest level <= 8192 unknowns: step with a
                                * stored A^{-1} (exact implicit Euler) instead of PCG */
+  int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one work-group, 2 cooperative grid */
 } mgrit_params;
 
 typedef struct {

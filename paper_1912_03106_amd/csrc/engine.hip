@@ -67,6 +67,10 @@ struct Handle {
   double* u0_dev = nullptr;       // [n0]
   double* seq_U = nullptr;        // sequential trajectory [n0][ld] (lazy)
   double* seq_ws = nullptr;
+  int coop_blocks = 0;            // cooperative stepper (lazy)
+  double* coop_ws = nullptr;
+  double* coop_part = nullptr;
+  unsigned* coop_bar = nullptr;
   mgrit_stats* st = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> ev;     // 4 per PCG iteration of a chunk (profiling)
@@ -789,15 +793,37 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   MG_HIP(hipMemsetAsync(U, 0, sizeof(double) * S0.n * ld, s));
   launch_tm_to_slabs(s, S0.n, 1, 1, h.u0_dev, U, ld, 0, S0.nat);
   int* flags = S0.pcg.flags;
-  MG_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), s));
+  MG_HIP(hipMemsetAsync(flags, 0, 8 * sizeof(int), s));
+  const bool coop = h.par.seq_kernel == 2 || (h.par.seq_kernel == 0 && S0.n >= 4096 && S0.op.W == 8);
   auto t0 = std::chrono::steady_clock::now();
-  launch_seq_small(s, S0.op, h.src, static_cast<int>(S0.N), 0, U, ld, nullptr, 0, ws,
-                   h.par.pcg_tol, h.par.pcg_max_iter, 0, flags);
-  MG_HIP(hipMemcpyAsync(S0.pcg.host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-  MG_HIP(hipStreamSynchronize(s));
+  if (coop) {
+    if (!h.coop_ws) {
+      h.coop_blocks = seq_coop_blocks();
+      h.coop_ws = h.arena.alloc<double>(5 * static_cast<size_t>(S0.n));
+      h.coop_part = h.arena.alloc<double>(8 * static_cast<size_t>(h.coop_blocks));
+      h.coop_bar = h.arena.alloc<unsigned>(2);
+    }
+    const int chunk = 512;
+    for (int64_t s0 = 1; s0 <= S0.N; s0 += chunk) {
+      const int64_t s1 = std::min<int64_t>(S0.N + 1, s0 + chunk);
+      MG_HIP(hipMemsetAsync(h.coop_bar, 0, 2 * sizeof(unsigned), s));
+      launch_seq_coop(s, S0.op, h.src, static_cast<int>(s0), static_cast<int>(s1), U, ld, h.coop_ws,
+                      h.coop_part, h.coop_bar, flags, h.par.pcg_tol, h.par.pcg_max_iter,
+                      h.coop_blocks);
+      MG_HIP(hipMemcpyAsync(S0.pcg.host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      MG_HIP(hipStreamSynchronize(s));
+      if (S0.pcg.host_flags[1]) break;
+    }
+  } else {
+    launch_seq_small(s, S0.op, h.src, static_cast<int>(S0.N), 0, U, ld, nullptr, 0, ws,
+                     h.par.pcg_tol, h.par.pcg_max_iter, 0, flags);
+    MG_HIP(hipMemcpyAsync(S0.pcg.host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+  }
   st->time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   st->phi_columns[0] += S0.N;
   st->pcg_sweeps[0] += S0.pcg.host_flags[2];
+  if (S0.pcg.host_flags[1] & 4) fail(MGRIT_HIP_ERROR, "a grid barrier of the sequential stepper timed out");
   if (S0.pcg.host_flags[1] & 1) fail(MGRIT_NONFINITE, "non-finite value in sequential stepping");
   if (S0.pcg.host_flags[1] & 2) fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in sequential stepping");
   const size_t tm_elems = static_cast<size_t>(S0.N + 1) * S0.n;
@@ -905,6 +931,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->autotune = 1;
   p->pcg_kernel = 0;
   p->coarse_inverse = 1;
+  p->seq_kernel = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {

@@ -163,6 +163,15 @@ void launch_coarse_step(hipStream_t s, const DevLevel& L, const SourceDev& src, 
                         double* U, int64_t ldu, int step, const double* G, int64_t ldg,
                         const double* Ainv, int64_t lda, double* b);
 
+// Cooperative sequential stepper: steps s_begin .. s_end-1 of U[:, s] =
+// Phi(U[:, s-1]) on `blocks` co-resident work-groups.  ws: [5n] doubles,
+// part: [blocks*8] doubles, bar_state: 2 zeroed unsigned; flags as for
+// launch_seq_small (bit 4 of flags[1]: a grid barrier timed out).
+int seq_coop_blocks();
+void launch_seq_coop(hipStream_t s, const DevLevel& L, const SourceDev& src, int s_begin,
+                     int s_end, double* U, int64_t ldu, double* ws, double* part,
+                     unsigned* bar_state, int* flags, double tol, int maxit, int blocks);
+
 // Single-workgroup sequential stepper for small levels: for s = 1..nsteps,
 // U[:, s] = Phi(U[:, s-1]) + G[:, s] (G may be null) by Jacobi-PCG.
 void launch_seq_small(hipStream_t s, const DevLevel& L, const SourceDev& src, int nsteps,

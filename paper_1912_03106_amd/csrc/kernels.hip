@@ -463,6 +463,175 @@ __global__ __launch_bounds__(kBlock) void k_coarse_gemv(int n, const double* __r
   }
 }
 
+// ----------------------------------------------------------------------------
+// Cooperative sequential stepper (the GPU sequential baseline): one grid of
+// co-resident work-groups advances U[:, s] = Phi(U[:, s-1]) step after step
+// with Jacobi-PCG spread over all work-groups.  Rows are distributed over the
+// grid's threads; a CG iteration is two phases separated by grid barriers
+// (A: p = D^{-1} r + beta p' with neighbours formed on the fly, q = A p,
+// partials of p.q;  B: x += alpha p, r -= alpha q, partials of r.z, r.r).
+// Reductions: per-block partials, summed by every block in block order.
+// The barrier spins a bounded number of times; on timeout it sets an error
+// bit and the kernel returns, so a launch always ends.
+
+constexpr unsigned kSpinLimit = 1u << 24;
+
+struct GridBar {
+  unsigned* count;
+  unsigned* gen;
+  int* flags;
+};
+
+__device__ bool grid_sync(const GridBar& g) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    __threadfence();
+    const unsigned my = __hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = atomicAdd(g.count, 1u);
+    if (arrived == gridDim.x - 1) {
+      atomicExch(g.count, 0u);
+      __threadfence();
+      atomicAdd(g.gen, 1u);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > kSpinLimit) {
+          atomicOr(g.flags + 1, 4);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Sum v over the block (fixed order) and store it at part[blockIdx.x * 8 + q].
+__device__ void block_store(double v, double* sh, double* part, int q) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) t += sh[k];
+    part[blockIdx.x * 8 + q] = t;
+  }
+  __syncthreads();
+}
+
+__device__ double grid_total(const double* part, int q) {
+  double t = 0.0;
+  for (unsigned b = 0; b < gridDim.x; ++b) t += part[b * 8 + q];
+  return t;
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_seq_coop(
+    int n, const int* __restrict__ col, const double* __restrict__ a,
+    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+    const double* __restrict__ dinv, const double* __restrict__ F, SourceDev src, double dt,
+    int64_t t0, int s_begin, int s_end, double* __restrict__ U, int64_t ldu,
+    double* __restrict__ ws, double* __restrict__ part, GridBar bar, double tol, int maxit) {
+  __shared__ double sh[16];
+  double* x = ws;
+  double* r = ws + n;
+  double* pb[2] = {ws + 2 * n, ws + 3 * n};
+  double* q = ws + 4 * n;
+  const int T = gridDim.x * blockDim.x;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const double tol2 = tol * tol;
+  int iters = 0;
+  for (int s = s_begin; s < s_end; ++s) {
+    const double t = static_cast<double>(t0 + s) * dt;
+    const double s0 = src.scale * pwm(t, src, 0), s1 = src.scale * pwm(t, src, 1),
+                 s2 = src.scale * pwm(t, src, 2);
+    double lrz = 0.0, lrr = 0.0, lbb = 0.0;
+    for (int i = tid; i < n; i += T) {
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      double bv = 0.0;
+      if (has_mass[i]) {
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+        for (int k = 0; k < W; ++k) bv += mi[k] * U[ci[k] * ldu + s - 1];
+      }
+      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      const double* ai = a + static_cast<int64_t>(i) * W;
+      double ax = 0.0;
+      for (int k = 0; k < W; ++k) ax += ai[k] * U[ci[k] * ldu + s - 1];
+      const double rv = bv - ax;
+      x[i] = U[i * ldu + s - 1];
+      r[i] = rv;
+      lrz += rv * (dinv[i] * rv);
+      lrr += rv * rv;
+      lbb += bv * bv;
+    }
+    block_store(lrz, sh, part, 3);
+    block_store(lrr, sh, part, 4);
+    block_store(lbb, sh, part, 5);
+    if (!grid_sync(bar)) return;
+    double rz = grid_total(part, 3), rr = grid_total(part, 4), bb = grid_total(part, 5);
+    if (bb == 0.0) bb = rr;
+    double beta = 0.0;
+    int par = 0, it = 0;
+    while (rr > tol2 * bb) {
+      if (it >= maxit) {
+        if (tid == 0) atomicOr(bar.flags + 1, 2);
+        return;
+      }
+      const double* po = pb[par];
+      double* pn = pb[par ^ 1];
+      double lpq = 0.0;
+      for (int i = tid; i < n; i += T) {
+        const int* ci = col + static_cast<int64_t>(i) * W;
+        const double* ai = a + static_cast<int64_t>(i) * W;
+        double qs = 0.0;
+        for (int k = 0; k < W; ++k) {
+          const int j = ci[k];
+          qs += ai[k] * fma(beta, po[j], dinv[j] * r[j]);
+        }
+        const double pi = fma(beta, po[i], dinv[i] * r[i]);
+        pn[i] = pi;
+        q[i] = qs;
+        lpq += pi * qs;
+      }
+      block_store(lpq, sh, part, 0);
+      if (!grid_sync(bar)) return;
+      const double alpha = rz / grid_total(part, 0);
+      double lz = 0.0;
+      lrr = 0.0;
+      for (int i = tid; i < n; i += T) {
+        x[i] += alpha * pn[i];
+        const double rv = r[i] - alpha * q[i];
+        r[i] = rv;
+        lz += rv * (dinv[i] * rv);
+        lrr += rv * rv;
+      }
+      block_store(lz, sh, part, 1);
+      block_store(lrr, sh, part, 2);
+      if (!grid_sync(bar)) return;
+      const double rzn = grid_total(part, 1);
+      rr = grid_total(part, 2);
+      if (!isfinite(rr)) {
+        if (tid == 0) atomicOr(bar.flags + 1, 1);
+        return;
+      }
+      beta = rzn / rz;
+      rz = rzn;
+      par ^= 1;
+      ++it;
+    }
+    iters += it;
+    for (int i = tid; i < n; i += T) U[i * ldu + s] = x[i];
+    if (!grid_sync(bar)) return;
+  }
+  if (tid == 0) atomicAdd(bar.flags + 2, iters);
+}
+
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 }  // namespace
@@ -594,6 +763,38 @@ void launch_coarse_step(hipStream_t s, const DevLevel& L, const SourceDev& src, 
   hipLaunchKernelGGL(k_coarse_gemv, dim3(ceil_div(L.n, 4)), dim3(kBlock), 0, s, L.n, Ainv, lda, b,
                      U, ldu, step, G, ldg);
   MG_HIP(hipGetLastError());
+}
+
+int seq_coop_blocks() {
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  MG_HIP(hipGetDevice(&dev));
+  MG_HIP(hipGetDeviceProperties(&prop, dev));
+  MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_seq_coop<8>, kBlock, 0));
+  const int fit = per_cu * prop.multiProcessorCount;
+  return fit < 128 ? fit : 128;
+}
+
+void launch_seq_coop(hipStream_t s, const DevLevel& L, const SourceDev& src, int s_begin,
+                     int s_end, double* U, int64_t ldu, double* ws, double* part,
+                     unsigned* bar_state, int* flags, double tol, int maxit, int blocks) {
+  if (s_end <= s_begin) return;
+  if (L.W != 8) fail(MGRIT_UNSUPPORTED, "cooperative stepper needs rows of width 8");
+  GridBar bar{bar_state, bar_state + 1, flags};
+  int64_t t0 = 0;
+  int n = L.n;
+  const int* col = L.col;
+  const double* a = L.a64;
+  const double* mm = L.m64;
+  const uint8_t* hm = L.has_mass;
+  const double* dinv = L.dinv64;
+  const double* F = L.F;
+  SourceDev sd = src;
+  double dt = L.dt;
+  void* args[] = {&n, &col, &a, &mm, &hm, &dinv, &F, &sd, &dt, &t0, &s_begin, &s_end,
+                  &U, &ldu, &ws, &part, &bar, &tol, &maxit};
+  MG_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_seq_coop<8>), dim3(blocks),
+                                    dim3(kBlock), args, 0, s));
 }
 
 void launch_seq_small(hipStream_t s, const DevLevel& L, const SourceDev& src, int nsteps,

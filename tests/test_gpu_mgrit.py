@@ -35,10 +35,13 @@ def cfg1_oracle():
     return cfg, U_seq, U_mg, hist
 
 
-def test_seq_solve_matches_oracle(cfg1_oracle):
-    print("seq cfg1", flush=True)
+@pytest.mark.parametrize("seq_kernel", [1, 2])
+def test_seq_solve_matches_oracle(cfg1_oracle, seq_kernel):
+    """GPU sequential stepping (one work-group, or the cooperative grid) vs the
+    oracle's direct-solve stepping."""
+    print(f"seq cfg1 kernel {seq_kernel}", flush=True)
     cfg, U_seq, _, _ = cfg1_oracle
-    s = _solver(cfg, pcg_tol=1e-13)
+    s = _solver(cfg, pcg_tol=1e-13, seq_kernel=seq_kernel)
     U, st = s.seq_solve()
     assert U.shape == U_seq.shape
     err = np.linalg.norm(U - U_seq, axis=1)[1:] / np.linalg.norm(U_seq, axis=1)[1:]
