@@ -801,12 +801,12 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
       h.coop_blocks = seq_coop_blocks();
       h.coop_ws = h.arena.alloc<double>(5 * static_cast<size_t>(S0.n));
       h.coop_part = h.arena.alloc<double>(8 * static_cast<size_t>(h.coop_blocks));
-      h.coop_bar = h.arena.alloc<unsigned>(2);
+      h.coop_bar = h.arena.alloc<unsigned>(coop_bar_words(h.coop_blocks));
     }
     const int chunk = 512;
     for (int64_t s0 = 1; s0 <= S0.N; s0 += chunk) {
       const int64_t s1 = std::min<int64_t>(S0.N + 1, s0 + chunk);
-      MG_HIP(hipMemsetAsync(h.coop_bar, 0, 2 * sizeof(unsigned), s));
+      MG_HIP(hipMemsetAsync(h.coop_bar, 0, coop_bar_words(h.coop_blocks) * sizeof(unsigned), s));
       launch_seq_coop(s, S0.op, h.src, static_cast<int>(s0), static_cast<int>(s1), U, ld, h.coop_ws,
                       h.coop_part, h.coop_bar, flags, h.par.pcg_tol, h.par.pcg_max_iter,
                       h.coop_blocks);

@@ -165,9 +165,10 @@ void launch_coarse_step(hipStream_t s, const DevLevel& L, const SourceDev& src, 
 
 // Cooperative sequential stepper: steps s_begin .. s_end-1 of U[:, s] =
 // Phi(U[:, s-1]) on `blocks` co-resident work-groups.  ws: [5n] doubles,
-// part: [blocks*8] doubles, bar_state: 2 zeroed unsigned; flags as for
+// part: [blocks*8] doubles, bar_state: coop_bar_words(blocks) zeroed unsigned; flags as for
 // launch_seq_small (bit 4 of flags[1]: a grid barrier timed out).
 int seq_coop_blocks();
+inline size_t coop_bar_words(int blocks) { return 16 * (static_cast<size_t>(blocks) + 1); }
 void launch_seq_coop(hipStream_t s, const DevLevel& L, const SourceDev& src, int s_begin,
                      int s_end, double* U, int64_t ldu, double* ws, double* part,
                      unsigned* bar_state, int* flags, double tol, int maxit, int blocks);

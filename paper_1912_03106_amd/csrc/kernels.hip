@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 
 #include "internal.h"
 
@@ -475,29 +476,35 @@ __global__ __launch_bounds__(kBlock) void k_coarse_gemv(int n, const double* __r
 // bit and the kernel returns, so a launch always ends.
 
 constexpr unsigned kSpinLimit = 1u << 24;
+constexpr int kMaxCoopBlocks = 1024;
+constexpr int kFlagStride = 16;   // one 64-byte line per block flag
 
+// Flag barrier: block b publishes its epoch in arrive[b] (its own cache
+// line, one release store); block 0 polls every flag with one thread per
+// flag (relaxed loads), then publishes the epoch in *release; the other
+// blocks poll it (relaxed) and take one acquire fence.  Release/acquire
+// operations are kept to one each per block and barrier because each one
+// maintains the XCD's L2.  Every wait is bounded.
 struct GridBar {
-  unsigned* count;
-  unsigned* gen;
+  unsigned* arrive;   // [gridDim.x * kFlagStride], zeroed before the launch
+  unsigned* release;  // one word, zeroed before the launch
   int* flags;
 };
 
-__device__ bool grid_sync(const GridBar& g) {
+__device__ bool grid_sync(const GridBar& g, unsigned& epoch) {
   __shared__ int ok;
+  ++epoch;
+  if (threadIdx.x == 0) ok = 1;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    ok = 1;
-    __threadfence();
-    const unsigned my = __hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = atomicAdd(g.count, 1u);
-    if (arrived == gridDim.x - 1) {
-      atomicExch(g.count, 0u);
-      __threadfence();
-      atomicAdd(g.gen, 1u);
-    } else {
+  if (threadIdx.x == 0)
+    __hip_atomic_store(g.arrive + blockIdx.x * kFlagStride, epoch, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  if (blockIdx.x == 0) {
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
       unsigned spins = 0;
-      while (__hip_atomic_load(g.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == my) {
-        __builtin_amdgcn_s_sleep(2);
+      while (__hip_atomic_load(g.arrive + b * kFlagStride, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
           atomicOr(g.flags + 1, 4);
           ok = 0;
@@ -505,7 +512,22 @@ __device__ bool grid_sync(const GridBar& g) {
         }
       }
     }
-    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      __hip_atomic_store(g.release, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(g.release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        atomicOr(g.flags + 1, 4);
+        ok = 0;
+        break;
+      }
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
   }
   __syncthreads();
   return ok != 0;
@@ -525,10 +547,31 @@ __device__ void block_store(double v, double* sh, double* part, int q) {
   __syncthreads();
 }
 
-__device__ double grid_total(const double* part, int q) {
-  double t = 0.0;
-  for (unsigned b = 0; b < gridDim.x; ++b) t += part[b * 8 + q];
-  return t;
+// Totals of partial quantities q0 .. q0+NQ-1 over all blocks: thread t
+// loads block t's partials, then a fixed butterfly per wave and the waves in
+// order.  Every block computes the same bits.
+template <int NQ>
+__device__ void grid_totals(const double* part, int q0, double (&out)[NQ], double* sh) {
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] += part[b * 8 + q0 + q];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    if (lane == 0) sh[wv * NQ + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double t = 0.0;
+    for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) t += sh[k * NQ + q];
+    out[q] = t;
+  }
+  __syncthreads();
 }
 
 template <int W>
@@ -539,6 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_seq_coop(
     int64_t t0, int s_begin, int s_end, double* __restrict__ U, int64_t ldu,
     double* __restrict__ ws, double* __restrict__ part, GridBar bar, double tol, int maxit) {
   __shared__ double sh[16];
+  __shared__ double shg[48];
   double* x = ws;
   double* r = ws + n;
   double* pb[2] = {ws + 2 * n, ws + 3 * n};
@@ -547,6 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_seq_coop(
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const double tol2 = tol * tol;
   int iters = 0;
+  unsigned epoch = 0;
   for (int s = s_begin; s < s_end; ++s) {
     const double t = static_cast<double>(t0 + s) * dt;
     const double s0 = src.scale * pwm(t, src, 0), s1 = src.scale * pwm(t, src, 1),
@@ -573,8 +618,10 @@ __global__ __launch_bounds__(kBlock) void k_seq_coop(
     block_store(lrz, sh, part, 3);
     block_store(lrr, sh, part, 4);
     block_store(lbb, sh, part, 5);
-    if (!grid_sync(bar)) return;
-    double rz = grid_total(part, 3), rr = grid_total(part, 4), bb = grid_total(part, 5);
+    if (!grid_sync(bar, epoch)) return;
+    double tot3[3];
+    grid_totals<3>(part, 3, tot3, shg);
+    double rz = tot3[0], rr = tot3[1], bb = tot3[2];
     if (bb == 0.0) bb = rr;
     double beta = 0.0;
     int par = 0, it = 0;
@@ -600,8 +647,10 @@ __global__ __launch_bounds__(kBlock) void k_seq_coop(
         lpq += pi * qs;
       }
       block_store(lpq, sh, part, 0);
-      if (!grid_sync(bar)) return;
-      const double alpha = rz / grid_total(part, 0);
+      if (!grid_sync(bar, epoch)) return;
+      double tot1[1];
+      grid_totals<1>(part, 0, tot1, shg);
+      const double alpha = rz / tot1[0];
       double lz = 0.0;
       lrr = 0.0;
       for (int i = tid; i < n; i += T) {
@@ -613,9 +662,11 @@ __global__ __launch_bounds__(kBlock) void k_seq_coop(
       }
       block_store(lz, sh, part, 1);
       block_store(lrr, sh, part, 2);
-      if (!grid_sync(bar)) return;
-      const double rzn = grid_total(part, 1);
-      rr = grid_total(part, 2);
+      if (!grid_sync(bar, epoch)) return;
+      double tot2[2];
+      grid_totals<2>(part, 1, tot2, shg);
+      const double rzn = tot2[0];
+      rr = tot2[1];
       if (!isfinite(rr)) {
         if (tid == 0) atomicOr(bar.flags + 1, 1);
         return;
@@ -627,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_seq_coop(
     }
     iters += it;
     for (int i = tid; i < n; i += T) U[i * ldu + s] = x[i];
-    if (!grid_sync(bar)) return;
+    if (!grid_sync(bar, epoch)) return;
   }
   if (tid == 0) atomicAdd(bar.flags + 2, iters);
 }
@@ -772,7 +823,11 @@ int seq_coop_blocks() {
   MG_HIP(hipGetDeviceProperties(&prop, dev));
   MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_seq_coop<8>, kBlock, 0));
   const int fit = per_cu * prop.multiProcessorCount;
-  return fit < 128 ? fit : 128;
+  int want = 128;
+  if (const char* e = std::getenv("MGRIT_COOP_BLOCKS")) want = std::atoi(e);
+  if (want < 1) want = 1;
+  want = fit < want ? fit : want;
+  return want < kMaxCoopBlocks ? want : kMaxCoopBlocks;
 }
 
 void launch_seq_coop(hipStream_t s, const DevLevel& L, const SourceDev& src, int s_begin,
@@ -780,7 +835,7 @@ void launch_seq_coop(hipStream_t s, const DevLevel& L, const SourceDev& src, int
                      unsigned* bar_state, int* flags, double tol, int maxit, int blocks) {
   if (s_end <= s_begin) return;
   if (L.W != 8) fail(MGRIT_UNSUPPORTED, "cooperative stepper needs rows of width 8");
-  GridBar bar{bar_state, bar_state + 1, flags};
+  GridBar bar{bar_state + kFlagStride, bar_state, flags};
   int64_t t0 = 0;
   int n = L.n;
   const int* col = L.col;
