@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libmgrit.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "pcg.hip", "setup.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "pcg.hip", "newton.hip", "setup.hip", "engine.hip"]
 HEADERS = ["internal.h", "setup.h"]
 
 CFLAGS = [

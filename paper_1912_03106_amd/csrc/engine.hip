@@ -45,6 +45,7 @@ struct LevelState {
   PcgWork pcg;       // batched Phi on this level (capacity N + 1 columns)
   PcgWork user;      // phi_step workspace (grown on demand)
   double* seq_ws = nullptr;
+  NlLevel nl;             // element data for the nonlinear model (n_tri = 0 if linear)
   int* nat = nullptr;     // internal unknown -> user-facing index
   double* Ainv = nullptr; // coarsest level, linear model: A^{-1} [n][ld_inv]
   int64_t ld_inv = 0;
@@ -74,6 +75,7 @@ struct Handle {
   mgrit_stats* st = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> ev;     // 4 per PCG iteration of a chunk (profiling)
+  std::vector<std::unique_ptr<NlWork>> nl_keep;
 };
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -235,8 +237,10 @@ static void autotune(Handle& h, LevelState& S) {
 // convergence); converged columns drop out of every kernel.  The host reads
 // the active-column count every pcg_check_every iterations.  Returns the
 // number of iterations in which some column was active.
+enum IterKind { IT_LIN64 = 0, IT_LIN32 = 1, IT_JAC = 2 };
+
 static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, double tol2,
-                       bool fp32, int active, bool fail_at_cap, int max_iter = -1) {
+                       int kind, int active, bool fail_at_cap, int max_iter = -1) {
   hipStream_t s = h.stream;
   const bool prof = h.par.profile_kernels && h.st && level < MGRIT_MAX_LEVELS;
   int it = 0, used = 0;
@@ -255,12 +259,14 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     const int k = std::min(chunk, cap - it);
     for (int t = 0; t < k; ++t) {
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t], s));
-      if (fp32) launch_pcg_pass_a32(s, L, w, ncols, it + t == 0);
+      if (kind == IT_JAC) launch_nl_pass_a(s, L, w, *w.nl, ncols, it + t == 0);
+      else if (kind == IT_LIN32) launch_pcg_pass_a32(s, L, w, ncols, it + t == 0);
       else launch_pcg_pass_a(s, L, w, ncols, it + t == 0);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 1], s));
       launch_reduce(s, w, ncols, RED_ALPHA, tol2, 1, nullptr);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 2], s));
-      if (fp32) launch_pcg_pass_b32(s, L, w, ncols);
+      if (kind == IT_JAC) launch_nl_pass_b(s, L, w, *w.nl, ncols);
+      else if (kind == IT_LIN32) launch_pcg_pass_b32(s, L, w, ncols);
       else launch_pcg_pass_b(s, L, w, ncols);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 3], s));
       launch_reduce(s, w, ncols, RED_BETA, tol2, 2, nullptr);
@@ -309,7 +315,7 @@ static int pcg_solve(Handle& h, int level, const DevLevel& L, PcgWork& w, int nc
     MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     MG_HIP(hipStreamSynchronize(s));
     if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
-    return pcg_iterate(h, level, L, w, ncols, tol2, false, w.host_flags[0], true);
+    return pcg_iterate(h, level, L, w, ncols, tol2, IT_LIN64, w.host_flags[0], true);
   }
   const double tin2 = h.par.ir_inner_tol * h.par.ir_inner_tol;
   launch_fill_u8(s, w.outer, ncols, 1);
@@ -325,10 +331,88 @@ static int pcg_solve(Handle& h, int level, const DevLevel& L, PcgWork& w, int nc
     if (sweep >= h.par.ir_max_iter)
       fail(MGRIT_PCG_NOT_CONVERGED, "iterative refinement did not converge in ir_max_iter sweeps (" +
                                         std::to_string(active) + " columns left)");
-    total += pcg_iterate(h, level, L, w, ncols, tin2, true, active, false);
+    total += pcg_iterate(h, level, L, w, ncols, tin2, IT_LIN32, active, false);
     launch_ir_update(s, L, w, ncols);
   }
   return total;
+}
+
+// Newton buffers of a workspace (allocated on first use).
+static NlWork& nl_work(Handle& h, LevelState& S, PcgWork& w) {
+  if (w.nl) return *w.nl;
+  auto* nw = new NlWork();
+  h.nl_keep.emplace_back(nw);
+  nw->fp32 = (h.par.precision == MGRIT_FP32_IR);
+  const size_t ev = static_cast<size_t>(S.nl.n_tri) * w.ld;
+  const size_t vec = static_cast<size_t>(w.n) * w.ld;
+  const size_t mat = vec * S.op.W;
+  nw->nu = h.arena.alloc<double>(ev);
+  nw->dnu = h.arena.alloc<double>(ev);
+  nw->gx = h.arena.alloc<double>(ev);
+  nw->gy = h.arena.alloc<double>(ev);
+  nw->R = h.arena.alloc<double>(vec);
+  nw->dg = h.arena.alloc<double>(vec);
+  nw->ref = h.arena.alloc<double>(w.ld);
+  if (nw->fp32) {
+    nw->J32 = h.arena.alloc<float>(mat);
+    nw->s32 = h.arena.alloc<float>(vec);
+  } else {
+    nw->J64 = h.arena.alloc<double>(mat);
+    nw->s64 = h.arena.alloc<double>(vec);
+    nw->r64 = h.arena.alloc<double>(vec);
+    nw->p64[0] = h.arena.alloc<double>(vec);
+    nw->p64[1] = h.arena.alloc<double>(vec);
+    nw->d64 = h.arena.alloc<double>(vec);
+  }
+  w.nl = nw;
+  return *nw;
+}
+
+// Batched Newton (saturating iron): x (= w.x, initialised with the guess)
+// is driven to ||R(x)|| <= newton_tol ||R(u_prev)|| per column.  Each step
+// assembles the per-column Jacobian, solves J d = -R by CG on the Jacobi-
+// scaled Jacobian to ir_inner_tol (FP32 for MGRIT_FP32_IR, else FP64) and
+// updates x in FP64.  Returns the number of inner CG iterations.
+static int newton_solve(Handle& h, int level, LevelState& S, PcgWork& w, int ncols, CView in,
+                        bool guess_is_input) {
+  hipStream_t s = h.stream;
+  NlWork& nw = nl_work(h, S, w);
+  const double tol2 = h.par.newton_tol * h.par.newton_tol;
+  const double tin2 = h.par.ir_inner_tol * h.par.ir_inner_tol;
+  // reference ||R(u_prev)||
+  launch_nl_elem(s, S.nl, ncols, w.ld, nullptr, in, nw);
+  launch_nl_residual(s, S.op, S.nl, w, nw, ncols, nullptr, in, in);
+  launch_nl_test(s, w, nw, ncols, 1, tol2);
+  if (!guess_is_input) {
+    launch_nl_elem(s, S.nl, ncols, w.ld, w.outer, CView{w.x, w.ld}, nw);
+    launch_nl_residual(s, S.op, S.nl, w, nw, ncols, w.outer, CView{w.x, w.ld}, in);
+    launch_nl_test(s, w, nw, ncols, 0, tol2);
+  }
+  auto read_count = [&]() {
+    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a Newton step");
+    return w.host_flags[0];
+  };
+  int refining = read_count();
+  int inner = 0;
+  for (int k = 0; refining > 0; ++k) {
+    if (k >= h.par.newton_max_iter)
+      fail(MGRIT_NEWTON_NOT_CONVERGED, "Newton did not converge in newton_max_iter iterations (" +
+                                           std::to_string(refining) + " columns left)");
+    launch_nl_jacobian(s, S.op, S.nl, w, nw, ncols);
+    launch_nl_cg_init(s, w, nw, ncols);
+    launch_reduce(s, w, ncols, RED_INIT, tin2, 3, nullptr);
+    const int act = read_count();
+    inner += pcg_iterate(h, level, S.op, w, ncols, tin2, IT_JAC, act, false);
+    launch_nl_update(s, w, nw, ncols);
+    launch_nl_elem(s, S.nl, ncols, w.ld, w.outer, CView{w.x, w.ld}, nw);
+    launch_nl_residual(s, S.op, S.nl, w, nw, ncols, w.outer, CView{w.x, w.ld}, in);
+    launch_nl_test(s, w, nw, ncols, 0, tol2);
+    refining = read_count();
+    if (h.st && level < MGRIT_MAX_LEVELS) h.st->newton_sweeps[level] += 1;
+  }
+  return inner;
 }
 
 // One batched application of Phi on level l:
@@ -356,7 +440,9 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
   hipStream_t s = h.stream;
   launch_source_table(s, h.src, S.op.dt, c.ncols, c.t_list, c.t_base, c.t_stride, w.src, w.ld);
   launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
-  const int it = pcg_solve(h, l, S.op, w, c.ncols, c.in);
+  const int it = S.nl.n_tri > 0
+                     ? newton_solve(h, l, S, w, c.ncols, c.in, c.ga.p == c.in.p && c.gb.p == nullptr)
+                     : pcg_solve(h, l, S.op, w, c.ncols, c.in);
   launch_axpby3(s, S.n, c.ncols, c.out, c.ldo, c.osx, CView{w.x, w.ld}, 1.0, c.oa, c.osb, c.ob);
   if (h.st && l < MGRIT_MAX_LEVELS) {
     h.st->phi_columns[l] += c.ncols;
@@ -465,6 +551,23 @@ static void coarsest_solve(Handle& h, int l) {
   hipStream_t s = h.stream;
   // u_0 = g_0
   launch_axpby3(s, S.n, 1, S.U, S.ld, 0.0, CView{}, 1.0, CView{S.G, S.ld}, 0.0, CView{});
+  if (S.nl.n_tri > 0) {
+    // nonlinear: one Newton-solved step at a time, u_s = Phi(u_{s-1}) + g_s
+    for (int64_t st = 1; st <= S.N; ++st) {
+      PhiCall c;
+      c.ncols = 1;
+      c.in = CView{S.U + st - 1, S.ld};
+      c.t_base = st - 1;
+      c.ga = CView{S.U + st, S.ld};
+      c.gb = CView{S.G + st, S.ld};
+      c.sgb = -1.0;
+      c.out = S.U + st;
+      c.ldo = S.ld;
+      c.oa = CView{S.G + st, S.ld};
+      phi_batch(h, l, S.pcg, c);
+    }
+    return;
+  }
   if (S.Ainv) {
     // implicit Euler with the stored inverse: u_s = A^{-1} ((M/dt) u_{s-1} + f(t_s)) + g_s
     for (int64_t st = 1; st <= S.N; ++st)
@@ -575,7 +678,7 @@ static void build_coarse_inverse(Handle& h, LevelState& S) {
     MG_HIP(hipStreamSynchronize(s));
     mgrit_stats* keep = h.st;
     h.st = nullptr;
-    pcg_iterate(h, 0, S.op, w, nc, tol2, false, w.host_flags[0], true, w.hist_cap);
+    pcg_iterate(h, 0, S.op, w, nc, tol2, IT_LIN64, w.host_flags[0], true, w.hist_cap);
     h.st = keep;
     // columns j0.. of the inverse (symmetric: rows j0.. as well)
     launch_axpby3(s, S.n, nc, S.Ainv + j0, S.ld_inv, 1.0, CView{w.x, w.ld}, 0.0, CView{}, 0.0,
@@ -602,7 +705,9 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (par->pcg_kernel < 0 || par->pcg_kernel > 2) fail(MGRIT_INVALID_ARGUMENT, "pcg_kernel");
   if (par->precision == MGRIT_FP32_IR && (!(par->ir_inner_tol > 0.0) || par->ir_max_iter < 1))
     fail(MGRIT_INVALID_ARGUMENT, "bad refinement settings");
-  if (ph.nonlinear) fail(MGRIT_UNSUPPORTED, "the nonlinear model is not available in this build");
+  if (ph.nonlinear && !ph.iron) fail(MGRIT_INVALID_ARGUMENT, "the nonlinear model needs the iron flags");
+  if (ph.nonlinear && (par->newton_max_iter < 1 || !(par->newton_tol > 0.0) || !(par->ir_inner_tol > 0.0)))
+    fail(MGRIT_INVALID_ARGUMENT, "bad Newton settings");
   if (ph.n_materials <= 0 || !ph.nu || !ph.sigma) fail(MGRIT_INVALID_ARGUMENT, "material table");
   if (!(ph.dt > 0.0) || ph.n_steps < 1) fail(MGRIT_INVALID_ARGUMENT, "time grid");
   if (ph.carrier != 0 && ph.carrier != 1) fail(MGRIT_INVALID_ARGUMENT, "carrier");
@@ -645,6 +750,20 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     S.coarsest = (l == L - 1);
     S.op = assemble_level(h.arena, s, prob->meshes[l], pats[l], ph, dt, &S.elem);
     S.nat = upload_vec(h.arena, s, pats[l].nat);
+    if (ph.nonlinear) {
+      S.nl.n_tri = S.elem.n_tri;
+      S.nl.tri_u = S.elem.tri_u;
+      S.nl.grad = S.elem.grad;
+      S.nl.area = S.elem.area;
+      S.nl.nu_lin = S.elem.nu;
+      S.nl.iron = S.elem.iron;
+      S.nl.cptr = S.elem.cptr;
+      S.nl.contrib = S.elem.contrib;
+      S.nl.diag = S.elem.diag;
+      S.nl.k1 = ph.bh_k1;
+      S.nl.k2 = ph.bh_k2;
+      S.nl.k3 = ph.bh_k3;
+    }
     dt *= par->m;
     N /= par->m;
   }
@@ -796,7 +915,21 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   MG_HIP(hipMemsetAsync(flags, 0, 8 * sizeof(int), s));
   const bool coop = h.par.seq_kernel == 2 || (h.par.seq_kernel == 0 && S0.n >= 4096 && S0.op.W == 8);
   auto t0 = std::chrono::steady_clock::now();
-  if (coop) {
+  if (S0.nl.n_tri > 0) {
+    // nonlinear: batched Newton on one column, step after step
+    for (int64_t st = 1; st <= S0.N; ++st) {
+      PhiCall c;
+      c.ncols = 1;
+      c.in = CView{U + st - 1, ld};
+      c.t_base = st - 1;
+      c.ga = c.in;
+      c.out = U + st;
+      c.ldo = ld;
+      phi_batch(h, 0, S0.pcg, c);
+    }
+    MG_HIP(hipStreamSynchronize(s));
+    std::memset(S0.pcg.host_flags, 0, 4 * sizeof(int));
+  } else if (coop) {
     if (!h.coop_ws) {
       h.coop_blocks = seq_coop_blocks();
       h.coop_ws = h.arena.alloc<double>(5 * static_cast<size_t>(S0.n));
@@ -821,8 +954,10 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
     MG_HIP(hipStreamSynchronize(s));
   }
   st->time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  st->phi_columns[0] += S0.N;
-  st->pcg_sweeps[0] += S0.pcg.host_flags[2];
+  if (S0.nl.n_tri == 0) {
+    st->phi_columns[0] += S0.N;
+    st->pcg_sweeps[0] += S0.pcg.host_flags[2];
+  }
   if (S0.pcg.host_flags[1] & 4) fail(MGRIT_HIP_ERROR, "a grid barrier of the sequential stepper timed out");
   if (S0.pcg.host_flags[1] & 1) fail(MGRIT_NONFINITE, "non-finite value in sequential stepping");
   if (S0.pcg.host_flags[1] & 2) fail(MGRIT_PCG_NOT_CONVERGED, "PCG did not converge in sequential stepping");

@@ -74,6 +74,22 @@ struct DevTransfer {
   double* val = nullptr;
 };
 
+// Element data of a level for the nonlinear model (device).
+struct NlLevel {
+  int n_tri = 0;
+  const int* tri_u = nullptr;     // [T][3] unknown index of each vertex, -1 = Dirichlet
+  const double* grad = nullptr;   // [T][3][2]
+  const double* area = nullptr;   // [T]
+  const double* nu_lin = nullptr; // [T] linear reluctivity
+  const uint8_t* iron = nullptr;  // [T] saturating law applies
+  const int* cptr = nullptr;      // contribution lists of the stored entries
+  const int* contrib = nullptr;
+  const int* diag = nullptr;      // [n] slot of the diagonal entry
+  double k1 = 0, k2 = 0, k3 = 0;
+};
+
+struct NlWork;
+
 // Batched-PCG workspace for up to `cap` columns of an n-row level.
 struct PcgWork {
   int n = 0, cap = 0, nrb = 0, rows_per_block = 0;
@@ -96,7 +112,37 @@ struct PcgWork {
   int* hist = nullptr;          // [max_iter] active columns of every PCG iteration
   int* host_hist = nullptr;     // pinned copy
   int hist_cap = 0;
+  NlWork* nl = nullptr;         // Newton buffers (nonlinear model, allocated on first use)
 };
+
+// Newton workspace of a PcgWork (same n, ld).
+struct NlWork {
+  bool fp32 = false;                   // inner solve in FP32
+  double *nu = nullptr, *dnu = nullptr, *gx = nullptr, *gy = nullptr;  // [T][ld]
+  double* R = nullptr;                 // [n][ld] Newton residual
+  double* dg = nullptr;                // [n][ld] diag(J)
+  double* ref = nullptr;               // [ld] ||R(u_prev)||^2
+  float* J32 = nullptr;                // [n][W][ld] scaled Jacobian (FP32 inner)
+  float* s32 = nullptr;                // [n][ld] scaling
+  double* J64 = nullptr;               // FP64 inner
+  double* s64 = nullptr;
+  double* r64 = nullptr;
+  double* p64[2] = {nullptr, nullptr};
+  double* d64 = nullptr;               // FP64 inner correction
+};
+
+void launch_nl_elem(hipStream_t s, const NlLevel& N, int ncols, int64_t ld, const uint8_t* outer,
+                    CView u, NlWork& nw);
+void launch_nl_residual(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
+                        int ncols, const uint8_t* outer, CView u, CView uprev);
+// ref_mode 1: ref = ||R||^2, every column with R != 0 refines; 0: refine while ||R||^2 > tol2 ref
+void launch_nl_test(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, int ref_mode, double tol2);
+void launch_nl_jacobian(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
+                        int ncols);
+void launch_nl_cg_init(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);
+void launch_nl_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols, int first);
+void launch_nl_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols);
+void launch_nl_update(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);
 
 enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3, RED_IR_INIT = 4 };
 

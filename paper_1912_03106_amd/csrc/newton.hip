@@ -1,0 +1,532 @@
+// Batched Newton for the saturating-iron model (Sec. 3.1, eq. 7-8 with
+// nu = nu(|grad A|^2); damped Newton of the time stepper, Sec. 5).
+//
+// Every column is an independent nonlinear system
+//     R(u) = (M/dt)(u - u_prev) + K(u) u - f(t) = 0,
+// K(u) assembled with nu_e = k1 exp(k2 B_e^2) + k3 in iron elements
+// (B_e^2 = |grad u_e|^2), the linear nu elsewhere.  Newton step:
+//     J(u) d = -R(u),  J = M/dt + sum_e [nu_e G_e + (2 nu'_e / area_e)(G_e u_e)(G_e u_e)^T],
+// G_e = area_e grad(phi) grad(phi)^T, nu' = d nu / d(B^2).
+// The Jacobian values are per column on the level's shared pattern
+// ([n][W][ld], column contiguous), Jacobi-scaled per column, and solved by
+// the same two-pass CG as the linear propagator with per-lane matrix values.
+//
+// Data per column: element fields (nu, nu', grad u) [T][ld]; residual R and
+// diag(J) [n][ld] in FP64; scaled Jacobian, scaling and CG vectors in the
+// inner precision.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace mg {
+namespace {
+
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+}
+
+__device__ __forceinline__ void tile_decode(int w, int ncc, int& rb, int& cc) {
+  if ((ncc & 7) == 0) {
+    const int xcd = w & 7, local = w >> 3, per = ncc >> 3;
+    cc = xcd + 8 * (local % per);
+    rb = local / per;
+  } else {
+    cc = w % ncc;
+    rb = w / ncc;
+  }
+}
+
+template <int NQ>
+__device__ __forceinline__ void block_partials(const double (&v)[NQ], double* out, int64_t qstride,
+                                               int c, bool on) {
+  __shared__ double red[NQ][4][kWave];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) red[q][wv][lane] = v[q];
+  __syncthreads();
+  if (wv == 0 && on) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      out[q * qstride + c] = ((red[q][0][lane] + red[q][1][lane]) + red[q][2][lane]) + red[q][3][lane];
+  }
+}
+
+// Element fields of every column: g = grad u_e, nu_e, nu'_e.
+// One wave per element (4 per work-group), lanes over columns.
+__global__ __launch_bounds__(kBlock) void k_nl_elem(
+    int n_tri, const int* __restrict__ tri_u, const double* __restrict__ grad,
+    const double* __restrict__ nu_lin, const uint8_t* __restrict__ iron, double k1, double k2,
+    double k3, int ncols, int64_t ld, const uint8_t* __restrict__ outer,
+    const double* __restrict__ u, int64_t ldu, double* __restrict__ nu_e,
+    double* __restrict__ dnu_e, double* __restrict__ gx, double* __restrict__ gy) {
+  const int c = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int e = blockIdx.y * 4 + wave_index();
+  if (e >= n_tri || c >= ncols) return;
+  if (outer && !outer[c]) return;
+  const int* v = tri_u + 3 * e;
+  const double* gr = grad + 6 * e;
+  double ux = 0.0, uy = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int vk = v[k];
+    const double uk = vk >= 0 ? u[vk * ldu + c] : 0.0;
+    ux += uk * gr[2 * k];
+    uy += uk * gr[2 * k + 1];
+  }
+  double nu = nu_lin[e], dnu = 0.0;
+  if (iron[e]) {
+    const double ex = exp(k2 * (ux * ux + uy * uy));
+    nu = k1 * ex + k3;
+    dnu = k1 * k2 * ex;
+  }
+  const int64_t o = static_cast<int64_t>(e) * ld + c;
+  nu_e[o] = nu;
+  dnu_e[o] = dnu;
+  gx[o] = ux;
+  gy[o] = uy;
+}
+
+// R_i = sum_t (M/dt)_it (u - u_prev)_col(t) + sum_{e at i} nu_e area_e grad(phi_a).g_e - f_i
+// (the diagonal entry's contribution list enumerates the elements at node i
+// with the node's local index a); partials of R.R.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_nl_residual(
+    int n, const int* __restrict__ col, const double* __restrict__ mm,
+    const uint8_t* __restrict__ has_mass, const double* __restrict__ F,
+    const int* __restrict__ cptr, const int* __restrict__ contrib,
+    const int* __restrict__ diag_slot, const double* __restrict__ area,
+    const double* __restrict__ grad, int ncols, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ outer, const double* __restrict__ src,
+    const double* __restrict__ u, int64_t ldu, const double* __restrict__ uprev, int64_t ldp,
+    const double* __restrict__ nu_e, const double* __restrict__ gx,
+    const double* __restrict__ gy, double* __restrict__ R, double* __restrict__ part, int nrb) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && (!outer || outer[c]);
+  double acc[1] = {0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    const double s0 = src[c], s1 = src[ld + c], s2 = src[2 * ld + c];
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      double rv = 0.0;
+      if (has_mass[i]) {
+        const int* ci = col + static_cast<int64_t>(i) * W;
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          const int j = ci[t];
+          rv += mi[t] * (u[j * ldu + c] - uprev[j * ldp + c]);
+        }
+      }
+      const int64_t slot = static_cast<int64_t>(i) * W + diag_slot[i];
+      for (int q = cptr[slot]; q < cptr[slot + 1]; ++q) {
+        const int code = contrib[q];
+        const int e = code / 9, a = (code % 9) / 3;
+        const int64_t o = static_cast<int64_t>(e) * ld + c;
+        rv += nu_e[o] * area[e] * (grad[6 * e + 2 * a] * gx[o] + grad[6 * e + 2 * a + 1] * gy[o]);
+      }
+      rv -= (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      R[i * ld + c] = rv;
+      acc[0] += rv * rv;
+    }
+  }
+  block_partials<1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// Jacobian values per column on the shared pattern, and its diagonal.
+template <int W, typename T>
+__global__ __launch_bounds__(kBlock) void k_nl_jacobian(
+    int n, const double* __restrict__ mm, const int* __restrict__ cptr,
+    const int* __restrict__ contrib, const int* __restrict__ diag_slot,
+    const double* __restrict__ area, const double* __restrict__ grad, int ncols, int ncc, int rpb,
+    int64_t ld, const uint8_t* __restrict__ outer, const double* __restrict__ nu_e,
+    const double* __restrict__ dnu_e, const double* __restrict__ gx,
+    const double* __restrict__ gy, T* __restrict__ J, double* __restrict__ dg) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && outer[c])) return;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+    const int ds = diag_slot[i];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int64_t slot = static_cast<int64_t>(i) * W + t;
+      double v = mm[slot];
+      for (int q = cptr[slot]; q < cptr[slot + 1]; ++q) {
+        const int code = contrib[q];
+        const int e = code / 9, a = (code % 9) / 3, b = code % 3;
+        const int64_t o = static_cast<int64_t>(e) * ld + c;
+        const double* g = grad + 6 * e;
+        const double gag = g[2 * a] * gx[o] + g[2 * a + 1] * gy[o];
+        const double gbg = g[2 * b] * gx[o] + g[2 * b + 1] * gy[o];
+        v += area[e] * (nu_e[o] * (g[2 * a] * g[2 * b] + g[2 * a + 1] * g[2 * b + 1]) +
+                        2.0 * dnu_e[o] * gag * gbg);
+      }
+      J[slot * ld + c] = static_cast<T>(v);
+      if (t == ds) dg[i * ld + c] = v;
+    }
+  }
+}
+
+// J^ = S J S with S = diag(J)^{-1/2} per column; stores S.
+template <int W, typename T>
+__global__ __launch_bounds__(kBlock) void k_nl_scale(int n, const int* __restrict__ col, int ncols,
+                                                     int ncc, int rpb, int64_t ld,
+                                                     const uint8_t* __restrict__ outer,
+                                                     const double* __restrict__ dg,
+                                                     T* __restrict__ J, T* __restrict__ sc) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && outer[c])) return;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+    const double si = 1.0 / sqrt(dg[i * ld + c]);
+    sc[i * ld + c] = static_cast<T>(si);
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int64_t slot = static_cast<int64_t>(i) * W + t;
+      const int j = col[slot];
+      const double sj = 1.0 / sqrt(dg[j * ld + c]);
+      J[slot * ld + c] = static_cast<T>(si * static_cast<double>(J[slot * ld + c]) * sj);
+    }
+  }
+}
+
+// Inner CG start for J d = -R: r^ = S(-R), d = 0; partials r^.r^, ||R||^2,
+// ||R||^2 (the inner tolerance is relative to the Newton residual).
+// Columns that are not refining contribute zeros (they stay inactive).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nl_cg_init(int n, int ncols, int ncc, int rpb,
+                                                       int64_t ld, const uint8_t* __restrict__ outer,
+                                                       const double* __restrict__ R,
+                                                       const T* __restrict__ sc, T* __restrict__ r,
+                                                       T* __restrict__ x, double* __restrict__ part,
+                                                       int nrb, int* __restrict__ flags) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[4] = 0;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols;
+  const bool live = on && outer[c];
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (live) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int64_t o = i * ld + c;
+      const double rv = -R[o];
+      const T rh = static_cast<T>(static_cast<double>(sc[o]) * rv);
+      r[o] = rh;
+      x[o] = T(0);
+      const double rd = static_cast<double>(rh);
+      acc[0] += rd * rd;
+      acc[1] += rv * rv;
+      acc[2] += rv * rv;
+    }
+  }
+  block_partials<3>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// Pass A with per-column matrix values J^[i][t][c].
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_cgj_pass_a(
+    int n, const int* __restrict__ col, const T* __restrict__ J, int ncols, int ncc, int rpb,
+    int64_t ld, const uint8_t* __restrict__ active, const double* __restrict__ beta, int first,
+    const T* __restrict__ r, const T* __restrict__ pold, T* __restrict__ pnew,
+    double* __restrict__ part, int nrb, int* __restrict__ flags, int* __restrict__ hist) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int it = flags[4];
+    hist[it] = flags[0];
+    flags[4] = it + 1;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && active[c];
+  double acc[1] = {0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    const T be = first ? T(0) : static_cast<T>(beta[c]);
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      T s = T(0);
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const int j = ci[t];
+        const T a = J[(static_cast<int64_t>(i) * W + t) * ld + c];
+        const T pj = first ? r[j * ld + c] : fma(be, pold[j * ld + c], r[j * ld + c]);
+        s += a * pj;
+      }
+      const int64_t o = i * ld + c;
+      const T pi = first ? r[o] : fma(be, pold[o], r[o]);
+      pnew[o] = pi;
+      acc[0] += static_cast<double>(pi) * static_cast<double>(s);
+    }
+  }
+  block_partials<1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// Pass B with per-column matrix values; x += alpha S p^, r^ -= alpha J^ p^.
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_cgj_pass_b(
+    int n, const int* __restrict__ col, const T* __restrict__ J, const T* __restrict__ sc,
+    const double* __restrict__ dg, int ncols, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ active, const double* __restrict__ alpha,
+    const T* __restrict__ p, T* __restrict__ x, T* __restrict__ r, double* __restrict__ part,
+    int nrb) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && active[c];
+  double acc[2] = {0.0, 0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    const T al = static_cast<T>(alpha[c]);
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const int* ci = col + static_cast<int64_t>(i) * W;
+      T q = T(0);
+#pragma unroll
+      for (int t = 0; t < W; ++t)
+        q += J[(static_cast<int64_t>(i) * W + t) * ld + c] * p[ci[t] * ld + c];
+      const int64_t o = i * ld + c;
+      x[o] = fma(al * sc[o], p[o], x[o]);
+      const T rv = r[o] - al * q;
+      r[o] = rv;
+      const double rd = static_cast<double>(rv);
+      acc[0] += rd * rd;
+      acc[1] += dg[o] * (rd * rd);
+    }
+  }
+  block_partials<2>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// u += d for the columns still refining.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nl_update(int n, int ncols, int ncc, int rpb, int64_t ld,
+                                                      const uint8_t* __restrict__ outer,
+                                                      const T* __restrict__ d,
+                                                      double* __restrict__ u) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && outer[c])) return;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+    u[i * ld + c] += static_cast<double>(d[i * ld + c]);
+  }
+}
+
+// Newton bookkeeping per column (one wave per column): sums the R.R partials
+// and, in REF mode, stores the reference ||R(u_prev)||^2 and marks every
+// column as refining; in TEST mode, keeps refining the columns with
+// ||R||^2 > tol2 ref.  Counts refining columns into flags[0].
+__global__ __launch_bounds__(kBlock) void k_nl_test(int ncols, int nrb, int64_t ld, int ref_mode,
+                                                    double tol2, const double* __restrict__ part,
+                                                    double* __restrict__ ref,
+                                                    uint8_t* __restrict__ outer,
+                                                    int* __restrict__ flags) {
+  __shared__ int cnt;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + wv;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const bool on = c < ncols && (ref_mode || outer[c]);
+  double t = 0.0;
+  if (on) {
+    for (int rb = lane; rb < nrb; rb += kWave) t += part[rb * ld + c];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  }
+  if (lane == 0 && c < ncols) {
+    int act = 0;
+    if (ref_mode) {
+      ref[c] = t;
+      act = t > 0.0;
+    } else if (on) {
+      act = t > tol2 * ref[c];
+    }
+    outer[c] = static_cast<uint8_t>(act);
+    if (!isfinite(t)) atomicOr(flags + 1, 1);
+    if (act) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt > 0) atomicAdd(flags, cnt);
+}
+
+__global__ void k_zero_flag0(int* flags) { flags[0] = 0; }
+
+inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+
+static int tiles(const PcgWork& w, int ncols, int& ncc) {
+  ncc = ceil_div(ncols, kWave);
+  return w.nrb * ncc;
+}
+
+void launch_nl_elem(hipStream_t s, const NlLevel& N, int ncols, int64_t ld, const uint8_t* outer,
+                    CView u, NlWork& nw) {
+  dim3 grid(ceil_div(ncols, kWave), ceil_div(N.n_tri, 4));
+  hipLaunchKernelGGL(k_nl_elem, grid, dim3(kBlock), 0, s, N.n_tri, N.tri_u, N.grad, N.nu_lin, N.iron,
+                     N.k1, N.k2, N.k3, ncols, ld, outer, u.p, u.ld, nw.nu, nw.dnu, nw.gx, nw.gy);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_nl_residual(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
+                        int ncols, const uint8_t* outer, CView u, CView uprev) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  auto k = (L.W == 8) ? k_nl_residual<8> : k_nl_residual<16>;
+  hipLaunchKernelGGL(k, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.m64, L.has_mass, L.F, N.cptr,
+                     N.contrib, N.diag, N.area, N.grad, ncols, ncc, w.rows_per_block, w.ld, outer,
+                     w.src, u.p, u.ld, uprev.p, uprev.ld, nw.nu, nw.gx, nw.gy, nw.R, w.part, w.nrb);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_nl_test(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, int ref_mode, double tol2) {
+  hipLaunchKernelGGL(k_zero_flag0, dim3(1), dim3(1), 0, s, w.flags);
+  hipLaunchKernelGGL(k_nl_test, dim3(ceil_div(ncols, 4)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
+                     ref_mode, tol2, w.part, nw.ref, w.outer, w.flags);
+  MG_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void jac_impl(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
+                     int ncols, T* J, T* sc) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  if (L.W == 8) {
+    hipLaunchKernelGGL((k_nl_jacobian<8, T>), dim3(nb), dim3(kBlock), 0, s, L.n, L.m64, N.cptr,
+                       N.contrib, N.diag, N.area, N.grad, ncols, ncc, w.rows_per_block, w.ld,
+                       w.outer, nw.nu, nw.dnu, nw.gx, nw.gy, J, nw.dg);
+    hipLaunchKernelGGL((k_nl_scale<8, T>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, ncols, ncc,
+                       w.rows_per_block, w.ld, w.outer, nw.dg, J, sc);
+  } else {
+    hipLaunchKernelGGL((k_nl_jacobian<16, T>), dim3(nb), dim3(kBlock), 0, s, L.n, L.m64, N.cptr,
+                       N.contrib, N.diag, N.area, N.grad, ncols, ncc, w.rows_per_block, w.ld,
+                       w.outer, nw.nu, nw.dnu, nw.gx, nw.gy, J, nw.dg);
+    hipLaunchKernelGGL((k_nl_scale<16, T>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, ncols, ncc,
+                       w.rows_per_block, w.ld, w.outer, nw.dg, J, sc);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_nl_jacobian(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
+                        int ncols) {
+  if (nw.fp32) jac_impl<float>(s, L, N, w, nw, ncols, nw.J32, nw.s32);
+  else jac_impl<double>(s, L, N, w, nw, ncols, nw.J64, nw.s64);
+}
+
+void launch_nl_cg_init(hipStream_t s, PcgWork& w, NlWork& nw, int ncols) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  if (nw.fp32)
+    hipLaunchKernelGGL(k_nl_cg_init<float>, dim3(nb), dim3(kBlock), 0, s, w.n, ncols, ncc,
+                       w.rows_per_block, w.ld, w.outer, nw.R, nw.s32, w.r32, w.x32, w.part, w.nrb,
+                       w.flags);
+  else
+    hipLaunchKernelGGL(k_nl_cg_init<double>, dim3(nb), dim3(kBlock), 0, s, w.n, ncols, ncc,
+                       w.rows_per_block, w.ld, w.outer, nw.R, nw.s64, nw.r64, nw.d64, w.part,
+                       w.nrb, w.flags);
+  MG_HIP(hipGetLastError());
+}
+
+template <typename T, int W>
+static void cgj_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first, const T* J,
+                  const T* r, T* pold, T* pnew) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  hipLaunchKernelGGL((k_cgj_pass_a<T, W>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, J, ncols, ncc,
+                     w.rows_per_block, w.ld, w.active, w.scal + 4 * w.ld, first, r, pold, pnew,
+                     w.part, w.nrb, w.flags, w.hist);
+}
+
+template <typename T, int W>
+static void cgj_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols, const T* J,
+                  const T* sc, const T* p, T* x, T* r) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  hipLaunchKernelGGL((k_cgj_pass_b<T, W>), dim3(nb), dim3(kBlock), 0, s, L.n, L.col, J, sc, nw.dg,
+                     ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, p, x, r,
+                     w.part, w.nrb);
+}
+
+void launch_nl_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols,
+                      int first) {
+  if (nw.fp32) {
+    float* po = w.p32[w.parity];
+    float* pn = w.p32[w.parity ^ 1];
+    if (L.W == 8) cgj_a<float, 8>(s, L, w, ncols, first, nw.J32, w.r32, po, pn);
+    else cgj_a<float, 16>(s, L, w, ncols, first, nw.J32, w.r32, po, pn);
+  } else {
+    double* po = nw.p64[w.parity];
+    double* pn = nw.p64[w.parity ^ 1];
+    if (L.W == 8) cgj_a<double, 8>(s, L, w, ncols, first, nw.J64, nw.r64, po, pn);
+    else cgj_a<double, 16>(s, L, w, ncols, first, nw.J64, nw.r64, po, pn);
+  }
+  w.parity ^= 1;
+  MG_HIP(hipGetLastError());
+}
+
+void launch_nl_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols) {
+  if (nw.fp32) {
+    const float* p = w.p32[w.parity];
+    if (L.W == 8) cgj_b<float, 8>(s, L, w, nw, ncols, nw.J32, nw.s32, p, w.x32, w.r32);
+    else cgj_b<float, 16>(s, L, w, nw, ncols, nw.J32, nw.s32, p, w.x32, w.r32);
+  } else {
+    const double* p = nw.p64[w.parity];
+    if (L.W == 8) cgj_b<double, 8>(s, L, w, nw, ncols, nw.J64, nw.s64, p, nw.d64, nw.r64);
+    else cgj_b<double, 16>(s, L, w, nw, ncols, nw.J64, nw.s64, p, nw.d64, nw.r64);
+  }
+  MG_HIP(hipGetLastError());
+}
+
+void launch_nl_update(hipStream_t s, PcgWork& w, NlWork& nw, int ncols) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  if (nw.fp32)
+    hipLaunchKernelGGL(k_nl_update<float>, dim3(nb), dim3(kBlock), 0, s, w.n, ncols, ncc,
+                       w.rows_per_block, w.ld, w.outer, w.x32, w.x);
+  else
+    hipLaunchKernelGGL(k_nl_update<double>, dim3(nb), dim3(kBlock), 0, s, w.n, ncols, ncc,
+                       w.rows_per_block, w.ld, w.outer, nw.d64, w.x);
+  MG_HIP(hipGetLastError());
+}
+
+}  // namespace mg

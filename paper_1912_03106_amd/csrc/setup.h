@@ -52,6 +52,7 @@ struct ElementData {
   int* cptr = nullptr;
   int* contrib = nullptr;
   int* diag = nullptr;
+  int* tri_u = nullptr;     // [n_tri][3] unknown index per vertex (-1 = Dirichlet)
 };
 
 void validate_mesh(const mgrit_mesh& m, int n_materials);

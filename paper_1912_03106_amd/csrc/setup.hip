@@ -365,6 +365,9 @@ DevLevel assemble_level(DeviceArena& A, hipStream_t s, const mgrit_mesh& m, cons
     keep->cptr = cptr;
     keep->contrib = contrib;
     keep->diag = diag;
+    std::vector<int> tu(3 * static_cast<size_t>(m.n_tri));
+    for (int64_t k = 0; k < 3LL * m.n_tri; ++k) tu[k] = P.index[m.tri[k]];
+    keep->tri_u = upload(A, s, tu);
   }
   return L;
 }

@@ -1,0 +1,126 @@
+"""GPU batched Newton (saturating iron, Sec. 3.1 / Sec. 5) against the oracle's
+Newton with direct solves, through the C ABI."""
+
+import numpy as np
+import pytest
+
+from workload import config, polar_mesh, Source, BHLaw
+from workload.configs import LevelSpec
+from oracle.stepping import Level, sequential
+from oracle.problem import build
+from oracle import mgrit
+
+pytestmark = pytest.mark.gpu
+
+PHI_TOL = 1e-10
+STRONG = Source(J0=4e7)     # |B| up to ~2 T: nu varies by orders of magnitude in the iron
+
+
+def _solver(cfg, **kw):
+    from paper_1912_03106_amd.solver import Solver
+    return Solver(cfg, **kw)
+
+
+def _col_err(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _small_cfg(**kw):
+    base = dict(meshes=[LevelSpec(16, 128), LevelSpec(16, 128)], n_steps=256, m=16,
+                t_final=0.005, source=STRONG)
+    base.update(kw)
+    return config("cfg4", **base)
+
+
+@pytest.fixture(scope="module")
+def nl_pair():
+    cfg = _small_cfg()
+    lev = Level(polar_mesh(16, 128), cfg.dt, cfg.source, bh=cfg.bh)
+    U = sequential(lev, np.zeros(lev.n), 40)
+    return cfg, lev, U
+
+
+@pytest.mark.parametrize("B", [1, 64, 97])
+def test_newton_phi_fp64_matches_oracle(nl_pair, B):
+    print(f"newton phi fp64 B={B}", flush=True)
+    cfg, lev, U = nl_pair
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, precision=_abi.FP64, ir_inner_tol=1e-6, newton_tol=1e-12)
+    rng = np.random.default_rng(B)
+    i_from = rng.integers(0, cfg.n_steps - 1, size=B)
+    u_prev = U[rng.integers(5, U.shape[0], size=B)]
+    got = s.phi(0, u_prev, i_from)
+    ref = lev.phi(u_prev, i_from)
+    assert max(lev.newton_iters[-B:]) >= 2          # genuinely nonlinear steps
+    err = _col_err(got, ref)
+    assert err.max() <= PHI_TOL, err.max()
+
+
+def test_newton_phi_fp32_inner_matches_oracle(nl_pair):
+    print("newton phi fp32 inner", flush=True)
+    cfg, lev, U = nl_pair
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, precision=_abi.FP32_IR, ir_inner_tol=1e-5, newton_tol=1e-12, newton_max_iter=12)
+    rng = np.random.default_rng(5)
+    i_from = rng.integers(0, cfg.n_steps - 1, size=65)
+    u_prev = U[rng.integers(5, U.shape[0], size=65)]
+    err = _col_err(s.phi(0, u_prev, i_from), lev.phi(u_prev, i_from))
+    assert err.max() <= PHI_TOL, err.max()
+
+
+def test_newton_phi_full_size_sampled_columns():
+    """The 64 x 512 level of the nonlinear workload (dt = 0.02/32768)."""
+    print("newton phi 64x512 sampled", flush=True)
+    cfg = config("cfg4", source=STRONG)
+    cfg.meshes = [LevelSpec(64, 512), LevelSpec(32, 256)]
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, precision=_abi.FP64, ir_inner_tol=1e-6, newton_tol=1e-12)
+    lev = Level(polar_mesh(64, 512), cfg.dt, cfg.source, bh=cfg.bh)
+    U = sequential(lev, np.zeros(lev.n), 6)
+    i_from = np.array([5, 8191, 20000, 32760])
+    u_prev = U[[3, 4, 5, 6]] * 40.0         # a saturated state
+    err = _col_err(s.phi(0, u_prev, i_from), lev.phi(u_prev, i_from))
+    assert err.max() <= PHI_TOL, err
+
+
+def test_newton_seq_solve_matches_oracle(nl_pair):
+    print("newton seq", flush=True)
+    cfg, lev, _ = nl_pair
+    cfg = _small_cfg(n_steps=64, t_final=64 * cfg.dt)
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, precision=_abi.FP64, ir_inner_tol=1e-6, newton_tol=1e-12)
+    U, _ = s.seq_solve()
+    U_ref = sequential(lev, np.zeros(lev.n), 64)
+    err = np.linalg.norm(U - U_ref, axis=1)[1:] / np.linalg.norm(U_ref, axis=1)[1:]
+    assert err.max() <= PHI_TOL * 10, err.max()
+
+
+def test_newton_mgrit_two_level_matches_oracle():
+    print("newton mgrit two-level", flush=True)
+    cfg = _small_cfg()
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=2)
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, precision=_abi.FP32_IR, ir_inner_tol=1e-5, newton_tol=1e-11,
+                newton_max_iter=12, pcg_tol=1e-12)
+    U, st = s.solve()
+    assert st["converged"]
+    for a, b in zip(st["rho"][:3], hist[:3]):
+        assert abs(a - b) <= 1e-8 * hist[0], (a, b)
+    assert _rel(U, U_seq) <= 1e-7
+    assert sum(st["newton_sweeps"]) > 0
+
+
+def test_newton_cap_is_reported(nl_pair):
+    cfg, lev, U = nl_pair
+    from paper_1912_03106_amd import MgritError, _abi
+    s = _solver(cfg, precision=_abi.FP64, newton_max_iter=1, newton_tol=1e-14)
+    with pytest.raises(MgritError) as e:
+        s.phi(0, U[[20, 30]] * 20.0, [10, 20])
+    assert e.value.name == "NEWTON_NOT_CONVERGED"
