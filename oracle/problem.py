@@ -23,7 +23,8 @@ def build(cfg, restriction="normalized"):
         if key not in fes:
             fes[key] = MachineFE(mesh)
         levels.append(Level(mesh, cfg.level_dt(l), cfg.source, cfg.bh, fe=fes[key],
-                            newton_tol=cfg.newton_tol, newton_maxit=cfg.newton_maxit))
+                            newton_tol=cfg.newton_tol, newton_maxit=cfg.newton_maxit,
+                            newton_halvings=cfg.newton_halvings))
     R, P = [], []
     for fine, coarse in zip(meshes, meshes[1:]):
         if (fine.n_r, fine.n_theta) == (coarse.n_r, coarse.n_theta):

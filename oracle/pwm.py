@@ -11,6 +11,12 @@ Two carriers:
       c(t) = 1 - 4 |f_c t - floor(f_c t + 1/2)|,   c(0) = 1.
 sgn(0) = 0.  One carrier is shared by the three phases.
 
+Start-up ramp (Sec. 3.3, nonlinear model): the source is multiplied by
+alpha(t) = (1 - cos(pi t / (R T))) / 2 for t < R T and by 1 afterwards, with
+T = 1/f and R = 2 periods.  The printed argument lacks the period; read
+literally (t in seconds) the factor would stay below 0.002 for the whole
+simulated time, so it is read as rising from 0 to 1 over the first R periods.
+
 Ties.  With the reference amplitude equal to the carrier peak, the time
 grids of the workloads hit r(t) = c(t) exactly (t = T/4: r_A = 1 = c), where
 the sign of a difference of two rounded values is decided by the last ulp of
@@ -45,6 +51,15 @@ def pwm(t, src, phase_index):
     """b_p(t) in {-1, 0, +1}."""
     d = reference(t, src, phase_index) - carrier(t, src.f_carrier, src.carrier)
     return np.where(np.abs(d) <= TIE_BAND, 0.0, np.sign(d))
+
+
+def ramp(t, src):
+    """Start-up factor alpha(t) of the nonlinear model (1 when src.ramp_periods = 0)."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    if src.ramp_periods <= 0:
+        return np.ones_like(t)
+    span = src.ramp_periods / src.freq
+    return np.where(t < span, 0.5 * (1.0 - np.cos(math.pi * t / span)), 1.0)
 
 
 def phase_signals(t, src):

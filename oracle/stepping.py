@@ -10,9 +10,15 @@ not backward Euler).  The source is sampled at the new time t_i = i*dt,
 computed as a product, never by accumulation.
 
 Linear model: one sparse LU factorisation per level, reused by every step.
-Nonlinear model: Newton with the exact Jacobian, initial guess u_{i-1},
-stop when ||R(u^k)||_2 <= tol * ||R(u^0)||_2 (at most `maxit` iterations),
-one direct solve per Newton step.
+Nonlinear model: damped Newton (Sec. 5.1: the nonlinear solves use Newton's
+method with damping) with the exact Jacobian, initial guess u_{i-1}, one
+direct solve per Newton step.  The paper does not say how it damps; the step
+length is chosen by the Armijo rule on the residual norm (Kelley, Iterative
+Methods for Linear and Nonlinear Equations, SIAM 1995, Sec. 8.1): the first
+lambda in 1, 1/2, ..., 2**-halvings with
+||R(u - lambda d)|| < (1 - 1e-4 lambda) ||R(u)||, else the last one tried
+(a trial whose residual is not finite is rejected).  Stop when
+||R(u^k)||_2 <= tol * ||R(u^0)||_2, at most `maxit` Newton steps.
 """
 
 import numpy as np
@@ -30,7 +36,7 @@ class Level:
     """The propagator of one MGRIT level: a mesh, a step size and the source."""
 
     def __init__(self, mesh, dt, source, bh=None, fe=None, newton_tol=1e-10,
-                 newton_maxit=8):
+                 newton_maxit=8, newton_halvings=6):
         self.fe = fe if fe is not None else MachineFE(mesh)
         self.n = self.fe.n
         self.dt = dt
@@ -39,8 +45,10 @@ class Level:
         self.nonlinear = bool(bh is not None and bh.nonlinear)
         self.newton_tol = newton_tol
         self.newton_maxit = newton_maxit
+        self.newton_halvings = newton_halvings
         self.Mdt = (self.fe.M / dt).tocsr()
         self.newton_iters = []
+        self.newton_lambdas = []
         if not self.nonlinear:
             self.A = (self.Mdt + self.fe.K).tocsc()
             self.lu = spla.splu(self.A)
@@ -48,8 +56,8 @@ class Level:
     def forcing(self, t):
         """f(t) for a vector of times t [B]: [B, n]."""
         b = pwm.phase_signals(t, self.source)            # [3, B]
-        s = self.source.J0 * self.source.amplitude
-        return s * (b.T @ self.fe.F)
+        s = self.source.J0 * self.source.amplitude * pwm.ramp(t, self.source)
+        return s[:, None] * (b.T @ self.fe.F)
 
     def rhs(self, u_prev, i_from):
         """(M/dt) u_prev + f(t_{i_from+1}) for each column of the batch."""
@@ -67,11 +75,24 @@ class Level:
         if r0 == 0.0:
             self.newton_iters.append(0)
             return u
+        rn = r0
         for k in range(1, self.newton_maxit + 1):
             J = (self.Mdt + self.fe.jacobian_nonlinear(u, self.bh)).tocsc()
-            u = u - spla.spsolve(J, r)
-            r = self.residual(u, u_prev, f)
-            if np.linalg.norm(r) <= self.newton_tol * r0:
+            d = spla.spsolve(J, r)
+            lam = 1.0
+            for h in range(self.newton_halvings + 1):
+                lam = 0.5 ** h
+                with np.errstate(over="ignore", invalid="ignore"):
+                    u_try = u - lam * d
+                    r_try = self.residual(u_try, u_prev, f)
+                    rn_try = np.linalg.norm(r_try)
+                if np.isfinite(rn_try) and rn_try < (1.0 - 1e-4 * lam) * rn:
+                    break
+            if not np.isfinite(rn_try):
+                raise NewtonFailure("non-finite residual at the shortest damped step")
+            u, r, rn = u_try, r_try, rn_try
+            self.newton_lambdas.append(lam)
+            if rn <= self.newton_tol * r0:
                 self.newton_iters.append(k)
                 return u
         raise NewtonFailure(f"Newton did not reach {self.newton_tol} in {self.newton_maxit} iterations")

@@ -78,3 +78,25 @@ def test_tie_band_changes_no_other_decision(name):
         for p in range(3):
             d = np.abs(pwm.reference(t, cfg.source, p) - pwm.carrier(t, cfg.source.f_carrier, cfg.source.carrier))
             assert np.all((d <= 1e-14) | (d > 1e-6))
+
+
+def test_startup_ramp_closed_form():
+    """alpha(t) = (1 - cos(pi t / (2T))) / 2 over the first two periods, then 1."""
+    src = Source(ramp_periods=2.0)
+    T = 1.0 / src.freq
+    t = np.array([0.0, T / 2, T, 1.5 * T, 2 * T, 3 * T])
+    want = [0.0, (1 - math.cos(math.pi / 4)) / 2, 0.5, (1 - math.cos(3 * math.pi / 4)) / 2, 1.0, 1.0]
+    assert np.allclose(pwm.ramp(t, src), want, rtol=0, atol=1e-15)
+    assert np.all(pwm.ramp(t, Source()) == 1.0)
+
+
+def test_ramp_scales_each_column_of_the_forcing():
+    from workload import polar_mesh
+    from oracle.stepping import Level
+    mesh = polar_mesh(4, 16)
+    t = np.array([1e-3, 7e-3, 0.019, 0.031, 0.05])
+    f_ramp = Level(mesh, 1e-4, Source(ramp_periods=2.0)).forcing(t)
+    f_flat = Level(mesh, 1e-4, Source()).forcing(t)
+    want = pwm.ramp(t, Source(ramp_periods=2.0))[:, None] * f_flat
+    assert np.allclose(f_ramp, want, rtol=1e-14, atol=0)
+    assert np.all(f_ramp[-1] == f_flat[-1])

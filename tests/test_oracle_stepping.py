@@ -119,3 +119,34 @@ def test_newton_solution_satisfies_residual():
     assert L.newton_iters[-1] >= 3
     nu, _ = L.fe.nu_nonlinear(L.fe.b_squared(u), bh)
     assert np.ptp(nu[L.fe.iron_cell]) > 100.0
+
+
+def test_damped_newton_reaches_the_root_plain_newton_misses():
+    """Damped Newton (Sec. 5.1; Armijo step lengths): at a source so strong
+    that a full Newton step from u = 0 overflows the reluctivity, plain Newton
+    fails while the damped iteration takes shortened steps and ends at a zero
+    of the residual."""
+    mesh = polar_mesh(8, 64)
+    bh = BHLaw(nonlinear=True)
+    plain = Level(mesh, 1e-4, Source(J0=3e8), bh=bh, newton_maxit=30, newton_halvings=0)
+    with pytest.raises(Exception):
+        plain.phi(np.zeros((1, plain.n)), [3])
+    L = Level(mesh, 1e-4, Source(J0=3e8), bh=bh, newton_maxit=30, newton_halvings=6)
+    u = L.phi(np.zeros((1, L.n)), [3])[0]
+    assert min(L.newton_lambdas) < 1.0
+    f = L.forcing(np.array([4e-4]))[0]
+    r0 = np.linalg.norm(L.residual(np.zeros(L.n), np.zeros(L.n), f))
+    assert np.linalg.norm(L.residual(u, np.zeros(L.n), f)) <= 1e-10 * r0
+
+
+def test_damping_does_not_move_the_root():
+    """Where plain Newton converges, damped Newton lands on the same solution."""
+    mesh = polar_mesh(8, 64)
+    bh = BHLaw(nonlinear=True)
+    out = []
+    for hv in (0, 6):
+        L = Level(mesh, 1e-4, Source(J0=1e8), bh=bh, newton_maxit=30, newton_halvings=hv)
+        out.append(L.phi(np.zeros((1, L.n)), [3])[0])
+        if hv:
+            assert min(L.newton_lambdas) < 1.0
+    assert np.linalg.norm(out[0] - out[1]) <= 1e-9 * np.linalg.norm(out[0])

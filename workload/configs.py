@@ -39,6 +39,7 @@ class Config:
     pcg_tol: float = 1e-12      # relative residual of every linear solve (FP64)
     newton_tol: float = 1e-10
     newton_maxit: int = 8
+    newton_halvings: int = 6    # damping: step lengths 1, 1/2, ..., 2**-newton_halvings
     coarse: str = "implicit_euler"  # or "learned"
 
     @property
@@ -87,13 +88,15 @@ _BASE = {
     # cfg2 with FP32 inner PCG + FP64 refinement and a seeded random guess
     "cfg3": Config("cfg3", [_L64, _L32, _L16], 16384, 16,
                    precision="fp32_ir", guess="uniform", guess_seed=3),
-    # nonlinear iron, 32768 steps over one period, three-level V m=16
+    # nonlinear iron, 32768 steps over one period, three-level V m=16; the
+    # source ramps in over two periods as in the nonlinear model
     "cfg4": Config("cfg4", [_L64, _L32, _L16], 32768, 16,
-                   precision="fp32_ir", bh=BHLaw(nonlinear=True)),
+                   precision="fp32_ir", bh=BHLaw(nonlinear=True),
+                   source=Source(ramp_periods=2.0)),
     # cfg4 with the learned coarsest-level propagator
     "cfg5": Config("cfg5", [_L64, _L32, _L16], 32768, 16,
                    precision="fp32_ir", bh=BHLaw(nonlinear=True),
-                   coarse="learned"),
+                   source=Source(ramp_periods=2.0), coarse="learned"),
 }
 
 CONFIG_NAMES = tuple(_BASE)

@@ -160,7 +160,9 @@ class Source:
     PWM signal of phase p obtained from a sine reference of frequency `freq`
     (phase angles `phases` plus a common `phase_offset`) and a carrier of
     frequency `f_carrier`.  `carrier` is "triangle" (c(0) = 1) or "sawtooth"
-    (the paper's trailing-edge carrier).
+    (the paper's trailing-edge carrier).  `ramp_periods` > 0 multiplies the
+    source by the smooth start-up factor of the nonlinear model over its first
+    `ramp_periods` electric periods (0: no ramp).
     """
     J0: float = 1.0e7
     freq: float = 50.0
@@ -169,6 +171,7 @@ class Source:
     carrier: str = "triangle"
     phase_offset: float = 0.0
     amplitude: float = 1.0
+    ramp_periods: float = 0.0
 
     @property
     def carrier_code(self) -> int:
