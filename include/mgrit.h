@@ -70,7 +70,9 @@ typedef struct {
  * nonlinear != 0; otherwise nu = nu[k].  The coil current density of a cell
  * is sign * J0 * amplitude * b_phase(t), b_p(t) = sgn(sin(2 pi freq t +
  * phases[p] + phase_offset) - c(t)), carrier c = triangle (0) or sawtooth (1)
- * of frequency f_carrier; sgn(0) = 0. */
+ * of frequency f_carrier; sgn(0) = 0.  ramp_periods = R > 0 multiplies the
+ * source by the start-up factor (1 - cos(pi t f / R)) / 2 for t < R / f and
+ * by 1 afterwards (nonlinear model, Sec. 3.3); 0 = no ramp. */
 typedef struct {
   int32_t n_materials;
   const double*  nu;          /* [n_materials] reluctivity, A m / Wb */
@@ -83,6 +85,7 @@ typedef struct {
   int32_t carrier;            /* 0 triangle (c(0) = 1), 1 sawtooth */
   double dt;                  /* finest step; t_i = i * dt */
   int64_t n_steps;            /* N_t on the finest level */
+  double ramp_periods;        /* start-up ramp length in electric periods (0 = none) */
 } mgrit_physics;
 
 typedef struct {
@@ -106,7 +109,7 @@ typedef struct {
   int32_t pcg_check_every;    /* PCG iterations between host convergence reads */
   double  ir_inner_tol;       /* FP32 inner PCG tolerance (MGRIT_FP32_IR)       */
   int32_t ir_max_iter;        /* refinement sweeps                              */
-  double  newton_tol;         /* ||R(u^k)|| <= newton_tol ||R(u^0)||           */
+  double  newton_tol;         /* ||R(u^k)|| <= newton_tol ||R(u_prev)||        */
   int32_t newton_max_iter;
   int32_t warm_start;         /* 1: linear solves start from the previous iterate */
   int32_t device_pointers;    /* 1: u_init / u_out of mgrit_solve are device pointers */
@@ -117,6 +120,12 @@ typedef struct {
   int32_t coarse_inverse;     /* 1: linear model, coarsest level <= 8192 unknowns: step with a
                                * stored A^{-1} (exact implicit Euler) instead of PCG */
   int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one work-group, 2 cooperative grid */
+  int32_t use_graphs;         /* 1: replay each check interval of CG iterations from a captured
+                               * hipGraph (not while profile_kernels = 1) */
+  int32_t newton_halvings;    /* damped Newton (Sec. 5.1): per column, the first step length
+                               * lambda in 1, 1/2, ..., 2^-newton_halvings with
+                               * ||R(u + lambda d)|| < (1 - 1e-4 lambda) ||R(u)||, else the
+                               * last one; 0 = plain Newton */
 } mgrit_params;
 
 typedef struct {

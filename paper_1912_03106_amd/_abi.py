@@ -43,6 +43,7 @@ class Physics(C.Structure):
         ("J0", C.c_double), ("amplitude", C.c_double), ("freq", C.c_double),
         ("f_carrier", C.c_double), ("phase_offset", C.c_double), ("phases", C.c_double * 3),
         ("carrier", C.c_int32), ("dt", C.c_double), ("n_steps", C.c_int64),
+        ("ramp_periods", C.c_double),
     ]
 
 
@@ -58,7 +59,7 @@ class Params(C.Structure):
         ("ir_max_iter", C.c_int32), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32),
         ("warm_start", C.c_int32), ("device_pointers", C.c_int32), ("profile_kernels", C.c_int32),
         ("autotune", C.c_int32), ("pcg_kernel", C.c_int32), ("coarse_inverse", C.c_int32),
-        ("seq_kernel", C.c_int32),
+        ("seq_kernel", C.c_int32), ("use_graphs", C.c_int32), ("newton_halvings", C.c_int32),
     ]
 
 

@@ -76,6 +76,21 @@ struct Handle {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> ev;     // 4 per PCG iteration of a chunk (profiling)
   std::vector<std::unique_ptr<NlWork>> nl_keep;
+  // hipGraphs of one check interval of CG iterations, keyed by what the
+  // captured launches depend on
+  // (workspace buffers are arena allocations, never reused while the handle
+  // lives, so a buffer address names one workspace)
+  struct GraphKey {
+    const void* x;
+    const void* L;
+    const void* nl;
+    int rpb, cpl, dia, parity, ncols, kind, chunk;
+    double tol2;
+    auto tie() const { return std::tie(x, L, nl, rpb, cpl, dia, parity, ncols, kind, chunk, tol2); }
+    bool operator<(const GraphKey& o) const { return tie() < o.tie(); }
+  };
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t capture_stream = nullptr;
 };
 
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -257,7 +272,38 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
       break;
     }
     const int k = std::min(chunk, cap - it);
-    for (int t = 0; t < k; ++t) {
+    // Later check intervals replay a captured graph of the same k launches
+    // (the first carries the `first` iteration and runs eagerly).
+    const bool graph = h.par.use_graphs && !prof && it > 0 && k == chunk && (chunk % 2) == 0;
+    if (graph) {
+      const Handle::GraphKey key{w.x, &L, w.nl, w.rows_per_block, w.cpl, w.dia ? 1 : 0, w.parity,
+                                      ncols, kind, chunk, tol2};
+      auto found = h.graphs.find(key);
+      if (found == h.graphs.end()) {
+        hipStream_t cs = h.capture_stream;
+        MG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const int keep_parity = w.parity;
+        for (int t = 0; t < k; ++t) {
+          if (kind == IT_JAC) launch_nl_pass_a(cs, L, w, *w.nl, ncols, 0);
+          else if (kind == IT_LIN32) launch_pcg_pass_a32(cs, L, w, ncols, 0);
+          else launch_pcg_pass_a(cs, L, w, ncols, 0);
+          launch_reduce(cs, w, ncols, RED_ALPHA, tol2, 1, nullptr);
+          if (kind == IT_JAC) launch_nl_pass_b(cs, L, w, *w.nl, ncols);
+          else if (kind == IT_LIN32) launch_pcg_pass_b32(cs, L, w, ncols);
+          else launch_pcg_pass_b(cs, L, w, ncols);
+          launch_reduce(cs, w, ncols, RED_BETA, tol2, 2, nullptr);
+        }
+        w.parity = keep_parity;
+        hipGraph_t g = nullptr;
+        MG_HIP(hipStreamEndCapture(cs, &g));
+        hipGraphExec_t ex = nullptr;
+        MG_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        MG_HIP(hipGraphDestroy(g));
+        found = h.graphs.emplace(key, ex).first;
+      }
+      MG_HIP(hipGraphLaunch(found->second, s));
+    }
+    for (int t = 0; t < k && !graph; ++t) {
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t], s));
       if (kind == IT_JAC) launch_nl_pass_a(s, L, w, *w.nl, ncols, it + t == 0);
       else if (kind == IT_LIN32) launch_pcg_pass_a32(s, L, w, ncols, it + t == 0);
@@ -353,6 +399,10 @@ static NlWork& nl_work(Handle& h, LevelState& S, PcgWork& w) {
   nw->R = h.arena.alloc<double>(vec);
   nw->dg = h.arena.alloc<double>(vec);
   nw->ref = h.arena.alloc<double>(w.ld);
+  nw->rcur = h.arena.alloc<double>(w.ld);
+  nw->lam = h.arena.alloc<double>(w.ld);
+  nw->fac = h.arena.alloc<double>(w.ld);
+  nw->ls = h.arena.alloc<uint8_t>(w.ld);
   if (nw->fp32) {
     nw->J32 = h.arena.alloc<float>(mat);
     nw->s32 = h.arena.alloc<float>(vec);
@@ -379,6 +429,7 @@ static int newton_solve(Handle& h, int level, LevelState& S, PcgWork& w, int nco
   NlWork& nw = nl_work(h, S, w);
   const double tol2 = h.par.newton_tol * h.par.newton_tol;
   const double tin2 = h.par.ir_inner_tol * h.par.ir_inner_tol;
+  const double lam_min = std::ldexp(1.0, -h.par.newton_halvings);
   // reference ||R(u_prev)||
   launch_nl_elem(s, S.nl, ncols, w.ld, nullptr, in, nw);
   launch_nl_residual(s, S.op, S.nl, w, nw, ncols, nullptr, in, in);
@@ -405,11 +456,17 @@ static int newton_solve(Handle& h, int level, LevelState& S, PcgWork& w, int nco
     launch_reduce(s, w, ncols, RED_INIT, tin2, 3, nullptr);
     const int act = read_count();
     inner += pcg_iterate(h, level, S.op, w, ncols, tin2, IT_JAC, act, false);
-    launch_nl_update(s, w, nw, ncols);
-    launch_nl_elem(s, S.nl, ncols, w.ld, w.outer, CView{w.x, w.ld}, nw);
-    launch_nl_residual(s, S.op, S.nl, w, nw, ncols, w.outer, CView{w.x, w.ld}, in);
-    launch_nl_test(s, w, nw, ncols, 0, tol2);
-    refining = read_count();
+    // damped update: per column, halve the step until the residual norm
+    // decreases enough (at most newton_halvings times)
+    launch_nl_ls_start(s, w, nw, ncols);
+    while (true) {
+      launch_nl_update(s, w, nw, ncols);
+      launch_nl_elem(s, S.nl, ncols, w.ld, nw.ls, CView{w.x, w.ld}, nw);
+      launch_nl_residual(s, S.op, S.nl, w, nw, ncols, nw.ls, CView{w.x, w.ld}, in);
+      launch_nl_ls(s, w, nw, ncols, tol2, lam_min);
+      if (read_count() == 0) break;
+    }
+    refining = w.host_flags[3];
     if (h.st && level < MGRIT_MAX_LEVELS) h.st->newton_sweeps[level] += 1;
   }
   return inner;
@@ -706,7 +763,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (par->precision == MGRIT_FP32_IR && (!(par->ir_inner_tol > 0.0) || par->ir_max_iter < 1))
     fail(MGRIT_INVALID_ARGUMENT, "bad refinement settings");
   if (ph.nonlinear && !ph.iron) fail(MGRIT_INVALID_ARGUMENT, "the nonlinear model needs the iron flags");
-  if (ph.nonlinear && (par->newton_max_iter < 1 || !(par->newton_tol > 0.0) || !(par->ir_inner_tol > 0.0)))
+  if (ph.nonlinear && (par->newton_max_iter < 1 || !(par->newton_tol > 0.0) || !(par->ir_inner_tol > 0.0) ||
+                       par->newton_halvings < 0 || par->newton_halvings > 40))
     fail(MGRIT_INVALID_ARGUMENT, "bad Newton settings");
   if (ph.n_materials <= 0 || !ph.nu || !ph.sigma) fail(MGRIT_INVALID_ARGUMENT, "material table");
   if (!(ph.dt > 0.0) || ph.n_steps < 1) fail(MGRIT_INVALID_ARGUMENT, "time grid");
@@ -722,6 +780,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   h.src.f_carrier = ph.f_carrier;
   for (int p = 0; p < 3; ++p) h.src.phi[p] = ph.phases[p] + ph.phase_offset;
   h.src.carrier = ph.carrier;
+  if (!(ph.ramp_periods >= 0.0)) fail(MGRIT_INVALID_ARGUMENT, "ramp_periods must be >= 0");
+  h.src.ramp_span = ph.ramp_periods > 0.0 ? ph.ramp_periods / ph.freq : 0.0;
 
   // host phase: validate every mesh, build patterns and transfers (no HIP call)
   std::vector<HostPattern> pats(L);
@@ -810,6 +870,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   h.u0_dev = h.arena.alloc<double>(h.lv[0].n);
   MG_HIP(hipEventCreate(&h.ev0));
   MG_HIP(hipEventCreate(&h.ev1));
+  MG_HIP(hipStreamCreateWithFlags(&h.capture_stream, hipStreamNonBlocking));
   const int chunk = std::max(1, std::min(par->pcg_check_every > 0 ? par->pcg_check_every : 16, 64));
   h.ev.resize(4 * chunk);
   for (auto& e : h.ev) MG_HIP(hipEventCreate(&e));
@@ -1067,6 +1128,8 @@ void mgrit_default_params(mgrit_params* p) {
   p->pcg_kernel = 0;
   p->coarse_inverse = 1;
   p->seq_kernel = 0;
+  p->use_graphs = 1;
+  p->newton_halvings = 6;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -1134,6 +1197,8 @@ void mgrit_destroy(void* hp) {
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   for (auto e : h->ev) (void)hipEventDestroy(e);
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   delete h;
 }
 

@@ -33,6 +33,7 @@ struct SourceDev {
   double freq, f_carrier;
   double phi[3];       // phases[p] + phase_offset
   int carrier;         // 0 triangle, 1 sawtooth
+  double ramp_span;    // start-up ramp length in seconds (0 = none)
 };
 
 // Column-block view: entry (row i, column c) at p[i * ld + c].
@@ -122,6 +123,10 @@ struct NlWork {
   double* R = nullptr;                 // [n][ld] Newton residual
   double* dg = nullptr;                // [n][ld] diag(J)
   double* ref = nullptr;               // [ld] ||R(u_prev)||^2
+  double* rcur = nullptr;              // [ld] ||R(u)||^2 at the current iterate
+  double* lam = nullptr;               // [ld] trial step length (damping)
+  double* fac = nullptr;               // [ld] factor of d in the next update
+  uint8_t* ls = nullptr;               // [ld] column still choosing its step length
   float* J32 = nullptr;                // [n][W][ld] scaled Jacobian (FP32 inner)
   float* s32 = nullptr;                // [n][ld] scaling
   double* J64 = nullptr;               // FP64 inner
@@ -142,7 +147,13 @@ void launch_nl_jacobian(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgW
 void launch_nl_cg_init(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);
 void launch_nl_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols, int first);
 void launch_nl_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols);
+// u += fac[c] d on the columns with ls[c] set
 void launch_nl_update(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);
+// ls = outer, lam = fac = 1, flags[3] = 0
+void launch_nl_ls_start(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);
+// step-length test of the searching columns; flags[0] = still searching,
+// flags[3] += refining columns accepted
+void launch_nl_ls(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, double tol2, double lam_min);
 
 enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3, RED_IR_INIT = 4 };
 

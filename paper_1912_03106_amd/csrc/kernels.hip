@@ -59,6 +59,15 @@ __device__ __forceinline__ double pwm(double t, const SourceDev& s, int p) {
   return d > 1e-12 ? 1.0 : (d < -1e-12 ? -1.0 : 0.0);
 }
 
+// Amplitude of the coil current density at time t: J0 * amplitude, times the
+// start-up factor (1 - cos(pi t / span)) / 2 while t < span (nonlinear
+// model, Sec. 3.3).
+__device__ __forceinline__ double source_scale(double t, const SourceDev& s) {
+  if (s.ramp_span > 0.0 && t < s.ramp_span)
+    return s.scale * (0.5 * (1.0 - cos(3.141592653589793 * t / s.ramp_span)));
+  return s.scale;
+}
+
 // Sum the per-lane values v[0..NQ) of the 4 waves of a work-group in a fixed
 // order and store them, for every lane's column, at out[q * qstride + c].
 template <int NQ>
@@ -166,8 +175,9 @@ __global__ void k_source_table(SourceDev s, double dt, int ncols, const int64_t*
   if (c >= ncols) return;
   const int64_t i_from = t_list ? t_list[c] : t_base + static_cast<int64_t>(c) * t_stride;
   const double t = static_cast<double>(i_from + 1) * dt;
+  const double a = source_scale(t, s);
 #pragma unroll
-  for (int p = 0; p < 3; ++p) table[p * ld + c] = s.scale * pwm(t, s, p);
+  for (int p = 0; p < 3; ++p) table[p * ld + c] = a * pwm(t, s, p);
 }
 
 __global__ void k_axpby3(int n, int ncols, double* __restrict__ out, int64_t ldo, double sx,
@@ -330,7 +340,8 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_small(
   for (int s = 1; s <= nsteps; ++s) {
     if (threadIdx.x == 0) {
       const double t = static_cast<double>(t0 + s) * dt;
-      for (int k = 0; k < 3; ++k) sgn[k] = src.scale * pwm(t, src, k);
+      const double amp = source_scale(t, src);
+      for (int k = 0; k < 3; ++k) sgn[k] = amp * pwm(t, src, k);
     }
     __syncthreads();
     const double s0 = sgn[0], s1 = sgn[1], s2 = sgn[2];
@@ -430,8 +441,10 @@ __global__ void k_coarse_rhs(int n, int W, const int* __restrict__ col,
                              const double* __restrict__ U, int64_t ldu, int s,
                              double* __restrict__ b) {
   __shared__ double sg[3];
-  if (threadIdx.x == 0)
-    for (int p = 0; p < 3; ++p) sg[p] = src.scale * pwm(t, src, p);
+  if (threadIdx.x == 0) {
+    const double amp = source_scale(t, src);
+    for (int p = 0; p < 3; ++p) sg[p] = amp * pwm(t, src, p);
+  }
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -594,8 +607,8 @@ __global__ __launch_bounds__(kBlock) void k_seq_coop(
   unsigned epoch = 0;
   for (int s = s_begin; s < s_end; ++s) {
     const double t = static_cast<double>(t0 + s) * dt;
-    const double s0 = src.scale * pwm(t, src, 0), s1 = src.scale * pwm(t, src, 1),
-                 s2 = src.scale * pwm(t, src, 2);
+    const double amp = source_scale(t, src);
+    const double s0 = amp * pwm(t, src, 0), s1 = amp * pwm(t, src, 1), s2 = amp * pwm(t, src, 2);
     double lrz = 0.0, lrr = 0.0, lbb = 0.0;
     for (int i = tid; i < n; i += T) {
       const int* ci = col + static_cast<int64_t>(i) * W;

@@ -334,21 +334,81 @@ __global__ __launch_bounds__(kBlock) void k_cgj_pass_b(
 // u += d for the columns still refining.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nl_update(int n, int ncols, int ncc, int rpb, int64_t ld,
-                                                      const uint8_t* __restrict__ outer,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const double* __restrict__ fac,
                                                       const T* __restrict__ d,
                                                       double* __restrict__ u) {
   int rb, cc;
   tile_decode(blockIdx.x, ncc, rb, cc);
   const int lane = threadIdx.x & 63, wv = wave_index();
   const int c = cc * kWave + lane;
-  if (!(c < ncols && outer[c])) return;
+  if (!(c < ncols && mask[c])) return;
+  const double f = fac[c];
   const int rpw = rpb >> 2;
   const int i0 = rb * rpb + wv * rpw;
   for (int k = 0; k < rpw; ++k) {
     const int i = i0 + k;
     if (i >= n) break;
-    u[i * ld + c] += static_cast<double>(d[i * ld + c]);
+    u[i * ld + c] += f * static_cast<double>(d[i * ld + c]);
   }
+}
+
+// Start of the damped step of every refining column: trial length 1.
+__global__ void k_nl_ls_start(int ncols, const uint8_t* __restrict__ outer,
+                              uint8_t* __restrict__ ls, double* __restrict__ lam,
+                              double* __restrict__ fac, int* __restrict__ flags) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) flags[3] = 0;
+  if (c >= ncols) return;
+  ls[c] = outer[c];
+  lam[c] = 1.0;
+  fac[c] = 1.0;
+}
+
+// Step-length test of every searching column (one wave per column; Armijo
+// rule on the residual 2-norm, Sec. 5.1 damping): t = ||R(u + lam d)||^2.
+// Accept when t < (1 - 1e-4 lam)^2 ||R(u)||^2, or when lam has reached
+// lam_min; an accepted column keeps refining while t > tol2 ref.  A rejected
+// column moves back to u + (lam/2) d (fac = -lam/2 for the next update).
+// flags[0] counts searching columns, flags[3] the refining columns accepted.
+__global__ __launch_bounds__(kBlock) void k_nl_ls(int ncols, int nrb, int64_t ld, double tol2,
+                                                  double lam_min, const double* __restrict__ part,
+                                                  const double* __restrict__ ref,
+                                                  double* __restrict__ rcur, double* __restrict__ lam,
+                                                  double* __restrict__ fac, uint8_t* __restrict__ ls,
+                                                  uint8_t* __restrict__ outer,
+                                                  int* __restrict__ flags) {
+  __shared__ int cnt[2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + wv;
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const bool on = c < ncols && ls[c];
+  double t = 0.0;
+  if (on) {
+    for (int rb = lane; rb < nrb; rb += kWave) t += part[rb * ld + c];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  }
+  if (lane == 0 && on) {
+    const double l = lam[c];
+    const double shrink = 1.0 - 1e-4 * l;
+    const bool ok = isfinite(t) && t < shrink * shrink * rcur[c];
+    if (ok || l <= lam_min) {
+      rcur[c] = t;
+      ls[c] = 0;
+      const int act = t > tol2 * ref[c];
+      outer[c] = static_cast<uint8_t>(act);
+      if (!isfinite(t)) atomicOr(flags + 1, 1);
+      if (act) atomicAdd(&cnt[1], 1);
+    } else {
+      fac[c] = -0.5 * l;
+      lam[c] = 0.5 * l;
+      atomicAdd(&cnt[0], 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt[0] > 0) atomicAdd(flags, cnt[0]);
+  if (threadIdx.x == 1 && cnt[1] > 0) atomicAdd(flags + 3, cnt[1]);
 }
 
 // Newton bookkeeping per column (one wave per column): sums the R.R partials
@@ -358,6 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_nl_update(int n, int ncols, int ncc,
 __global__ __launch_bounds__(kBlock) void k_nl_test(int ncols, int nrb, int64_t ld, int ref_mode,
                                                     double tol2, const double* __restrict__ part,
                                                     double* __restrict__ ref,
+                                                    double* __restrict__ rcur,
                                                     uint8_t* __restrict__ outer,
                                                     int* __restrict__ flags) {
   __shared__ int cnt;
@@ -375,8 +436,10 @@ __global__ __launch_bounds__(kBlock) void k_nl_test(int ncols, int nrb, int64_t 
     int act = 0;
     if (ref_mode) {
       ref[c] = t;
+      rcur[c] = t;
       act = t > 0.0;
     } else if (on) {
+      rcur[c] = t;
       act = t > tol2 * ref[c];
     }
     outer[c] = static_cast<uint8_t>(act);
@@ -422,7 +485,7 @@ void launch_nl_residual(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgW
 void launch_nl_test(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, int ref_mode, double tol2) {
   hipLaunchKernelGGL(k_zero_flag0, dim3(1), dim3(1), 0, s, w.flags);
   hipLaunchKernelGGL(k_nl_test, dim3(ceil_div(ncols, 4)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
-                     ref_mode, tol2, w.part, nw.ref, w.outer, w.flags);
+                     ref_mode, tol2, w.part, nw.ref, nw.rcur, w.outer, w.flags);
   MG_HIP(hipGetLastError());
 }
 
@@ -522,10 +585,23 @@ void launch_nl_update(hipStream_t s, PcgWork& w, NlWork& nw, int ncols) {
   const int nb = tiles(w, ncols, ncc);
   if (nw.fp32)
     hipLaunchKernelGGL(k_nl_update<float>, dim3(nb), dim3(kBlock), 0, s, w.n, ncols, ncc,
-                       w.rows_per_block, w.ld, w.outer, w.x32, w.x);
+                       w.rows_per_block, w.ld, nw.ls, nw.fac, w.x32, w.x);
   else
     hipLaunchKernelGGL(k_nl_update<double>, dim3(nb), dim3(kBlock), 0, s, w.n, ncols, ncc,
-                       w.rows_per_block, w.ld, w.outer, nw.d64, w.x);
+                       w.rows_per_block, w.ld, nw.ls, nw.fac, nw.d64, w.x);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_nl_ls_start(hipStream_t s, PcgWork& w, NlWork& nw, int ncols) {
+  hipLaunchKernelGGL(k_nl_ls_start, dim3(ceil_div(ncols, kBlock)), dim3(kBlock), 0, s, ncols,
+                     w.outer, nw.ls, nw.lam, nw.fac, w.flags);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_nl_ls(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, double tol2, double lam_min) {
+  hipLaunchKernelGGL(k_zero_flag0, dim3(1), dim3(1), 0, s, w.flags);
+  hipLaunchKernelGGL(k_nl_ls, dim3(ceil_div(ncols, 4)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
+                     tol2, lam_min, w.part, nw.ref, nw.rcur, nw.lam, nw.fac, nw.ls, w.outer, w.flags);
   MG_HIP(hipGetLastError());
 }
 

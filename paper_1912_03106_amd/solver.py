@@ -65,7 +65,8 @@ class Solver:
             len(nu), _ptr(mats["nu"], C.c_double), _ptr(mats["sigma"], C.c_double),
             _ptr(mats["iron"], C.c_int32), int(bh.nonlinear), bh.k1, bh.k2, bh.k3,
             src.J0, src.amplitude, src.freq, src.f_carrier, src.phase_offset,
-            (C.c_double * 3)(*src.phases), src.carrier_code, cfg.dt, cfg.n_steps)
+            (C.c_double * 3)(*src.phases), src.carrier_code, cfg.dt, cfg.n_steps,
+            src.ramp_periods)
         self._mesh_arr = mesh_arr
         self._prob = _abi.Problem(len(self.meshes), mesh_arr, phys)
         par = _abi.Params()
@@ -77,6 +78,7 @@ class Solver:
         par.pcg_tol = cfg.pcg_tol
         par.newton_tol = cfg.newton_tol
         par.newton_max_iter = cfg.newton_maxit
+        par.newton_halvings = cfg.newton_halvings
         par.device_pointers = int(self.device_io)
         for k, v in overrides.items():
             if not hasattr(par, k):

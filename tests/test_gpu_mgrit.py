@@ -171,3 +171,35 @@ def test_mgrit_coarsest_solver_variants_agree(cfg1_oracle, coarse_inverse):
     for a, b in zip(st["rho"], hist):
         assert abs(a - b) <= 1e-9 * hist[0]
     assert _rel(U, U_seq) <= MGRIT_GATE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_graph_replay_matches_eager_launches(cfg1_oracle, precision):
+    """Check intervals of CG iterations replayed from captured hipGraphs give
+    bit-identical iterates to launching every kernel from the host."""
+    print(f"graphs vs eager {precision}", flush=True)
+    from paper_1912_03106_amd import _abi
+    cfg, U_seq, _, hist = cfg1_oracle
+    prec = _abi.FP64 if precision == "fp64" else _abi.FP32_IR
+    runs = []
+    for g in (0, 1):
+        s = _solver(cfg, pcg_tol=1e-12, precision=prec, use_graphs=g)
+        U, st = s.solve()
+        U2, st2 = s.solve()          # replays graphs captured by the first solve
+        assert np.array_equal(U, U2) and st["rho"] == st2["rho"]
+        runs.append((U, st))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1]["rho"] == runs[1][1]["rho"]
+    assert _rel(runs[1][0], U_seq) <= MGRIT_GATE
+
+
+def test_seq_solve_with_startup_ramp_matches_oracle():
+    """The start-up ramp of the nonlinear model's source, on the linear machine."""
+    print("seq cfg1 ramp", flush=True)
+    from workload import Source
+    cfg = config("cfg1", source=Source(ramp_periods=2.0), n_steps=256, t_final=0.005)
+    H, _ = build(cfg)
+    U_ref = stepping.sequential(H.levels[0], np.zeros(H.levels[0].n), cfg.n_steps)
+    U, _ = _solver(cfg, pcg_tol=1e-13).seq_solve()
+    err = np.linalg.norm(U - U_ref, axis=1)[1:] / np.linalg.norm(U_ref, axis=1)[1:]
+    assert err.max() <= SEQ_TOL, err.max()
