@@ -8,13 +8,20 @@ batched FP64 Jacobi-PCG, stop at a 1e-8 relative C-point residual.
 One bench step = one complete MGRIT solve to the tolerance (every part of the
 hot path: F/C relaxation, C-point residual, restriction, FAS right-hand side,
 coarse solves, correction).  `value` is the useful throughput n0 * N_t / T of
-that solve in DOF-steps/s, inputs resident on the GPU.
+that solve in DOF-steps/s, inputs resident on the GPU.  The timed solve stops
+the level-0 relaxation solves at max(1e-12 ||b||, 1e-4 ||r_0||) (r_0: residual
+of the warm start); the C-point residual that decides convergence and every
+coarse level solve to 1e-12 ||b||.
 
-Also reported (same JSON line): GPU sequential stepping on the same problem
-(timed on a prefix of the horizon and scaled to N_t), the F-relaxation
-DOF-steps/s, the roofline of the dominant kernel (PCG pass B) from HIP-event
-timings of every launch in the timed region, and the CPU oracle timed on this
-host.
+Also reported (same JSON line):
+  - the same solve with every linear solve to 1e-12 ||b|| ("plain"),
+  - the FP32 + FP64-refinement workload (random initial guess) with early-
+    stopped level-0 relaxation and FP64 coarse levels,
+  - GPU sequential stepping over the whole horizon,
+  - the roofline of the dominant kernel (PCG pass B) from HIP-event timings of
+    every launch in the timed region,
+  - the CPU oracle timed on this host; the states it computes on its sample
+    of the horizon also give each GPU solution's deviation from the oracle.
 """
 
 import argparse
@@ -67,9 +74,10 @@ def pass_b_roofline(st, solver, unit):
             "bytes_per_launch": round(bytes_total / launches)}
 
 
-def cpu_baseline(cfg, budget_s=12.0):
+def cpu_baseline(cfg, budget_s=12.0, keep_every=64):
     """The oracle's sequential stepping (SuperLU factor + one triangular solve
-    pair per step, single thread) on a prefix of the same workload."""
+    pair per step, single thread) on a prefix of the same workload.  Returns
+    the JSON record and the oracle states at every keep_every-th step."""
     import numpy as np
     from workload import polar_mesh
     from oracle.stepping import Level
@@ -79,17 +87,51 @@ def cpu_baseline(cfg, budget_s=12.0):
     t_fact = time.perf_counter() - t0
     u = np.zeros(lev.n)
     steps = 0
+    kept = {}
     t1 = time.perf_counter()
     while time.perf_counter() - t1 < budget_s and steps < cfg.n_steps:
         u = lev.phi(u[None], [steps])[0]
         steps += 1
+        if steps % keep_every == 0:
+            kept[steps] = u
     el = time.perf_counter() - t1
-    return {"value": round(lev.n * steps / el, 1), "unit": "DOF-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"sequential implicit Euler, SuperLU, first {steps} of {cfg.n_steps} steps "
-                      f"on the {spec.n_r}x{spec.n_theta} mesh (factorisation {t_fact:.2f} s excluded); "
-                      f"host has {os.cpu_count()} logical CPUs",
-            "extrapolated_full_horizon_s": round(el / steps * cfg.n_steps + t_fact, 1)}
+    rec = {"value": round(lev.n * steps / el, 1), "unit": "DOF-steps/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"sequential implicit Euler, SuperLU, first {steps} of {cfg.n_steps} steps "
+                     f"on the {spec.n_r}x{spec.n_theta} mesh (factorisation {t_fact:.2f} s excluded); "
+                     f"host has {os.cpu_count()} logical CPUs",
+           "extrapolated_full_horizon_s": round(el / steps * cfg.n_steps + t_fact, 1)}
+    return rec, kept
+
+
+def oracle_deviation(kept, U):
+    """max over the oracle's kept steps of ||U_gpu[i] - U_oracle[i]|| / ||U_oracle[i]||."""
+    import numpy as np
+    worst = 0.0
+    for i, u in kept.items():
+        worst = max(worst, float(np.linalg.norm(U[i] - u) / np.linalg.norm(u)))
+    return worst
+
+
+def timed_solve(cfg, stream, label, **kw):
+    """Set up a solver, run one MGRIT solve into a device buffer, return
+    (seconds, stats, solver, output tensor)."""
+    import torch
+    from paper_1912_03106_amd.solver import Solver
+    log(f"setup {label}")
+    solver = Solver(cfg, stream=stream.cuda_stream, device_io=True, **kw)
+    out = torch.empty((cfg.n_steps + 1, solver.n0), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = solver.solve(out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log(f"{label}: {len(st['rho']) - 1} iterations, {el:.2f} s")
+    return el, st, solver, out
+
+
+HEADLINE_ETA = 1e-4      # level-0 relaxation: stop at max(pcg_tol ||b||, eta ||r_0||)
+FP32_ETA = 1e-3
 
 
 def main():
@@ -97,12 +139,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--config", default="cfg2")
     ap.add_argument("--seq-prefix", type=int, default=0,
                     help="run only this many steps of the GPU sequential baseline and scale "
                          "to N_t (0 = the whole horizon)")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the plain-tolerance and FP32 + refinement solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-parallel "
@@ -111,18 +154,21 @@ def main():
 
     import torch
     from workload import config
+    from paper_1912_03106_amd import _abi
     from paper_1912_03106_amd.solver import Solver
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    cfg = config(args.config)
-    log(f"setup {cfg.name}")
-    solver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1)
+    cfg = config("cfg2")
+
+    # headline: timed solves (HIP events around every CG pass, replayed graphs)
+    log("setup cfg2 (timed)")
+    solver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1,
+                    pcg_tol_eta=HEADLINE_ETA)
     n0 = solver.n0
     out = torch.empty((cfg.n_steps + 1, n0), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-
     for w in range(args.warmup):
         solver.solve(out=out)
         log(f"warmup {w + 1}/{args.warmup} done")
@@ -141,29 +187,79 @@ def main():
     rho = st["rho"]
     n_t = cfg.level_steps(1)                     # intervals = C-point residual columns per iteration
     frelax_cols = st["phi_columns"][0] - len(rho) * n_t
+    roof = pass_b_roofline(st, solver, 8)
+    shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family"), solver.kernel_shape(l)))
+              for l in range(cfg.n_levels)]
+    U_head = out.cpu().numpy()
+    solver.close()
+    del out
+
+    variants = {}
+    U_var = {}
+    if not args.no_variants:
+        t, vst, vs, vout = timed_solve(cfg, stream, "plain FP64 (every solve to 1e-12)")
+        variants["plain_fp64"] = {"time_to_solution_s": round(t, 3), "iterations": len(vst["rho"]) - 1,
+                                  "pcg_sweeps": vst["pcg_sweeps"][:cfg.n_levels]}
+        U_var["plain_fp64"] = vout.cpu().numpy()
+        vs.close()
+        del vout
+        cfg3 = config("cfg3")
+        guess = torch.from_numpy(cfg3.initial_guess(n0)).to("cuda")
+        log("setup cfg3 FP32 + refinement")
+        vs = Solver(cfg3, stream=stream.cuda_stream, device_io=True, pcg_tol_eta=FP32_ETA,
+                    precision_coarse=_abi.FP64)
+        vout = torch.empty_like(guess)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, vst = vs.solve(u_init=guess, out=vout)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        log(f"FP32 + refinement: {len(vst['rho']) - 1} iterations, {t:.2f} s")
+        variants["fp32_ir"] = {"time_to_solution_s": round(t, 3), "iterations": len(vst["rho"]) - 1,
+                               "pcg_sweeps": vst["pcg_sweeps"][:cfg.n_levels],
+                               "guess": "U(-1e-3, 1e-3), seed 3",
+                               "level0_stop": f"max(1e-12 ||b||, {FP32_ETA:g} ||r_0||)",
+                               "coarse_levels": "FP64 PCG to 1e-12 ||b||",
+                               "autotuned_kernels": [dict(zip(("rows_per_block", "cols_per_lane", "family"),
+                                                              vs.kernel_shape(l)))
+                                                     for l in range(cfg.n_levels)]}
+        U_var["fp32_ir"] = vout.cpu().numpy()
+        vs.close()
+        del vout, guess
+        import numpy as np
+        for k, U in U_var.items():
+            variants[k]["rel_diff_vs_timed_solve"] = float(np.linalg.norm(U - U_head) / np.linalg.norm(U_head))
 
     seq = None
     if not args.no_seq:
         pre = min(args.seq_prefix, cfg.n_steps) if args.seq_prefix > 0 else cfg.n_steps
-        pcfg = config(args.config, n_steps=pre, t_final=pre * cfg.dt)
+        pcfg = config("cfg2", n_steps=pre, t_final=pre * cfg.dt)
         pcfg.meshes = cfg.meshes[:1] * 2
         ps = Solver(pcfg, stream=stream.cuda_stream, device_io=True)
         pout = torch.empty((pre + 1, n0), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
+        log(f"GPU sequential stepping, {pre} steps")
         ts = time.perf_counter()
         _, sst = ps.seq_solve(out=pout)
         torch.cuda.synchronize()
         tseq = time.perf_counter() - ts
-        seq = {"kernel": "cooperative multi-work-group Jacobi-PCG stepper (warm start u_{i-1})",
+        seq = {"kernel": "cooperative multi-work-group Jacobi-PCG stepper (warm start u_{i-1}, 1e-12)",
                "steps_run": pre,
                "time_s_run": round(tseq, 3), "time_s_full_horizon": round(tseq * cfg.n_steps / pre, 2),
                "dof_steps_per_s": round(n0 * pre / tseq, 1),
                "pcg_iterations_per_step": round(sst["pcg_sweeps"][0] / pre, 1)}
         ps.close()
-        log(f"sequential prefix {pre} steps: {tseq:.2f} s")
+        del pout
+        log(f"sequential {pre} steps: {tseq:.2f} s")
 
-    roof = pass_b_roofline(st, solver, 8 if cfg.precision == "fp64" else 4)
-    cpu = None if args.no_cpu else cpu_baseline(cfg)
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle sample")
+        cpu, kept = cpu_baseline(cfg)
+        cpu["gpu_deviation_on_sample"] = {"timed_solve": oracle_deviation(kept, U_head)}
+        for k, U in U_var.items():
+            cpu["gpu_deviation_on_sample"][k] = oracle_deviation(kept, U)
+
     line = {
         "metric": "MGRIT time to 1e-8 rel. resid vs GPU seq. stepping; F-relax DOF-steps/s, GB/s",
         "value": round(value, 1), "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -171,7 +267,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "linear eddy-current machine, 64x512 polar P1 mesh (n=32256), "
                                "16384 implicit-Euler steps over 0.02 s, PWM 20 kHz; 3-level V-cycle "
-                               "m=16 FCF, spatial coarsening 64x512/32x256/16x128; FP64 Jacobi-PCG",
+                               "m=16 FCF, spatial coarsening 64x512/32x256/16x128; FP64 Jacobi-PCG; "
+                               f"level-0 relaxation solves stop at max(1e-12 ||b||, {HEADLINE_ETA:g} "
+                               "||r_0||), C-point residual and coarse levels at 1e-12 ||b||",
                    "n_dof": n0, "n_steps": cfg.n_steps, "levels": cfg.n_levels, "m": cfg.m},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -182,12 +280,14 @@ def main():
                   "level0_phi": frelax_cols, "pcg_sweeps": st["pcg_sweeps"][:cfg.n_levels],
                   "pass_a_time_s": [round(x, 3) for x in st["kernel_time_s"][0][:cfg.n_levels]],
                   "pass_b_time_s": [round(x, 3) for x in st["kernel_time_s"][1][:cfg.n_levels]]},
+        "variants": variants or None,
         "gpu_sequential": seq,
-        "autotuned_kernels": [dict(zip(("rows_per_block", "cols_per_lane", "family"),
-                                       solver.kernel_shape(l))) for l in range(cfg.n_levels)],
+        "autotuned_kernels": shapes,
     }
     if seq:
         line["mgrit"]["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon"] / per, 3)
+        for v in variants.values():
+            v["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon"] / v["time_to_solution_s"], 3)
     print(json.dumps(line), flush=True)
 
 

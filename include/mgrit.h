@@ -121,11 +121,19 @@ typedef struct {
                                * stored A^{-1} (exact implicit Euler) instead of PCG */
   int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one work-group, 2 cooperative grid */
   int32_t use_graphs;         /* 1: replay each check interval of CG iterations from a captured
-                               * hipGraph (not while profile_kernels = 1) */
+                               * hipGraph (not while profile_kernels = 1: launches stay eager so
+                               * that HIP events time each pass) */
   int32_t newton_halvings;    /* damped Newton (Sec. 5.1): per column, the first step length
                                * lambda in 1, 1/2, ..., 2^-newton_halvings with
                                * ||R(u + lambda d)|| < (1 - 1e-4 lambda) ||R(u)||, else the
                                * last one; 0 = plain Newton */
+  double  pcg_tol_eta;        /* > 0: the linear solves of the level-0 F- and C-relaxation of
+                               * mgrit_solve stop at ||r|| <= max(pcg_tol ||b||, eta ||r_0||), r_0
+                               * the residual of their warm start (the previous iterate), which
+                               * shrinks as MGRIT converges; the C-point residual and all coarse
+                               * levels keep pcg_tol ||b||.  0 = pcg_tol ||b|| throughout */
+  int32_t precision_coarse;   /* arithmetic of the linear solves on levels >= 1: -1 = precision,
+                               * else MGRIT_FP64 or MGRIT_FP32_IR (level 0 always uses precision) */
 } mgrit_params;
 
 typedef struct {

@@ -60,6 +60,7 @@ class Params(C.Structure):
         ("warm_start", C.c_int32), ("device_pointers", C.c_int32), ("profile_kernels", C.c_int32),
         ("autotune", C.c_int32), ("pcg_kernel", C.c_int32), ("coarse_inverse", C.c_int32),
         ("seq_kernel", C.c_int32), ("use_graphs", C.c_int32), ("newton_halvings", C.c_int32),
+        ("pcg_tol_eta", C.c_double), ("precision_coarse", C.c_int32),
     ]
 
 

@@ -34,6 +34,7 @@ struct LevelState {
   int64_t N = 0;     // steps on this level
   int64_t NT = 0;    // intervals (N / m) on non-coarsest levels
   bool coarsest = false;
+  int prec = 0;      // arithmetic of this level's linear solves (MGRIT_FP64 / MGRIT_FP32_IR)
   int64_t ld = 0;    // column stride of the storage
   int64_t ss = 0;    // slab stride
   double* U = nullptr;
@@ -90,6 +91,8 @@ struct Handle {
     bool operator<(const GraphKey& o) const { return tie() < o.tie(); }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
+  double tol_now = 1e-12;   // relative residual of the linear solves
+  double eta_now = 0.0;     // > 0: linear solves also stop at eta times their initial residual
   hipStream_t capture_stream = nullptr;
 };
 
@@ -99,7 +102,7 @@ constexpr int kMinRowsPerBlock = 16;
 constexpr int kMaxInverseN = 8192;   // largest coarsest level given a stored inverse
 static const int kRowsPerBlockCandidates[] = {16, 32, 64, 128, 256};
 
-static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block) {
+static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block, int prec) {
   w.n = n;
   w.cap = cap;
   w.ld = round_up(cap > 0 ? cap : 1, kWave);
@@ -120,7 +123,8 @@ static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block)
   w.src = h.arena.alloc<double>(3 * static_cast<size_t>(w.ld));
   w.active = h.arena.alloc<uint8_t>(w.ld);
   w.outer = h.arena.alloc<uint8_t>(w.ld);
-  if (h.par.precision == MGRIT_FP32_IR) {
+  w.prec = prec;
+  if (prec == MGRIT_FP32_IR) {
     w.r32 = h.arena.alloc<float>(vec);
     w.x32 = h.arena.alloc<float>(vec);
     w.p32[0] = h.arena.alloc<float>(vec);
@@ -164,8 +168,8 @@ static void autotune(Handle& h, LevelState& S) {
   const int ncols = w.cap;
   w.dia = (h.par.pcg_kernel == 2);
   if (!h.par.autotune || S.n < 4096 || ncols < kWave) return;
-  const bool fp32 = h.par.precision == MGRIT_FP32_IR;
-  const TuneKey key{S.n, S.op.W, ncols, h.par.precision, S.op.dia_R * 4 + h.par.pcg_kernel};
+  const bool fp32 = w.prec == MGRIT_FP32_IR;
+  const TuneKey key{S.n, S.op.W, ncols, w.prec, S.op.dia_R * 4 + h.par.pcg_kernel};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -274,10 +278,12 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     const int k = std::min(chunk, cap - it);
     // Later check intervals replay a captured graph of the same k launches
     // (the first carries the `first` iteration and runs eagerly).
+    // (HIP events recorded inside a graph do not time its kernels reliably,
+    // so profiled solves launch eagerly)
     const bool graph = h.par.use_graphs && !prof && it > 0 && k == chunk && (chunk % 2) == 0;
     if (graph) {
       const Handle::GraphKey key{w.x, &L, w.nl, w.rows_per_block, w.cpl, w.dia ? 1 : 0, w.parity,
-                                      ncols, kind, chunk, tol2};
+                                 ncols, kind, chunk, tol2};
       auto found = h.graphs.find(key);
       if (found == h.graphs.end()) {
         hipStream_t cs = h.capture_stream;
@@ -354,21 +360,25 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
 //            A d = r by FP32 Jacobi-PCG to ir_inner_tol (relative), x += d.
 static int pcg_solve(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, CView in) {
   hipStream_t s = h.stream;
-  const double tol2 = h.par.pcg_tol * h.par.pcg_tol;
-  if (h.par.precision == MGRIT_FP64) {
+  const double tol2 = h.tol_now * h.tol_now;
+  const double eta2 = h.eta_now * h.eta_now;
+  if (w.prec == MGRIT_FP64) {
     launch_pcg_init(s, L, w, ncols, in);
-    launch_reduce(s, w, ncols, RED_INIT, tol2, 3, nullptr);
+    launch_reduce(s, w, ncols, RED_INIT, tol2, 3, nullptr, eta2);
     MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     MG_HIP(hipStreamSynchronize(s));
     if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
     return pcg_iterate(h, level, L, w, ncols, tol2, IT_LIN64, w.host_flags[0], true);
   }
-  const double tin2 = h.par.ir_inner_tol * h.par.ir_inner_tol;
+  // inner FP32 tolerance: ir_inner_tol, or the reduction the outer test asks
+  // for when that is looser (half of eta, so one sweep normally suffices)
+  const double tin = std::min(0.1, std::max(h.par.ir_inner_tol, 0.5 * h.eta_now));
+  const double tin2 = tin * tin;
   launch_fill_u8(s, w.outer, ncols, 1);
   int total = 0;
   for (int sweep = 0;; ++sweep) {
     launch_ir_residual(s, L, w, ncols, in);
-    launch_reduce(s, w, ncols, RED_IR_INIT, tol2, 3, nullptr);
+    launch_reduce(s, w, ncols, sweep == 0 ? RED_IR_FIRST : RED_IR_INIT, tol2, 3, nullptr, eta2);
     MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     MG_HIP(hipStreamSynchronize(s));
     if (w.host_flags[1]) fail(MGRIT_NONFINITE, "non-finite value in a linear solve");
@@ -388,7 +398,7 @@ static NlWork& nl_work(Handle& h, LevelState& S, PcgWork& w) {
   if (w.nl) return *w.nl;
   auto* nw = new NlWork();
   h.nl_keep.emplace_back(nw);
-  nw->fp32 = (h.par.precision == MGRIT_FP32_IR);
+  nw->fp32 = (w.prec == MGRIT_FP32_IR);
   const size_t ev = static_cast<size_t>(S.nl.n_tri) * w.ld;
   const size_t vec = static_cast<size_t>(w.n) * w.ld;
   const size_t mat = vec * S.op.W;
@@ -721,7 +731,7 @@ static void build_coarse_inverse(Handle& h, LevelState& S) {
   const int chunk = std::min(S.n, 2048);
   const int keep_max = h.par.pcg_max_iter;
   h.par.pcg_max_iter = std::max(keep_max, 20000);   // history buffer size for this solve
-  alloc_pcg(h, w, S.n, chunk, rows_per_block_for(S.n));
+  alloc_pcg(h, w, S.n, chunk, rows_per_block_for(S.n), MGRIT_FP64);
   h.par.pcg_max_iter = keep_max;
   S.ld_inv = round_up(S.n, kWave);
   S.Ainv = h.arena.alloc<double>(static_cast<size_t>(S.n) * S.ld_inv);
@@ -750,15 +760,20 @@ static void build_coarse_inverse(Handle& h, LevelState& S) {
 static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params* par) {
   if (!prob || !par) fail(MGRIT_INVALID_ARGUMENT, "null problem or params");
   h.par = *par;
+  h.tol_now = h.par.pcg_tol;
   h.phys = prob->phys;
   const mgrit_physics& ph = prob->phys;
   const int L = prob->n_levels;
   if (L < 1 || L > MGRIT_MAX_LEVELS || !prob->meshes) fail(MGRIT_INVALID_ARGUMENT, "n_levels out of range");
   if (par->m < 2) fail(MGRIT_INVALID_ARGUMENT, "m must be > 1");
   if (par->gamma < 0) fail(MGRIT_INVALID_ARGUMENT, "gamma must be >= 0");
-  if (!(par->pcg_tol > 0.0) || par->pcg_max_iter < 1) fail(MGRIT_INVALID_ARGUMENT, "bad PCG settings");
+  if (!(par->pcg_tol > 0.0) || par->pcg_max_iter < 1 || !(par->pcg_tol_eta >= 0.0))
+    fail(MGRIT_INVALID_ARGUMENT, "bad PCG settings");
   if (par->precision != MGRIT_FP64 && par->precision != MGRIT_FP32_IR)
     fail(MGRIT_INVALID_ARGUMENT, "precision must be MGRIT_FP64 or MGRIT_FP32_IR");
+  if (par->precision_coarse != -1 && par->precision_coarse != MGRIT_FP64 &&
+      par->precision_coarse != MGRIT_FP32_IR)
+    fail(MGRIT_INVALID_ARGUMENT, "precision_coarse must be -1, MGRIT_FP64 or MGRIT_FP32_IR");
   if (par->pcg_kernel < 0 || par->pcg_kernel > 2) fail(MGRIT_INVALID_ARGUMENT, "pcg_kernel");
   if (par->precision == MGRIT_FP32_IR && (!(par->ir_inner_tol > 0.0) || par->ir_max_iter < 1))
     fail(MGRIT_INVALID_ARGUMENT, "bad refinement settings");
@@ -863,7 +878,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     // level l's batched Phi serves its own sweeps (NT columns) and, on
     // coarse levels, the FAS right-hand side (N columns)
     const int cap = static_cast<int>((l == 0 ? S.NT : S.N) + 1);
-    alloc_pcg(h, S.pcg, S.n, cap, rpb);
+    S.prec = (l == 0 || par->precision_coarse < 0) ? par->precision : par->precision_coarse;
+    alloc_pcg(h, S.pcg, S.n, cap, rpb, S.prec);
   }
   const int64_t ld0 = h.lv[0].pcg.ld > h.lv[0].ld ? h.lv[0].pcg.ld : h.lv[0].ld;
   h.host_sums = static_cast<double*>(h.arena.alloc_host(sizeof(double) * (ld0 + 64)));
@@ -926,14 +942,22 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
   double rho0 = 0.0;
   int status = MGRIT_OK;
   for (int it = 0;; ++it) {
+    // Only the level-0 relaxation stops its solves early (eta times the
+    // warm-start residual, which shrinks as MGRIT converges).  Coarse levels
+    // keep pcg_tol: their warm-start residuals do not shrink (the FAS right-
+    // hand side and the coarse solve evaluate Phi at different inputs), so
+    // loose coarse solves would leave an error floor in the correction.
+    h.tol_now = h.par.pcg_tol;
+    h.eta_now = h.par.pcg_tol_eta;
     MG_HIP(hipEventRecord(h.ev0, s));
     relax(h, 0);
+    h.eta_now = 0.0;
     MG_HIP(hipEventRecord(h.ev1, s));
     MG_HIP(hipEventSynchronize(h.ev1));
     float ms = 0.f;
     MG_HIP(hipEventElapsedTime(&ms, h.ev0, h.ev1));
     st->time_relax_s += 1e-3 * ms;
-    c_residual(h, 0);
+    c_residual(h, 0);         // the convergence measure always uses pcg_tol
     const double rho = residual_norm(h, 0);
     if (st->n_history < MGRIT_MAX_HISTORY) st->rho[st->n_history++] = rho;
     if (it == 0) rho0 = rho;
@@ -959,6 +983,8 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
 
 static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st) {
   hipStream_t s = h.stream;
+  h.tol_now = h.par.pcg_tol;
+  h.eta_now = 0.0;
   LevelState& S0 = h.lv[0];
   if (!u_out) fail(MGRIT_INVALID_ARGUMENT, "u_out is null");
   load_u0(h, u0);
@@ -1032,12 +1058,15 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
 
 static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, const double* u_prev,
                           double* u_next) {
+  h.tol_now = h.par.pcg_tol;
+  h.eta_now = 0.0;
   if (level < 0 || level >= static_cast<int>(h.lv.size())) fail(MGRIT_INVALID_ARGUMENT, "level");
   if (B < 0 || (B > 0 && (!i_from || !u_prev || !u_next))) fail(MGRIT_INVALID_ARGUMENT, "phi_step arguments");
   if (B == 0) return;
   LevelState& S = h.lv[level];
   hipStream_t s = h.stream;
-  if (S.user.cap < B) alloc_pcg(h, S.user, S.n, static_cast<int>(round_up(B, kWave)), rows_per_block_for(S.n));
+  if (S.user.cap < B)
+    alloc_pcg(h, S.user, S.n, static_cast<int>(round_up(B, kWave)), rows_per_block_for(S.n), S.prec);
   PcgWork& w = S.user;
   // same kernel family and tile shape as the level's own sweeps
   set_rows_per_block(w, S.pcg.rows_per_block);
@@ -1130,6 +1159,8 @@ void mgrit_default_params(mgrit_params* p) {
   p->seq_kernel = 0;
   p->use_graphs = 1;
   p->newton_halvings = 6;
+  p->pcg_tol_eta = 0.0;
+  p->precision_coarse = -1;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {

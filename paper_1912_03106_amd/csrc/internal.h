@@ -94,6 +94,7 @@ struct NlWork;
 // Batched-PCG workspace for up to `cap` columns of an n-row level.
 struct PcgWork {
   int n = 0, cap = 0, nrb = 0, rows_per_block = 0;
+  int prec = 0;                 // MGRIT_FP64 or MGRIT_FP32_IR (this workspace's solves)
   int cpl = 1;                  // columns per lane of the CG passes (1 or 2)
   bool dia = false;             // use the diagonal-window CG passes
   int64_t ld = 0;
@@ -155,7 +156,7 @@ void launch_nl_ls_start(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);
 // flags[3] += refining columns accepted
 void launch_nl_ls(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, double tol2, double lam_min);
 
-enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3, RED_IR_INIT = 4 };
+enum ReduceMode { RED_INIT = 0, RED_ALPHA = 1, RED_BETA = 2, RED_SUM = 3, RED_IR_INIT = 4, RED_IR_FIRST = 5 };
 
 // --- setup kernels ---------------------------------------------------------
 void launch_elem_geometry(hipStream_t s, int n_tri, const double* xy, const int* tri,
@@ -175,8 +176,10 @@ void launch_source_table(hipStream_t s, const SourceDev& src, double dt, int nco
 void launch_axpby3(hipStream_t s, int n, int ncols, double* out, int64_t ldo, double sx,
                    CView x, double sa, CView a, double sb, CView b);
 void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in);
+// eta2 > 0 (RED_INIT, RED_IR_FIRST): a column also stops once its residual
+// is below eta2 times its initial residual (squared norms).
 void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
-                   double* sums_out);
+                   double* sums_out, double eta2 = 0.0);
 // CG on the scaled system (pcg.hip).
 // pass A: p^ = r^ + beta p^_old, partials of p^.A^p^ (flips w.parity)
 void launch_pcg_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first);

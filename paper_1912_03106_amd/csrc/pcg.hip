@@ -612,7 +612,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(int n, int ncols, int ncc,
 //   SUM:     plain sums into sums_out
 //   IR_INIT: outer test on the FP64 residual; inner start (rz, reference rr)
 __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t ld, int mode,
-                                                   int nq, double tol2,
+                                                   int nq, double tol2, double eta2,
                                                    const double* __restrict__ part,
                                                    double* __restrict__ scal,
                                                    uint8_t* __restrict__ active,
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
   __syncthreads();
   bool on = c < ncols;
   if (on && (mode == RED_ALPHA || mode == RED_BETA)) on = active[c] != 0;
-  if (on && mode == RED_IR_INIT) on = outer[c] != 0;
+  if (on && (mode == RED_IR_INIT || mode == RED_IR_FIRST)) on = outer[c] != 0;
   double T[3] = {0.0, 0.0, 0.0};
   if (on) {
     const int64_t qs = static_cast<int64_t>(nrb) * ld;
@@ -642,11 +642,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
     double* bb = scal + 2 * ld;
     double* al = scal + 3 * ld;
     double* be = scal + 4 * ld;
+    double* thr = scal + 6 * ld;       // outer stopping threshold (refinement)
     int act = 0;
     bool bad = false;
     if (mode == RED_INIT) {
       double b2 = T[2];
       if (b2 == 0.0) b2 = T[1];
+      if (eta2 > 0.0) b2 = fmax(b2, (eta2 / tol2) * T[1]);
       rz[c] = T[0];
       rr[c] = T[1];
       bb[c] = b2;
@@ -675,11 +677,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
         if (!act || bad) b = 0.0;
       }
       be[c] = b;
-    } else if (mode == RED_IR_INIT) {
+    } else if (mode == RED_IR_INIT || mode == RED_IR_FIRST) {
       if (on) {
-        double b2 = T[2];
-        if (b2 == 0.0) b2 = T[1];
-        act = T[1] > tol2 * b2;        // outer (FP64) convergence test
+        if (mode == RED_IR_FIRST) {
+          double b2 = T[2];
+          if (b2 == 0.0) b2 = T[1];
+          thr[c] = fmax(tol2 * b2, eta2 * T[1]);
+        }
+        act = T[1] > thr[c];           // outer (FP64) convergence test
         outer[c] = static_cast<uint8_t>(act);
         rz[c] = T[0];
         rr[c] = T[1];
@@ -698,7 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int ncols, int nrb, int64_t l
   }
   __syncthreads();
   if (threadIdx.x == 0 && cnt > 0 &&
-      (mode == RED_INIT || mode == RED_BETA || mode == RED_IR_INIT))
+      (mode == RED_INIT || mode == RED_BETA || mode == RED_IR_INIT || mode == RED_IR_FIRST))
     atomicAdd(flags, cnt);
 }
 
@@ -776,9 +781,9 @@ void launch_cg_init_identity(hipStream_t s, const DevLevel& L, PcgWork& w, int j
 }
 
 void launch_reduce(hipStream_t s, PcgWork& w, int ncols, int mode, double tol2, int nq,
-                   double* sums_out) {
+                   double* sums_out, double eta2) {
   hipLaunchKernelGGL(k_reduce, dim3(ceil_div(ncols, 4)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
-                     mode, nq, tol2, w.part, w.scal, w.active, w.flags, sums_out, w.outer);
+                     mode, nq, tol2, eta2, w.part, w.scal, w.active, w.flags, sums_out, w.outer);
   MG_HIP(hipGetLastError());
 }
 

@@ -115,10 +115,18 @@ class Solver:
         return self.level_info(0)[0]
 
     # -- entry points ----------------------------------------------------
+    @staticmethod
+    def _check_device(t, shape):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected a contiguous float64 CUDA tensor of shape {shape}")
+
     def _io(self, arr, shape, zero_ok=True):
         if arr is None:
             return None, None
         if self.device_io:
+            self._check_device(arr, shape)
             return arr, C.c_void_p(arr.data_ptr())
         a = np.ascontiguousarray(arr, dtype=np.float64)
         if a.shape != shape:
@@ -129,6 +137,7 @@ class Solver:
         if self.device_io:
             if out is None:
                 raise ValueError("device_io solvers need a preallocated device output")
+            self._check_device(out, shape)
             return out, C.c_void_p(out.data_ptr())
         if out is None:
             out = np.empty(shape)

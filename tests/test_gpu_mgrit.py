@@ -203,3 +203,23 @@ def test_seq_solve_with_startup_ramp_matches_oracle():
     U, _ = _solver(cfg, pcg_tol=1e-13).seq_solve()
     err = np.linalg.norm(U - U_ref, axis=1)[1:] / np.linalg.norm(U_ref, axis=1)[1:]
     assert err.max() <= SEQ_TOL, err.max()
+
+
+@pytest.mark.parametrize("variant", ["fp64_eta", "fp32ir_eta_coarse_fp64"])
+def test_early_stopped_relaxation_reaches_the_same_solution(variant):
+    """Level-0 relaxation solves stopped at max(pcg_tol ||b||, eta ||r_0||)
+    (the C-point residual and the coarse levels keep pcg_tol): the same
+    fixed point, within one or two iterations of the strict solves."""
+    print(f"mgrit early stop {variant}", flush=True)
+    from paper_1912_03106_amd import _abi
+    cfg = _sc_cfg()
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    kw = dict(pcg_tol=1e-12, pcg_tol_eta=1e-3)
+    if variant != "fp64_eta":
+        kw.update(precision=_abi.FP32_IR, precision_coarse=_abi.FP64)
+    U, st = _solver(cfg, **kw).solve()
+    assert st["converged"]
+    assert len(st["rho"]) <= 11 + 2
+    assert _rel(U, U_seq) <= MGRIT_GATE
