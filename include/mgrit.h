@@ -134,6 +134,9 @@ typedef struct {
                                * levels keep pcg_tol ||b||.  0 = pcg_tol ||b|| throughout */
   int32_t precision_coarse;   /* arithmetic of the linear solves on levels >= 1: -1 = precision,
                                * else MGRIT_FP64 or MGRIT_FP32_IR (level 0 always uses precision) */
+  int32_t coarse_model;       /* coarsest-level propagator: 0 implicit Euler (Sec. 2.1
+                               * re-discretisation), 1 implicit Euler plus the learned correction
+                               * (needs mgrit_train_coarse or mgrit_set_coarse_weights) */
 } mgrit_params;
 
 typedef struct {
@@ -154,6 +157,8 @@ typedef struct {
   double  kernel_time_s[2][MGRIT_MAX_LEVELS];   /* needs profile_kernels = 1 */
   double  time_relax_s;       /* finest-level F/C relaxation time (device events) */
   double  time_total_s;
+  int32_t coarse_fallback;    /* coarse_model = 1: iteration after which the residual grew and
+                               * the coarsest level went back to implicit Euler; -1 = never */
 } mgrit_stats;
 
 /* Fill *par with the defaults (m = 16, FCF, FP64, normalized restriction,
@@ -195,6 +200,72 @@ int phi_step(void* h, int32_t level, int32_t B, const int64_t* i_from,
  * (1 general sparse rows, 2 diagonal window).  Any output pointer may be NULL. */
 int mgrit_level_info(void* h, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
                      int32_t* kernel_shape);
+
+/* ---- Learned coarse propagator (coarsest level, coarse_model = 1) ----------
+ * MGRIT admits any coarse propagator (Sec. 2.1: re-discretisation is one
+ * choice); with FAS the fixed point is the fine solution whatever it is.  The
+ * learned one is Psi(u) = p + s_out delta, p the implicit-Euler coarse step of
+ * u, delta a 3-layer message-passing network (width 64, tanh) on the coarsest
+ * mesh's interior-node graph.  Node features (F = m + 7): u/s_u, p/s_u, the
+ * node's forcing at T_k + j dT/m (j = 0..m) over s_f, conductor / iron / coil
+ * flags (node touches such a cell) and (r - r_in)/(r_out - r_in) with r_in,
+ * r_out the radii of the mesh's first and last node.  The weight blob is FP32
+ * (the master copy; products use its bf16 rounding and accumulate in FP32):
+ *   [s_u, s_f, s_out, 0], W_in[F][64], b_in[64],
+ *   3 x {Ws[64][64], Wn[64][64], b[64]}, w_out[64], b_out[1].
+ * Layer l: h_l = h_{l-1} + tanh(h_{l-1} Ws + mean_neighbours(h_{l-1}) Wn + b);
+ * h_0 = tanh(x W_in + b_in); delta = h_3 w_out + b_out. */
+typedef struct {
+  int32_t n_traj;        /* trajectories generated (columns of one batched Phi)     */
+  int32_t epochs;
+  int32_t batch;         /* samples per Adam step                                    */
+  double  lr;            /* Adam rate (cosine decay to lr/10 over the run)           */
+  double  amp_spread;    /* source amplitude factors uniform in [1 - s, 1 + s]       */
+  double  val_fraction;  /* trajectories held out for validation                     */
+  uint64_t seed;
+  double  perturb;       /* at every coarse step each trajectory's state moves towards a
+                          * random other trajectory's by a factor uniform in
+                          * [-perturb, perturb] before the pair is taken (0 = none)  */
+} mgrit_train_params;
+
+typedef struct {
+  int64_t n_train, n_val;   /* (u_k, u_{k+1}) pairs                                  */
+  int64_t steps;            /* Adam steps                                            */
+  double  loss_first, loss_last;  /* mean scaled squared error, first / last epoch   */
+  /* sqrt(sum ||Psi(u_k) - u_{k+1}||^2 / sum ||u_{k+1} - u_k||^2) with Psi = implicit
+   * Euler (ie) or the trained propagator (learned), on both sets */
+  double  train_err_ie, train_err_learned, val_err_ie, val_err_learned;
+  double  time_data_s, time_train_s;
+} mgrit_train_stats;
+
+/* Trains the learned coarse propagator of a hierarchy with two or more levels:
+ * n_traj trajectories of the level above the coarsest (its own Phi, each with
+ * a source amplitude factor and a phase shift drawn from seed), restricted to
+ * the coarsest mesh every m steps, give the pairs (u_k, u_{k+1}); p = implicit
+ * Euler on the coarsest level; loss = mean ((Psi - u_{k+1}) / s_out)^2; Adam
+ * (beta 0.9 / 0.999, eps 1e-8) from Glorot-uniform weights with a zero output
+ * layer.  Replaces the handle's weights.  Errors: INVALID_ARGUMENT, UNSUPPORTED. */
+int mgrit_train_coarse(void* h, const mgrit_train_params* tp, mgrit_train_stats* ts);
+
+/* Number of weights of the learned propagator (0 if the hierarchy has none). */
+int64_t mgrit_coarse_n_params(void* h);
+/* Copy a weight blob in (resets the Adam moments) or out; n must equal
+ * mgrit_coarse_n_params; the three scales must be > 0. */
+int mgrit_set_coarse_weights(void* h, const float* w, int64_t n);
+int mgrit_get_coarse_weights(void* h, float* w, int64_t n);
+/* Psi for B samples on the coarsest level (host arrays, user node order):
+ * u, p [B][n_c] (p = the implicit-Euler step of u), k[B] input coarse steps
+ * (T_k = k dT), amp / dphi [B] source amplitude factors and phase shifts (NULL =
+ * 1 and 0).  psi [B][n_c] out. */
+int mgrit_coarse_apply(void* h, int32_t B, const int64_t* k, const double* amp, const double* dphi,
+                       const double* u, const double* p, double* psi);
+/* Loss (mean scaled squared error against y [B][n_c]) and its gradient with
+ * respect to every weight (FP32, the scales get 0), same arguments. */
+int mgrit_coarse_gradient(void* h, int32_t B, const int64_t* k, const double* amp,
+                          const double* dphi, const double* u, const double* p, const double* y,
+                          double* loss, float* grad);
+/* One Adam step of the weights with a given gradient (moments kept between calls). */
+int mgrit_coarse_adam(void* h, const float* grad, double lr);
 
 void mgrit_destroy(void* h);
 const char* mgrit_strerror(int status);

@@ -23,7 +23,10 @@ FP64, FP32_IR = 0, 1
 R_NORMALIZED, R_TRANSPOSE, R_INJECTION = 0, 1, 2
 
 EXPORTS = ("mgrit_default_params", "mgrit_setup", "mgrit_solve", "mgrit_seq_solve", "phi_step",
-           "mgrit_level_info", "mgrit_destroy", "mgrit_strerror", "mgrit_last_error")
+           "mgrit_level_info", "mgrit_destroy", "mgrit_strerror", "mgrit_last_error",
+           "mgrit_train_coarse", "mgrit_coarse_n_params", "mgrit_set_coarse_weights",
+           "mgrit_get_coarse_weights", "mgrit_coarse_apply", "mgrit_coarse_gradient",
+           "mgrit_coarse_adam")
 
 
 class Mesh(C.Structure):
@@ -60,7 +63,7 @@ class Params(C.Structure):
         ("warm_start", C.c_int32), ("device_pointers", C.c_int32), ("profile_kernels", C.c_int32),
         ("autotune", C.c_int32), ("pcg_kernel", C.c_int32), ("coarse_inverse", C.c_int32),
         ("seq_kernel", C.c_int32), ("use_graphs", C.c_int32), ("newton_halvings", C.c_int32),
-        ("pcg_tol_eta", C.c_double), ("precision_coarse", C.c_int32),
+        ("pcg_tol_eta", C.c_double), ("precision_coarse", C.c_int32), ("coarse_model", C.c_int32),
     ]
 
 
@@ -73,6 +76,25 @@ class Stats(C.Structure):
         ("kernel_launches", (C.c_int64 * MAX_LEVELS) * 2), ("kernel_columns", C.c_int64 * MAX_LEVELS),
         ("kernel_time_s", (C.c_double * MAX_LEVELS) * 2),
         ("time_relax_s", C.c_double), ("time_total_s", C.c_double),
+        ("coarse_fallback", C.c_int32),
+    ]
+
+
+class TrainParams(C.Structure):
+    _fields_ = [
+        ("n_traj", C.c_int32), ("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+        ("amp_spread", C.c_double), ("val_fraction", C.c_double), ("seed", C.c_uint64),
+        ("perturb", C.c_double),
+    ]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [
+        ("n_train", C.c_int64), ("n_val", C.c_int64), ("steps", C.c_int64),
+        ("loss_first", C.c_double), ("loss_last", C.c_double),
+        ("train_err_ie", C.c_double), ("train_err_learned", C.c_double),
+        ("val_err_ie", C.c_double), ("val_err_learned", C.c_double),
+        ("time_data_s", C.c_double), ("time_train_s", C.c_double),
     ]
 
 
@@ -111,6 +133,21 @@ def lib():
     L.mgrit_strerror.restype = C.c_char_p
     L.mgrit_last_error.argtypes = [vp]
     L.mgrit_last_error.restype = C.c_char_p
+    fp = C.POINTER(C.c_float)
+    L.mgrit_train_coarse.argtypes = [vp, C.POINTER(TrainParams), C.POINTER(TrainStats)]
+    L.mgrit_train_coarse.restype = C.c_int
+    L.mgrit_coarse_n_params.argtypes = [vp]
+    L.mgrit_coarse_n_params.restype = C.c_int64
+    L.mgrit_set_coarse_weights.argtypes = [vp, fp, C.c_int64]
+    L.mgrit_set_coarse_weights.restype = C.c_int
+    L.mgrit_get_coarse_weights.argtypes = [vp, fp, C.c_int64]
+    L.mgrit_get_coarse_weights.restype = C.c_int
+    L.mgrit_coarse_apply.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    L.mgrit_coarse_apply.restype = C.c_int
+    L.mgrit_coarse_gradient.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp, dp, fp]
+    L.mgrit_coarse_gradient.restype = C.c_int
+    L.mgrit_coarse_adam.argtypes = [vp, fp, C.c_double]
+    L.mgrit_coarse_adam.restype = C.c_int
     del dp
     _LIB = L
     return L

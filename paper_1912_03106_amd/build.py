@@ -19,8 +19,8 @@ LIB = os.path.join(PKG, "libmgrit.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "pcg.hip", "newton.hip", "setup.hip", "engine.hip"]
-HEADERS = ["internal.h", "setup.h"]
+SOURCES = ["kernels.hip", "pcg.hip", "newton.hip", "gnn.hip", "setup.hip", "engine.hip"]
+HEADERS = ["internal.h", "setup.h", "source_dev.h"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -91,6 +91,13 @@ struct Handle {
     bool operator<(const GraphKey& o) const { return tie() < o.tie(); }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // learned coarse propagator on the coarsest level
+  GnnModel gnn;
+  bool has_gnn = false;
+  bool learned_off = false;  // switched back to implicit Euler in this solve
+  double* gnn_tmp = nullptr; // [n_c][ld_c] implicit-Euler part of a coarse step
+  const double* col_amp = nullptr;   // per-column source amplitude factors / phase
+  const double* col_dphi = nullptr;  // shifts of phi_batch (training data only)
   double tol_now = 1e-12;   // relative residual of the linear solves
   double eta_now = 0.0;     // > 0: linear solves also stop at eta times their initial residual
   hipStream_t capture_stream = nullptr;
@@ -505,16 +512,52 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
   if (c.ncols > w.cap) fail(MGRIT_INVALID_ARGUMENT, "batched Phi wider than its workspace");
   LevelState& S = h.lv[l];
   hipStream_t s = h.stream;
-  launch_source_table(s, h.src, S.op.dt, c.ncols, c.t_list, c.t_base, c.t_stride, w.src, w.ld);
-  launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
-  const int it = S.nl.n_tri > 0
-                     ? newton_solve(h, l, S, w, c.ncols, c.in, c.ga.p == c.in.p && c.gb.p == nullptr)
-                     : pcg_solve(h, l, S.op, w, c.ncols, c.in);
+  launch_source_table(s, h.src, S.op.dt, c.ncols, c.t_list, c.t_base, c.t_stride, w.src, w.ld,
+                      h.col_amp, h.col_dphi);
+  int it = 0;
+  if (S.Ainv) {
+    // coarsest linear level: the stored inverse, the same implicit-Euler
+    // step as its sequential solve
+    launch_ie_inverse_batch(s, S.op, c.ncols, w.src, w.ld, c.in, S.Ainv, S.ld_inv, w.r, w.x, w.ld);
+  } else {
+    launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
+    it = S.nl.n_tri > 0
+             ? newton_solve(h, l, S, w, c.ncols, c.in, c.ga.p == c.in.p && c.gb.p == nullptr)
+             : pcg_solve(h, l, S.op, w, c.ncols, c.in);
+  }
   launch_axpby3(s, S.n, c.ncols, c.out, c.ldo, c.osx, CView{w.x, w.ld}, 1.0, c.oa, c.osb, c.ob);
   if (h.st && l < MGRIT_MAX_LEVELS) {
     h.st->phi_columns[l] += c.ncols;
     h.st->pcg_sweeps[l] += it;
   }
+}
+
+// The coarse propagator of level l: implicit Euler, or on the coarsest level
+// with coarse_model = 1 implicit Euler plus the learned correction,
+//   out = osx * (p + s_out delta) + oa + osb * ob,   p = Phi_IE(in).
+static bool learned_active(const Handle& h, int l) {
+  return h.par.coarse_model == 1 && !h.learned_off && l == static_cast<int>(h.lv.size()) - 1;
+}
+
+static void psi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
+  if (!learned_active(h, l)) {
+    phi_batch(h, l, w, c);
+    return;
+  }
+  if (c.ncols <= 0) return;
+  LevelState& S = h.lv[l];
+  hipStream_t s = h.stream;
+  PhiCall ie = c;
+  ie.out = h.gnn_tmp;
+  ie.ldo = S.ld;
+  ie.osx = 1.0;
+  ie.oa = CView{};
+  ie.ob = CView{};
+  ie.osb = 0.0;
+  phi_batch(h, l, w, ie);
+  gnn_forward(s, h.gnn, h.src, c.ncols, c.t_list, c.t_base, c.t_stride, nullptr, nullptr, c.in,
+              CView{h.gnn_tmp, S.ld}, h.gnn_tmp, S.ld, false);
+  launch_axpby3(s, S.n, c.ncols, c.out, c.ldo, c.osx, CView{h.gnn_tmp, S.ld}, 1.0, c.oa, c.osb, c.ob);
 }
 
 static double* slab(LevelState& S, int j) { return S.U + static_cast<int64_t>(j) * S.ss; }
@@ -618,8 +661,27 @@ static void coarsest_solve(Handle& h, int l) {
   hipStream_t s = h.stream;
   // u_0 = g_0
   launch_axpby3(s, S.n, 1, S.U, S.ld, 0.0, CView{}, 1.0, CView{S.G, S.ld}, 0.0, CView{});
-  if (S.nl.n_tri > 0) {
-    // nonlinear: one Newton-solved step at a time, u_s = Phi(u_{s-1}) + g_s
+  if (S.Ainv) {
+    // implicit Euler with the stored inverse (the same kernels as the batched
+    // coarse steps of the FAS right-hand side, so both evaluate the same
+    // propagator), the learned correction in place if active, then + g_s
+    PcgWork& w = S.pcg;
+    const bool learned = learned_active(h, l);
+    for (int64_t st = 1; st <= S.N; ++st) {
+      launch_source_table(s, h.src, S.op.dt, 1, nullptr, st - 1, 0, w.src, w.ld);
+      launch_ie_inverse_batch(s, S.op, 1, w.src, w.ld, CView{S.U + st - 1, S.ld}, S.Ainv, S.ld_inv,
+                              w.r, w.x, w.ld);
+      if (learned)
+        gnn_forward(s, h.gnn, h.src, 1, nullptr, st - 1, 0, nullptr, nullptr, CView{S.U + st - 1, S.ld},
+                    CView{w.x, w.ld}, w.x, w.ld, false);
+      launch_axpby3(s, S.n, 1, S.U + st, S.ld, 1.0, CView{w.x, w.ld}, 1.0, CView{S.G + st, S.ld}, 0.0,
+                    CView{});
+    }
+    if (h.st && l < MGRIT_MAX_LEVELS) h.st->phi_columns[l] += S.N;
+    return;
+  }
+  if (S.nl.n_tri > 0 || learned_active(h, l)) {
+    // one step at a time, u_s = Psi(u_{s-1}) + g_s (Newton for the nonlinear model)
     for (int64_t st = 1; st <= S.N; ++st) {
       PhiCall c;
       c.ncols = 1;
@@ -631,16 +693,8 @@ static void coarsest_solve(Handle& h, int l) {
       c.out = S.U + st;
       c.ldo = S.ld;
       c.oa = CView{S.G + st, S.ld};
-      phi_batch(h, l, S.pcg, c);
+      psi_batch(h, l, S.pcg, c);
     }
-    return;
-  }
-  if (S.Ainv) {
-    // implicit Euler with the stored inverse: u_s = A^{-1} ((M/dt) u_{s-1} + f(t_s)) + g_s
-    for (int64_t st = 1; st <= S.N; ++st)
-      launch_coarse_step(s, S.op, h.src, static_cast<double>(st) * S.op.dt, S.U, S.ld,
-                         static_cast<int>(st), S.G, S.ld, S.Ainv, S.ld_inv, S.bvec);
-    if (h.st && l < MGRIT_MAX_LEVELS) h.st->phi_columns[l] += S.N;
     return;
   }
   MG_HIP(hipMemsetAsync(S.pcg.flags, 0, 4 * sizeof(int), s));
@@ -685,7 +739,7 @@ static void coarse_correct(Handle& h, int l) {
   c.oa = CView{S.U2 + 1, S.ld};
   c.ob = CView{S.RR + 1, S.ld};
   c.osb = 1.0;
-  phi_batch(h, l + 1, C.pcg, c);
+  psi_batch(h, l + 1, C.pcg, c);
   // v = u2, load the coarse problem
   if (C.coarsest) {
     launch_axpby3(s, C.n, np, C.U, C.ld, 1.0, CView{S.U2, S.ld}, 0.0, CView{}, 0.0, CView{});
@@ -756,6 +810,8 @@ static void build_coarse_inverse(Handle& h, LevelState& S) {
 
 // ---------------------------------------------------------------------------
 // Setup.
+
+static void setup_gnn(Handle& h, const mgrit_mesh& mesh, const HostPattern& pat, const mgrit_physics& ph);
 
 static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params* par) {
   if (!prob || !par) fail(MGRIT_INVALID_ARGUMENT, "null problem or params");
@@ -897,6 +953,11 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   }
   if (L > 1 && !ph.nonlinear && par->coarse_inverse && h.lv.back().n <= kMaxInverseN)
     build_coarse_inverse(h, h.lv.back());
+  if (L > 1) setup_gnn(h, prob->meshes[L - 1], pats[L - 1], ph);
+  if (par->coarse_model != 0 && par->coarse_model != 1)
+    fail(MGRIT_INVALID_ARGUMENT, "coarse_model must be 0 or 1");
+  if (par->coarse_model == 1 && !h.has_gnn)
+    fail(MGRIT_UNSUPPORTED, "the learned coarse propagator needs two or more levels and m <= 25");
   MG_HIP(hipStreamSynchronize(s));
 }
 
@@ -939,8 +1000,12 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
   }
   launch_tm_to_slabs(s, S0.n, 1, 1, h.u0_dev, S0.U, S0.ld, 0, S0.nat);
   auto t0 = std::chrono::steady_clock::now();
-  double rho0 = 0.0;
+  double rho0 = 0.0, rho_prev = 0.0;
   int status = MGRIT_OK;
+  h.learned_off = false;
+  st->coarse_fallback = -1;
+  if (h.par.coarse_model == 1 && !h.gnn.ready)
+    fail(MGRIT_INVALID_ARGUMENT, "coarse_model = 1 needs trained or set coarse weights");
   for (int it = 0;; ++it) {
     // Only the level-0 relaxation stops its solves early (eta times the
     // warm-start residual, which shrinks as MGRIT converges).  Coarse levels
@@ -961,6 +1026,13 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
     const double rho = residual_norm(h, 0);
     if (st->n_history < MGRIT_MAX_HISTORY) st->rho[st->n_history++] = rho;
     if (it == 0) rho0 = rho;
+    // the learned coarse propagator is judged by the residual: if it grows,
+    // the rest of the solve uses implicit Euler
+    if (h.par.coarse_model == 1 && !h.learned_off && it > 0 && rho > rho_prev) {
+      h.learned_off = true;
+      st->coarse_fallback = it;
+    }
+    rho_prev = rho;
     if (rho == 0.0 || rho <= h.par.tol * rho0) {
       st->converged = 1;
       break;
@@ -1103,6 +1175,464 @@ static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, co
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned coarse propagator: model set-up, training data, training.
+
+static void arena_free(Handle& h, void* p) {
+  for (size_t k = 0; k < h.arena.ptrs.size(); ++k)
+    if (h.arena.ptrs[k] == p) {
+      (void)hipFree(p);
+      h.arena.ptrs.erase(h.arena.ptrs.begin() + k);
+      return;
+    }
+}
+
+// Graph, node flags and weight storage of the coarsest level.
+static void setup_gnn(Handle& h, const mgrit_mesh& mesh, const HostPattern& pat,
+                      const mgrit_physics& ph) {
+  LevelState& C = h.lv.back();
+  GnnModel& g = h.gnn;
+  g.n = C.n;
+  g.m = h.m;
+  g.dT = C.op.dt;
+  g.off = gnn_offsets(h.m);
+  if (g.off.F > 32) return;                  // input features are padded to 32
+  hipStream_t s = h.stream;
+  const int n = C.n, W = pat.W;
+  std::vector<int> ptr(n + 1, 0), idx;
+  for (int i = 0; i < n; ++i) {
+    const size_t first = idx.size();
+    for (int k = 0; k < W; ++k) {
+      const int j = pat.col[static_cast<size_t>(i) * W + k];
+      if (j == i) continue;
+      bool seen = false;
+      for (size_t q = first; q < idx.size(); ++q) seen = seen || idx[q] == j;
+      if (!seen) idx.push_back(j);
+    }
+    if (idx.size() == first) fail(MGRIT_UNSUPPORTED, "coarsest mesh has an unknown without neighbours");
+    ptr[i + 1] = static_cast<int>(idx.size());
+  }
+  // flags per unknown: conductor, iron, coil (touches such a cell), radius
+  std::vector<float> flags(static_cast<size_t>(n) * 4, 0.f);
+  for (int t = 0; t < mesh.n_tri; ++t) {
+    const int mat = mesh.cell_mat[t];
+    const bool cond = ph.sigma[mat] > 0.0;
+    const bool iron = ph.iron && ph.iron[mat] != 0;
+    const bool coil = mesh.cell_phase[t] >= 0 && mesh.cell_sign[t] != 0;
+    for (int a = 0; a < 3; ++a) {
+      const int k = pat.index[mesh.tri[3 * t + a]];
+      if (k < 0) continue;
+      if (cond) flags[4 * k + 0] = 1.f;
+      if (iron) flags[4 * k + 1] = 1.f;
+      if (coil) flags[4 * k + 2] = 1.f;
+    }
+  }
+  const int N = mesh.n_nodes;
+  const double rin = std::hypot(mesh.xy[0], mesh.xy[1]);
+  const double rout = std::hypot(mesh.xy[2 * (N - 1)], mesh.xy[2 * (N - 1) + 1]);
+  for (int v = 0; v < N; ++v) {
+    const int k = pat.index[v];
+    if (k < 0) continue;
+    const double r = std::hypot(mesh.xy[2 * v], mesh.xy[2 * v + 1]);
+    flags[4 * k + 3] = static_cast<float>((r - rin) / (rout - rin));
+  }
+  g.gptr = upload_vec(h.arena, s, ptr);
+  g.gidx = upload_vec(h.arena, s, idx);
+  g.flags = h.arena.alloc<float>(flags.size());
+  MG_HIP(hipMemcpyAsync(g.flags, flags.data(), sizeof(float) * flags.size(), hipMemcpyHostToDevice, s));
+  g.F3 = C.op.F;
+  const size_t np = static_cast<size_t>(g.off.n_params);
+  g.w32 = h.arena.alloc<float>(np);
+  g.wbf = h.arena.alloc<uint16_t>(np);
+  g.grad = h.arena.alloc<float>(np);
+  g.m1 = h.arena.alloc<float>(np);
+  g.m2 = h.arena.alloc<float>(np);
+  MG_HIP(hipMemsetAsync(g.w32, 0, sizeof(float) * np, s));
+  MG_HIP(hipMemsetAsync(g.wbf, 0, sizeof(uint16_t) * np, s));
+  MG_HIP(hipMemsetAsync(g.grad, 0, sizeof(float) * np, s));
+  MG_HIP(hipMemsetAsync(g.m1, 0, sizeof(float) * np, s));
+  MG_HIP(hipMemsetAsync(g.m2, 0, sizeof(float) * np, s));
+  h.gnn_tmp = h.arena.alloc<double>(static_cast<size_t>(C.n) * C.ld);
+  if (h.par.coarse_model == 1) {
+    gnn_alloc_samples(g, h.arena, static_cast<int>(C.N + 1));
+    gnn_alloc_rows(g, h.arena, static_cast<int64_t>(C.n) * (C.N + 1));
+  }
+  h.has_gnn = true;
+}
+
+static void set_weights_impl(Handle& h, const float* w, int64_t count) {
+  if (!h.has_gnn) fail(MGRIT_UNSUPPORTED, "no learned coarse propagator on this hierarchy");
+  GnnModel& g = h.gnn;
+  if (!w || count != g.off.n_params) fail(MGRIT_INVALID_ARGUMENT, "weight vector size");
+  if (!(w[0] > 0.f) || !(w[1] > 0.f) || !(w[2] > 0.f)) fail(MGRIT_INVALID_ARGUMENT, "scales must be > 0");
+  hipStream_t s = h.stream;
+  const size_t np = static_cast<size_t>(count);
+  MG_HIP(hipMemcpyAsync(g.w32, w, sizeof(float) * np, hipMemcpyHostToDevice, s));
+  MG_HIP(hipMemsetAsync(g.m1, 0, sizeof(float) * np, s));
+  MG_HIP(hipMemsetAsync(g.m2, 0, sizeof(float) * np, s));
+  g.adam_step = 0;
+  gnn_round_weights(s, g);
+  MG_HIP(hipStreamSynchronize(s));
+  g.ready = true;
+}
+
+// Host rows [B][n] (user order) of up to three arrays -> dense [n][B] (internal order).
+struct GnnStaging {
+  Handle& h;
+  std::vector<void*> bufs;
+  explicit GnnStaging(Handle& hh) : h(hh) {}
+  template <class T>
+  T* alloc(size_t n) {
+    T* p = h.arena.alloc<T>(n);
+    bufs.push_back(p);
+    return p;
+  }
+  ~GnnStaging() {
+    (void)hipStreamSynchronize(h.stream);
+    for (void* p : bufs) arena_free(h, p);
+  }
+};
+
+static double* stage_rows(GnnStaging& st, const double* host, int B, int n, const int* nat) {
+  hipStream_t s = st.h.stream;
+  double* tm = st.alloc<double>(static_cast<size_t>(B) * n);
+  double* cols = st.alloc<double>(static_cast<size_t>(B) * n);
+  MG_HIP(hipMemcpyAsync(tm, host, sizeof(double) * B * n, hipMemcpyHostToDevice, s));
+  launch_tm_to_slabs(s, n, B, 1, tm, cols, B, 0, nat);
+  return cols;
+}
+
+// Forward (and optionally backward) of the network on host samples.
+static void coarse_eval_impl(Handle& h, int B, const int64_t* k, const double* amp, const double* dphi,
+                             const double* u, const double* p, const double* y, double* psi_out,
+                             double* loss, float* grad) {
+  if (!h.has_gnn) fail(MGRIT_UNSUPPORTED, "no learned coarse propagator on this hierarchy");
+  GnnModel& g = h.gnn;
+  if (!g.ready) fail(MGRIT_INVALID_ARGUMENT, "coarse weights are not set");
+  if (B < 1 || !k || !u || !p) fail(MGRIT_INVALID_ARGUMENT, "coarse model arguments");
+  LevelState& C = h.lv.back();
+  hipStream_t s = h.stream;
+  const int n = C.n;
+  gnn_alloc_samples(g, h.arena, B);
+  gnn_alloc_rows(g, h.arena, static_cast<int64_t>(n) * B);
+  GnnStaging st(h);
+  double* uc = stage_rows(st, u, B, n, C.nat);
+  double* pc = stage_rows(st, p, B, n, C.nat);
+  int64_t* kd = st.alloc<int64_t>(B);
+  MG_HIP(hipMemcpyAsync(kd, k, sizeof(int64_t) * B, hipMemcpyHostToDevice, s));
+  double *ad = nullptr, *dd = nullptr;
+  if (amp) {
+    ad = st.alloc<double>(B);
+    MG_HIP(hipMemcpyAsync(ad, amp, sizeof(double) * B, hipMemcpyHostToDevice, s));
+  }
+  if (dphi) {
+    dd = st.alloc<double>(B);
+    MG_HIP(hipMemcpyAsync(dd, dphi, sizeof(double) * B, hipMemcpyHostToDevice, s));
+  }
+  double* psi = st.alloc<double>(static_cast<size_t>(n) * B);
+  const bool train = (y != nullptr);
+  gnn_forward(s, g, h.src, B, kd, 0, 0, ad, dd, CView{uc, B}, CView{pc, B}, psi, B, train);
+  if (train) {
+    double* yc = stage_rows(st, y, B, n, C.nat);
+    double* ld = st.alloc<double>(1);
+    MG_HIP(hipMemsetAsync(ld, 0, sizeof(double), s));
+    MG_HIP(hipMemsetAsync(g.grad, 0, sizeof(float) * g.off.n_params, s));
+    gnn_backward(s, g, B, psi, yc, ld);
+    double lsum = 0.0;
+    MG_HIP(hipMemcpyAsync(&lsum, ld, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (grad) MG_HIP(hipMemcpyAsync(grad, g.grad, sizeof(float) * g.off.n_params, hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = lsum / (static_cast<double>(n) * B);
+  }
+  if (psi_out) {
+    double* tm = st.alloc<double>(static_cast<size_t>(B) * n);
+    launch_slabs_to_tm(s, n, B, 1, psi, B, 0, tm, C.nat);
+    MG_HIP(hipMemcpyAsync(psi_out, tm, sizeof(double) * B * n, hipMemcpyDeviceToHost, s));
+  }
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+static void coarse_adam_impl(Handle& h, const float* grad, double lr) {
+  if (!h.has_gnn || !h.gnn.ready) fail(MGRIT_INVALID_ARGUMENT, "coarse weights are not set");
+  if (!grad || !(lr > 0.0)) fail(MGRIT_INVALID_ARGUMENT, "coarse Adam arguments");
+  GnnModel& g = h.gnn;
+  hipStream_t s = h.stream;
+  MG_HIP(hipMemcpyAsync(g.grad, grad, sizeof(float) * g.off.n_params, hipMemcpyHostToDevice, s));
+  gnn_adam(s, g, lr, ++g.adam_step);
+  MG_HIP(hipStreamSynchronize(s));
+}
+
+static uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+static double uniform01(uint64_t& x) { return static_cast<double>(splitmix64(x) >> 11) * 0x1.0p-53; }
+
+// Training data from the level above the coarsest (its own propagator, m of
+// its steps per coarse step, restricted to the coarse mesh), implicit-Euler
+// predictions on the coarsest level, then Adam on the scaled squared error.
+static void train_impl(Handle& h, const mgrit_train_params* tp, mgrit_train_stats* ts) {
+  if (!tp || !ts) fail(MGRIT_INVALID_ARGUMENT, "null training parameters or statistics");
+  if (h.lv.size() < 2 || !h.has_gnn) fail(MGRIT_UNSUPPORTED, "no learned coarse propagator on this hierarchy");
+  if (tp->n_traj < 2 || tp->epochs < 1 || tp->batch < 1 || !(tp->lr > 0.0) ||
+      !(tp->perturb >= 0.0 && tp->perturb <= 1.0) ||
+      !(tp->amp_spread >= 0.0 && tp->amp_spread < 1.0) ||
+      !(tp->val_fraction >= 0.0 && tp->val_fraction < 1.0))
+    fail(MGRIT_INVALID_ARGUMENT, "bad training parameters");
+  *ts = mgrit_train_stats{};
+  h.st = nullptr;
+  h.tol_now = h.par.pcg_tol;
+  h.eta_now = 0.0;
+  hipStream_t s = h.stream;
+  const int L = static_cast<int>(h.lv.size());
+  LevelState& C = h.lv[L - 1];
+  LevelState& Gl = h.lv[L - 2];
+  GnnModel& g = h.gnn;
+  const int nt = tp->n_traj, m = h.m, n = C.n;
+  const int64_t Nc = C.N;
+  auto t0 = std::chrono::steady_clock::now();
+  GnnStaging st(h);
+
+  // per-trajectory source amplitude factors and phase shifts
+  uint64_t rng = tp->seed;
+  std::vector<double> amp(nt), dphi(nt);
+  for (int b = 0; b < nt; ++b) {
+    amp[b] = 1.0 + tp->amp_spread * (2.0 * uniform01(rng) - 1.0);
+    dphi[b] = 6.283185307179586 * (uniform01(rng) - 0.5);
+  }
+  double* amp_d = st.alloc<double>(nt);
+  double* dphi_d = st.alloc<double>(nt);
+  MG_HIP(hipMemcpyAsync(amp_d, amp.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+  MG_HIP(hipMemcpyAsync(dphi_d, dphi.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+
+  // trajectories on the generating level: at every coarse step the state is
+  // moved towards another trajectory's by alpha in [-perturb, perturb] (so
+  // that pairs also sample how deviations propagate), restricted, advanced
+  // by m steps and restricted again: the pair (input, target)
+  const int64_t ldt = round_up(nt, kWave);
+  double* X = st.alloc<double>(static_cast<size_t>(Gl.n) * ldt);
+  double* Xn = st.alloc<double>(static_cast<size_t>(Gl.n) * ldt);
+  MG_HIP(hipMemsetAsync(X, 0, sizeof(double) * Gl.n * ldt, s));
+  const int64_t nq = Nc * nt;
+  const int64_t ldD = round_up(nq, kWave);
+  double* D = st.alloc<double>(static_cast<size_t>(n) * ldD);   // inputs
+  double* Y = st.alloc<double>(static_cast<size_t>(n) * ldD);   // targets
+  double* P = st.alloc<double>(static_cast<size_t>(n) * ldD);   // implicit Euler of the inputs
+  int* perm_d = st.alloc<int>(nt);
+  double* alpha_d = st.alloc<double>(nt);
+  std::vector<int> perm(nt);
+  std::vector<double> alpha(nt);
+  PcgWork gw, cw;
+  alloc_pcg(h, gw, Gl.n, nt, Gl.pcg.rows_per_block, Gl.prec);
+  gw.cpl = Gl.pcg.cpl;
+  gw.dia = Gl.pcg.dia;
+  alloc_pcg(h, cw, C.n, nt, C.pcg.rows_per_block, C.prec);
+  cw.cpl = C.pcg.cpl;
+  cw.dia = C.pcg.dia;
+  h.col_amp = amp_d;
+  h.col_dphi = dphi_d;
+  struct Reset {
+    Handle& h;
+    ~Reset() { h.col_amp = h.col_dphi = nullptr; }
+  } reset{h};
+  auto restrict_to = [&](const double* src, double* dst) {
+    if (Gl.has_transfer) launch_transfer(s, Gl.R, nt, CView{src, ldt}, 1.0, dst, ldD, 0.0);
+    else launch_axpby3(s, n, nt, dst, ldD, 1.0, CView{src, ldt}, 0.0, CView{}, 0.0, CView{});
+  };
+  for (int64_t k = 0; k < Nc; ++k) {
+    if (tp->perturb > 0.0 && k > 0) {
+      for (int b = 0; b < nt; ++b) {
+        perm[b] = static_cast<int>(splitmix64(rng) % static_cast<uint64_t>(nt));
+        alpha[b] = tp->perturb * (2.0 * uniform01(rng) - 1.0);
+      }
+      MG_HIP(hipStreamSynchronize(s));      // the previous step's perm / alpha are consumed
+      MG_HIP(hipMemcpyAsync(perm_d, perm.data(), sizeof(int) * nt, hipMemcpyHostToDevice, s));
+      MG_HIP(hipMemcpyAsync(alpha_d, alpha.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
+      gnn_mix(s, Gl.n, nt, X, ldt, perm_d, alpha_d, Xn);
+      std::swap(X, Xn);
+    }
+    restrict_to(X, D + k * nt);
+    for (int j = 0; j < m; ++j) {
+      PhiCall c;
+      c.ncols = nt;
+      c.in = CView{X, ldt};
+      c.t_base = k * m + j;
+      c.t_stride = 0;
+      c.ga = c.in;
+      c.out = Xn;
+      c.ldo = ldt;
+      phi_batch(h, L - 2, gw, c);
+      std::swap(X, Xn);
+    }
+    restrict_to(X, Y + k * nt);
+  }
+  for (int64_t k = 0; k < Nc; ++k) {
+    PhiCall c;
+    c.ncols = nt;
+    c.in = CView{D + k * nt, ldD};
+    c.t_base = k;
+    c.t_stride = 0;
+    c.ga = c.in;
+    c.out = P + k * nt;
+    c.ldo = ldD;
+    phi_batch(h, L - 1, cw, c);
+  }
+  h.col_amp = h.col_dphi = nullptr;
+  MG_HIP(hipStreamSynchronize(s));
+  auto t1 = std::chrono::steady_clock::now();
+  ts->time_data_s = std::chrono::duration<double>(t1 - t0).count();
+
+  // samples q = k nt + b: u = D[q], p = P[q], y = Y[q]
+  const int ntr_traj = std::max(1, nt - static_cast<int>(std::lround(tp->val_fraction * nt)));
+  std::vector<int64_t> k_all(nq), train, val;
+  std::vector<double> amp_all(nq), dphi_all(nq);
+  for (int64_t q = 0; q < nq; ++q) {
+    const int b = static_cast<int>(q % nt);
+    k_all[q] = q / nt;
+    amp_all[q] = amp[b];
+    dphi_all[q] = dphi[b];
+    (b < ntr_traj ? train : val).push_back(q);
+  }
+  int64_t* k_all_d = st.alloc<int64_t>(nq);
+  double* amp_all_d = st.alloc<double>(nq);
+  double* dphi_all_d = st.alloc<double>(nq);
+  MG_HIP(hipMemcpyAsync(k_all_d, k_all.data(), sizeof(int64_t) * nq, hipMemcpyHostToDevice, s));
+  MG_HIP(hipMemcpyAsync(amp_all_d, amp_all.data(), sizeof(double) * nq, hipMemcpyHostToDevice, s));
+  MG_HIP(hipMemcpyAsync(dphi_all_d, dphi_all.data(), sizeof(double) * nq, hipMemcpyHostToDevice, s));
+
+  // scales: RMS state, peak nodal forcing, RMS implicit-Euler error
+  double* csum = st.alloc<double>(static_cast<size_t>(nq));
+  std::vector<double> hs(nq);
+  gnn_colsq(s, n, static_cast<int>(nq), Y, nullptr, ldD, csum);
+  MG_HIP(hipMemcpyAsync(hs.data(), csum, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  double su2 = 0.0;
+  for (int64_t q : train) su2 += hs[q];
+  gnn_colsq(s, n, static_cast<int>(nq), Y, P, ldD, csum);
+  MG_HIP(hipMemcpyAsync(hs.data(), csum, sizeof(double) * nq, hipMemcpyDeviceToHost, s));
+  std::vector<double> F3(3 * static_cast<size_t>(n));
+  MG_HIP(hipMemcpyAsync(F3.data(), C.op.F, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  double so2 = 0.0;
+  for (int64_t q : train) so2 += hs[q];
+  double fmax = 0.0;
+  for (int i = 0; i < n; ++i)
+    fmax = std::max(fmax, std::fabs(F3[i]) + std::fabs(F3[n + i]) + std::fabs(F3[2 * n + i]));
+  const double cnt = static_cast<double>(train.size()) * n;
+  const float s_u = static_cast<float>(std::sqrt(su2 / cnt));
+  const float s_f = static_cast<float>(h.src.scale * (1.0 + tp->amp_spread) * fmax);
+  const float s_out = static_cast<float>(std::sqrt(so2 / cnt));
+  if (!(s_u > 0.f) || !(s_f > 0.f) || !(s_out > 0.f))
+    fail(MGRIT_INVALID_ARGUMENT, "training data are identically zero (no source?)");
+
+  // initial weights: Glorot-uniform hidden matrices, zero biases and output
+  {
+    const GnnOffsets& o = g.off;
+    std::vector<float> w(static_cast<size_t>(o.n_params), 0.f);
+    w[0] = s_u;
+    w[1] = s_f;
+    w[2] = s_out;
+    uint64_t wr = tp->seed ^ 0x5DEECE66Dull;
+    auto glorot = [&](int64_t off, int fan_in, int fan_out) {
+      const double lim = std::sqrt(6.0 / (fan_in + fan_out));
+      for (int64_t e = 0; e < static_cast<int64_t>(fan_in) * fan_out; ++e)
+        w[off + e] = static_cast<float>(lim * (2.0 * uniform01(wr) - 1.0));
+    };
+    glorot(o.w_in, o.F, 64);
+    for (int l = 0; l < 3; ++l) {
+      glorot(o.ws[l], 64, 64);
+      glorot(o.wn[l], 64, 64);
+    }
+    set_weights_impl(h, w.data(), o.n_params);
+  }
+
+  // Adam over shuffled minibatches, cosine decay of the rate to lr/10
+  const int S = static_cast<int>(std::min<int64_t>(tp->batch, static_cast<int64_t>(train.size())));
+  const int64_t spe = static_cast<int64_t>(train.size()) / S;
+  gnn_alloc_samples(g, h.arena, S);
+  gnn_alloc_rows(g, h.arena, static_cast<int64_t>(n) * S);
+  double* Ub = st.alloc<double>(static_cast<size_t>(n) * S);
+  double* Pb = st.alloc<double>(static_cast<size_t>(n) * S);
+  double* Yb = st.alloc<double>(static_cast<size_t>(n) * S);
+  double* Psib = st.alloc<double>(static_cast<size_t>(n) * S);
+  int64_t* idx_d = st.alloc<int64_t>(static_cast<size_t>(spe) * S);
+  int64_t* k_b = st.alloc<int64_t>(S);
+  double* amp_b = st.alloc<double>(S);
+  double* dphi_b = st.alloc<double>(S);
+  double* loss_d = st.alloc<double>(tp->epochs);
+  MG_HIP(hipMemsetAsync(loss_d, 0, sizeof(double) * tp->epochs, s));
+  const int64_t total = spe * tp->epochs;
+  int64_t step = 0;
+  std::vector<int64_t> order(train);
+  uint64_t sh = tp->seed ^ 0x9E3779B97F4A7C15ull;
+  for (int e = 0; e < tp->epochs; ++e) {
+    for (int64_t i = static_cast<int64_t>(order.size()) - 1; i > 0; --i) {
+      const int64_t j = static_cast<int64_t>(splitmix64(sh) % static_cast<uint64_t>(i + 1));
+      std::swap(order[i], order[j]);
+    }
+    MG_HIP(hipStreamSynchronize(s));          // the previous epoch's indices are consumed
+    MG_HIP(hipMemcpyAsync(idx_d, order.data(), sizeof(int64_t) * spe * S, hipMemcpyHostToDevice, s));
+    for (int64_t b = 0; b < spe; ++b, ++step) {
+      const int64_t* ib = idx_d + b * S;
+      gnn_gather(s, n, S, ib, D, ldD, Ub);
+      gnn_gather(s, n, S, ib, P, ldD, Pb);
+      gnn_gather(s, n, S, ib, Y, ldD, Yb);
+      gnn_gather_meta(s, S, ib, k_all_d, amp_all_d, dphi_all_d, k_b, amp_b, dphi_b);
+      const double lr = tp->lr * (0.1 + 0.45 * (1.0 + std::cos(3.141592653589793 * step / total)));
+      gnn_forward(s, g, h.src, S, k_b, 0, 0, amp_b, dphi_b, CView{Ub, S}, CView{Pb, S}, Psib, S, true);
+      MG_HIP(hipMemsetAsync(g.grad, 0, sizeof(float) * g.off.n_params, s));
+      gnn_backward(s, g, S, Psib, Yb, loss_d + e);
+      gnn_adam(s, g, lr, ++g.adam_step);
+    }
+  }
+  std::vector<double> losses(tp->epochs);
+  MG_HIP(hipMemcpyAsync(losses.data(), loss_d, sizeof(double) * tp->epochs, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  const double per_epoch = static_cast<double>(spe) * S * n;
+  ts->loss_first = losses.front() / per_epoch;
+  ts->loss_last = losses.back() / per_epoch;
+
+  // relative errors of implicit Euler and of the learned step on both sets
+  auto evaluate = [&](const std::vector<int64_t>& list, double& err_ie, double& err_l) {
+    double se = 0.0, sl = 0.0, sd = 0.0;
+    std::vector<double> a(S), b2(S), c(S);
+    double* cs = st.alloc<double>(3 * static_cast<size_t>(S));
+    for (size_t q0 = 0; q0 < list.size(); q0 += S) {
+      const int B = static_cast<int>(std::min<size_t>(S, list.size() - q0));
+      MG_HIP(hipStreamSynchronize(s));
+      MG_HIP(hipMemcpyAsync(idx_d, list.data() + q0, sizeof(int64_t) * B, hipMemcpyHostToDevice, s));
+      gnn_gather(s, n, B, idx_d, D, ldD, Ub);
+      gnn_gather(s, n, B, idx_d, P, ldD, Pb);
+      gnn_gather(s, n, B, idx_d, Y, ldD, Yb);
+      gnn_gather_meta(s, B, idx_d, k_all_d, amp_all_d, dphi_all_d, k_b, amp_b, dphi_b);
+      gnn_forward(s, g, h.src, B, k_b, 0, 0, amp_b, dphi_b, CView{Ub, B}, CView{Pb, B}, Psib, B, false);
+      gnn_colsq(s, n, B, Pb, Yb, B, cs);
+      gnn_colsq(s, n, B, Psib, Yb, B, cs + S);
+      gnn_colsq(s, n, B, Yb, Ub, B, cs + 2 * S);
+      MG_HIP(hipMemcpyAsync(a.data(), cs, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+      MG_HIP(hipMemcpyAsync(b2.data(), cs + S, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+      MG_HIP(hipMemcpyAsync(c.data(), cs + 2 * S, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+      MG_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < B; ++q) {
+        se += a[q];
+        sl += b2[q];
+        sd += c[q];
+      }
+    }
+    err_ie = sd > 0.0 ? std::sqrt(se / sd) : 0.0;
+    err_l = sd > 0.0 ? std::sqrt(sl / sd) : 0.0;
+  };
+  evaluate(train, ts->train_err_ie, ts->train_err_learned);
+  evaluate(val, ts->val_err_ie, ts->val_err_learned);
+  ts->n_train = static_cast<int64_t>(train.size());
+  ts->n_val = static_cast<int64_t>(val.size());
+  ts->steps = total;
+  ts->time_train_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+}
+
 }  // namespace mg
 
 // ---------------------------------------------------------------------------
@@ -1219,6 +1749,61 @@ int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int6
     kernel_shape[2] = S.pcg.dia ? 2 : 1;
   }
   return MGRIT_OK;
+}
+
+int mgrit_train_coarse(void* hp, const mgrit_train_params* tp, mgrit_train_stats* ts) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] { mg::train_impl(*h, tp, ts); });
+}
+
+int64_t mgrit_coarse_n_params(void* hp) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  return (h && h->has_gnn) ? h->gnn.off.n_params : 0;
+}
+
+int mgrit_set_coarse_weights(void* hp, const float* w, int64_t n) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] { mg::set_weights_impl(*h, w, n); });
+}
+
+int mgrit_get_coarse_weights(void* hp, float* w, int64_t n) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] {
+    if (!h->has_gnn) mg::fail(MGRIT_UNSUPPORTED, "no learned coarse propagator on this hierarchy");
+    if (!w || n != h->gnn.off.n_params) mg::fail(MGRIT_INVALID_ARGUMENT, "weight vector size");
+    MG_HIP(hipMemcpyAsync(w, h->gnn.w32, sizeof(float) * n, hipMemcpyDeviceToHost, h->stream));
+    MG_HIP(hipStreamSynchronize(h->stream));
+  });
+}
+
+int mgrit_coarse_apply(void* hp, int32_t B, const int64_t* k, const double* amp, const double* dphi,
+                       const double* u, const double* p, double* psi) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] {
+    if (!psi) mg::fail(MGRIT_INVALID_ARGUMENT, "psi is null");
+    mg::coarse_eval_impl(*h, B, k, amp, dphi, u, p, nullptr, psi, nullptr, nullptr);
+  });
+}
+
+int mgrit_coarse_gradient(void* hp, int32_t B, const int64_t* k, const double* amp,
+                          const double* dphi, const double* u, const double* p, const double* y,
+                          double* loss, float* grad) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] {
+    if (!y || !loss || !grad) mg::fail(MGRIT_INVALID_ARGUMENT, "y, loss and grad are required");
+    mg::coarse_eval_impl(*h, B, k, amp, dphi, u, p, y, nullptr, loss, grad);
+  });
+}
+
+int mgrit_coarse_adam(void* hp, const float* grad, double lr) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] { mg::coarse_adam_impl(*h, grad, lr); });
 }
 
 void mgrit_destroy(void* hp) {

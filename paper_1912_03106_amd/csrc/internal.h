@@ -170,9 +170,11 @@ void launch_load_vectors(hipStream_t s, const DevLevel& L, const int* cptr, cons
                          const int* cell_sign);
 
 // --- batched Phi / PCG kernels (FP64) ---------------------------------------
+// amp / dphi: optional per-column amplitude factors and phase shifts
 void launch_source_table(hipStream_t s, const SourceDev& src, double dt, int ncols,
                          const int64_t* t_list, int64_t t_base, int64_t t_stride,
-                         double* table, int64_t ld);
+                         double* table, int64_t ld, const double* amp = nullptr,
+                         const double* dphi = nullptr);
 void launch_axpby3(hipStream_t s, int n, int ncols, double* out, int64_t ldo, double sx,
                    CView x, double sa, CView a, double sb, CView b);
 void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in);
@@ -218,10 +220,6 @@ void launch_slabs_to_cols(hipStream_t s, int n, int64_t npts, int m, const doubl
 
 // Columns j0 .. j0+ncols-1 of the identity as CG right-hand sides (x = 0).
 void launch_cg_init_identity(hipStream_t s, const DevLevel& L, PcgWork& w, int j0, int ncols);
-// One coarse step with a stored inverse: U[:, step] = Ainv ((M/dt) U[:, step-1] + f(t)) + G[:, step].
-void launch_coarse_step(hipStream_t s, const DevLevel& L, const SourceDev& src, double t,
-                        double* U, int64_t ldu, int step, const double* G, int64_t ldg,
-                        const double* Ainv, int64_t lda, double* b);
 
 // Cooperative sequential stepper: steps s_begin .. s_end-1 of U[:, s] =
 // Phi(U[:, s-1]) on `blocks` co-resident work-groups.  ws: [5n] doubles,
@@ -238,5 +236,72 @@ void launch_seq_coop(hipStream_t s, const DevLevel& L, const SourceDev& src, int
 void launch_seq_small(hipStream_t s, const DevLevel& L, const SourceDev& src, int nsteps,
                       int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
                       double* ws, double tol, int maxit, int warm, int* flags);
+
+// ---------------------------------------------------------------------------
+// Learned coarse propagator (gnn.hip).  Weight blob (FP32 master, used as
+// bf16): [s_u, s_f, s_out, 0], W_in [F][64], b_in [64], per layer Ws [64][64],
+// Wn [64][64], b [64], then w_out [64], b_out [1]; F = m + 7 features.
+struct GnnOffsets {
+  int F = 0;
+  int64_t w_in = 0, b_in = 0, ws[3] = {0, 0, 0}, wn[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+  int64_t w_out = 0, b_out = 0, n_params = 0;
+};
+GnnOffsets gnn_offsets(int m);
+
+struct GnnModel {
+  int n = 0, m = 0;
+  double dT = 0.0;              // coarse step
+  GnnOffsets off;
+  int* gptr = nullptr;          // [n+1] neighbour lists (internal numbering)
+  int* gidx = nullptr;
+  float* flags = nullptr;       // [n][4] conductor, iron, coil, normalised radius
+  const double* F3 = nullptr;   // [3][n] phase load vectors of the level
+  float* w32 = nullptr;         // [n_params] master weights
+  uint16_t* wbf = nullptr;      // [n_params] bf16 copies
+  float* grad = nullptr;        // [n_params]
+  float *m1 = nullptr, *m2 = nullptr;   // Adam moments
+  int adam_step = 0;
+  bool ready = false;           // weights set or trained
+  // activations (rows = n * samples)
+  int64_t rows_cap = 0;
+  int s_cap = 0;
+  float* h[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* a[3] = {nullptr, nullptr, nullptr};
+  float* t[3] = {nullptr, nullptr, nullptr};
+  float *x = nullptr, *g0 = nullptr, *g1 = nullptr, *dz = nullptr, *y = nullptr, *dd = nullptr;
+  float *part_w = nullptr, *part_b = nullptr;
+  double* part_loss = nullptr;
+  double* tab = nullptr;        // [S][m+1][3] source samples
+};
+
+struct DeviceArena;
+void gnn_alloc_rows(GnnModel& g, DeviceArena& arena, int64_t rows);
+void gnn_alloc_samples(GnnModel& g, DeviceArena& arena, int S);
+void gnn_round_weights(hipStream_t s, GnnModel& g);
+// out(i, s) = p(i, s) + s_out delta for S samples with input coarse steps
+// k_list[s] (or k_base + s k_stride); keep = store activations for backward
+void gnn_forward(hipStream_t s, GnnModel& g, const SourceDev& src, int S, const int64_t* k_list,
+                 int64_t k_base, int64_t k_stride, const double* amp, const double* dphi,
+                 CView u, CView p, double* out, int64_t ldo, bool keep);
+// loss of the last forward (psi, y dense [n][S]) added to *loss_acc; gradients into g.grad
+void gnn_backward(hipStream_t s, GnnModel& g, int S, const double* psi, const double* y,
+                  double* loss_acc);
+void gnn_adam(hipStream_t s, GnnModel& g, double lr, int step);
+void gnn_gather(hipStream_t s, int n, int S, const int64_t* idx, const double* src, int64_t ld,
+                double* dst);
+void gnn_gather_meta(hipStream_t s, int S, const int64_t* idx, const int64_t* k_all,
+                     const double* amp_all, const double* dphi_all, int64_t* k_b, double* amp_b,
+                     double* dphi_b);
+// Implicit Euler with a stored inverse for ncols columns: B = (M/dt) u + f
+// (f from the source table src[3][lds]), X = Ainv B; B and X are [n][ld].
+void launch_ie_inverse_batch(hipStream_t s, const DevLevel& L, int ncols, const double* src, int64_t lds,
+                             CView u, const double* Ainv, int64_t lda, double* B, double* X,
+                             int64_t ld);
+// Y[:, b] = X[:, b] + alpha[b] (X[:, perm[b]] - X[:, b]), b < nt (Y != X)
+void gnn_mix(hipStream_t s, int n, int nt, const double* X, int64_t ld, const int* perm,
+             const double* alpha, double* Y);
+// out[c] = sum_i (a - b)^2 (b may be null) over the n rows of column c
+void gnn_colsq(hipStream_t s, int n, int ncols, const double* a, const double* b, int64_t ld,
+               double* out);
 
 }  // namespace mg

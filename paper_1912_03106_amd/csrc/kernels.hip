@@ -20,6 +20,7 @@
 #include <cstdlib>
 
 #include "internal.h"
+#include "source_dev.h"
 
 namespace mg {
 
@@ -43,29 +44,6 @@ __device__ __forceinline__ void tile_decode(int w, int nrb, int ncc, int& rb, in
     rb = w / ncc;
   }
   (void)nrb;
-}
-
-// PWM signal b_p(t) = sgn(sin(2 pi f t + phi_p) - c(t)) (Sec. 3.2, 3.3).
-// A difference within 1e-12 of zero is a tie (sgn = 0): the time grids hit
-// r = c exactly (reference and carrier both at their peak 1 at t = T/4), and
-// the last ulp of the sine must not decide the sign there.
-__device__ __forceinline__ double pwm(double t, const SourceDev& s, int p) {
-  const double two_pi = 6.283185307179586;  // 2*pi rounded to double
-  const double ref = sin(two_pi * s.freq * t + s.phi[p]);
-  const double x = s.f_carrier * t;
-  const double c = (s.carrier == 0) ? 1.0 - 4.0 * fabs(x - floor(x + 0.5))
-                                    : 2.0 * (x - floor(x)) - 1.0;
-  const double d = ref - c;
-  return d > 1e-12 ? 1.0 : (d < -1e-12 ? -1.0 : 0.0);
-}
-
-// Amplitude of the coil current density at time t: J0 * amplitude, times the
-// start-up factor (1 - cos(pi t / span)) / 2 while t < span (nonlinear
-// model, Sec. 3.3).
-__device__ __forceinline__ double source_scale(double t, const SourceDev& s) {
-  if (s.ramp_span > 0.0 && t < s.ramp_span)
-    return s.scale * (0.5 * (1.0 - cos(3.141592653589793 * t / s.ramp_span)));
-  return s.scale;
 }
 
 // Sum the per-lane values v[0..NQ) of the 4 waves of a work-group in a fixed
@@ -167,17 +145,23 @@ __global__ void k_load_vectors(int n, int W, const int* __restrict__ cptr,
 // ----------------------------------------------------------------------------
 // Batched Phi / PCG.
 
-// table[p][c] = J0*amp * b_p(t) at the new time t = (i_from(c) + 1) * dt.
+// table[p][c] = J0*amp * b_p(t) at the new time t = (i_from(c) + 1) * dt;
+// optional per-column amplitude factors and phase shifts (training data).
 __global__ void k_source_table(SourceDev s, double dt, int ncols, const int64_t* __restrict__ t_list,
-                               int64_t t_base, int64_t t_stride, double* __restrict__ table,
+                               int64_t t_base, int64_t t_stride, const double* __restrict__ amp,
+                               const double* __restrict__ dphi, double* __restrict__ table,
                                int64_t ld) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols) return;
   const int64_t i_from = t_list ? t_list[c] : t_base + static_cast<int64_t>(c) * t_stride;
   const double t = static_cast<double>(i_from + 1) * dt;
-  const double a = source_scale(t, s);
+  SourceDev sc = s;
+  if (amp) sc.scale *= amp[c];
+  if (dphi)
+    for (int p = 0; p < 3; ++p) sc.phi[p] += dphi[c];
+  const double a = source_scale(t, sc);
 #pragma unroll
-  for (int p = 0; p < 3; ++p) table[p * ld + c] = a * pwm(t, s, p);
+  for (int p = 0; p < 3; ++p) table[p * ld + c] = a * pwm(t, sc, p);
 }
 
 __global__ void k_axpby3(int n, int ncols, double* __restrict__ out, int64_t ldo, double sx,
@@ -433,48 +417,38 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_small(
   if (threadIdx.x == 0) atomicAdd(flags + 2, total_iters);
 }
 
-// Coarsest level with a stored inverse (linear model).  One step:
-//   b = (M/dt) U[:, s-1] + f(t_s);   U[:, s] = A^{-1} b + G[:, s].
-__global__ void k_coarse_rhs(int n, int W, const int* __restrict__ col,
-                             const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
-                             const double* __restrict__ F, SourceDev src, double t,
-                             const double* __restrict__ U, int64_t ldu, int s,
-                             double* __restrict__ b) {
-  __shared__ double sg[3];
-  if (threadIdx.x == 0) {
-    const double amp = source_scale(t, src);
-    for (int p = 0; p < 3; ++p) sg[p] = amp * pwm(t, src, p);
-  }
-  __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Batched implicit-Euler right-hand sides b[i][c] = (M/dt) u[:, c] + f_c
+// (f from the per-column source table src[3][ld]).
+__global__ void k_ie_rhs_batch(int n, int W, int ncols, const int* __restrict__ col,
+                               const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+                               const double* __restrict__ F, const double* __restrict__ src,
+                               int64_t lds, const double* __restrict__ U, int64_t ldu,
+                               double* __restrict__ B, int64_t ldb) {
+  const int c = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (c >= ncols || i >= n) return;
   double bv = 0.0;
-  if (has_mass[i]) {
+  if (has_mass[i])
     for (int k = 0; k < W; ++k)
-      bv += mm[static_cast<int64_t>(i) * W + k] * U[col[static_cast<int64_t>(i) * W + k] * ldu + s - 1];
-  }
-  bv += (sg[0] * F[i] + sg[1] * F[n + i]) + sg[2] * F[2 * n + i];
-  b[i] = bv;
+      bv += mm[static_cast<int64_t>(i) * W + k] * U[col[static_cast<int64_t>(i) * W + k] * ldu + c];
+  bv += (src[c] * F[i] + src[lds + c] * F[n + i]) + src[2 * lds + c] * F[2 * n + i];
+  B[i * ldb + c] = bv;
 }
 
-// y_i = sum_j Ainv[i][j] b_j (+ g_i): one wave per row, lanes stride over j,
-// fixed butterfly.  Ainv is symmetric, stored [n][lda].
-__global__ __launch_bounds__(kBlock) void k_coarse_gemv(int n, const double* __restrict__ Ainv,
-                                                        int64_t lda, const double* __restrict__ b,
-                                                        double* __restrict__ U, int64_t ldu, int s,
-                                                        const double* __restrict__ G, int64_t ldg) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wave_index();
+// X[i][c] = sum_j Ainv[i][j] B[j][c]: a wave per (row, 64 columns); the
+// row of Ainv is wave-uniform, the columns of B coalesced.
+__global__ __launch_bounds__(kBlock) void k_inv_apply(int n, int ncols, const double* __restrict__ Ainv,
+                                                      int64_t lda, const double* __restrict__ B,
+                                                      int64_t ldb, double* __restrict__ X,
+                                                      int64_t ldx) {
+  const int c = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + wave_index();
   if (i >= n) return;
   const double* row = Ainv + static_cast<int64_t>(i) * lda;
   double acc = 0.0;
-  for (int j = lane; j < n; j += kWave) acc += row[j] * b[j];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) {
-    double v = acc;
-    if (G) v += G[i * ldg + s];
-    U[i * ldu + s] = v;
-  }
+  if (c < ncols)
+    for (int j = 0; j < n; ++j) acc += row[j] * B[static_cast<int64_t>(j) * ldb + c];
+  if (c < ncols) X[i * ldx + c] = acc;
 }
 
 // ----------------------------------------------------------------------------
@@ -735,10 +709,10 @@ void launch_load_vectors(hipStream_t s, const DevLevel& L, const int* cptr, cons
 
 void launch_source_table(hipStream_t s, const SourceDev& src, double dt, int ncols,
                          const int64_t* t_list, int64_t t_base, int64_t t_stride, double* table,
-                         int64_t ld) {
+                         int64_t ld, const double* amp, const double* dphi) {
   if (ncols <= 0) return;
   hipLaunchKernelGGL(k_source_table, dim3(ceil_div(ncols, 256)), dim3(256), 0, s, src, dt, ncols,
-                     t_list, t_base, t_stride, table, ld);
+                     t_list, t_base, t_stride, amp, dphi, table, ld);
   MG_HIP(hipGetLastError());
 }
 
@@ -819,13 +793,14 @@ void launch_slabs_to_cols(hipStream_t s, int n, int64_t npts, int m, const doubl
   MG_HIP(hipGetLastError());
 }
 
-void launch_coarse_step(hipStream_t s, const DevLevel& L, const SourceDev& src, double t,
-                        double* U, int64_t ldu, int step, const double* G, int64_t ldg,
-                        const double* Ainv, int64_t lda, double* b) {
-  hipLaunchKernelGGL(k_coarse_rhs, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, L.W, L.col,
-                     L.m64, L.has_mass, L.F, src, t, U, ldu, step, b);
-  hipLaunchKernelGGL(k_coarse_gemv, dim3(ceil_div(L.n, 4)), dim3(kBlock), 0, s, L.n, Ainv, lda, b,
-                     U, ldu, step, G, ldg);
+void launch_ie_inverse_batch(hipStream_t s, const DevLevel& L, int ncols, const double* src, int64_t lds,
+                             CView u, const double* Ainv, int64_t lda, double* B, double* X,
+                             int64_t ld) {
+  if (ncols <= 0) return;
+  dim3 grid(ceil_div(ncols, kWave), ceil_div(L.n, 4));
+  hipLaunchKernelGGL(k_ie_rhs_batch, grid, dim3(kBlock), 0, s, L.n, L.W, ncols, L.col, L.m64,
+                     L.has_mass, L.F, src, lds, u.p, u.ld, B, ld);
+  hipLaunchKernelGGL(k_inv_apply, grid, dim3(kBlock), 0, s, L.n, ncols, Ainv, lda, B, ld, X, ld);
   MG_HIP(hipGetLastError());
 }
 

@@ -178,6 +178,73 @@ class Solver:
                                                   out.ctypes.data_as(C.c_void_p)))
         return out
 
+    # -- learned coarse propagator ---------------------------------------
+    def coarse_n_params(self):
+        return int(self._L.mgrit_coarse_n_params(self._h))
+
+    def train_coarse(self, n_traj=64, epochs=10, batch=64, lr=2e-3, amp_spread=0.2,
+                     val_fraction=0.2, seed=0, perturb=0.0):
+        tp = _abi.TrainParams(n_traj, epochs, batch, lr, amp_spread, val_fraction, seed, perturb)
+        ts = _abi.TrainStats()
+        _check(self._L, self._h, self._L.mgrit_train_coarse(self._h, C.byref(tp), C.byref(ts)))
+        return {name: getattr(ts, name) for name, _ in _abi.TrainStats._fields_}
+
+    def set_coarse_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(self._L, self._h, self._L.mgrit_set_coarse_weights(
+            self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+    def get_coarse_weights(self):
+        w = np.empty(self.coarse_n_params(), dtype=np.float32)
+        _check(self._L, self._h, self._L.mgrit_get_coarse_weights(
+            self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+        return w
+
+    @staticmethod
+    def _opt(a, B):
+        if a is None:
+            return None, None
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (B,)))
+        return a, a.ctypes.data_as(C.c_void_p)
+
+    def _coarse_args(self, k, u, p, amp, dphi):
+        u = np.ascontiguousarray(np.atleast_2d(u), dtype=np.float64)
+        p = np.ascontiguousarray(np.atleast_2d(p), dtype=np.float64)
+        B = u.shape[0]
+        n = self.level_info(len(self.meshes) - 1)[0]
+        if u.shape != (B, n) or p.shape != (B, n):
+            raise ValueError(f"u and p must be [B, {n}]")
+        k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int64), (B,)))
+        a, ap = self._opt(amp, B)
+        d, dp = self._opt(dphi, B)
+        keep = (u, p, k, a, d)
+        return keep, B, k.ctypes.data_as(C.c_void_p), ap, dp, u.ctypes.data_as(C.c_void_p), \
+            p.ctypes.data_as(C.c_void_p)
+
+    def coarse_apply(self, k, u, p, amp=None, dphi=None):
+        keep, B, kp, ap, dp, up, pp = self._coarse_args(k, u, p, amp, dphi)
+        out = np.empty_like(keep[0])
+        _check(self._L, self._h, self._L.mgrit_coarse_apply(self._h, B, kp, ap, dp, up, pp,
+                                                            out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def coarse_gradient(self, k, u, p, y, amp=None, dphi=None):
+        keep, B, kp, ap, dp, up, pp = self._coarse_args(k, u, p, amp, dphi)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        if y.shape != keep[0].shape:
+            raise ValueError("y must match u")
+        loss = C.c_double()
+        g = np.empty(self.coarse_n_params(), dtype=np.float32)
+        _check(self._L, self._h, self._L.mgrit_coarse_gradient(
+            self._h, B, kp, ap, dp, up, pp, y.ctypes.data_as(C.c_void_p), C.byref(loss),
+            g.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss.value, g
+
+    def coarse_adam(self, grad, lr):
+        g = np.ascontiguousarray(grad, dtype=np.float32)
+        _check(self._L, self._h, self._L.mgrit_coarse_adam(
+            self._h, g.ctypes.data_as(C.POINTER(C.c_float)), lr))
+
     def close(self):
         if getattr(self, "_h", None):
             self._L.mgrit_destroy(self._h)
@@ -206,4 +273,5 @@ def stats_dict(st):
         kernel_launches=[list(st.kernel_launches[0]), list(st.kernel_launches[1])],
         kernel_columns=list(st.kernel_columns),
         kernel_time_s=[list(st.kernel_time_s[0]), list(st.kernel_time_s[1])],
+        coarse_fallback=st.coarse_fallback,
     )

@@ -39,7 +39,8 @@ def test_library_exports_every_declared_symbol():
 
 
 STRUCTS = {"mgrit_mesh": _abi.Mesh, "mgrit_physics": _abi.Physics, "mgrit_problem": _abi.Problem,
-           "mgrit_params": _abi.Params, "mgrit_stats": _abi.Stats}
+           "mgrit_params": _abi.Params, "mgrit_stats": _abi.Stats,
+           "mgrit_train_params": _abi.TrainParams, "mgrit_train_stats": _abi.TrainStats}
 
 
 def test_struct_layout_matches_header(tmp_path):
