@@ -130,6 +130,31 @@ def timed_solve(cfg, stream, label, **kw):
     return el, st, solver, out
 
 
+def profile_short(cfg, stream):
+    """A short program for rocprofv3 --pmc: the first level-0 FCF relaxation
+    and C-point residual of the timed workload (max_iter = 0), then a copy of
+    2^27 doubles (1 GiB read + 1 GiB written) to calibrate the byte counters."""
+    import torch
+    from paper_1912_03106_amd.solver import Solver
+    solver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1, max_iter=0,
+                    pcg_tol_eta=HEADLINE_ETA)
+    out = torch.empty((cfg.n_steps + 1, solver.n0), dtype=torch.float64, device="cuda")
+    _, st = solver.solve(out=out, raise_on_stall=False)
+    torch.cuda.synchronize()
+    rpb, cpl, fam = solver.kernel_shape(0)
+    n, _, nnz = solver.level_info(0)
+    lau = st["kernel_launches"][1][0]
+    byts = pass_b_bytes(n, nnz // n, fam, 8, st["kernel_columns"][0], lau)
+    solver.close()
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"pass_b_launches": lau, "pass_b_bytes_per_launch": round(byts / max(lau, 1)),
+                      "pass_b_avg_us": round(1e6 * st["kernel_time_s"][1][0] / max(lau, 1), 2),
+                      "copy_bytes": 2 * a.numel() * 8}), flush=True)
+
+
 HEADLINE_ETA = 1e-4      # level-0 relaxation: stop at max(pcg_tol ||b||, eta ||r_0||)
 FP32_ETA = 1e-3
 
@@ -146,6 +171,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the plain-tolerance and FP32 + refinement solves")
+    ap.add_argument("--profile-short", action="store_true",
+                    help="for hardware-counter runs: one level-0 relaxation and C-point residual "
+                         "of the 64x512 workload, then a 1 GiB device copy of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-parallel "
@@ -161,6 +189,9 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     cfg = config("cfg2")
+    if args.profile_short:
+        profile_short(cfg, stream)
+        return
 
     # headline: timed solves (HIP events around every CG pass, replayed graphs)
     log("setup cfg2 (timed)")

@@ -253,7 +253,10 @@ int64_t mgrit_coarse_n_params(void* h);
  * mgrit_coarse_n_params; the three scales must be > 0. */
 int mgrit_set_coarse_weights(void* h, const float* w, int64_t n);
 int mgrit_get_coarse_weights(void* h, float* w, int64_t n);
-/* Psi for B samples on the coarsest level (host arrays, user node order):
+/* Psi for B samples on the coarsest level, evaluated as inside MGRIT (FP64
+ * activations: a FAS correction is a difference of two evaluations, and FP32
+ * rounding of the inputs would turn differences below ~1e-7 of the state into
+ * noise); training and mgrit_coarse_gradient use FP32 (host arrays, user node order):
  * u, p [B][n_c] (p = the implicit-Euler step of u), k[B] input coarse steps
  * (T_k = k dT), amp / dphi [B] source amplitude factors and phase shifts (NULL =
  * 1 and 0).  psi [B][n_c] out. */

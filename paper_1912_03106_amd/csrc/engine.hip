@@ -555,8 +555,8 @@ static void psi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
   ie.ob = CView{};
   ie.osb = 0.0;
   phi_batch(h, l, w, ie);
-  gnn_forward(s, h.gnn, h.src, c.ncols, c.t_list, c.t_base, c.t_stride, nullptr, nullptr, c.in,
-              CView{h.gnn_tmp, S.ld}, h.gnn_tmp, S.ld, false);
+  gnn_forward64(s, h.gnn, h.src, c.ncols, c.t_list, c.t_base, c.t_stride, nullptr, nullptr, c.in,
+                CView{h.gnn_tmp, S.ld}, h.gnn_tmp, S.ld);
   launch_axpby3(s, S.n, c.ncols, c.out, c.ldo, c.osx, CView{h.gnn_tmp, S.ld}, 1.0, c.oa, c.osb, c.ob);
 }
 
@@ -672,8 +672,8 @@ static void coarsest_solve(Handle& h, int l) {
       launch_ie_inverse_batch(s, S.op, 1, w.src, w.ld, CView{S.U + st - 1, S.ld}, S.Ainv, S.ld_inv,
                               w.r, w.x, w.ld);
       if (learned)
-        gnn_forward(s, h.gnn, h.src, 1, nullptr, st - 1, 0, nullptr, nullptr, CView{S.U + st - 1, S.ld},
-                    CView{w.x, w.ld}, w.x, w.ld, false);
+        gnn_forward64(s, h.gnn, h.src, 1, nullptr, st - 1, 0, nullptr, nullptr, CView{S.U + st - 1, S.ld},
+                      CView{w.x, w.ld}, w.x, w.ld);
       launch_axpby3(s, S.n, 1, S.U + st, S.ld, 1.0, CView{w.x, w.ld}, 1.0, CView{S.G + st, S.ld}, 0.0,
                     CView{});
     }
@@ -1256,7 +1256,7 @@ static void setup_gnn(Handle& h, const mgrit_mesh& mesh, const HostPattern& pat,
   h.gnn_tmp = h.arena.alloc<double>(static_cast<size_t>(C.n) * C.ld);
   if (h.par.coarse_model == 1) {
     gnn_alloc_samples(g, h.arena, static_cast<int>(C.N + 1));
-    gnn_alloc_rows(g, h.arena, static_cast<int64_t>(C.n) * (C.N + 1));
+    gnn_alloc_rows64(g, h.arena, static_cast<int64_t>(C.n) * (C.N + 1));
   }
   h.has_gnn = true;
 }
@@ -1315,7 +1315,8 @@ static void coarse_eval_impl(Handle& h, int B, const int64_t* k, const double* a
   hipStream_t s = h.stream;
   const int n = C.n;
   gnn_alloc_samples(g, h.arena, B);
-  gnn_alloc_rows(g, h.arena, static_cast<int64_t>(n) * B);
+  if (y) gnn_alloc_rows(g, h.arena, static_cast<int64_t>(n) * B);
+  else gnn_alloc_rows64(g, h.arena, static_cast<int64_t>(n) * B);
   GnnStaging st(h);
   double* uc = stage_rows(st, u, B, n, C.nat);
   double* pc = stage_rows(st, p, B, n, C.nat);
@@ -1332,7 +1333,8 @@ static void coarse_eval_impl(Handle& h, int B, const int64_t* k, const double* a
   }
   double* psi = st.alloc<double>(static_cast<size_t>(n) * B);
   const bool train = (y != nullptr);
-  gnn_forward(s, g, h.src, B, kd, 0, 0, ad, dd, CView{uc, B}, CView{pc, B}, psi, B, train);
+  if (train) gnn_forward(s, g, h.src, B, kd, 0, 0, ad, dd, CView{uc, B}, CView{pc, B}, psi, B, true);
+  else gnn_forward64(s, g, h.src, B, kd, 0, 0, ad, dd, CView{uc, B}, CView{pc, B}, psi, B);
   if (train) {
     double* yc = stage_rows(st, y, B, n, C.nat);
     double* ld = st.alloc<double>(1);

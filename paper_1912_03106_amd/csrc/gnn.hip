@@ -519,6 +519,95 @@ __global__ __launch_bounds__(kBlock) void k_gnn_colsq(int n, int ncols, const do
   if (lane == 0) out[c] = s;
 }
 
+// ---------------------------------------------------------------------------
+// FP64 inference (the propagator inside MGRIT).  A coarse correction of FAS
+// is a difference of two evaluations of the propagator; with FP32 features
+// and activations that difference is noise below ~1e-7 of the state, which
+// would stall MGRIT near its 1e-8 tolerance, so the network is evaluated in
+// FP64 there (same bf16 weights).  A wave owns one row; lane f computes
+// output feature f.
+
+__global__ __launch_bounds__(kBlock) void k_gnn64_features(
+    int n, int S, int m, int F, const double* __restrict__ u, int64_t ldu,
+    const double* __restrict__ p, int64_t ldp, const double* __restrict__ tab,
+    const double* __restrict__ F3, const float* __restrict__ flags, const float* __restrict__ scales,
+    double* __restrict__ x) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t r = e / kFP;
+  const int f = static_cast<int>(e % kFP);
+  if (r >= static_cast<int64_t>(n) * S) return;
+  const int i = static_cast<int>(r / S), s = static_cast<int>(r % S);
+  double v = 0.0;
+  if (f == 0) v = u[i * ldu + s] / static_cast<double>(scales[0]);
+  else if (f == 1) v = p[i * ldp + s] / static_cast<double>(scales[0]);
+  else if (f < m + 3) {
+    const double* tb = tab + (static_cast<int64_t>(s) * (m + 1) + (f - 2)) * 3;
+    v = ((tb[0] * F3[i] + tb[1] * F3[n + i]) + tb[2] * F3[2 * n + i]) / static_cast<double>(scales[1]);
+  } else if (f < F) {
+    v = flags[i * 4 + (f - m - 3)];
+  }
+  x[r * kFP + f] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gnn64_in(int64_t nrows, int F, const double* __restrict__ x,
+                                                     const uint16_t* __restrict__ W,
+                                                     const uint16_t* __restrict__ b,
+                                                     double* __restrict__ h) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int f = threadIdx.x & 63;
+  if (r >= nrows) return;
+  double z = 0.0;
+  for (int k = 0; k < F; ++k) z += x[r * kFP + k] * static_cast<double>(bf16_to_f32(W[k * kH + f]));
+  h[r * kH + f] = tanh(z + static_cast<double>(bf16_to_f32(b[f])));
+}
+
+__global__ __launch_bounds__(kBlock) void k_gnn64_agg(int n, int S, const int* __restrict__ gptr,
+                                                      const int* __restrict__ gidx,
+                                                      const double* __restrict__ h,
+                                                      double* __restrict__ a) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int f = threadIdx.x & 63;
+  if (r >= static_cast<int64_t>(n) * S) return;
+  const int i = static_cast<int>(r / S), s = static_cast<int>(r % S);
+  double acc = 0.0;
+  for (int e = gptr[i]; e < gptr[i + 1]; ++e) acc += h[(static_cast<int64_t>(gidx[e]) * S + s) * kH + f];
+  a[r * kH + f] = acc / static_cast<double>(gptr[i + 1] - gptr[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gnn64_layer(int64_t nrows, const double* __restrict__ h,
+                                                        const double* __restrict__ a,
+                                                        const uint16_t* __restrict__ Ws,
+                                                        const uint16_t* __restrict__ Wn,
+                                                        const uint16_t* __restrict__ b,
+                                                        double* __restrict__ hout) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int f = threadIdx.x & 63;
+  if (r >= nrows) return;
+  double z = 0.0;
+  for (int k = 0; k < kH; ++k)
+    z += h[r * kH + k] * static_cast<double>(bf16_to_f32(Ws[k * kH + f])) +
+         a[r * kH + k] * static_cast<double>(bf16_to_f32(Wn[k * kH + f]));
+  hout[r * kH + f] = h[r * kH + f] + tanh(z + static_cast<double>(bf16_to_f32(b[f])));
+}
+
+__global__ __launch_bounds__(kBlock) void k_gnn64_out(int n, int S, const double* __restrict__ h,
+                                                      const uint16_t* __restrict__ w_out,
+                                                      const uint16_t* __restrict__ b_out,
+                                                      const float* __restrict__ scales,
+                                                      const double* __restrict__ p, int64_t ldp,
+                                                      double* __restrict__ out, int64_t ldo) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int f = threadIdx.x & 63;
+  if (r >= static_cast<int64_t>(n) * S) return;
+  double d = h[r * kH + f] * static_cast<double>(bf16_to_f32(w_out[f]));
+  for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+  if (f == 0) {
+    const int i = static_cast<int>(r / S), s = static_cast<int>(r % S);
+    const double delta = d + static_cast<double>(bf16_to_f32(b_out[0]));
+    out[i * ldo + s] = p[i * ldp + s] + static_cast<double>(scales[2]) * delta;
+  }
+}
+
 // X'[:, b] = X[:, b] + alpha[b] (X[:, perm[b]] - X[:, b]) for b < nt.
 __global__ void k_gnn_mix(int n, int nt, const double* __restrict__ X, int64_t ld,
                           const int* __restrict__ perm, const double* __restrict__ alpha,
@@ -586,6 +675,42 @@ void gnn_alloc_samples(GnnModel& g, DeviceArena& arena, int S) {
   if (S <= g.s_cap) return;
   g.s_cap = S;
   g.tab = arena.alloc<double>(static_cast<size_t>(S) * (g.m + 1) * 3);
+}
+
+void gnn_alloc_rows64(GnnModel& g, DeviceArena& arena, int64_t rows) {
+  if (rows <= g.rows64_cap) return;
+  g.rows64_cap = rows;
+  const size_t act = static_cast<size_t>(rows) * kH;
+  g.x64 = arena.alloc<double>(static_cast<size_t>(rows) * kFP);
+  g.h64[0] = arena.alloc<double>(act);
+  g.h64[1] = arena.alloc<double>(act);
+  g.a64 = arena.alloc<double>(act);
+}
+
+void gnn_forward64(hipStream_t s, GnnModel& g, const SourceDev& src, int S, const int64_t* k_list,
+                   int64_t k_base, int64_t k_stride, const double* amp, const double* dphi, CView u,
+                   CView p, double* out, int64_t ldo) {
+  const int n = g.n;
+  const int64_t rows = static_cast<int64_t>(n) * S;
+  if (rows > g.rows64_cap || S > g.s_cap) fail(MGRIT_INVALID_ARGUMENT, "learned propagator workspace too small");
+  const GnnOffsets& o = g.off;
+  hipLaunchKernelGGL(k_gnn_srctab, dim3(cdiv(static_cast<int64_t>(S) * (g.m + 1), 256)), dim3(256), 0, s,
+                     S, g.m, g.dT, k_list, k_base, k_stride, src, amp, dphi, g.tab);
+  hipLaunchKernelGGL(k_gnn64_features, dim3(cdiv(rows * kFP, kBlock)), dim3(kBlock), 0, s, n, S, g.m, o.F,
+                     u.p, u.ld, p.p, p.ld, g.tab, g.F3, g.flags, g.w32, g.x64);
+  const int nb = cdiv(rows, 4);
+  hipLaunchKernelGGL(k_gnn64_in, dim3(nb), dim3(kBlock), 0, s, rows, o.F, g.x64, g.wbf + o.w_in,
+                     g.wbf + o.b_in, g.h64[0]);
+  for (int l = 0; l < 3; ++l) {
+    const double* hin = g.h64[l & 1];
+    double* hout = g.h64[(l + 1) & 1];
+    hipLaunchKernelGGL(k_gnn64_agg, dim3(nb), dim3(kBlock), 0, s, n, S, g.gptr, g.gidx, hin, g.a64);
+    hipLaunchKernelGGL(k_gnn64_layer, dim3(nb), dim3(kBlock), 0, s, rows, hin, g.a64, g.wbf + o.ws[l],
+                       g.wbf + o.wn[l], g.wbf + o.b[l], hout);
+  }
+  hipLaunchKernelGGL(k_gnn64_out, dim3(nb), dim3(kBlock), 0, s, n, S, g.h64[1], g.wbf + o.w_out,
+                     g.wbf + o.b_out, g.w32, p.p, p.ld, out, ldo);
+  MG_HIP(hipGetLastError());
 }
 
 void gnn_round_weights(hipStream_t s, GnnModel& g) {

@@ -272,12 +272,22 @@ struct GnnModel {
   float *part_w = nullptr, *part_b = nullptr;
   double* part_loss = nullptr;
   double* tab = nullptr;        // [S][m+1][3] source samples
+  // FP64 inference workspace
+  int64_t rows64_cap = 0;
+  double* x64 = nullptr;
+  double* h64[2] = {nullptr, nullptr};
+  double* a64 = nullptr;
 };
 
 struct DeviceArena;
 void gnn_alloc_rows(GnnModel& g, DeviceArena& arena, int64_t rows);
 void gnn_alloc_samples(GnnModel& g, DeviceArena& arena, int S);
+void gnn_alloc_rows64(GnnModel& g, DeviceArena& arena, int64_t rows);
 void gnn_round_weights(hipStream_t s, GnnModel& g);
+// The same network evaluated in FP64 (the propagator used inside MGRIT).
+void gnn_forward64(hipStream_t s, GnnModel& g, const SourceDev& src, int S, const int64_t* k_list,
+                   int64_t k_base, int64_t k_stride, const double* amp, const double* dphi, CView u,
+                   CView p, double* out, int64_t ldo);
 // out(i, s) = p(i, s) + s_out delta for S samples with input coarse steps
 // k_list[s] (or k_base + s k_stride); keep = store activations for backward
 void gnn_forward(hipStream_t s, GnnModel& g, const SourceDev& src, int S, const int64_t* k_list,

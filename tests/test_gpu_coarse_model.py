@@ -60,6 +60,8 @@ def _scales(cfg, fe, u):
 
 
 def test_forward_matches_oracle(coarse):
+    """The propagator as MGRIT evaluates it (FP64 activations, bf16 weights)
+    against the oracle's FP64 network with the same rounded weights."""
     print("coarse model forward", flush=True)
     cfg, fe, ptr, idx, flags = coarse
     u, p, k, amp, dphi = _samples(cfg, fe, 5, 0)
@@ -72,7 +74,7 @@ def test_forward_matches_oracle(coarse):
     x = gnn.features(u, p, k, cfg.level_dt(1), cfg.m, fe, cfg.source, flags, par["scales"], amp, dphi)
     want, _ = gnn.forward(gnn.rounded(par), x, p, ptr, idx)
     corr_err = np.linalg.norm((got - p) - (want - p)) / np.linalg.norm(want - p)
-    assert corr_err <= 1e-4, corr_err
+    assert corr_err <= 1e-10, corr_err
 
 
 def test_gradient_matches_oracle(coarse):
@@ -152,14 +154,17 @@ def test_untrained_random_network_still_converges(coarse):
     s = _solver(cfg, coarse_model=1)
     s.set_coarse_weights(vec)
     U, st = s.solve()
-    assert st["converged"]
+    assert st["converged"] and st["coarse_fallback"] == -1
     assert np.linalg.norm(U - U_seq) <= MGRIT_GATE * np.linalg.norm(U_seq)
 
 
 def test_training_gain(coarse):
     """Trained on trajectories of the fine propagator with varied sources: the
     learned step is closer to m fine steps than implicit Euler on held-out
-    trajectories, and MGRIT with it reaches the same solution."""
+    trajectories (about 3.5x here), and MGRIT with it reaches the same solution
+    without falling back to implicit Euler.  (Its MGRIT iteration count, 10
+    against 8 here, is printed: the coarse correction depends on how the
+    propagator maps errors, which trajectory pairs do not train.)"""
     print("coarse model training", flush=True)
     cfg, fe, *_ = coarse
     H, _ = build(cfg)
@@ -175,5 +180,5 @@ def test_training_gain(coarse):
     _, st0 = ref.solve()
     print("iterations: learned", len(st["rho"]) - 1, "implicit Euler", len(st0["rho"]) - 1,
           "fallback", st["coarse_fallback"], flush=True)
-    assert st["converged"]
+    assert st["converged"] and st["coarse_fallback"] == -1
     assert np.linalg.norm(U - U_seq) <= MGRIT_GATE * np.linalg.norm(U_seq)
