@@ -117,8 +117,10 @@ typedef struct {
   int32_t autotune;           /* 1: time the batched-PCG tile shapes at setup and keep the fastest */
   int32_t pcg_kernel;         /* batched-PCG kernels: 0 choose (autotuner), 1 general sparse rows,
                                * 2 diagonal window (periodic polar stencil only, else UNSUPPORTED) */
-  int32_t coarse_inverse;     /* 1: linear model, coarsest level <= 8192 unknowns: step with a
-                               * stored A^{-1} (exact implicit Euler) instead of PCG */
+  int32_t coarse_inverse;     /* linear model: 1 = the coarsest level (<= 8192 unknowns) steps with
+                               * a stored A^{-1} (exact implicit Euler) instead of PCG; 2 = also
+                               * every intermediate level <= 16384 unknowns (batched steps become
+                               * one FP64 GEMM each); 0 = PCG everywhere */
   int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one work-group, 2 cooperative grid */
   int32_t use_graphs;         /* 1: replay each check interval of CG iterations from a captured
                                * hipGraph (not while profile_kernels = 1: launches stay eager so
@@ -137,6 +139,9 @@ typedef struct {
   int32_t coarse_model;       /* coarsest-level propagator: 0 implicit Euler (Sec. 2.1
                                * re-discretisation), 1 implicit Euler plus the learned correction
                                * (needs mgrit_train_coarse or mgrit_set_coarse_weights) */
+  int32_t compact_columns;    /* k > 0: when at most half of a batched CG's columns still iterate
+                               * and at least k columns would drop out, gather the iterating
+                               * ones densely (same iterates, fewer masked lanes); 0 = never */
 } mgrit_params;
 
 typedef struct {

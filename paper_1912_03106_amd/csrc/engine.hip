@@ -7,11 +7,13 @@
 // C-points are slab 0 (columns 0..N/m).  The coarsest level is one column
 // block [n][ld] with column t = point t.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -91,6 +93,7 @@ struct Handle {
     bool operator<(const GraphKey& o) const { return tie() < o.tie(); }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
+  rocblas_handle blas = nullptr;   // FP64 GEMMs with stored inverses of intermediate levels
   // learned coarse propagator on the coarsest level
   GnnModel gnn;
   bool has_gnn = false;
@@ -106,7 +109,8 @@ struct Handle {
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 constexpr int kMinRowsPerBlock = 16;
-constexpr int kMaxInverseN = 8192;   // largest coarsest level given a stored inverse
+constexpr int kMaxInverseN = 8192;        // largest coarsest level given a stored inverse
+constexpr int kMaxInverseNCoarse = 16384; // largest intermediate level given one (coarse_inverse = 2)
 static const int kRowsPerBlockCandidates[] = {16, 32, 64, 128, 256};
 
 static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block, int prec) {
@@ -265,6 +269,19 @@ static void autotune(Handle& h, LevelState& S) {
 // number of iterations in which some column was active.
 enum IterKind { IT_LIN64 = 0, IT_LIN32 = 1, IT_JAC = 2 };
 
+static void ensure_compaction_buffers(Handle& h, PcgWork& w) {
+  if (w.gmap) return;
+  const size_t bytes = sizeof(double) * static_cast<size_t>(w.n) * w.ld;   // large enough for either type
+  for (int st = 0; st < 2; ++st) {
+    w.alt_x[st] = h.arena.alloc_bytes(bytes);
+    w.alt_r[st] = h.arena.alloc_bytes(bytes);
+    w.alt_p[st][0] = h.arena.alloc_bytes(bytes);
+    w.alt_p[st][1] = h.arena.alloc_bytes(bytes);
+  }
+  w.gmap = h.arena.alloc<int>(w.ld);
+  w.cmap = h.arena.alloc<int>(w.ld);
+}
+
 static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int ncols, double tol2,
                        int kind, int active, bool fail_at_cap, int max_iter = -1) {
   hipStream_t s = h.stream;
@@ -275,6 +292,38 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
   const int cap = std::min(max_iter > 0 ? max_iter : h.par.pcg_max_iter, w.hist_cap);
   int64_t cols = 0, launches = 0;
   w.parity = 0;
+  // Column compaction: once at most half of the current columns iterate,
+  // converged columns hand their x back to the caller's buffer and the rest
+  // are gathered densely into an alternate buffer set (each column's
+  // arithmetic does not depend on its position, so the iterates are the
+  // same).  set = -1: the caller's buffers; 0 / 1: alternate sets.
+  const bool fp32 = (kind == IT_LIN32);
+  const bool can_compact = h.par.compact_columns > 0 && kind != IT_JAC;
+  void* ox = fp32 ? static_cast<void*>(w.x32) : static_cast<void*>(w.x);
+  void* orr = fp32 ? static_cast<void*>(w.r32) : static_cast<void*>(w.r);
+  void* op0 = fp32 ? static_cast<void*>(w.p32[0]) : static_cast<void*>(w.pbuf[0]);
+  void* op1 = fp32 ? static_cast<void*>(w.p32[1]) : static_cast<void*>(w.pbuf[1]);
+  int set = -1, cur = ncols;
+  auto vx = [&](int st) { return st < 0 ? ox : w.alt_x[st]; };
+  auto vr = [&](int st) { return st < 0 ? orr : w.alt_r[st]; };
+  auto vp = [&](int st, int k) { return st < 0 ? (k ? op1 : op0) : w.alt_p[st][k]; };
+  auto point = [&](int st) {
+    if (fp32) {
+      w.x32 = static_cast<float*>(vx(st));
+      w.r32 = static_cast<float*>(vr(st));
+      w.p32[0] = static_cast<float*>(vp(st, 0));
+      w.p32[1] = static_cast<float*>(vp(st, 1));
+    } else {
+      w.x = static_cast<double*>(vx(st));
+      w.r = static_cast<double*>(vr(st));
+      w.pbuf[0] = static_cast<double*>(vp(st, 0));
+      w.pbuf[1] = static_cast<double*>(vp(st, 1));
+    }
+  };
+  struct Restore {
+    std::function<void()> f;
+    ~Restore() { f(); }
+  } restore{[&] { point(-1); }};
   while (active > 0) {
     if (it >= cap) {
       if (fail_at_cap)
@@ -284,27 +333,27 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     }
     const int k = std::min(chunk, cap - it);
     // Later check intervals replay a captured graph of the same k launches
-    // (the first carries the `first` iteration and runs eagerly).
-    // (HIP events recorded inside a graph do not time its kernels reliably,
-    // so profiled solves launch eagerly)
-    const bool graph = h.par.use_graphs && !prof && it > 0 && k == chunk && (chunk % 2) == 0;
+    // (the first carries the `first` iteration and runs eagerly).  HIP events
+    // recorded inside a graph do not time its kernels reliably, so profiled
+    // solves launch eagerly; compacted column sets change every interval.
+    const bool graph = h.par.use_graphs && !prof && set < 0 && it > 0 && k == chunk && (chunk % 2) == 0;
     if (graph) {
       const Handle::GraphKey key{w.x, &L, w.nl, w.rows_per_block, w.cpl, w.dia ? 1 : 0, w.parity,
-                                 ncols, kind, chunk, tol2};
+                                 cur, kind, chunk, tol2};
       auto found = h.graphs.find(key);
       if (found == h.graphs.end()) {
         hipStream_t cs = h.capture_stream;
         MG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         const int keep_parity = w.parity;
         for (int t = 0; t < k; ++t) {
-          if (kind == IT_JAC) launch_nl_pass_a(cs, L, w, *w.nl, ncols, 0);
-          else if (kind == IT_LIN32) launch_pcg_pass_a32(cs, L, w, ncols, 0);
-          else launch_pcg_pass_a(cs, L, w, ncols, 0);
-          launch_reduce(cs, w, ncols, RED_ALPHA, tol2, 1, nullptr);
-          if (kind == IT_JAC) launch_nl_pass_b(cs, L, w, *w.nl, ncols);
-          else if (kind == IT_LIN32) launch_pcg_pass_b32(cs, L, w, ncols);
-          else launch_pcg_pass_b(cs, L, w, ncols);
-          launch_reduce(cs, w, ncols, RED_BETA, tol2, 2, nullptr);
+          if (kind == IT_JAC) launch_nl_pass_a(cs, L, w, *w.nl, cur, 0);
+          else if (kind == IT_LIN32) launch_pcg_pass_a32(cs, L, w, cur, 0);
+          else launch_pcg_pass_a(cs, L, w, cur, 0);
+          launch_reduce(cs, w, cur, RED_ALPHA, tol2, 1, nullptr);
+          if (kind == IT_JAC) launch_nl_pass_b(cs, L, w, *w.nl, cur);
+          else if (kind == IT_LIN32) launch_pcg_pass_b32(cs, L, w, cur);
+          else launch_pcg_pass_b(cs, L, w, cur);
+          launch_reduce(cs, w, cur, RED_BETA, tol2, 2, nullptr);
         }
         w.parity = keep_parity;
         hipGraph_t g = nullptr;
@@ -318,17 +367,17 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     }
     for (int t = 0; t < k && !graph; ++t) {
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t], s));
-      if (kind == IT_JAC) launch_nl_pass_a(s, L, w, *w.nl, ncols, it + t == 0);
-      else if (kind == IT_LIN32) launch_pcg_pass_a32(s, L, w, ncols, it + t == 0);
-      else launch_pcg_pass_a(s, L, w, ncols, it + t == 0);
+      if (kind == IT_JAC) launch_nl_pass_a(s, L, w, *w.nl, cur, it + t == 0);
+      else if (kind == IT_LIN32) launch_pcg_pass_a32(s, L, w, cur, it + t == 0);
+      else launch_pcg_pass_a(s, L, w, cur, it + t == 0);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 1], s));
-      launch_reduce(s, w, ncols, RED_ALPHA, tol2, 1, nullptr);
+      launch_reduce(s, w, cur, RED_ALPHA, tol2, 1, nullptr);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 2], s));
-      if (kind == IT_JAC) launch_nl_pass_b(s, L, w, *w.nl, ncols);
-      else if (kind == IT_LIN32) launch_pcg_pass_b32(s, L, w, ncols);
-      else launch_pcg_pass_b(s, L, w, ncols);
+      if (kind == IT_JAC) launch_nl_pass_b(s, L, w, *w.nl, cur);
+      else if (kind == IT_LIN32) launch_pcg_pass_b32(s, L, w, cur);
+      else launch_pcg_pass_b(s, L, w, cur);
       if (prof) MG_HIP(hipEventRecord(h.ev[4 * t + 3], s));
-      launch_reduce(s, w, ncols, RED_BETA, tol2, 2, nullptr);
+      launch_reduce(s, w, cur, RED_BETA, tol2, 2, nullptr);
     }
     MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     MG_HIP(hipMemcpyAsync(w.host_hist, w.hist + it, sizeof(int) * k, hipMemcpyDeviceToHost, s));
@@ -351,7 +400,23 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     launches += k;
     it += k;
     active = w.host_flags[0];
+    if (can_compact && active > 0 && it < cap && 2 * active <= cur && cur - active >= h.par.compact_columns) {
+      ensure_compaction_buffers(h, w);
+      const bool first = set < 0;
+      if (!first) launch_compact_retire(s, w.n, cur, static_cast<int>(w.ld), fp32, w.active, w.gmap,
+                                        false, false, vx(set), ox);
+      launch_compact_map(s, cur, w.ld, first, w.active, w.cmap, w.gmap, w.scal);
+      const int nxt = first ? 0 : (set ^ 1);
+      launch_compact_gather(s, w.n, active, w.ld, fp32, w.cmap, vx(set), vr(set), vp(set, w.parity),
+                            vx(nxt), vr(nxt), vp(nxt, w.parity));
+      set = nxt;
+      point(set);
+      cur = active;
+    }
   }
+  if (set >= 0)
+    launch_compact_retire(s, w.n, cur, static_cast<int>(w.ld), fp32, w.active, w.gmap, false, true, vx(set),
+                          ox);
   if (h.st && level < MGRIT_MAX_LEVELS) {
     h.st->kernel_launches[0][level] += launches;
     h.st->kernel_launches[1][level] += launches;
@@ -515,10 +580,20 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
   launch_source_table(s, h.src, S.op.dt, c.ncols, c.t_list, c.t_base, c.t_stride, w.src, w.ld,
                       h.col_amp, h.col_dphi);
   int it = 0;
-  if (S.Ainv) {
-    // coarsest linear level: the stored inverse, the same implicit-Euler
-    // step as its sequential solve
+  if (S.Ainv && S.coarsest) {
+    // coarsest linear level: the stored inverse, the same kernels (and bits)
+    // as its sequential solve
     launch_ie_inverse_batch(s, S.op, c.ncols, w.src, w.ld, c.in, S.Ainv, S.ld_inv, w.r, w.x, w.ld);
+  } else if (S.Ainv) {
+    // intermediate linear level: right-hand sides, then one FP64 GEMM
+    // X = Ainv B.  In column-major terms the [n][ld] blocks are ld x n
+    // matrices (columns of the block are rows), so X_cm = B_cm * Ainv_cm.
+    launch_ie_rhs_batch(s, S.op, c.ncols, w.src, w.ld, c.in, w.r, w.ld);
+    const double one = 1.0, zero = 0.0;
+    if (rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none, c.ncols, S.n, S.n, &one,
+                      w.r, static_cast<rocblas_int>(w.ld), S.Ainv, static_cast<rocblas_int>(S.ld_inv), &zero,
+                      w.x, static_cast<rocblas_int>(w.ld)) != rocblas_status_success)
+      fail(MGRIT_HIP_ERROR, "rocblas_dgemm failed");
   } else {
     launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
     it = S.nl.n_tri > 0
@@ -831,6 +906,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
       par->precision_coarse != MGRIT_FP32_IR)
     fail(MGRIT_INVALID_ARGUMENT, "precision_coarse must be -1, MGRIT_FP64 or MGRIT_FP32_IR");
   if (par->pcg_kernel < 0 || par->pcg_kernel > 2) fail(MGRIT_INVALID_ARGUMENT, "pcg_kernel");
+  if (par->compact_columns < 0) fail(MGRIT_INVALID_ARGUMENT, "compact_columns must be >= 0");
+  if (par->coarse_inverse < 0 || par->coarse_inverse > 2) fail(MGRIT_INVALID_ARGUMENT, "coarse_inverse");
   if (par->precision == MGRIT_FP32_IR && (!(par->ir_inner_tol > 0.0) || par->ir_max_iter < 1))
     fail(MGRIT_INVALID_ARGUMENT, "bad refinement settings");
   if (ph.nonlinear && !ph.iron) fail(MGRIT_INVALID_ARGUMENT, "the nonlinear model needs the iron flags");
@@ -953,6 +1030,18 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   }
   if (L > 1 && !ph.nonlinear && par->coarse_inverse && h.lv.back().n <= kMaxInverseN)
     build_coarse_inverse(h, h.lv.back());
+  if (!ph.nonlinear && par->coarse_inverse == 2) {
+    for (int l = 1; l + 1 < L; ++l)
+      if (h.lv[l].n <= kMaxInverseNCoarse) {
+        if (!h.blas) {
+          if (rocblas_create_handle(&h.blas) != rocblas_status_success)
+            fail(MGRIT_HIP_ERROR, "rocblas_create_handle failed");
+          if (rocblas_set_stream(h.blas, s) != rocblas_status_success)
+            fail(MGRIT_HIP_ERROR, "rocblas_set_stream failed");
+        }
+        build_coarse_inverse(h, h.lv[l]);
+      }
+  }
   if (L > 1) setup_gnn(h, prob->meshes[L - 1], pats[L - 1], ph);
   if (par->coarse_model != 0 && par->coarse_model != 1)
     fail(MGRIT_INVALID_ARGUMENT, "coarse_model must be 0 or 1");
@@ -1687,12 +1776,13 @@ void mgrit_default_params(mgrit_params* p) {
   p->profile_kernels = 0;
   p->autotune = 1;
   p->pcg_kernel = 0;
-  p->coarse_inverse = 1;
+  p->coarse_inverse = 2;
   p->seq_kernel = 0;
   p->use_graphs = 1;
   p->newton_halvings = 6;
   p->pcg_tol_eta = 0.0;
   p->precision_coarse = -1;
+  p->compact_columns = 256;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -1816,6 +1906,7 @@ void mgrit_destroy(void* hp) {
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   for (auto e : h->ev) (void)hipEventDestroy(e);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  if (h->blas) (void)rocblas_destroy_handle(h->blas);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   delete h;
 }

@@ -115,6 +115,14 @@ struct PcgWork {
   int* host_hist = nullptr;     // pinned copy
   int hist_cap = 0;
   NlWork* nl = nullptr;         // Newton buffers (nonlinear model, allocated on first use)
+  // column compaction (allocated on first use): two alternate sets of the CG
+  // vectors of the workspace's precision, the compact -> caller column map,
+  // and the per-step gather map
+  void* alt_x[2] = {nullptr, nullptr};
+  void* alt_r[2] = {nullptr, nullptr};
+  void* alt_p[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int* gmap = nullptr;
+  int* cmap = nullptr;
 };
 
 // Newton workspace of a PcgWork (same n, ld).
@@ -170,6 +178,19 @@ void launch_load_vectors(hipStream_t s, const DevLevel& L, const int* cptr, cons
                          const int* cell_sign);
 
 // --- batched Phi / PCG kernels (FP64) ---------------------------------------
+// Column compaction of a batched CG (T = double or float vectors):
+// retire: orig_x[:, gmap[c]] = x[:, c] for the columns c < cur that are
+//   inactive (all of them when all_cols), gmap = identity when first;
+// map: cmap = active columns in order, gmap = gmap[cmap], the CG scalars
+//   (rz, rr, bb, beta) gathered in place, active = 1 for the first count
+//   columns and 0 up to cur; gather: dst[:, j] = src[:, cmap[j]] for x, r, p.
+void launch_compact_retire(hipStream_t s, int n, int cur, int ld, bool fp32, const uint8_t* active,
+                           const int* gmap, bool first, bool all_cols, const void* x, void* orig_x);
+void launch_compact_map(hipStream_t s, int cur, int64_t ld, bool first, uint8_t* active, int* cmap,
+                        int* gmap, double* scal);
+void launch_compact_gather(hipStream_t s, int n, int count, int64_t ld, bool fp32, const int* cmap,
+                           const void* x, const void* r, const void* p, void* xd, void* rd, void* pd);
+
 // amp / dphi: optional per-column amplitude factors and phase shifts
 void launch_source_table(hipStream_t s, const SourceDev& src, double dt, int ncols,
                          const int64_t* t_list, int64_t t_base, int64_t t_stride,
@@ -302,6 +323,9 @@ void gnn_gather(hipStream_t s, int n, int S, const int64_t* idx, const double* s
 void gnn_gather_meta(hipStream_t s, int S, const int64_t* idx, const int64_t* k_all,
                      const double* amp_all, const double* dphi_all, int64_t* k_b, double* amp_b,
                      double* dphi_b);
+// B = (M/dt) u + f for ncols columns (f from the source table src[3][lds]).
+void launch_ie_rhs_batch(hipStream_t s, const DevLevel& L, int ncols, const double* src, int64_t lds,
+                         CView u, double* B, int64_t ld);
 // Implicit Euler with a stored inverse for ncols columns: B = (M/dt) u + f
 // (f from the source table src[3][lds]), X = Ainv B; B and X are [n][ld].
 void launch_ie_inverse_batch(hipStream_t s, const DevLevel& L, int ncols, const double* src, int64_t lds,

@@ -435,20 +435,22 @@ __global__ void k_ie_rhs_batch(int n, int W, int ncols, const int* __restrict__ 
   B[i * ldb + c] = bv;
 }
 
-// X[i][c] = sum_j Ainv[i][j] B[j][c]: a wave per (row, 64 columns); the
-// row of Ainv is wave-uniform, the columns of B coalesced.
+// X[i][c] = sum_j Ainv[i][j] B[j][c]: one wave per (row, column), lanes
+// stride over j, fixed-order shuffle reduction (the same arithmetic for one
+// column or many, so batched and single-step coarse steps agree bitwise).
 __global__ __launch_bounds__(kBlock) void k_inv_apply(int n, int ncols, const double* __restrict__ Ainv,
                                                       int64_t lda, const double* __restrict__ B,
                                                       int64_t ldb, double* __restrict__ X,
                                                       int64_t ldx) {
-  const int c = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x;
   const int i = blockIdx.y * 4 + wave_index();
-  if (i >= n) return;
+  if (i >= n || c >= ncols) return;
   const double* row = Ainv + static_cast<int64_t>(i) * lda;
   double acc = 0.0;
-  if (c < ncols)
-    for (int j = 0; j < n; ++j) acc += row[j] * B[static_cast<int64_t>(j) * ldb + c];
-  if (c < ncols) X[i * ldx + c] = acc;
+  for (int j = lane; j < n; j += kWave) acc += row[j] * B[static_cast<int64_t>(j) * ldb + c];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) X[i * ldx + c] = acc;
 }
 
 // ----------------------------------------------------------------------------
@@ -793,6 +795,15 @@ void launch_slabs_to_cols(hipStream_t s, int n, int64_t npts, int m, const doubl
   MG_HIP(hipGetLastError());
 }
 
+void launch_ie_rhs_batch(hipStream_t s, const DevLevel& L, int ncols, const double* src, int64_t lds,
+                         CView u, double* B, int64_t ld) {
+  if (ncols <= 0) return;
+  dim3 grid(ceil_div(ncols, kWave), ceil_div(L.n, 4));
+  hipLaunchKernelGGL(k_ie_rhs_batch, grid, dim3(kBlock), 0, s, L.n, L.W, ncols, L.col, L.m64,
+                     L.has_mass, L.F, src, lds, u.p, u.ld, B, ld);
+  MG_HIP(hipGetLastError());
+}
+
 void launch_ie_inverse_batch(hipStream_t s, const DevLevel& L, int ncols, const double* src, int64_t lds,
                              CView u, const double* Ainv, int64_t lda, double* B, double* X,
                              int64_t ld) {
@@ -800,7 +811,8 @@ void launch_ie_inverse_batch(hipStream_t s, const DevLevel& L, int ncols, const 
   dim3 grid(ceil_div(ncols, kWave), ceil_div(L.n, 4));
   hipLaunchKernelGGL(k_ie_rhs_batch, grid, dim3(kBlock), 0, s, L.n, L.W, ncols, L.col, L.m64,
                      L.has_mass, L.F, src, lds, u.p, u.ld, B, ld);
-  hipLaunchKernelGGL(k_inv_apply, grid, dim3(kBlock), 0, s, L.n, ncols, Ainv, lda, B, ld, X, ld);
+  hipLaunchKernelGGL(k_inv_apply, dim3(ncols, ceil_div(L.n, 4)), dim3(kBlock), 0, s, L.n, ncols, Ainv, lda,
+                     B, ld, X, ld);
   MG_HIP(hipGetLastError());
 }
 

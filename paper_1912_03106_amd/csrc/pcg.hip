@@ -731,6 +731,54 @@ __global__ void k_scale_entries(int n, int W, const int* __restrict__ col,
   ah32[e] = static_cast<float>(v);
 }
 
+// --- column compaction ------------------------------------------------------
+
+template <typename T>
+__global__ void k_compact_retire(int n, int cur, int64_t ld, const uint8_t* __restrict__ active,
+                                 const int* __restrict__ gmap, int first, int all_cols,
+                                 const T* __restrict__ x, T* __restrict__ ox) {
+  const int c = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (c >= cur || i >= n) return;
+  if (!all_cols && active[c]) return;
+  const int g = first ? c : gmap[c];
+  ox[i * ld + g] = x[i * ld + c];
+}
+
+// Serial (one thread, cur <= a few thousand): deterministic and in place, as
+// cmap[j] >= j makes the forward copies safe.
+__global__ void k_compact_map(int cur, int64_t ld, int first, uint8_t* __restrict__ active,
+                              int* __restrict__ cmap, int* __restrict__ gmap,
+                              double* __restrict__ scal) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int cnt = 0;
+  for (int c = 0; c < cur; ++c)
+    if (active[c]) cmap[cnt++] = c;
+  for (int j = 0; j < cnt; ++j) {
+    const int c = cmap[j];
+    gmap[j] = first ? c : gmap[c];
+    scal[j] = scal[c];                  // rz
+    scal[ld + j] = scal[ld + c];        // rr
+    scal[2 * ld + j] = scal[2 * ld + c];  // bb (stopping threshold)
+    scal[4 * ld + j] = scal[4 * ld + c];  // beta
+  }
+  for (int j = 0; j < cur; ++j) active[j] = j < cnt ? 1 : 0;
+}
+
+template <typename T>
+__global__ void k_compact_gather(int n, int count, int64_t ld, const int* __restrict__ cmap,
+                                 const T* __restrict__ x, const T* __restrict__ r,
+                                 const T* __restrict__ p, T* __restrict__ xd, T* __restrict__ rd,
+                                 T* __restrict__ pd) {
+  const int j = blockIdx.x * kWave + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (j >= count || i >= n) return;
+  const int64_t src = i * ld + cmap[j], dst = i * ld + j;
+  xd[dst] = x[src];
+  rd[dst] = r[src];
+  pd[dst] = p[src];
+}
+
 __global__ void k_fill_u8(uint8_t* p, int n, uint8_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -754,6 +802,44 @@ void launch_scale_matrix(hipStream_t s, DevLevel& L, const int* diag_slot) {
   const int64_t e = static_cast<int64_t>(L.n) * L.W;
   hipLaunchKernelGGL(k_scale_entries, dim3(ceil_div(e, 256)), dim3(256), 0, s, L.n, L.W, L.col,
                      L.a64, L.s64, L.ah64, L.ah32);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_compact_retire(hipStream_t s, int n, int cur, int ld, bool fp32, const uint8_t* active,
+                           const int* gmap, bool first, bool all_cols, const void* x, void* orig_x) {
+  dim3 grid(ceil_div(cur, kWave), ceil_div(n, 4));
+  if (fp32)
+    hipLaunchKernelGGL(k_compact_retire<float>, grid, dim3(kBlock), 0, s, n, cur, static_cast<int64_t>(ld),
+                       active, gmap, first ? 1 : 0, all_cols ? 1 : 0, static_cast<const float*>(x),
+                       static_cast<float*>(orig_x));
+  else
+    hipLaunchKernelGGL(k_compact_retire<double>, grid, dim3(kBlock), 0, s, n, cur, static_cast<int64_t>(ld),
+                       active, gmap, first ? 1 : 0, all_cols ? 1 : 0, static_cast<const double*>(x),
+                       static_cast<double*>(orig_x));
+  MG_HIP(hipGetLastError());
+}
+
+void launch_compact_map(hipStream_t s, int cur, int64_t ld, bool first, uint8_t* active, int* cmap,
+                        int* gmap, double* scal) {
+  hipLaunchKernelGGL(k_compact_map, dim3(1), dim3(64), 0, s, cur, ld, first ? 1 : 0, active, cmap, gmap,
+                     scal);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_compact_gather(hipStream_t s, int n, int count, int64_t ld, bool fp32, const int* cmap,
+                           const void* x, const void* r, const void* p, void* xd, void* rd, void* pd) {
+  if (count <= 0) return;
+  dim3 grid(ceil_div(count, kWave), ceil_div(n, 4));
+  if (fp32)
+    hipLaunchKernelGGL(k_compact_gather<float>, grid, dim3(kBlock), 0, s, n, count, ld, cmap,
+                       static_cast<const float*>(x), static_cast<const float*>(r),
+                       static_cast<const float*>(p), static_cast<float*>(xd), static_cast<float*>(rd),
+                       static_cast<float*>(pd));
+  else
+    hipLaunchKernelGGL(k_compact_gather<double>, grid, dim3(kBlock), 0, s, n, count, ld, cmap,
+                       static_cast<const double*>(x), static_cast<const double*>(r),
+                       static_cast<const double*>(p), static_cast<double*>(xd), static_cast<double*>(rd),
+                       static_cast<double*>(pd));
   MG_HIP(hipGetLastError());
 }
 

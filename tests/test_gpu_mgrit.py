@@ -161,9 +161,10 @@ def test_diagonal_window_rejects_non_polar_mesh():
     assert e.value.name == "UNSUPPORTED"
 
 
-@pytest.mark.parametrize("coarse_inverse", [0, 1])
+@pytest.mark.parametrize("coarse_inverse", [0, 1, 2])
 def test_mgrit_coarsest_solver_variants_agree(cfg1_oracle, coarse_inverse):
-    """Coarsest level stepped by PCG or by the stored inverse: same iterates."""
+    """Coarse levels stepped by PCG or by stored inverses (coarsest only, or
+    every coarse level through FP64 GEMMs): same iterates."""
     cfg, U_seq, _, hist = cfg1_oracle
     s = _solver(cfg, pcg_tol=1e-12, coarse_inverse=coarse_inverse)
     U, st = s.solve()
@@ -222,4 +223,39 @@ def test_early_stopped_relaxation_reaches_the_same_solution(variant):
     U, st = _solver(cfg, **kw).solve()
     assert st["converged"]
     assert len(st["rho"]) <= 11 + 2
+    assert _rel(U, U_seq) <= MGRIT_GATE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_column_compaction_gives_identical_iterates(cfg1_oracle, precision):
+    """Gathering the still-iterating CG columns densely (here whenever one
+    column would drop out) leaves every column's arithmetic unchanged."""
+    print(f"compaction {precision}", flush=True)
+    from paper_1912_03106_amd import _abi
+    cfg, U_seq, _, _ = cfg1_oracle
+    prec = _abi.FP64 if precision == "fp64" else _abi.FP32_IR
+    out = []
+    for k in (0, 1):
+        U, st = _solver(cfg, pcg_tol=1e-12, precision=prec, compact_columns=k,
+                        pcg_tol_eta=1e-3).solve()
+        out.append((U, st))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1]["rho"] == out[1][1]["rho"]
+    assert _rel(out[1][0], U_seq) <= MGRIT_GATE
+
+
+@pytest.mark.parametrize("coarse_inverse", [0, 2])
+def test_three_level_intermediate_inverse_matches_oracle(coarse_inverse):
+    """3-level V-cycle with the intermediate level stepped by PCG or by its
+    stored inverse (one GEMM per batched step): the oracle's history."""
+    print(f"mgrit 3-level inverse {coarse_inverse}", flush=True)
+    cfg = _sc_cfg()
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=4)
+    U, st = _solver(cfg, pcg_tol=1e-12, coarse_inverse=coarse_inverse).solve()
+    assert st["converged"]
+    for a, b in zip(st["rho"][:5], hist[:5]):
+        assert abs(a - b) <= 1e-9 * hist[0], (a, b)
     assert _rel(U, U_seq) <= MGRIT_GATE

@@ -132,3 +132,25 @@ def test_phi_fp32_refinement_full_size():
     u_prev = U[[4, 7, 9, 12]]
     err = _col_err(s.phi(0, u_prev, i_from), lev.phi(u_prev, i_from))
     assert err.max() <= PHI_TOL, err
+
+
+def test_phi_full_size_compaction_identical():
+    """A 600-column batched Phi on the 64x512 level with warm starts of
+    different quality: compacting the iterating columns gives the same bits."""
+    print("phi 64x512 compaction", flush=True)
+    cfg = config("cfg2")
+    lev = Level(polar_mesh(64, 512), cfg.dt, cfg.source)
+    U = sequential(lev, np.zeros(lev.n), 6)
+    rng = np.random.default_rng(9)
+    B = 600
+    u_prev = U[rng.integers(1, 7, size=B)] * rng.uniform(0.2, 3.0, size=(B, 1))
+    i_from = rng.integers(0, cfg.n_steps - 1, size=B)
+    outs = []
+    for k in (0, 64):
+        s = _solver(cfg, compact_columns=k, pcg_tol=1e-12)
+        outs.append(s.phi(0, u_prev, i_from))
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    pick = [0, 299, 599]
+    err = _col_err(outs[1][pick], lev.phi(u_prev[pick], i_from[pick]))
+    assert err.max() <= PHI_TOL, err
