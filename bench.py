@@ -156,6 +156,64 @@ def profile_short(cfg, stream):
                       "copy_bytes": 2 * a.numel() * 8}), flush=True)
 
 
+def nonlinear(N, stream):
+    """Saturating iron (Brauer law, damped Newton per step, FP32 inner CG with
+    FP64 Newton residual), start-up ramp, 3-level V-cycle on the first N steps."""
+    import torch
+    from workload import config
+    from paper_1912_03106_amd.solver import Solver
+    full = config("cfg4")
+    cfg = config("cfg4", n_steps=N, t_final=N * full.dt)
+    rec = {"workload": f"nonlinear eddy-current machine 64x512, first {N} of 32768 steps "
+                       f"(dt = {full.dt:.3e} s), 3-level V m=16, FP32 inner CG + FP64 Newton"}
+    out = None
+    for label, kw in (("implicit_euler", {}), ("implicit_euler_eta1e-3", {"pcg_tol_eta": 1e-3})):
+        log(f"nonlinear {label}")
+        s = Solver(cfg, stream=stream.cuda_stream, device_io=True, **kw)
+        if out is None:
+            out = torch.empty((N + 1, s.n0), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = s.solve(out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rec[label] = {"time_s": round(t, 2), "iterations": len(st["rho"]) - 1,
+                      "newton_sweeps": st["newton_sweeps"][:3], "pcg_sweeps": st["pcg_sweeps"][:3],
+                      "dof_steps_per_s": round(s.n0 * N / t, 1)}
+        log(f"nonlinear {label}: {len(st['rho']) - 1} iterations, {t:.1f} s")
+        s.close()
+    log("nonlinear learned coarse propagator: training")
+    s = Solver(cfg, stream=stream.cuda_stream, device_io=True, coarse_model=1, pcg_tol_eta=1e-3)
+    ts = s.train_coarse(n_traj=128, epochs=8, batch=64, lr=2e-3, seed=5, perturb=0.3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = s.solve(out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    rec["learned_eta1e-3"] = {"time_s": round(t, 2), "iterations": len(st["rho"]) - 1,
+                              "coarse_fallback": st["coarse_fallback"],
+                              "training": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in ts.items()}}
+    log(f"nonlinear learned: {len(st['rho']) - 1} iterations, {t:.1f} s")
+    s.close()
+    pre = min(N, 512)
+    pcfg = config("cfg4", n_steps=pre, t_final=pre * full.dt)
+    pcfg.meshes = cfg.meshes[:1] * 2
+    ps = Solver(pcfg, stream=stream.cuda_stream, device_io=True)
+    pout = torch.empty((pre + 1, ps.n0), dtype=torch.float64, device="cuda")
+    log(f"nonlinear sequential, {pre} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, sst = ps.seq_solve(out=pout)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    rec["gpu_sequential"] = {"steps_run": pre, "time_s_run": round(t, 2),
+                             "time_s_scaled_to_N": round(t * N / pre, 1),
+                             "newton_per_step": round(sst["newton_sweeps"][0] / pre, 2)}
+    for k in ("implicit_euler", "implicit_euler_eta1e-3", "learned_eta1e-3"):
+        rec[k]["speedup_vs_gpu_sequential"] = round(rec["gpu_sequential"]["time_s_scaled_to_N"] / rec[k]["time_s"], 3)
+    print(json.dumps(rec), flush=True)
+
+
 HEADLINE_ETA = 1e-4      # level-0 relaxation: stop at max(pcg_tol ||b||, eta ||r_0||)
 FP32_ETA = 1e-3
 
@@ -172,6 +230,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the plain-tolerance and FP32 + refinement solves")
+    ap.add_argument("--nonlinear", type=int, default=0, metavar="N",
+                    help="instead: the saturating-iron workload (64x512, dt = 0.02/32768) on its "
+                         "first N steps (N divisible by 256): MGRIT with implicit Euler and with "
+                         "the learned coarse propagator, and sequential stepping on a prefix")
     ap.add_argument("--profile-short", action="store_true",
                     help="for hardware-counter runs: one level-0 relaxation and C-point residual "
                          "of the 64x512 workload, then a 1 GiB device copy of known size")
@@ -192,6 +254,9 @@ def main():
     cfg = config("cfg2")
     if args.profile_short:
         profile_short(cfg, stream)
+        return
+    if args.nonlinear:
+        nonlinear(args.nonlinear, stream)
         return
 
     # headline: timed solves (HIP events around every CG pass, replayed graphs)

@@ -515,11 +515,14 @@ static int newton_solve(Handle& h, int level, LevelState& S, PcgWork& w, int nco
   // reference ||R(u_prev)||
   launch_nl_elem(s, S.nl, ncols, w.ld, nullptr, in, nw);
   launch_nl_residual(s, S.op, S.nl, w, nw, ncols, nullptr, in, in);
-  launch_nl_test(s, w, nw, ncols, 1, tol2);
+  // level-0 relaxation with pcg_tol_eta: Newton also stops at eta times the
+  // residual of its warm start
+  const double eta2 = h.eta_now * h.eta_now;
+  launch_nl_test(s, w, nw, ncols, 1, tol2, guess_is_input ? eta2 : 0.0);
   if (!guess_is_input) {
     launch_nl_elem(s, S.nl, ncols, w.ld, w.outer, CView{w.x, w.ld}, nw);
     launch_nl_residual(s, S.op, S.nl, w, nw, ncols, w.outer, CView{w.x, w.ld}, in);
-    launch_nl_test(s, w, nw, ncols, 0, tol2);
+    launch_nl_test(s, w, nw, ncols, 0, tol2, eta2);
   }
   auto read_count = [&]() {
     MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -150,7 +150,10 @@ void launch_nl_elem(hipStream_t s, const NlLevel& N, int ncols, int64_t ld, cons
 void launch_nl_residual(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
                         int ncols, const uint8_t* outer, CView u, CView uprev);
 // ref_mode 1: ref = ||R||^2, every column with R != 0 refines; 0: refine while ||R||^2 > tol2 ref
-void launch_nl_test(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, int ref_mode, double tol2);
+// eta2 > 0: the stopping threshold becomes max(tol2 ||R(u_prev)||^2, eta2 ||R(guess)||^2)
+// (in ref_mode the guess is u_prev itself, pass 0 when it is not)
+void launch_nl_test(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, int ref_mode, double tol2,
+                    double eta2 = 0.0);
 void launch_nl_jacobian(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
                         int ncols);
 void launch_nl_cg_init(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);

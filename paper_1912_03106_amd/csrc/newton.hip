@@ -416,7 +416,8 @@ __global__ __launch_bounds__(kBlock) void k_nl_ls(int ncols, int nrb, int64_t ld
 // column as refining; in TEST mode, keeps refining the columns with
 // ||R||^2 > tol2 ref.  Counts refining columns into flags[0].
 __global__ __launch_bounds__(kBlock) void k_nl_test(int ncols, int nrb, int64_t ld, int ref_mode,
-                                                    double tol2, const double* __restrict__ part,
+                                                    double tol2, double eta2,
+                                                    const double* __restrict__ part,
                                                     double* __restrict__ ref,
                                                     double* __restrict__ rcur,
                                                     uint8_t* __restrict__ outer,
@@ -434,12 +435,15 @@ __global__ __launch_bounds__(kBlock) void k_nl_test(int ncols, int nrb, int64_t 
   }
   if (lane == 0 && c < ncols) {
     int act = 0;
+    // eta2 > 0: also stop once ||R||^2 <= eta2 times that of the initial
+    // guess (ref is kept as threshold / tol2)
     if (ref_mode) {
-      ref[c] = t;
+      ref[c] = eta2 > 0.0 ? fmax(t, (eta2 / tol2) * t) : t;
       rcur[c] = t;
       act = t > 0.0;
     } else if (on) {
       rcur[c] = t;
+      if (eta2 > 0.0) ref[c] = fmax(ref[c], (eta2 / tol2) * t);
       act = t > tol2 * ref[c];
     }
     outer[c] = static_cast<uint8_t>(act);
@@ -482,10 +486,11 @@ void launch_nl_residual(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgW
   MG_HIP(hipGetLastError());
 }
 
-void launch_nl_test(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, int ref_mode, double tol2) {
+void launch_nl_test(hipStream_t s, PcgWork& w, NlWork& nw, int ncols, int ref_mode, double tol2,
+                    double eta2) {
   hipLaunchKernelGGL(k_zero_flag0, dim3(1), dim3(1), 0, s, w.flags);
   hipLaunchKernelGGL(k_nl_test, dim3(ceil_div(ncols, 4)), dim3(kBlock), 0, s, ncols, w.nrb, w.ld,
-                     ref_mode, tol2, w.part, nw.ref, nw.rcur, w.outer, w.flags);
+                     ref_mode, tol2, eta2, w.part, nw.ref, nw.rcur, w.outer, w.flags);
   MG_HIP(hipGetLastError());
 }
 

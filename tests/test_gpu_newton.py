@@ -176,3 +176,19 @@ def test_damped_newton_hard_steps_match_oracle():
     with pytest.raises(MgritError) as e:
         plain.phi(0, u_prev, i_from)
     assert e.value.name in ("NONFINITE", "NEWTON_NOT_CONVERGED")
+
+
+def test_newton_early_stopped_relaxation_reaches_the_same_solution():
+    """Level-0 relaxation Newton solves stopped at eta times their warm-start
+    residual: MGRIT still converges to the sequential solution."""
+    print("newton mgrit early stop", flush=True)
+    cfg = _small_cfg()
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, precision=_abi.FP32_IR, ir_inner_tol=1e-5, newton_tol=1e-11,
+                newton_max_iter=GPU_MAXIT, pcg_tol=1e-12, pcg_tol_eta=1e-3)
+    U, st = s.solve()
+    assert st["converged"]
+    assert _rel(U, U_seq) <= 1e-7
