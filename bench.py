@@ -131,6 +131,36 @@ def timed_solve(cfg, stream, label, **kw):
     return el, st, solver, out
 
 
+def summarize_pmc(fetch_csv, write_csv, bench_json):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the timed solve's CG
+    pass-B launches (the last `launches` pass-B dispatches of the run; the
+    earlier ones belong to the set-up), each scaled by true / counted bytes of
+    the 1 GiB calibration copy."""
+    import csv
+    with open(bench_json) as f:
+        launches = json.loads(f.readline())["roofline"]["launches"]
+    out = {"timed_launches": launches}
+    for key, path, ctr in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        pb, cp = [], []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != ctr:
+                    continue
+                if "k_cg_pass_b" in r["Kernel_Name"]:
+                    pb.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+                elif r["Kernel_Name"] == "__amd_rocclr_copyBuffer" and int(r["Grid_Size"]) >= 131072:
+                    cp.append(float(r["Counter_Value"]))
+        if len(pb) < launches or not cp:
+            raise SystemExit(f"{path}: too few pass-B or no calibration-copy dispatches")
+        pb = [v for _, v in sorted(pb)[-launches:]]
+        scale = (2 ** 30 / 1024) / cp[-1]
+        out[key] = {"dispatches": len(pb), "raw_kib_per_launch": sum(pb) / len(pb),
+                    "calibration_copy_kib": cp[-1], "scale": scale,
+                    "bytes_per_launch": 1024 * scale * sum(pb) / len(pb)}
+    out["traffic_bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    return out
+
+
 def profile_short(cfg, stream):
     """A short program for rocprofv3 --pmc: the first level-0 FCF relaxation
     and C-point residual of the timed workload (max_iter = 0), then a copy of
@@ -234,10 +264,21 @@ def main():
                     help="instead: the saturating-iron workload (64x512, dt = 0.02/32768) on its "
                          "first N steps (N divisible by 256): MGRIT with implicit Euler and with "
                          "the learned coarse propagator, and sequential stepping on a prefix")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed solve, copy 2^27 doubles (1 GiB read, 1 GiB written) so that "
+                         "rocprofv3 byte counters can be calibrated on a kernel of known traffic")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="print the per-launch HBM traffic of CG pass B from two rocprofv3 --pmc "
+                         "counter_collection.csv files (FETCH_SIZE, WRITE_SIZE), calibrated by the copy; "
+                         "the last `launches` pass-B dispatches (from the bench line of the same run) "
+                         "are the timed solve's")
     ap.add_argument("--profile-short", action="store_true",
                     help="for hardware-counter runs: one level-0 relaxation and C-point residual "
                          "of the 64x512 workload, then a 1 GiB device copy of known size")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-parallel "
               "decomposition over several GPUs is not part of this build.", file=sys.stderr)
@@ -290,6 +331,12 @@ def main():
     U_head = out.cpu().numpy()
     solver.close()
     del out
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     variants = {}
     U_var = {}
