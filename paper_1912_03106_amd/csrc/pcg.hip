@@ -418,15 +418,21 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_b_dia(
     V lo0 = ld_p(wrap_index(i0 - R - 1, n)), lo1 = ld_p(wrap_index(i0 - R, n));
     V m0 = ld_p(wrap_index(i0 - 1, n)), m1 = ld_p(i0), m2 = ld_p(wrap_index(i0 + 1, n));
     V hi0 = ld_p(wrap_index(i0 + R, n)), hi1 = ld_p(wrap_index(i0 + R + 1, n));
-    for (int kk = 0; kk < rpw; ++kk) {
-      const int i = i0 + kk;
-      if (i >= n) break;
+    // x and r of the next row are loaded one row ahead (the stores of this
+    // row go to other addresses), so that their latency overlaps this row
+    V xn = V::load(x + i0 * ld + c0), rn = V::load(r + i0 * ld + c0);
+    const int iend = (i0 + rpw < n) ? i0 + rpw : n;
+    for (int i = i0; i < iend; ++i) {
       const T* a = dv + static_cast<int64_t>(i) * 8;
       const int64_t o = i * ld + c0;
       const T si = sc[i];
       const double di = dg[i];
-      V xi = V::load(x + o);
-      V ri = V::load(r + o);
+      V xi = xn;
+      V ri = rn;
+      if (i + 1 < iend) {
+        xn = V::load(x + o + ld);
+        rn = V::load(r + o + ld);
+      }
 #pragma unroll
       for (int k = 0; k < CPL; ++k) {
         const T q = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
