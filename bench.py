@@ -37,6 +37,27 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the timed solve's pass-B launches, from the two rocprofv3
+# --pmc runs summarised in profiles/cg_pass_b_64x512_hbm_traffic.md (each
+# counter scaled by a 1 GiB copy).  Valid only for the kernel and solver
+# sources they were taken with: reported as null once those change.
+TRAFFIC_MEASURED = {
+    "sources_sha256": "f099878a8a3df5176f671c1d9a7c1b49d7ae272edf437d34d64794b49460b616",
+    "bytes_per_launch": 922783327,
+    "profile": "profiles/cg_pass_b_64x512_hbm_traffic.md",
+}
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pcg.hip", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_1912_03106_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC_MEASURED["sources_sha256"]:
+        return None
+    return TRAFFIC_MEASURED["bytes_per_launch"]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -326,6 +347,11 @@ def main():
     n_t = cfg.level_steps(1)                     # intervals = C-point residual columns per iteration
     frelax_cols = st["phi_columns"][0] - len(rho) * n_t
     roof = pass_b_roofline(st, solver, 8)
+    if roof is not None:
+        roof["traffic"] = measured_traffic()
+        if roof["traffic"] is not None:
+            roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["bytes_per_launch"], 3)
+            roof["traffic_profile"] = TRAFFIC_MEASURED["profile"]
     shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family"), solver.kernel_shape(l)))
               for l in range(cfg.n_levels)]
     U_head = out.cpu().numpy()
