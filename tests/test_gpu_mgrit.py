@@ -259,3 +259,69 @@ def test_three_level_intermediate_inverse_matches_oracle(coarse_inverse):
     for a, b in zip(st["rho"][:5], hist[:5]):
         assert abs(a - b) <= 1e-9 * hist[0], (a, b)
     assert _rel(U, U_seq) <= MGRIT_GATE
+
+
+@pytest.fixture(scope="module")
+def full_size_oracle_states():
+    """The oracle's sequential states of the 64x512 / 16384-step workload at
+    a few time points of its first 2048 steps (SuperLU, a few seconds)."""
+    cfg = config("cfg2")
+    from workload import polar_mesh
+    lev = stepping.Level(polar_mesh(64, 512), cfg.dt, cfg.source)
+    U = stepping.sequential(lev, np.zeros(lev.n), 2048)
+    return {i: U[i] for i in (16, 256, 1000, 2048)}
+
+
+@pytest.mark.parametrize("variant", ["fp64_timed", "fp32_ir"])
+def test_full_size_mgrit_sampled_against_oracle(full_size_oracle_states, variant):
+    """The 64x512 / 16384-step / 3-level workload in the launch configuration
+    bench.py times (and its FP32 + refinement variant with the random guess):
+    sampled time points against the oracle's sequential stepping."""
+    print(f"full-size mgrit {variant}", flush=True)
+    from paper_1912_03106_amd import _abi
+    if variant == "fp64_timed":
+        cfg = config("cfg2")
+        s = _solver(cfg, profile_kernels=1, pcg_tol_eta=1e-4)
+        U, st = s.solve()
+    else:
+        cfg = config("cfg3")
+        s = _solver(cfg, pcg_tol_eta=1e-3, precision_coarse=_abi.FP64)
+        U, st = s.solve(u_init=cfg.initial_guess(s.n0))
+    assert st["converged"]
+    assert st["rho"][-1] <= 1e-8 * st["rho"][0]
+    for i, u in full_size_oracle_states.items():
+        err = np.linalg.norm(U[i] - u) / np.linalg.norm(u)
+        assert err <= MGRIT_GATE, (i, err)
+
+
+def test_mgrit_degenerate_cases():
+    """One coarse interval (N_t = m), a zero source (the exact solution is
+    zero from the start), an empty Phi batch, and a one-level hierarchy."""
+    print("mgrit degenerate", flush=True)
+    from paper_1912_03106_amd import MgritError
+    from workload import Source
+    # N_t = m: the coarse grid has a single interval
+    cfg = config("cfg1", n_steps=16, t_final=16 * config("cfg1").dt)
+    H, _ = build(cfg)
+    U_seq = stepping.sequential(H.levels[0], np.zeros(H.levels[0].n), 16)
+    U, st = _solver(cfg, pcg_tol=1e-13).solve()
+    assert st["converged"] and len(st["rho"]) <= 2
+    assert _rel(U, U_seq) <= 1e-10
+    # zero source: rho_0 = 0 stops at once with the zero trajectory
+    cfg0 = config("cfg1", source=Source(J0=0.0))
+    U0, st0 = _solver(cfg0).solve()
+    assert st0["converged"] and st0["rho"] == [0.0] and not U0.any()
+    # empty batch
+    s = _solver(config("cfg1"))
+    out = s.phi(0, np.zeros((0, s.n0)), np.zeros(0, dtype=np.int64))
+    assert out.shape == (0, s.n0)
+    # one level: sequential stepping works, MGRIT needs two levels
+    cfg1l = config("cfg1", n_steps=64, t_final=64 * config("cfg1").dt)
+    cfg1l.meshes = cfg1l.meshes[:1]
+    s1 = _solver(cfg1l)
+    Useq1, _ = s1.seq_solve()
+    ref = stepping.sequential(H.levels[0], np.zeros(H.levels[0].n), 64)
+    assert _rel(Useq1, ref) <= 1e-9
+    with pytest.raises(MgritError) as e:
+        s1.solve()
+    assert e.value.name == "INVALID_ARGUMENT"
