@@ -109,6 +109,7 @@ struct Handle {
 static int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 constexpr int kMinRowsPerBlock = 16;
+constexpr size_t kMaxGraphs = 256;       // cached CG-interval graphs per handle
 constexpr int kMaxInverseN = 8192;        // largest coarsest level given a stored inverse
 constexpr int kMaxInverseNCoarse = 16384; // largest intermediate level given one (coarse_inverse = 2)
 static const int kRowsPerBlockCandidates[] = {16, 32, 64, 128, 256};
@@ -342,6 +343,11 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
                                  cur, kind, chunk, tol2};
       auto found = h.graphs.find(key);
       if (found == h.graphs.end()) {
+        if (h.graphs.size() >= kMaxGraphs) {   // many distinct shapes: start over
+          MG_HIP(hipStreamSynchronize(s));
+          for (auto& g : h.graphs) (void)hipGraphExecDestroy(g.second);
+          h.graphs.clear();
+        }
         hipStream_t cs = h.capture_stream;
         MG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         const int keep_parity = w.parity;
