@@ -101,6 +101,7 @@ struct Handle {
   double* gnn_tmp = nullptr; // [n_c][ld_c] implicit-Euler part of a coarse step
   const double* col_amp = nullptr;   // per-column source amplitude factors / phase
   const double* col_dphi = nullptr;  // shifts of phi_batch (training data only)
+  bool verbose = false;      // MGRIT_VERBOSE: one line per MGRIT iteration on stderr
   double tol_now = 1e-12;   // relative residual of the linear solves
   double eta_now = 0.0;     // > 0: linear solves also stop at eta times their initial residual
   hipStream_t capture_stream = nullptr;
@@ -901,6 +902,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (!prob || !par) fail(MGRIT_INVALID_ARGUMENT, "null problem or params");
   h.par = *par;
   h.tol_now = h.par.pcg_tol;
+  h.verbose = std::getenv("MGRIT_VERBOSE") != nullptr;
   h.phys = prob->phys;
   const mgrit_physics& ph = prob->phys;
   const int L = prob->n_levels;
@@ -1124,6 +1126,10 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
     const double rho = residual_norm(h, 0);
     if (st->n_history < MGRIT_MAX_HISTORY) st->rho[st->n_history++] = rho;
     if (it == 0) rho0 = rho;
+    if (h.verbose) {
+      std::fprintf(stderr, "[mgrit] iteration %d: rho/rho_0 = %.3e\n", it, rho0 > 0.0 ? rho / rho0 : 0.0);
+      std::fflush(stderr);
+    }
     // the learned coarse propagator is judged by the residual: if it grows,
     // the rest of the solve uses implicit Euler
     if (h.par.coarse_model == 1 && !h.learned_off && it > 0 && rho > rho_prev) {
