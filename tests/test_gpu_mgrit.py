@@ -281,7 +281,7 @@ def test_full_size_mgrit_sampled_against_oracle(full_size_oracle_states, variant
     from paper_1912_03106_amd import _abi
     if variant == "fp64_timed":
         cfg = config("cfg2")
-        s = _solver(cfg, profile_kernels=1, pcg_tol_eta=1e-4)
+        s = _solver(cfg, profile_kernels=1, pcg_tol_eta=1e-3)
         U, st = s.solve()
     else:
         cfg = config("cfg3")
