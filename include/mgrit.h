@@ -141,9 +141,11 @@ typedef struct {
   int32_t coarse_model;       /* coarsest-level propagator: 0 implicit Euler (Sec. 2.1
                                * re-discretisation), 1 implicit Euler plus the learned correction
                                * (needs mgrit_train_coarse or mgrit_set_coarse_weights) */
-  int32_t compact_columns;    /* k > 0: when at most half of a batched CG's columns still iterate
-                               * and at least k columns would drop out, gather the iterating
-                               * ones densely (same iterates, fewer masked lanes); 0 = never */
+  int32_t compact_columns;    /* k > 0: when at most compact_fraction of a batched CG's columns
+                               * still iterate and at least k columns would drop out, gather the
+                               * iterating ones densely (same iterates, fewer masked lanes);
+                               * 0 = never */
+  double  compact_fraction;   /* see compact_columns (default 0.75) */
 } mgrit_params;
 
 typedef struct {

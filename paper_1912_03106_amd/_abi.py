@@ -64,7 +64,7 @@ class Params(C.Structure):
         ("autotune", C.c_int32), ("pcg_kernel", C.c_int32), ("coarse_inverse", C.c_int32),
         ("seq_kernel", C.c_int32), ("use_graphs", C.c_int32), ("newton_halvings", C.c_int32),
         ("pcg_tol_eta", C.c_double), ("precision_coarse", C.c_int32), ("coarse_model", C.c_int32),
-        ("compact_columns", C.c_int32),
+        ("compact_columns", C.c_int32), ("compact_fraction", C.c_double),
     ]
 
 

@@ -407,7 +407,8 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     launches += k;
     it += k;
     active = w.host_flags[0];
-    if (can_compact && active > 0 && it < cap && 2 * active <= cur && cur - active >= h.par.compact_columns) {
+    if (can_compact && active > 0 && it < cap &&
+        static_cast<double>(active) <= h.par.compact_fraction * cur && cur - active >= h.par.compact_columns) {
       ensure_compaction_buffers(h, w);
       const bool first = set < 0;
       if (!first) launch_compact_retire(s, w.n, cur, static_cast<int>(w.ld), fp32, w.active, w.gmap,
@@ -918,6 +919,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     fail(MGRIT_INVALID_ARGUMENT, "precision_coarse must be -1, MGRIT_FP64 or MGRIT_FP32_IR");
   if (par->pcg_kernel < 0 || par->pcg_kernel > 2) fail(MGRIT_INVALID_ARGUMENT, "pcg_kernel");
   if (par->compact_columns < 0) fail(MGRIT_INVALID_ARGUMENT, "compact_columns must be >= 0");
+  if (!(par->compact_fraction > 0.0 && par->compact_fraction < 1.0))
+    fail(MGRIT_INVALID_ARGUMENT, "compact_fraction must be in (0, 1)");
   if (par->coarse_inverse < 0 || par->coarse_inverse > 2) fail(MGRIT_INVALID_ARGUMENT, "coarse_inverse");
   if (par->precision == MGRIT_FP32_IR && (!(par->ir_inner_tol > 0.0) || par->ir_max_iter < 1))
     fail(MGRIT_INVALID_ARGUMENT, "bad refinement settings");
@@ -1798,6 +1801,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->pcg_tol_eta = 0.0;
   p->precision_coarse = -1;
   p->compact_columns = 256;
+  p->compact_fraction = 0.75;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
