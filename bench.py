@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 # counter scaled by a 1 GiB copy).  Valid only for the kernel and solver
 # sources they were taken with: reported as null once those change.
 TRAFFIC_MEASURED = {
-    "sources_sha256": "f099878a8a3df5176f671c1d9a7c1b49d7ae272edf437d34d64794b49460b616",
-    "bytes_per_launch": 922783327,
+    "sources_sha256": "e21cec221b330797a8f931a130a3a384fed141ad2a7d3115c546db314c5f60b3",
+    "bytes_per_launch": 773489572,
     "profile": "profiles/cg_pass_b_64x512_hbm_traffic.md",
 }
 
