@@ -79,13 +79,13 @@ def pass_b_roofline(st, solver, unit):
     names = set()
     for l in range(solver.cfg.n_levels):
         n, _, nnz = solver.level_info(l)
-        rpb, cpl, fam = solver.kernel_shape(l)
+        rpb, cpl, fam, depth = solver.kernel_shape(l)
         lau = st["kernel_launches"][1][l]
         bytes_total += pass_b_bytes(n, nnz // n, fam, unit, st["kernel_columns"][l], lau)
         launches += lau
         t += st["kernel_time_s"][1][l]
         T = "double" if unit == 8 else "float"
-        names.add(f"k_cg_pass_b_dia<{T}, {cpl}>" if fam == 2 else f"k_cg_pass_b<{T}, {nnz // n}, {cpl}>")
+        names.add(f"k_cg_pass_b_dia<{T}, {cpl}, {depth}>" if fam == 2 else f"k_cg_pass_b<{T}, {nnz // n}, {cpl}>")
     if launches == 0 or t <= 0:
         return None
     achieved = bytes_total / t / 1e9
@@ -193,7 +193,7 @@ def profile_short(cfg, stream):
     out = torch.empty((cfg.n_steps + 1, solver.n0), dtype=torch.float64, device="cuda")
     _, st = solver.solve(out=out, raise_on_stall=False)
     torch.cuda.synchronize()
-    rpb, cpl, fam = solver.kernel_shape(0)
+    rpb, cpl, fam, depth = solver.kernel_shape(0)
     n, _, nnz = solver.level_info(0)
     lau = st["kernel_launches"][1][0]
     byts = pass_b_bytes(n, nnz // n, fam, 8, st["kernel_columns"][0], lau)
@@ -367,7 +367,7 @@ def main():
         if roof["traffic"] is not None:
             roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["bytes_per_launch"], 3)
             roof["traffic_profile"] = TRAFFIC_MEASURED["profile"]
-    shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family"), solver.kernel_shape(l)))
+    shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family", "prefetch_rows"), solver.kernel_shape(l)))
               for l in range(cfg.n_levels)]
     U_head = out.cpu().numpy()
     solver.close()
@@ -405,7 +405,7 @@ def main():
                                "guess": "U(-1e-3, 1e-3), seed 3",
                                "level0_stop": f"max(1e-12 ||b||, {FP32_ETA:g} ||r_0||)",
                                "coarse_levels": "stored inverses (FP64)",
-                               "autotuned_kernels": [dict(zip(("rows_per_block", "cols_per_lane", "family"),
+                               "autotuned_kernels": [dict(zip(("rows_per_block", "cols_per_lane", "family", "prefetch_rows"),
                                                               vs.kernel_shape(l)))
                                                      for l in range(cfg.n_levels)]}
         U_var["fp32_ir"] = vout.cpu().numpy()

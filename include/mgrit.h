@@ -146,6 +146,9 @@ typedef struct {
                                * iterating ones densely (same iterates, fewer masked lanes);
                                * 0 = never */
   double  compact_fraction;   /* see compact_columns (default 0.75) */
+  int32_t pcg_prefetch;       /* diagonal-window PCG kernels: rows of loads in flight per wave,
+                               * 1, 2 or 4; 0 = the autotuner's choice (1 without autotune).
+                               * Results do not depend on it. */
 } mgrit_params;
 
 typedef struct {
@@ -204,9 +207,11 @@ int phi_step(void* h, int32_t level, int32_t B, const int64_t* i_from,
              const double* u_prev, double* u_next);
 
 /* Sizes of a level: unknowns, steps, stored entries of the operator (fixed
- * row width times n), and kernel_shape[3] of its batched PCG kernels as the
+ * row width times n), and kernel_shape[4] of its batched PCG kernels as the
  * autotuner chose them: rows per work-group, columns per lane, kernel family
- * (1 general sparse rows, 2 diagonal window).  Any output pointer may be NULL. */
+ * (1 general sparse rows, 2 diagonal window) and rows of loads in flight per
+ * wave (1, 2 or 4; diagonal window only, else 1).  Any output pointer may be
+ * NULL. */
 int mgrit_level_info(void* h, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
                      int32_t* kernel_shape);
 

@@ -65,6 +65,7 @@ class Params(C.Structure):
         ("seq_kernel", C.c_int32), ("use_graphs", C.c_int32), ("newton_halvings", C.c_int32),
         ("pcg_tol_eta", C.c_double), ("precision_coarse", C.c_int32), ("coarse_model", C.c_int32),
         ("compact_columns", C.c_int32), ("compact_fraction", C.c_double),
+        ("pcg_prefetch", C.c_int32),
     ]
 
 
@@ -126,7 +127,7 @@ def lib():
     L.phi_step.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.phi_step.restype = C.c_int
     L.mgrit_level_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
-                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32 * 3)]
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32 * 4)]
     L.mgrit_level_info.restype = C.c_int
     L.mgrit_destroy.argtypes = [vp]
     L.mgrit_destroy.restype = None

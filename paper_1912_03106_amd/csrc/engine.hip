@@ -87,9 +87,11 @@ struct Handle {
     const void* x;
     const void* L;
     const void* nl;
-    int rpb, cpl, dia, parity, ncols, kind, chunk;
+    int rpb, cpl, dia, depth, parity, ncols, kind, chunk;
     double tol2;
-    auto tie() const { return std::tie(x, L, nl, rpb, cpl, dia, parity, ncols, kind, chunk, tol2); }
+    auto tie() const {
+      return std::tie(x, L, nl, rpb, cpl, dia, depth, parity, ncols, kind, chunk, tol2);
+    }
     bool operator<(const GraphKey& o) const { return tie() < o.tie(); }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -164,14 +166,15 @@ static void set_rows_per_block(PcgWork& w, int rpb) {
 // and keep the fastest.  Results are cached per (n, W, columns, precision)
 // for the life of the process.
 struct TuneKey {
-  int n, W, cols, prec, dia;
+  int n, W, cols, prec, dia, depth;
   bool operator<(const TuneKey& o) const {
-    return std::tie(n, W, cols, prec, dia) < std::tie(o.n, o.W, o.cols, o.prec, o.dia);
+    return std::tie(n, W, cols, prec, dia, depth) < std::tie(o.n, o.W, o.cols, o.prec, o.dia, o.depth);
   }
 };
 struct TuneChoice {
   int rpb, cpl;
   bool dia;
+  int depth;
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tune_cache;
@@ -180,9 +183,11 @@ static void autotune(Handle& h, LevelState& S) {
   PcgWork& w = S.pcg;
   const int ncols = w.cap;
   w.dia = (h.par.pcg_kernel == 2);
+  const int forced_depth = h.par.pcg_prefetch;
+  w.depth = forced_depth > 0 ? forced_depth : 1;
   if (!h.par.autotune || S.n < 4096 || ncols < kWave) return;
   const bool fp32 = w.prec == MGRIT_FP32_IR;
-  const TuneKey key{S.n, S.op.W, ncols, w.prec, S.op.dia_R * 4 + h.par.pcg_kernel};
+  const TuneKey key{S.n, S.op.W, ncols, w.prec, S.op.dia_R * 4 + h.par.pcg_kernel, forced_depth};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -190,6 +195,7 @@ static void autotune(Handle& h, LevelState& S) {
       set_rows_per_block(w, it->second.rpb);
       w.cpl = it->second.cpl;
       w.dia = it->second.dia;
+      w.depth = it->second.depth;
       return;
     }
   }
@@ -210,19 +216,25 @@ static void autotune(Handle& h, LevelState& S) {
   launch_fill_u8(s, w.active, ncols, 1);
   const int reps = 4;
   float best = 1e30f;
-  int best_rpb = w.rows_per_block, best_cpl = 1;
+  int best_rpb = w.rows_per_block, best_cpl = 1, best_depth = 1;
   bool best_dia = false;
   const int nr = static_cast<int>(sizeof(kRowsPerBlockCandidates) / sizeof(int));
-  for (int cand = 0; cand < 4 * nr; ++cand) {
+  static const int kDepths[3] = {1, 2, 4};
+  for (int cand = 0; cand < 4 * nr * 3; ++cand) {
     const int rpb = kRowsPerBlockCandidates[cand % nr];
     const int cpl = 1 + ((cand / nr) & 1);
-    const bool dia = (cand / (2 * nr)) != 0;
+    const bool dia = ((cand / (2 * nr)) & 1) != 0;
+    const int depth = kDepths[cand / (4 * nr)];
     if (dia && S.op.dia_R == 0) continue;
     if ((dia && h.par.pcg_kernel == 1) || (!dia && h.par.pcg_kernel == 2)) continue;
     if (!dia && cpl == 2 && S.op.W != 8) continue;
+    // depth applies to the diagonal-window family and needs rows to walk
+    if ((!dia || depth > rpb / 4) && depth != 1) continue;
+    if (forced_depth > 0 && dia && depth != forced_depth) continue;
     set_rows_per_block(w, rpb);
     w.cpl = cpl;
     w.dia = dia;
+    w.depth = depth;
     for (int warm = 0; warm < 2; ++warm) {
       if (warm) MG_HIP(hipEventRecord(h.ev0, s));
       for (int r = 0; r < reps; ++r) {
@@ -245,12 +257,13 @@ static void autotune(Handle& h, LevelState& S) {
       best_rpb = rpb;
       best_cpl = cpl;
       best_dia = dia;
+      best_depth = depth;
     }
     if (std::getenv("MGRIT_TUNE_LOG")) {
       const double unit = fp32 ? 4.0 : 8.0;
       const double bytes = 8.0 * unit * S.n * static_cast<double>(ncols);  // A + B vector passes
-      std::fprintf(stderr, "[mgrit tune] n=%d cols=%d %s %s rpb=%d cpl=%d: iteration %.1f us, %.0f GB/s\n",
-                   S.n, ncols, fp32 ? "fp32" : "fp64", dia ? "diag" : "ell", rpb, cpl,
+      std::fprintf(stderr, "[mgrit tune] n=%d cols=%d %s %s rpb=%d cpl=%d depth=%d: iteration %.1f us, %.0f GB/s\n",
+                   S.n, ncols, fp32 ? "fp32" : "fp64", dia ? "diag" : "ell", rpb, cpl, depth,
                    1e3 * ms / reps, bytes / (1e-3 * ms / reps) / 1e9);
     }
   }
@@ -258,8 +271,9 @@ static void autotune(Handle& h, LevelState& S) {
   set_rows_per_block(w, best_rpb);
   w.cpl = best_cpl;
   w.dia = best_dia;
+  w.depth = best_dia ? best_depth : 1;
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune_cache[key] = {best_rpb, best_cpl, best_dia};
+  g_tune_cache[key] = {best_rpb, best_cpl, best_dia, w.depth};
 }
 
 // ---------------------------------------------------------------------------
@@ -340,7 +354,7 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     // solves launch eagerly; compacted column sets change every interval.
     const bool graph = h.par.use_graphs && !prof && set < 0 && it > 0 && k == chunk && (chunk % 2) == 0;
     if (graph) {
-      const Handle::GraphKey key{w.x, &L, w.nl, w.rows_per_block, w.cpl, w.dia ? 1 : 0, w.parity,
+      const Handle::GraphKey key{w.x, &L, w.nl, w.rows_per_block, w.cpl, w.dia ? 1 : 0, w.depth, w.parity,
                                  cur, kind, chunk, tol2};
       auto found = h.graphs.find(key);
       if (found == h.graphs.end()) {
@@ -918,6 +932,9 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
       par->precision_coarse != MGRIT_FP32_IR)
     fail(MGRIT_INVALID_ARGUMENT, "precision_coarse must be -1, MGRIT_FP64 or MGRIT_FP32_IR");
   if (par->pcg_kernel < 0 || par->pcg_kernel > 2) fail(MGRIT_INVALID_ARGUMENT, "pcg_kernel");
+  if (par->pcg_prefetch != 0 && par->pcg_prefetch != 1 && par->pcg_prefetch != 2 &&
+      par->pcg_prefetch != 4)
+    fail(MGRIT_INVALID_ARGUMENT, "pcg_prefetch must be 0, 1, 2 or 4");
   if (par->compact_columns < 0) fail(MGRIT_INVALID_ARGUMENT, "compact_columns must be >= 0");
   if (!(par->compact_fraction > 0.0 && par->compact_fraction < 1.0))
     fail(MGRIT_INVALID_ARGUMENT, "compact_fraction must be in (0, 1)");
@@ -1251,6 +1268,7 @@ static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, co
   set_rows_per_block(w, S.pcg.rows_per_block);
   w.cpl = S.pcg.cpl;
   w.dia = S.pcg.dia;
+  w.depth = S.pcg.depth;
   // staging: time-major input/output and the column-block copy of u_prev
   double* tm = h.arena.alloc<double>(static_cast<size_t>(B) * S.n);
   double* cols = h.arena.alloc<double>(static_cast<size_t>(S.n) * w.ld);
@@ -1538,9 +1556,11 @@ static void train_impl(Handle& h, const mgrit_train_params* tp, mgrit_train_stat
   alloc_pcg(h, gw, Gl.n, nt, Gl.pcg.rows_per_block, Gl.prec);
   gw.cpl = Gl.pcg.cpl;
   gw.dia = Gl.pcg.dia;
+  gw.depth = Gl.pcg.depth;
   alloc_pcg(h, cw, C.n, nt, C.pcg.rows_per_block, C.prec);
   cw.cpl = C.pcg.cpl;
   cw.dia = C.pcg.dia;
+  cw.depth = C.pcg.depth;
   h.col_amp = amp_d;
   h.col_dphi = dphi_d;
   struct Reset {
@@ -1802,6 +1822,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->precision_coarse = -1;
   p->compact_columns = 256;
   p->compact_fraction = 0.75;
+  p->pcg_prefetch = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -1858,6 +1879,7 @@ int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int6
     kernel_shape[0] = S.pcg.rows_per_block;
     kernel_shape[1] = S.pcg.cpl;
     kernel_shape[2] = S.pcg.dia ? 2 : 1;
+    kernel_shape[3] = S.pcg.dia ? S.pcg.depth : 1;
   }
   return MGRIT_OK;
 }

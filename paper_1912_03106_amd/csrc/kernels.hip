@@ -31,19 +31,20 @@ __device__ __forceinline__ int wave_index() {
 }
 
 // Work-group -> (row block, 64-column chunk).  Work-groups are dispatched
-// round-robin over the 8 XCDs (XCD = id % 8); when the chunk count is a
-// multiple of 8 each XCD owns a fixed set of chunks and walks their rows in
-// order, so the +-n_theta neighbour rows are L2 hits on the same XCD.
+// round-robin over the 8 XCDs (XCD = id % 8).  The tiles, ordered chunk by
+// chunk and row block by row block within a chunk, are cut into 8 contiguous
+// ranges of nearly equal size, one per XCD, which walks its range in order:
+// the +-n_theta neighbour rows a tile reads belong to tiles of the same XCD
+// run at about the same time, and so are L2 hits.  A bijection on the grid
+// (gridDim.x = row blocks x chunks), whatever the chunk count.
 __device__ __forceinline__ void tile_decode(int w, int nrb, int ncc, int& rb, int& cc) {
-  if ((ncc & 7) == 0) {
-    const int xcd = w & 7, local = w >> 3, per = ncc >> 3;
-    cc = xcd + 8 * (local % per);
-    rb = local / per;
-  } else {
-    cc = w % ncc;
-    rb = w / ncc;
-  }
-  (void)nrb;
+  const int nrb_ = nrb;
+  (void)ncc;
+  const int T = static_cast<int>(gridDim.x);   // = row blocks x chunks
+  const int x = w & 7, k = w >> 3, q = T >> 3, rem = T & 7;
+  const int tile = x * q + (x < rem ? x : rem) + k;
+  cc = tile / nrb_;
+  rb = tile - cc * nrb_;
 }
 
 // Sum the per-lane values v[0..NQ) of the 4 waves of a work-group in a fixed

@@ -28,14 +28,12 @@ __device__ __forceinline__ int wave_index() {
 }
 
 __device__ __forceinline__ void tile_decode(int w, int ncc, int& rb, int& cc) {
-  if ((ncc & 7) == 0) {
-    const int xcd = w & 7, local = w >> 3, per = ncc >> 3;
-    cc = xcd + 8 * (local % per);
-    rb = local / per;
-  } else {
-    cc = w % ncc;
-    rb = w / ncc;
-  }
+  const int nrb_ = static_cast<int>(gridDim.x) / ncc;
+  const int T = static_cast<int>(gridDim.x);   // = row blocks x chunks
+  const int x = w & 7, k = w >> 3, q = T >> 3, rem = T & 7;
+  const int tile = x * q + (x < rem ? x : rem) + k;
+  cc = tile / nrb_;
+  rb = tile - cc * nrb_;
 }
 
 template <int NQ>

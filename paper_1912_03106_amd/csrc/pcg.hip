@@ -36,16 +36,15 @@ __device__ __forceinline__ int wave_index() {
   return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
 }
 
-// Work-group -> (row block, column chunk); see kernels.hip for the XCD note.
+// Work-group -> (row block, column chunk): contiguous tile ranges per XCD, as
+// in kernels.hip.
 __device__ __forceinline__ void tile_decode(int w, int ncc, int& rb, int& cc) {
-  if ((ncc & 7) == 0) {
-    const int xcd = w & 7, local = w >> 3, per = ncc >> 3;
-    cc = xcd + 8 * (local % per);
-    rb = local / per;
-  } else {
-    cc = w % ncc;
-    rb = w / ncc;
-  }
+  const int nrb_ = static_cast<int>(gridDim.x) / ncc;
+  const int T = static_cast<int>(gridDim.x);   // = row blocks x chunks
+  const int x = w & 7, k = w >> 3, q = T >> 3, rem = T & 7;
+  const int tile = x * q + (x < rem ? x : rem) + k;
+  cc = tile / nrb_;
+  rb = tile - cc * nrb_;
 }
 
 template <typename T, int CPL>
@@ -330,7 +329,12 @@ struct PDir {
   }
 };
 
-template <typename T, int CPL>
+// The three new window rows of a row (and the row's own streams) are loaded
+// D rows ahead into a ring of D register slots, so that a wave walking rpw
+// rows keeps D rows of loads in flight instead of waiting for one row's loads
+// per row; the arithmetic of a row, and its order, do not depend on D.
+
+template <typename T, int CPL, int D>
 __global__ __launch_bounds__(kBlock) void k_cg_pass_a_dia(
     int n, int R, const T* __restrict__ dv, int ncols, int ncc, int rpb, int64_t ld,
     const uint8_t* __restrict__ active, const double* __restrict__ beta, int first,
@@ -361,33 +365,59 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_a_dia(
   const int rpw = rpb >> 2;
   const int i0 = rb * rpb + wv * rpw;
   if (any && i0 < n) {
-    V lo0 = P.load(wrap_index(i0 - R - 1, n)), lo1 = P.load(wrap_index(i0 - R, n));
-    V m0 = P.load(wrap_index(i0 - 1, n)), m1 = P.load(i0), m2 = P.load(wrap_index(i0 + 1, n));
-    V hi0 = P.load(wrap_index(i0 + R, n)), hi1 = P.load(wrap_index(i0 + R + 1, n));
-    for (int kk = 0; kk < rpw; ++kk) {
-      const int i = i0 + kk;
-      if (i >= n) break;
-      const T* a = dv + static_cast<int64_t>(i) * 8;
+    const int iend = (i0 + rpw < n) ? i0 + rpw : n;
+    // slot d holds, for a row j = d (mod D), the r^ and p^_old values of the
+    // rows j-R, j+1 and j+R+1 (index 0, 1, 2)
+    V sr[D][3], sp[D][3];
+    auto fill = [&](int d, int j) {
+      const int rows[3] = {wrap_index(j - R, n), wrap_index(j + 1, n), wrap_index(j + R + 1, n)};
 #pragma unroll
-      for (int k = 0; k < CPL; ++k) {
-        const T s = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
-                    a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
-        acc[0][k] += static_cast<double>(m1.v[k]) * static_cast<double>(s);
+      for (int e = 0; e < 3; ++e) {
+        const int64_t o = rows[e] * ld + c0;
+        sr[d][e] = V::load(r + o);
+        if (!P.first) sp[d][e] = V::load(pold + o);
       }
-      m1.store(pnew + i * ld + c0);
-      lo0 = lo1;
-      lo1 = P.load(wrap_index(i + 1 - R, n));
-      m0 = m1;
-      m1 = m2;
-      m2 = P.load(wrap_index(i + 2, n));
-      hi0 = hi1;
-      hi1 = P.load(wrap_index(i + R + 2, n));
+    };
+    auto take = [&](int d, int e) {
+      V v = sr[d][e];
+      if (!P.first) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) v.v[k] = fma(P.be[k], sp[d][e].v[k], v.v[k]);
+      }
+      return v;
+    };
+    V lo0 = P.load(wrap_index(i0 - R - 1, n)), m0 = P.load(wrap_index(i0 - 1, n));
+    V m1 = P.load(i0), hi0 = P.load(wrap_index(i0 + R, n));
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (i0 + d < iend) fill(d, i0 + d);
+    for (int ib = i0; ib < iend; ib += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int i = ib + d;
+        if (i < iend) {
+          const V lo1 = take(d, 0), m2 = take(d, 1), hi1 = take(d, 2);
+          if (i + D < iend) fill(d, i + D);
+          const T* a = dv + static_cast<int64_t>(i) * 8;
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) {
+            const T s = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
+                        a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
+            acc[0][k] += static_cast<double>(m1.v[k]) * static_cast<double>(s);
+          }
+          m1.store(pnew + i * ld + c0);
+          lo0 = lo1;
+          m0 = m1;
+          m1 = m2;
+          hi0 = hi1;
+        }
+      }
     }
   }
   block_partials<1, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
 }
 
-template <typename T, int CPL>
+template <typename T, int CPL, int D>
 __global__ __launch_bounds__(kBlock) void k_cg_pass_b_dia(
     int n, int R, const T* __restrict__ dv, const T* __restrict__ sc, const double* __restrict__ dg,
     int ncols, int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
@@ -415,52 +445,62 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_b_dia(
   const int i0 = rb * rpb + wv * rpw;
   auto ld_p = [&](int row) { return V::load(p + row * ld + c0); };
   if (any && i0 < n) {
-    V lo0 = ld_p(wrap_index(i0 - R - 1, n)), lo1 = ld_p(wrap_index(i0 - R, n));
-    V m0 = ld_p(wrap_index(i0 - 1, n)), m1 = ld_p(i0), m2 = ld_p(wrap_index(i0 + 1, n));
-    V hi0 = ld_p(wrap_index(i0 + R, n)), hi1 = ld_p(wrap_index(i0 + R + 1, n));
-    // x and r of the next row are loaded one row ahead (the stores of this
-    // row go to other addresses), so that their latency overlaps this row
-    V xn = V::load(x + i0 * ld + c0), rn = V::load(r + i0 * ld + c0);
     const int iend = (i0 + rpw < n) ? i0 + rpw : n;
-    for (int i = i0; i < iend; ++i) {
-      const T* a = dv + static_cast<int64_t>(i) * 8;
-      const int64_t o = i * ld + c0;
-      const T si = sc[i];
-      const double di = dg[i];
-      V xi = xn;
-      V ri = rn;
-      if (i + 1 < iend) {
-        xn = V::load(x + o + ld);
-        rn = V::load(r + o + ld);
-      }
+    // slot d holds, for a row j = d (mod D), p^ of the rows j-R, j+1, j+R+1
+    // and x, r^ of row j
+    V sl[D], sm[D], sh[D], sx[D], sr[D];
+    auto fill = [&](int d, int j) {
+      sl[d] = ld_p(wrap_index(j - R, n));
+      sm[d] = ld_p(wrap_index(j + 1, n));
+      sh[d] = ld_p(wrap_index(j + R + 1, n));
+      sx[d] = V::load(x + j * ld + c0);
+      sr[d] = V::load(r + j * ld + c0);
+    };
+    V lo0 = ld_p(wrap_index(i0 - R - 1, n)), m0 = ld_p(wrap_index(i0 - 1, n));
+    V m1 = ld_p(i0), hi0 = ld_p(wrap_index(i0 + R, n));
 #pragma unroll
-      for (int k = 0; k < CPL; ++k) {
-        const T q = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
-                    a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
-        xi.v[k] = fma(al[k] * si, m1.v[k], xi.v[k]);
-        ri.v[k] = ri.v[k] - al[k] * q;
-        const double rd = static_cast<double>(ri.v[k]);
-        acc[0][k] += rd * rd;
-        acc[1][k] += di * (rd * rd);
-      }
-      if (all) {
-        xi.store(x + o);
-        ri.store(r + o);
-      } else {
+    for (int d = 0; d < D; ++d)
+      if (i0 + d < iend) fill(d, i0 + d);
+    for (int ib = i0; ib < iend; ib += D) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
-          if (on[k]) {
-            x[o + k] = xi.v[k];
-            r[o + k] = ri.v[k];
+      for (int d = 0; d < D; ++d) {
+        const int i = ib + d;
+        if (i < iend) {
+          const V lo1 = sl[d], m2 = sm[d], hi1 = sh[d];
+          V xi = sx[d], ri = sr[d];
+          // the stores of row i go to other addresses than the loads of row i + D
+          if (i + D < iend) fill(d, i + D);
+          const T* a = dv + static_cast<int64_t>(i) * 8;
+          const int64_t o = i * ld + c0;
+          const T si = sc[i];
+          const double di = dg[i];
+#pragma unroll
+          for (int k = 0; k < CPL; ++k) {
+            const T q = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
+                        a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
+            xi.v[k] = fma(al[k] * si, m1.v[k], xi.v[k]);
+            ri.v[k] = ri.v[k] - al[k] * q;
+            const double rd = static_cast<double>(ri.v[k]);
+            acc[0][k] += rd * rd;
+            acc[1][k] += di * (rd * rd);
           }
+          if (all) {
+            xi.store(x + o);
+            ri.store(r + o);
+          } else {
+#pragma unroll
+            for (int k = 0; k < CPL; ++k)
+              if (on[k]) {
+                x[o + k] = xi.v[k];
+                r[o + k] = ri.v[k];
+              }
+          }
+          lo0 = lo1;
+          m0 = m1;
+          m1 = m2;
+          hi0 = hi1;
+        }
       }
-      lo0 = lo1;
-      lo1 = ld_p(wrap_index(i + 1 - R, n));
-      m0 = m1;
-      m1 = m2;
-      m2 = ld_p(wrap_index(i + 2, n));
-      hi0 = hi1;
-      hi1 = ld_p(wrap_index(i + R + 2, n));
     }
   }
   block_partials<2, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
@@ -753,22 +793,54 @@ __global__ void k_compact_retire(int n, int cur, int64_t ld, const uint8_t* __re
 
 // Serial (one thread, cur <= a few thousand): deterministic and in place, as
 // cmap[j] >= j makes the forward copies safe.
-__global__ void k_compact_map(int cur, int64_t ld, int first, uint8_t* __restrict__ active,
-                              int* __restrict__ cmap, int* __restrict__ gmap,
-                              double* __restrict__ scal) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int cnt = 0;
-  for (int c = 0; c < cur; ++c)
-    if (active[c]) cmap[cnt++] = c;
-  for (int j = 0; j < cnt; ++j) {
-    const int c = cmap[j];
-    gmap[j] = first ? c : gmap[c];
-    scal[j] = scal[c];                  // rz
-    scal[ld + j] = scal[ld + c];        // rr
-    scal[2 * ld + j] = scal[2 * ld + c];  // bb (stopping threshold)
-    scal[4 * ld + j] = scal[4 * ld + c];  // beta
+// One work-group: the iterating columns keep their order and move to the
+// front, with their CG scalars (rz, rr, bb, beta) and original column ids;
+// cmap[j] = the old position of new column j.  In place, chunk by chunk: a
+// column's new position j never exceeds its old one c, positions of chunk
+// t + 1 are all >= every target of chunk t, and within a chunk every value is
+// read before any is written.
+constexpr int kCompactThreads = 1024;
+__global__ __launch_bounds__(kCompactThreads) void k_compact_map(
+    int cur, int64_t ld, int first, uint8_t* __restrict__ active, int* __restrict__ cmap,
+    int* __restrict__ gmap, double* __restrict__ scal) {
+  constexpr int kWaves = kCompactThreads / kWave;
+  __shared__ int wsum[kWaves];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int base = 0;
+  for (int c0 = 0; c0 < cur; c0 += kCompactThreads) {
+    const int c = c0 + t;
+    const bool on = (c < cur) && active[c];
+    const unsigned long long bal = __ballot(on);
+    if (lane == 0) wsum[wv] = __popcll(bal);
+    __syncthreads();
+    int off = base, total = 0;
+    for (int k = 0; k < kWaves; ++k) {
+      if (k < wv) off += wsum[k];
+      total += wsum[k];
+    }
+    const int j = off + __popcll(bal & ((1ull << lane) - 1ull));
+    int g = 0;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v4 = 0.0;
+    if (on) {
+      g = first ? c : gmap[c];
+      v0 = scal[c];            // rz
+      v1 = scal[ld + c];       // rr
+      v2 = scal[2 * ld + c];   // bb (stopping threshold)
+      v4 = scal[4 * ld + c];   // beta
+    }
+    __syncthreads();
+    if (on) {
+      cmap[j] = c;
+      gmap[j] = g;
+      scal[j] = v0;
+      scal[ld + j] = v1;
+      scal[2 * ld + j] = v2;
+      scal[4 * ld + j] = v4;
+    }
+    base += total;
+    __syncthreads();
   }
-  for (int j = 0; j < cur; ++j) active[j] = j < cnt ? 1 : 0;
+  for (int k = t; k < cur; k += kCompactThreads) active[k] = k < base ? 1 : 0;
 }
 
 template <typename T>
@@ -827,7 +899,7 @@ void launch_compact_retire(hipStream_t s, int n, int cur, int ld, bool fp32, con
 
 void launch_compact_map(hipStream_t s, int cur, int64_t ld, bool first, uint8_t* active, int* cmap,
                         int* gmap, double* scal) {
-  hipLaunchKernelGGL(k_compact_map, dim3(1), dim3(64), 0, s, cur, ld, first ? 1 : 0, active, cmap, gmap,
+  hipLaunchKernelGGL(k_compact_map, dim3(1), dim3(kCompactThreads), 0, s, cur, ld, first ? 1 : 0, active, cmap, gmap,
                      scal);
   MG_HIP(hipGetLastError());
 }
@@ -899,24 +971,40 @@ static void pass_b_impl(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols,
                      r, w.part, w.nrb);
 }
 
-template <typename T, int CPL>
-static void pass_a_dia(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first,
-                       const T* dv, const T* r, T* pold, T* pnew) {
+template <typename T, int CPL, int D>
+static void pass_a_dia_d(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first,
+                         const T* dv, const T* r, T* pold, T* pnew) {
   int ncc;
   const int nb = grid_tiles(w, ncols, CPL, ncc);
-  hipLaunchKernelGGL((k_cg_pass_a_dia<T, CPL>), dim3(nb), dim3(kBlock), 0, s, L.n, L.dia_R, dv,
+  hipLaunchKernelGGL((k_cg_pass_a_dia<T, CPL, D>), dim3(nb), dim3(kBlock), 0, s, L.n, L.dia_R, dv,
                      ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 4 * w.ld, first, r, pold,
                      pnew, w.part, w.nrb, w.flags, w.hist);
 }
 
 template <typename T, int CPL>
-static void pass_b_dia(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, const T* dv,
-                       const T* sc, const T* p, T* x, T* r) {
+static void pass_a_dia(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, int first,
+                       const T* dv, const T* r, T* pold, T* pnew) {
+  if (w.depth >= 4) pass_a_dia_d<T, CPL, 4>(s, L, w, ncols, first, dv, r, pold, pnew);
+  else if (w.depth == 2) pass_a_dia_d<T, CPL, 2>(s, L, w, ncols, first, dv, r, pold, pnew);
+  else pass_a_dia_d<T, CPL, 1>(s, L, w, ncols, first, dv, r, pold, pnew);
+}
+
+template <typename T, int CPL, int D>
+static void pass_b_dia_d(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, const T* dv,
+                         const T* sc, const T* p, T* x, T* r) {
   int ncc;
   const int nb = grid_tiles(w, ncols, CPL, ncc);
-  hipLaunchKernelGGL((k_cg_pass_b_dia<T, CPL>), dim3(nb), dim3(kBlock), 0, s, L.n, L.dia_R, dv, sc,
-                     L.d64, ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, p, x,
-                     r, w.part, w.nrb);
+  hipLaunchKernelGGL((k_cg_pass_b_dia<T, CPL, D>), dim3(nb), dim3(kBlock), 0, s, L.n, L.dia_R, dv,
+                     sc, L.d64, ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, p,
+                     x, r, w.part, w.nrb);
+}
+
+template <typename T, int CPL>
+static void pass_b_dia(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, const T* dv,
+                       const T* sc, const T* p, T* x, T* r) {
+  if (w.depth >= 4) pass_b_dia_d<T, CPL, 4>(s, L, w, ncols, dv, sc, p, x, r);
+  else if (w.depth == 2) pass_b_dia_d<T, CPL, 2>(s, L, w, ncols, dv, sc, p, x, r);
+  else pass_b_dia_d<T, CPL, 1>(s, L, w, ncols, dv, sc, p, x, r);
 }
 
 void launch_build_dia(hipStream_t s, DevLevel& L, int* bad) {

@@ -102,10 +102,11 @@ class Solver:
         return n.value, N.value, nnz.value
 
     def kernel_shape(self, level):
-        """(rows per work-group, columns per lane, family) of the level's batched
-        PCG kernels as the autotuner chose them; family 1 = general sparse rows,
-        2 = diagonal window."""
-        shape = (C.c_int32 * 3)()
+        """(rows per work-group, columns per lane, family, prefetch depth) of the
+        level's batched PCG kernels as the autotuner chose them; family 1 =
+        general sparse rows, 2 = diagonal window; depth = rows of loads in
+        flight per wave."""
+        shape = (C.c_int32 * 4)()
         _check(self._L, self._h, self._L.mgrit_level_info(self._h, level, None, None, None,
                                                           C.byref(shape)))
         return tuple(shape)

@@ -244,6 +244,39 @@ def test_column_compaction_gives_identical_iterates(cfg1_oracle, precision):
     assert _rel(out[1][0], U_seq) <= MGRIT_GATE
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_prefetch_depth_gives_identical_iterates(precision):
+    """The diagonal-window CG passes load their window rows 1, 2 or 4 rows
+    ahead; a row's arithmetic is the same, so the iterates are bitwise equal.
+    On the 16x126 mesh n = 1890, so with 16-row walks the last wave has 2
+    rows (a partly filled ring), and column compaction runs as well."""
+    print(f"prefetch depth {precision}", flush=True)
+    from paper_1912_03106_amd import _abi
+    cfg = config("cfg1", meshes=[LevelSpec(16, 126), LevelSpec(16, 126)])
+    H, _ = build(cfg)
+    U_seq = stepping.sequential(H.levels[0], np.zeros(H.levels[0].n), cfg.n_steps)
+    prec = _abi.FP64 if precision == "fp64" else _abi.FP32_IR
+    out = []
+    for depth in (1, 2, 4):
+        s = _solver(cfg, pcg_tol=1e-12, precision=prec, pcg_kernel=2, pcg_prefetch=depth,
+                    compact_columns=1, pcg_tol_eta=1e-3)
+        assert s.kernel_shape(0)[2:] == (2, depth)
+        out.append(s.solve())
+        s.close()
+    for U, st in out[1:]:
+        assert np.array_equal(U, out[0][0])
+        assert st["rho"] == out[0][1]["rho"]
+    assert out[0][1]["converged"]
+    assert _rel(out[0][0], U_seq) <= MGRIT_GATE
+
+
+def test_prefetch_depth_is_validated(cfg1_oracle):
+    from paper_1912_03106_amd._abi import MgritError
+    cfg = cfg1_oracle[0]
+    with pytest.raises(MgritError, match="INVALID_ARGUMENT"):
+        _solver(cfg, pcg_prefetch=3)
+
+
 @pytest.mark.parametrize("coarse_inverse", [0, 2])
 def test_three_level_intermediate_inverse_matches_oracle(coarse_inverse):
     """3-level V-cycle with the intermediate level stepped by PCG or by its
