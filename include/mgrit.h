@@ -106,12 +106,19 @@ typedef struct {
   int32_t max_iter;           /* MGRIT iterations (coarse corrections)         */
   double  pcg_tol;            /* relative residual of every linear solve       */
   int32_t pcg_max_iter;
-  int32_t pcg_check_every;    /* PCG iterations between host convergence reads */
+  int32_t pcg_check_every;    /* PCG iterations between host reads of the active-column count
+                               * (the points where column compaction can happen; default 4) */
   double  ir_inner_tol;       /* FP32 inner PCG tolerance (MGRIT_FP32_IR)       */
   int32_t ir_max_iter;        /* refinement sweeps                              */
   double  newton_tol;         /* ||R(u^k)|| <= newton_tol ||R(u_prev)||        */
   int32_t newton_max_iter;
-  int32_t warm_start;         /* 1: linear solves start from the previous iterate */
+  int32_t warm_start;         /* 0: every solve starts from its input; 1: from the previous
+                               * iterate at the same point; 2: as 1, and the level-0
+                               * F-relaxation solves add the change of their input since
+                               * that iterate was computed, u_j + (u_{j-1} - u_{j-1}^old)
+                               * (Phi is nearly the identity on slowly varying changes at small
+                               * steps, so this start is much closer; then pcg_tol_eta can be
+                               * larger at the same accuracy) */
   int32_t device_pointers;    /* 1: u_init / u_out of mgrit_solve are device pointers */
   int32_t profile_kernels;    /* 1: time every PCG pass with HIP events (mgrit_stats.kernel_*) */
   int32_t autotune;           /* 1: time the batched-PCG tile shapes at setup and keep the fastest */
@@ -145,10 +152,18 @@ typedef struct {
                                * still iterate and at least k columns would drop out, gather the
                                * iterating ones densely (same iterates, fewer masked lanes);
                                * 0 = never */
-  double  compact_fraction;   /* see compact_columns (default 0.75) */
+  double  compact_fraction;   /* see compact_columns (default 0.9; compact_columns default 64) */
   int32_t pcg_prefetch;       /* diagonal-window PCG kernels: rows of loads in flight per wave,
                                * 1, 2 or 4; 0 = the autotuner's choice (1 without autotune).
                                * Results do not depend on it. */
+  double  residual_eta;       /* > 0: the level-0 C-point residual solves (Alg. 1, the residual
+                               * before restriction) also stop at residual_eta times their
+                               * warm-start residual.  Their warm start is the current C-point
+                               * value, so that residual is proportional to the MGRIT residual
+                               * and the stop is relative to it; 0 = pcg_tol only (default). */
+  int32_t pcg_rows_narrow;    /* rows per work-group of the batched PCG passes once at most 128
+                               * columns still iterate (shorter dependent-load walks): 0 = the
+                               * autotuner's choice, -1 = never switch, 16/32/64/128/256 = this */
 } mgrit_params;
 
 typedef struct {

@@ -65,7 +65,7 @@ class Params(C.Structure):
         ("seq_kernel", C.c_int32), ("use_graphs", C.c_int32), ("newton_halvings", C.c_int32),
         ("pcg_tol_eta", C.c_double), ("precision_coarse", C.c_int32), ("coarse_model", C.c_int32),
         ("compact_columns", C.c_int32), ("compact_fraction", C.c_double),
-        ("pcg_prefetch", C.c_int32),
+        ("pcg_prefetch", C.c_int32), ("residual_eta", C.c_double), ("pcg_rows_narrow", C.c_int32),
     ]
 
 

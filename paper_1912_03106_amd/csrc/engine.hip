@@ -42,6 +42,10 @@ struct LevelState {
   double* U = nullptr;
   double* G = nullptr;
   double* RES = nullptr;                          // [n][ld] C-point residual
+  // warm_start = 2 (level 0): change of the input of the next F-point solve,
+  // and the C-points as the previous F-relaxation started from them
+  double* dlt = nullptr;
+  double* csnap = nullptr;
   double *U2 = nullptr, *G2 = nullptr, *RR = nullptr;  // next level, C-point columns
   bool has_transfer = false;
   DevTransfer R, P;
@@ -166,16 +170,22 @@ static void set_rows_per_block(PcgWork& w, int rpb) {
 // and keep the fastest.  Results are cached per (n, W, columns, precision)
 // for the life of the process.
 struct TuneKey {
-  int n, W, cols, prec, dia, depth;
+  int n, W, cols, prec, dia, depth, narrow;
   bool operator<(const TuneKey& o) const {
-    return std::tie(n, W, cols, prec, dia, depth) < std::tie(o.n, o.W, o.cols, o.prec, o.dia, o.depth);
+    return std::tie(n, W, cols, prec, dia, depth, narrow) <
+           std::tie(o.n, o.W, o.cols, o.prec, o.dia, o.depth, o.narrow);
   }
 };
 struct TuneChoice {
   int rpb, cpl;
   bool dia;
-  int depth;
+  int depth, rpb_narrow;
 };
+// Once at most this many columns of a batched CG still iterate, its passes
+// switch to the narrow rows-per-work-group choice: a wave's walk over its rows
+// is a chain of dependent loads, so with few columns a launch is as long as
+// the walk, and shorter walks in more work-groups finish sooner.
+constexpr int kNarrowCols = 128;
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tune_cache;
 
@@ -185,9 +195,12 @@ static void autotune(Handle& h, LevelState& S) {
   w.dia = (h.par.pcg_kernel == 2);
   const int forced_depth = h.par.pcg_prefetch;
   w.depth = forced_depth > 0 ? forced_depth : 1;
+  const int forced_narrow = h.par.pcg_rows_narrow;
+  w.rpb_narrow = forced_narrow > 0 ? forced_narrow : 0;
   if (!h.par.autotune || S.n < 4096 || ncols < kWave) return;
   const bool fp32 = w.prec == MGRIT_FP32_IR;
-  const TuneKey key{S.n, S.op.W, ncols, w.prec, S.op.dia_R * 4 + h.par.pcg_kernel, forced_depth};
+  const TuneKey key{S.n, S.op.W, ncols, w.prec, S.op.dia_R * 4 + h.par.pcg_kernel, forced_depth,
+                    forced_narrow};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -196,6 +209,7 @@ static void autotune(Handle& h, LevelState& S) {
       w.cpl = it->second.cpl;
       w.dia = it->second.dia;
       w.depth = it->second.depth;
+      w.rpb_narrow = it->second.rpb_narrow;
       return;
     }
   }
@@ -272,8 +286,41 @@ static void autotune(Handle& h, LevelState& S) {
   w.cpl = best_cpl;
   w.dia = best_dia;
   w.depth = best_dia ? best_depth : 1;
+  // narrow column sets: the same kernels with shorter walks
+  w.rpb_narrow = forced_narrow > 0 ? forced_narrow : 0;
+  if (forced_narrow == 0 && ncols > kNarrowCols) {
+    float best_n = 1e30f;
+    for (int rpb : kRowsPerBlockCandidates) {
+      if (rpb > best_rpb || rpb / 4 < w.depth) continue;
+      set_rows_per_block(w, rpb);
+      for (int warm = 0; warm < 2; ++warm) {
+        if (warm) MG_HIP(hipEventRecord(h.ev0, s));
+        for (int r = 0; r < reps; ++r) {
+          if (fp32) launch_pcg_pass_a32(s, S.op, w, kNarrowCols, 0);
+          else launch_pcg_pass_a(s, S.op, w, kNarrowCols, 0);
+          launch_reduce(s, w, kNarrowCols, RED_SUM, 0.0, 1, w.scal + 6 * w.ld);
+          if (fp32) launch_pcg_pass_b32(s, S.op, w, kNarrowCols);
+          else launch_pcg_pass_b(s, S.op, w, kNarrowCols);
+          launch_reduce(s, w, kNarrowCols, RED_SUM, 0.0, 2, w.scal + 6 * w.ld);
+        }
+      }
+      MG_HIP(hipEventRecord(h.ev1, s));
+      MG_HIP(hipEventSynchronize(h.ev1));
+      float ms = 0.f;
+      MG_HIP(hipEventElapsedTime(&ms, h.ev0, h.ev1));
+      if (std::getenv("MGRIT_TUNE_LOG"))
+        std::fprintf(stderr, "[mgrit tune] n=%d narrow cols=%d rpb=%d: iteration %.1f us\n", S.n,
+                     kNarrowCols, rpb, 1e3 * ms / reps);
+      if (ms < best_n) {
+        best_n = ms;
+        w.rpb_narrow = rpb;
+      }
+    }
+    if (w.rpb_narrow == best_rpb) w.rpb_narrow = 0;
+    set_rows_per_block(w, best_rpb);
+  }
   std::lock_guard<std::mutex> g(g_tune_mu);
-  g_tune_cache[key] = {best_rpb, best_cpl, best_dia, w.depth};
+  g_tune_cache[key] = {best_rpb, best_cpl, best_dia, w.depth, w.rpb_narrow};
 }
 
 // ---------------------------------------------------------------------------
@@ -308,7 +355,7 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
   const int cap = std::min(max_iter > 0 ? max_iter : h.par.pcg_max_iter, w.hist_cap);
   int64_t cols = 0, launches = 0;
   w.parity = 0;
-  // Column compaction: once at most half of the current columns iterate,
+  // Column compaction: once at most compact_fraction of the current columns iterate,
   // converged columns hand their x back to the caller's buffer and the rest
   // are gathered densely into an alternate buffer set (each column's
   // arithmetic does not depend on its position, so the iterates are the
@@ -336,10 +383,14 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
       w.pbuf[1] = static_cast<double*>(vp(st, 1));
     }
   };
+  const int rpb_full = w.rows_per_block;
   struct Restore {
     std::function<void()> f;
     ~Restore() { f(); }
-  } restore{[&] { point(-1); }};
+  } restore{[&] {
+    point(-1);
+    if (w.rows_per_block != rpb_full) set_rows_per_block(w, rpb_full);
+  }};
   while (active > 0) {
     if (it >= cap) {
       if (fail_at_cap)
@@ -421,6 +472,10 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     launches += k;
     it += k;
     active = w.host_flags[0];
+    // few columns left: shorter walks (decided by the active count alone, so
+    // that runs with and without compaction take the same partial sums)
+    if (w.rpb_narrow > 0 && w.rows_per_block != w.rpb_narrow && active <= kNarrowCols)
+      set_rows_per_block(w, w.rpb_narrow);
     if (can_compact && active > 0 && it < cap &&
         static_cast<double>(active) <= h.par.compact_fraction * cur && cur - active >= h.par.compact_columns) {
       ensure_compaction_buffers(h, w);
@@ -595,6 +650,7 @@ struct PhiCall {
   double osx = 1.0;
   CView oa, ob;
   double osb = 0.0;
+  double* dout = nullptr;   // if set: dout = x - out (before out is written), ld = ldo
 };
 
 static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
@@ -625,6 +681,9 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
              ? newton_solve(h, l, S, w, c.ncols, c.in, c.ga.p == c.in.p && c.gb.p == nullptr)
              : pcg_solve(h, l, S.op, w, c.ncols, c.in);
   }
+  if (c.dout)
+    launch_axpby3(s, S.n, c.ncols, c.dout, c.ldo, 1.0, CView{w.x, w.ld}, -1.0, CView{c.out, c.ldo},
+                  0.0, CView{});
   launch_axpby3(s, S.n, c.ncols, c.out, c.ldo, c.osx, CView{w.x, w.ld}, 1.0, c.oa, c.osb, c.ob);
   if (h.st && l < MGRIT_MAX_LEVELS) {
     h.st->phi_columns[l] += c.ncols;
@@ -667,14 +726,33 @@ static double* gslab(LevelState& S, int j) {
 
 static void f_relax(Handle& h, int l) {
   LevelState& S = h.lv[l];
+  hipStream_t s = h.stream;
   const bool warm = S.relaxed && h.par.warm_start;
+  // warm_start = 2: the previous iterate u_j was Phi(u_j-1^old); start from
+  // u_j + (u_j-1 - u_j-1^old).  dlt carries the input change from one solve
+  // to the next (dlt = x - u_j^old after solve j); for j = 1 it is the change
+  // of the C-points since the previous F-relaxation (C-relaxation or coarse
+  // correction).  Level 0 only: its FAS right-hand side is zero, so u_j^old
+  // stays Phi(u_j-1^old).
+  const bool delta = S.dlt && !S.G;
+  const int nt = static_cast<int>(S.NT);
+  if (delta) {
+    if (warm)
+      launch_axpby3(s, S.n, nt, S.dlt, S.ld, 0.0, CView{}, 1.0, CView{slab(S, 0), S.ld}, -1.0,
+                    CView{S.csnap, S.ld});
+    launch_axpby3(s, S.n, nt, S.csnap, S.ld, 0.0, CView{}, 1.0, CView{slab(S, 0), S.ld}, 0.0, CView{});
+  }
   for (int j = 1; j < h.m; ++j) {
     PhiCall c;
-    c.ncols = static_cast<int>(S.NT);
+    c.ncols = nt;
     c.in = CView{slab(S, j - 1), S.ld};
     c.t_base = j - 1;
     c.t_stride = h.m;
-    if (warm) {
+    if (warm && delta) {
+      c.ga = CView{slab(S, j), S.ld};
+      c.gb = CView{S.dlt, S.ld};
+      c.sgb = 1.0;
+    } else if (warm) {
       c.ga = CView{slab(S, j), S.ld};
       c.gb = CView{gslab(S, j), S.ld};
       c.sgb = -1.0;
@@ -684,6 +762,7 @@ static void f_relax(Handle& h, int l) {
     c.out = slab(S, j);
     c.ldo = S.ld;
     c.oa = CView{gslab(S, j), S.ld};
+    if (delta) c.dout = S.dlt;
     phi_batch(h, l, S.pcg, c);
   }
   S.relaxed = true;
@@ -932,9 +1011,17 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
       par->precision_coarse != MGRIT_FP32_IR)
     fail(MGRIT_INVALID_ARGUMENT, "precision_coarse must be -1, MGRIT_FP64 or MGRIT_FP32_IR");
   if (par->pcg_kernel < 0 || par->pcg_kernel > 2) fail(MGRIT_INVALID_ARGUMENT, "pcg_kernel");
+  if (par->warm_start < 0 || par->warm_start > 2) fail(MGRIT_INVALID_ARGUMENT, "warm_start must be 0, 1 or 2");
   if (par->pcg_prefetch != 0 && par->pcg_prefetch != 1 && par->pcg_prefetch != 2 &&
       par->pcg_prefetch != 4)
     fail(MGRIT_INVALID_ARGUMENT, "pcg_prefetch must be 0, 1, 2 or 4");
+  if (!(par->residual_eta >= 0.0 && par->residual_eta < 1.0))
+    fail(MGRIT_INVALID_ARGUMENT, "residual_eta must be in [0, 1)");
+  {
+    const int rn = par->pcg_rows_narrow;
+    if (!(rn == 0 || rn == -1 || rn == 16 || rn == 32 || rn == 64 || rn == 128 || rn == 256))
+      fail(MGRIT_INVALID_ARGUMENT, "pcg_rows_narrow must be 0, -1, 16, 32, 64, 128 or 256");
+  }
   if (par->compact_columns < 0) fail(MGRIT_INVALID_ARGUMENT, "compact_columns must be >= 0");
   if (!(par->compact_fraction > 0.0 && par->compact_fraction < 1.0))
     fail(MGRIT_INVALID_ARGUMENT, "compact_fraction must be in (0, 1)");
@@ -1028,6 +1115,10 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
         MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss * par->m, s));
       }
       S.RES = h.arena.alloc<double>(S.ss);
+      if (l == 0 && par->warm_start == 2) {
+        S.dlt = h.arena.alloc<double>(S.ss);
+        S.csnap = h.arena.alloc<double>(S.ss);
+      }
       const int nc = pats[l + 1].n;
       const size_t cs = static_cast<size_t>(nc) * S.ld;
       S.U2 = h.arena.alloc<double>(cs);
@@ -1142,7 +1233,12 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
     float ms = 0.f;
     MG_HIP(hipEventElapsedTime(&ms, h.ev0, h.ev1));
     st->time_relax_s += 1e-3 * ms;
-    c_residual(h, 0);         // the convergence measure always uses pcg_tol
+    // the C-point residual solves start from the current C-point values, so
+    // their initial residual shrinks with the MGRIT residual: residual_eta
+    // is a relative accuracy of the residual itself
+    h.eta_now = h.par.residual_eta;
+    c_residual(h, 0);
+    h.eta_now = 0.0;
     const double rho = residual_norm(h, 0);
     if (st->n_history < MGRIT_MAX_HISTORY) st->rho[st->n_history++] = rho;
     if (it == 0) rho0 = rho;
@@ -1269,6 +1365,7 @@ static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, co
   w.cpl = S.pcg.cpl;
   w.dia = S.pcg.dia;
   w.depth = S.pcg.depth;
+  w.rpb_narrow = S.pcg.rpb_narrow;
   // staging: time-major input/output and the column-block copy of u_prev
   double* tm = h.arena.alloc<double>(static_cast<size_t>(B) * S.n);
   double* cols = h.arena.alloc<double>(static_cast<size_t>(S.n) * w.ld);
@@ -1557,10 +1654,12 @@ static void train_impl(Handle& h, const mgrit_train_params* tp, mgrit_train_stat
   gw.cpl = Gl.pcg.cpl;
   gw.dia = Gl.pcg.dia;
   gw.depth = Gl.pcg.depth;
+  gw.rpb_narrow = Gl.pcg.rpb_narrow;
   alloc_pcg(h, cw, C.n, nt, C.pcg.rows_per_block, C.prec);
   cw.cpl = C.pcg.cpl;
   cw.dia = C.pcg.dia;
   cw.depth = C.pcg.depth;
+  cw.rpb_narrow = C.pcg.rpb_narrow;
   h.col_amp = amp_d;
   h.col_dphi = dphi_d;
   struct Reset {
@@ -1804,7 +1903,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->max_iter = 64;
   p->pcg_tol = 1e-12;
   p->pcg_max_iter = 5000;
-  p->pcg_check_every = 16;
+  p->pcg_check_every = 4;
   p->ir_inner_tol = 1e-5;
   p->ir_max_iter = 20;
   p->newton_tol = 1e-10;
@@ -1820,9 +1919,11 @@ void mgrit_default_params(mgrit_params* p) {
   p->newton_halvings = 6;
   p->pcg_tol_eta = 0.0;
   p->precision_coarse = -1;
-  p->compact_columns = 256;
-  p->compact_fraction = 0.75;
+  p->compact_columns = 64;
+  p->compact_fraction = 0.9;
   p->pcg_prefetch = 0;
+  p->residual_eta = 0.0;
+  p->pcg_rows_narrow = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {

@@ -98,6 +98,7 @@ struct PcgWork {
   int cpl = 1;                  // columns per lane of the CG passes (1 or 2)
   bool dia = false;             // use the diagonal-window CG passes
   int depth = 1;                // rows of loads in flight per wave (diagonal-window passes: 1, 2, 4)
+  int rpb_narrow = 0;           // rows per work-group once few columns iterate (0 = keep)
   int64_t ld = 0;
   double *x = nullptr, *r = nullptr;
   double* pbuf[2] = {nullptr, nullptr};  // search directions, ping-pong

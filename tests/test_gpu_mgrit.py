@@ -206,11 +206,15 @@ def test_seq_solve_with_startup_ramp_matches_oracle():
     assert err.max() <= SEQ_TOL, err.max()
 
 
-@pytest.mark.parametrize("variant", ["fp64_eta", "fp32ir_eta_coarse_fp64"])
+@pytest.mark.parametrize("variant", ["fp64_eta", "fp32ir_eta_coarse_fp64", "fp64_delta_start",
+                                     "fp32ir_delta_start"])
 def test_early_stopped_relaxation_reaches_the_same_solution(variant):
     """Level-0 relaxation solves stopped at max(pcg_tol ||b||, eta ||r_0||)
-    (the C-point residual and the coarse levels keep pcg_tol): the same
-    fixed point, within one or two iterations of the strict solves."""
+    (the coarse levels keep pcg_tol): the same fixed point, within one or two
+    iterations of the strict solves.  The delta-start variants also start the
+    F-relaxation solves from the previous iterate plus the change of their
+    input (warm_start = 2) and stop the C-point residual solves at 1e-4 of
+    their warm-start residual."""
     print(f"mgrit early stop {variant}", flush=True)
     from paper_1912_03106_amd import _abi
     cfg = _sc_cfg()
@@ -218,7 +222,9 @@ def test_early_stopped_relaxation_reaches_the_same_solution(variant):
     n = H.levels[0].n
     U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
     kw = dict(pcg_tol=1e-12, pcg_tol_eta=1e-3)
-    if variant != "fp64_eta":
+    if variant.endswith("delta_start"):
+        kw.update(pcg_tol_eta=3e-3, warm_start=2, residual_eta=1e-4)
+    if variant.startswith("fp32ir"):
         kw.update(precision=_abi.FP32_IR, precision_coarse=_abi.FP64)
     U, st = _solver(cfg, **kw).solve()
     assert st["converged"]
@@ -226,18 +232,21 @@ def test_early_stopped_relaxation_reaches_the_same_solution(variant):
     assert _rel(U, U_seq) <= MGRIT_GATE
 
 
+@pytest.mark.parametrize("narrow", [-1, 16])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-def test_column_compaction_gives_identical_iterates(cfg1_oracle, precision):
+def test_column_compaction_gives_identical_iterates(cfg1_oracle, precision, narrow):
     """Gathering the still-iterating CG columns densely (here whenever one
-    column would drop out) leaves every column's arithmetic unchanged."""
-    print(f"compaction {precision}", flush=True)
+    column would drop out) leaves every column's arithmetic unchanged, also
+    when the passes switch to 16-row work-groups once at most 128 columns
+    iterate (narrow = 16; on this 64-interval workload from the first check)."""
+    print(f"compaction {precision} narrow {narrow}", flush=True)
     from paper_1912_03106_amd import _abi
     cfg, U_seq, _, _ = cfg1_oracle
     prec = _abi.FP64 if precision == "fp64" else _abi.FP32_IR
     out = []
     for k in (0, 1):
         U, st = _solver(cfg, pcg_tol=1e-12, precision=prec, compact_columns=k,
-                        pcg_tol_eta=1e-3).solve()
+                        pcg_tol_eta=1e-3, pcg_rows_narrow=narrow).solve()
         out.append((U, st))
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1]["rho"] == out[1][1]["rho"]
@@ -270,11 +279,13 @@ def test_prefetch_depth_gives_identical_iterates(precision):
     assert _rel(out[0][0], U_seq) <= MGRIT_GATE
 
 
-def test_prefetch_depth_is_validated(cfg1_oracle):
+@pytest.mark.parametrize("bad", [dict(pcg_prefetch=3), dict(warm_start=3), dict(residual_eta=1.0),
+                                 dict(residual_eta=-1e-3), dict(pcg_rows_narrow=48)])
+def test_solver_parameters_are_validated(cfg1_oracle, bad):
     from paper_1912_03106_amd._abi import MgritError
     cfg = cfg1_oracle[0]
     with pytest.raises(MgritError, match="INVALID_ARGUMENT"):
-        _solver(cfg, pcg_prefetch=3)
+        _solver(cfg, **bad)
 
 
 @pytest.mark.parametrize("coarse_inverse", [0, 2])
@@ -312,13 +323,15 @@ def test_full_size_mgrit_sampled_against_oracle(full_size_oracle_states, variant
     sampled time points against the oracle's sequential stepping."""
     print(f"full-size mgrit {variant}", flush=True)
     from paper_1912_03106_amd import _abi
+    # bench.py's timed settings
+    timed = dict(pcg_tol_eta=3e-3, warm_start=2, residual_eta=1e-4)
     if variant == "fp64_timed":
         cfg = config("cfg2")
-        s = _solver(cfg, profile_kernels=1, pcg_tol_eta=1e-3)
+        s = _solver(cfg, profile_kernels=1, **timed)
         U, st = s.solve()
     else:
         cfg = config("cfg3")
-        s = _solver(cfg, pcg_tol_eta=1e-3, precision_coarse=_abi.FP64)
+        s = _solver(cfg, precision_coarse=_abi.FP64, **timed)
         U, st = s.solve(u_init=cfg.initial_guess(s.n0))
     assert st["converged"]
     assert st["rho"][-1] <= 1e-8 * st["rho"][0]
