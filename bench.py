@@ -42,8 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # counter scaled by a 1 GiB copy).  Valid only for the kernel and solver
 # sources they were taken with: reported as null once those change.
 TRAFFIC_MEASURED = {
-    "sources_sha256": "e21cec221b330797a8f931a130a3a384fed141ad2a7d3115c546db314c5f60b3",
-    "bytes_per_launch": 773489572,
+    "sources_sha256": "d34671f2134041f1a5adf52f7301b3cd3b4f0f780bb20990a348b75da9e46864",
+    "bytes_per_launch": 766088435,
+    "kernel": "k_cg_pass_b_dia<double, 1, 1> (the autotuner's level-0 choice in the profiled run)",
     "profile": "profiles/cg_pass_b_64x512_hbm_traffic.md",
 }
 
@@ -370,6 +371,7 @@ def main():
         if roof["traffic"] is not None:
             roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["bytes_per_launch"], 3)
             roof["traffic_profile"] = TRAFFIC_MEASURED["profile"]
+            roof["traffic_kernel"] = TRAFFIC_MEASURED["kernel"]
     shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family", "prefetch_rows"), solver.kernel_shape(l)))
               for l in range(cfg.n_levels)]
     U_head = out.cpu().numpy()
