@@ -334,6 +334,11 @@ struct PDir {
 // rows keeps D rows of loads in flight instead of waiting for one row's loads
 // per row; the arithmetic of a row, and its order, do not depend on D.
 
+// Pass A needs p^.A^p^ only, and A^ is symmetric: with the upper offsets
+// o = +1, +R, +R+1 (mod n) every off-diagonal pair is met once, from its
+// lower row, so
+//   p^.A^p^ = sum_i p_i (a_ii p_i + 2 (a_i,i+1 p_i+1 + a_i,i+R p_i+R + a_i,i+R+1 p_i+R+1))
+// and a wave's window is the rows i, i+1, i+R, i+R+1: two new rows per row.
 template <typename T, int CPL, int D>
 __global__ __launch_bounds__(kBlock) void k_cg_pass_a_dia(
     int n, int R, const T* __restrict__ dv, int ncols, int ncc, int rpb, int64_t ld,
@@ -367,12 +372,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_a_dia(
   if (any && i0 < n) {
     const int iend = (i0 + rpw < n) ? i0 + rpw : n;
     // slot d holds, for a row j = d (mod D), the r^ and p^_old values of the
-    // rows j-R, j+1 and j+R+1 (index 0, 1, 2)
-    V sr[D][3], sp[D][3];
+    // rows j+1 and j+R+1 (index 0, 1)
+    V sr[D][2], sp[D][2];
     auto fill = [&](int d, int j) {
-      const int rows[3] = {wrap_index(j - R, n), wrap_index(j + 1, n), wrap_index(j + R + 1, n)};
+      const int rows[2] = {wrap_index(j + 1, n), wrap_index(j + R + 1, n)};
 #pragma unroll
-      for (int e = 0; e < 3; ++e) {
+      for (int e = 0; e < 2; ++e) {
         const int64_t o = rows[e] * ld + c0;
         sr[d][e] = V::load(r + o);
         if (!P.first) sp[d][e] = V::load(pold + o);
@@ -386,7 +391,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_a_dia(
       }
       return v;
     };
-    V lo0 = P.load(wrap_index(i0 - R - 1, n)), m0 = P.load(wrap_index(i0 - 1, n));
     V m1 = P.load(i0), hi0 = P.load(wrap_index(i0 + R, n));
 #pragma unroll
     for (int d = 0; d < D; ++d)
@@ -396,18 +400,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_a_dia(
       for (int d = 0; d < D; ++d) {
         const int i = ib + d;
         if (i < iend) {
-          const V lo1 = take(d, 0), m2 = take(d, 1), hi1 = take(d, 2);
+          const V m2 = take(d, 0), hi1 = take(d, 1);
           if (i + D < iend) fill(d, i + D);
           const T* a = dv + static_cast<int64_t>(i) * 8;
 #pragma unroll
           for (int k = 0; k < CPL; ++k) {
-            const T s = a[0] * lo0.v[k] + a[1] * lo1.v[k] + a[2] * m0.v[k] + a[3] * m1.v[k] +
-                        a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
+            const T up = a[4] * m2.v[k] + a[5] * hi0.v[k] + a[6] * hi1.v[k];
+            const T s = a[3] * m1.v[k] + T(2) * up;
             acc[0][k] += static_cast<double>(m1.v[k]) * static_cast<double>(s);
           }
           m1.store(pnew + i * ld + c0);
-          lo0 = lo1;
-          m0 = m1;
           m1 = m2;
           hi0 = hi1;
         }
