@@ -8,11 +8,16 @@ batched FP64 Jacobi-PCG, stop at a 1e-8 relative C-point residual.
 One bench step = one complete MGRIT solve to the tolerance (every part of the
 hot path: F/C relaxation, C-point residual, restriction, FAS right-hand side,
 coarse solves, correction).  `value` is the useful throughput n0 * N_t / T of
-that solve in DOF-steps/s, inputs resident on the GPU.  The timed solve stops
-the level-0 relaxation solves at max(1e-12 ||b||, 1e-3 ||r_0||) (r_0: residual
-of the warm start); the C-point residual that decides convergence solves to
-1e-12 ||b||; the coarse levels step with stored inverses (exact implicit
-Euler: one FP64 GEMM per batched step on 32x256).
+that solve in DOF-steps/s, inputs resident on the GPU.  In the timed solve:
+  - the level-0 F-relaxation solves start from the previous iterate plus the
+    change of their input since it was computed;
+  - the level-0 relaxation solves stop at max(1e-12 ||b||, 3e-3 ||r_0||)
+    (r_0: residual of the start);
+  - the C-point residual solves, which start from the current C-point values,
+    stop at max(1e-12 ||b||, 1e-4 ||r_0||), i.e. at a relative accuracy of the
+    residual itself;
+  - the coarse levels step with stored inverses (exact implicit Euler: one FP64
+    GEMM per batched step on 32x256).
 
 Also reported (same JSON line):
   - the same solve with every linear solve to 1e-12 ||b|| ("plain"),

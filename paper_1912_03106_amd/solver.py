@@ -32,7 +32,10 @@ def _check(L, h, rc):
 
 
 class Solver:
-    """One mgrit_setup handle for a workload configuration."""
+    """One mgrit_setup handle for a workload configuration.
+
+    Keyword overrides set fields of mgrit_params by name (an unknown name
+    raises), e.g. pcg_tol_eta=3e-3, warm_start=2, residual_eta=1e-4."""
 
     def __init__(self, cfg, meshes=None, stream=None, device_io=False, **overrides):
         self._L = _abi.lib()
