@@ -123,3 +123,20 @@ def test_host_validation_nonfinite_coordinate():
     meshes[0].xy = meshes[0].xy.copy()
     meshes[0].xy[7, 0] = np.nan
     assert _status_of(lambda: _solver(cfg, meshes=meshes)) in ("NONFINITE", "INVALID_ARGUMENT")
+
+
+@pytest.mark.parametrize("bad", [dict(pcg_prefetch=3), dict(warm_start=3), dict(residual_eta=1.0),
+                                 dict(residual_eta=-1e-3), dict(pcg_rows_narrow=48),
+                                 dict(compact_fraction=1.0), dict(compact_columns=-1),
+                                 dict(pcg_kernel=5), dict(pcg_tol_eta=-1.0)])
+def test_host_validation_solver_parameters(bad):
+    """Every mgrit_params check runs before the first HIP call."""
+    assert _status_of(lambda: _solver(config("cfg1"), **bad)) == "INVALID_ARGUMENT"
+
+
+def test_default_params_of_the_cg_loop():
+    L = _abi.lib()
+    p = _abi.Params()
+    L.mgrit_default_params(C.byref(p))
+    assert (p.pcg_check_every, p.compact_columns, p.compact_fraction) == (4, 64, 0.9)
+    assert (p.pcg_prefetch, p.pcg_rows_narrow, p.residual_eta, p.pcg_tol_eta) == (0, 0, 0.0, 0.0)
