@@ -108,7 +108,9 @@ typedef struct {
   int32_t pcg_max_iter;
   int32_t pcg_check_every;    /* PCG iterations between host reads of the active-column count
                                * (the points where column compaction can happen; default 4) */
-  double  ir_inner_tol;       /* FP32 inner PCG tolerance (MGRIT_FP32_IR)       */
+  double  ir_inner_tol;       /* relative tolerance of the inner CG: FP32 refinement steps and
+                               * Newton corrections; a solve with an early stop at eta times its
+                               * start residual uses min(0.1, max(ir_inner_tol, eta / 2)) */
   int32_t ir_max_iter;        /* refinement sweeps                              */
   double  newton_tol;         /* ||R(u^k)|| <= newton_tol ||R(u_prev)||        */
   int32_t newton_max_iter;

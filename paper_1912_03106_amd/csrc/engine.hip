@@ -587,7 +587,12 @@ static int newton_solve(Handle& h, int level, LevelState& S, PcgWork& w, int nco
   hipStream_t s = h.stream;
   NlWork& nw = nl_work(h, S, w);
   const double tol2 = h.par.newton_tol * h.par.newton_tol;
-  const double tin2 = h.par.ir_inner_tol * h.par.ir_inner_tol;
+  // inexact Newton: one step with a relative inner tolerance tau cuts the
+  // residual by about tau, so a solve that stops at eta times its warm-start
+  // residual needs no inner tolerance below eta / 2 (as for the refinement)
+  const double tin = h.eta_now > 0.0 ? std::min(0.1, std::max(h.par.ir_inner_tol, 0.5 * h.eta_now))
+                                      : h.par.ir_inner_tol;
+  const double tin2 = tin * tin;
   const double lam_min = std::ldexp(1.0, -h.par.newton_halvings);
   // reference ||R(u_prev)||
   launch_nl_elem(s, S.nl, ncols, w.ld, nullptr, in, nw);
