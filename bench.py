@@ -218,6 +218,8 @@ def nonlinear(N, stream, learned=True, ie=True):
     FP64 Newton residual), start-up ramp, 3-level V-cycle on the first N steps."""
     import torch
     from workload import config
+    # these solves run for minutes: one progress line per MGRIT iteration
+    os.environ.setdefault("MGRIT_VERBOSE", "1")
     from paper_1912_03106_amd.solver import Solver
     full = config("cfg4")
     cfg = config("cfg4", n_steps=N, t_final=N * full.dt)
@@ -248,6 +250,7 @@ def nonlinear(N, stream, learned=True, ie=True):
         log("nonlinear learned coarse propagator: training")
         s = Solver(cfg, stream=stream.cuda_stream, device_io=True, coarse_model=1, pcg_tol_eta=1e-3)
         ts = s.train_coarse(n_traj=128, epochs=8, batch=64, lr=2e-3, seed=5, perturb=0.3)
+        log(f"nonlinear learned: trained ({ts['time_data_s']:.0f} s data, {ts['time_train_s']:.0f} s Adam)")
         if out is None:
             out = torch.empty((N + 1, s.n0), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
