@@ -140,11 +140,11 @@ typedef struct {
                                * last one; 0 = plain Newton */
   double  pcg_tol_eta;        /* > 0: the linear solves of the level-0 F- and C-relaxation of
                                * mgrit_solve stop at ||r|| <= max(pcg_tol ||b||, eta ||r_0||), r_0
-                               * the residual of their warm start (the previous iterate), which
-                               * shrinks as MGRIT converges; their Newton iterations likewise at
-                               * ||R|| <= max(newton_tol ||R(u_prev)||, eta ||R(warm start)||).
-                               * The C-point residual and all coarse levels keep the strict
-                               * tolerances.  0 = strict throughout */
+                               * the residual of their start (see warm_start), which shrinks as
+                               * MGRIT converges; their Newton iterations likewise at
+                               * ||R|| <= max(newton_tol ||R(u_prev)||, eta ||R(start)||).  The
+                               * C-point residual keeps pcg_tol unless residual_eta > 0; all
+                               * coarse levels keep the strict tolerances.  0 = strict */
   int32_t precision_coarse;   /* arithmetic of the linear solves on levels >= 1: -1 = precision,
                                * else MGRIT_FP64 or MGRIT_FP32_IR (level 0 always uses precision) */
   int32_t coarse_model;       /* coarsest-level propagator: 0 implicit Euler (Sec. 2.1
