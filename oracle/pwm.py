@@ -63,6 +63,10 @@ def ramp(t, src):
 
 
 def phase_signals(t, src):
-    """[3, len(t)] array of b_p(t)."""
+    """[3, len(t)] array of b_p(t); with src.signal == "sine" the sine
+    references r_p(t) themselves (the smooth source that drives the
+    nested-iteration start, Sec. 4.1)."""
     t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    if getattr(src, "signal", "pwm") == "sine":
+        return np.stack([reference(t, src, p) for p in range(3)])
     return np.stack([pwm(t, src, p) for p in range(3)])

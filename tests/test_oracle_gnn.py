@@ -166,3 +166,49 @@ def test_parameter_count_and_layout():
     assert gnn.n_params(m) == 4 + 23 * 64 + 64 + 3 * (2 * 64 * 64 + 64) + 64 + 1
     v = np.arange(gnn.n_params(m), dtype=np.float64)
     assert np.array_equal(gnn.pack(gnn.unpack(v, m), m), v)
+
+
+def test_node_flags_from_the_band_layout():
+    """Node flags of the 16 x 128 machine mesh derived independently of the
+    finite-element matrices: every radial cell row of 5 mm belongs to one band
+    of the layout (rows 0-4 rotor iron, 5-6 bar band, 7 air gap, 8-10 slot
+    band, 11-15 stator iron); in the bar band a cell is an aluminium bar when
+    its centre angle lies in the first half of a 1/28 pitch, in the slot band
+    a coil when it lies in the first half of a 1/36 pitch (integer tests on
+    (2j+1) * pitches mod 256, exact); interior node (i, j) touches the cells
+    (i-1, j-1), (i-1, j), (i, j-1), (i, j).  Flags: conductor, iron, coil,
+    normalised radius i/16."""
+    n_r, n_t = 16, 128
+    fe = MachineFE(polar_mesh(n_r, n_t))
+    got = gnn.node_flags(fe)
+    assert got.shape == ((n_r - 1) * n_t, 4)
+
+    def cell(i, j):
+        j %= n_t
+        bar = ((2 * j + 1) * 28) % 256 < 128
+        slot = ((2 * j + 1) * 36) % 256 < 128
+        if i <= 4:
+            return "iron"
+        if i <= 6:
+            return "bar" if bar else "iron"
+        if i == 7:
+            return "air"
+        if i <= 10:
+            return "coil" if slot else "iron"
+        return "iron"
+
+    want = np.zeros_like(got)
+    for i in range(1, n_r):
+        for j in range(n_t):
+            kinds = {cell(i - 1, j - 1), cell(i - 1, j), cell(i, j - 1), cell(i, j)}
+            k = (i - 1) * n_t + j
+            want[k] = ["bar" in kinds, "iron" in kinds, "coil" in kinds, i / n_r]
+    assert np.array_equal(got[:, :3], want[:, :3])
+    assert np.allclose(got[:, 3], want[:, 3], rtol=0, atol=1e-12)
+    # hand-checked nodes: (1, 0) rotor iron only; (6, 0) bar cell (5, 0) next
+    # to iron cell (5, 127); (8, 0) slot cell (8, 0) next to the tooth (8, 127)
+    assert list(got[0, :3]) == [0, 1, 0]
+    assert list(got[5 * n_t, :3]) == [1, 1, 0]
+    assert list(got[7 * n_t, :3]) == [0, 1, 1]
+    # ring 7 touches only the bar band and the air gap: no coil there
+    assert not got[6 * n_t:7 * n_t, 2].any()

@@ -162,7 +162,9 @@ class Source:
     frequency `f_carrier`.  `carrier` is "triangle" (c(0) = 1) or "sawtooth"
     (the paper's trailing-edge carrier).  `ramp_periods` > 0 multiplies the
     source by the smooth start-up factor of the nonlinear model over its first
-    `ramp_periods` electric periods (0: no ramp).
+    `ramp_periods` electric periods (0: no ramp).  `signal` "sine" drives the
+    coils with the sine references themselves instead of their PWM signals
+    (the smooth source of the nested-iteration start, Sec. 4.1).
     """
     J0: float = 1.0e7
     freq: float = 50.0
@@ -172,6 +174,7 @@ class Source:
     phase_offset: float = 0.0
     amplitude: float = 1.0
     ramp_periods: float = 0.0
+    signal: str = "pwm"
 
     @property
     def carrier_code(self) -> int:
