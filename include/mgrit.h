@@ -223,6 +223,26 @@ int mgrit_seq_solve(void* h, const double* u0, double* u_out, mgrit_stats* st);
 int phi_step(void* h, int32_t level, int32_t B, const int64_t* i_from,
              const double* u_prev, double* u_next);
 
+/* Allocation-free phi_step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same operation, layout and errors as phi_step, except that
+ * i_from [B], u_prev [B][n_level] and u_next [B][n_level] are DEVICE
+ * pointers owned by the caller.  Every workspace of the call lives in one
+ * static device array of the library, 134.8 MiB per GPU, which each GPU the
+ * library runs on holds until the process ends; the call allocates nothing
+ * (no hipMalloc / hipFree, no allocating library routine) and does not use
+ * graph replay or column compaction (the same iterates as phi_step).
+ * Limits: n_level * round_up(B, 64) <= 2^21 (e.g. B <= 64 on the 64 x 512
+ * mesh, B <= 1024 on 16 x 128), B <= 32768, pcg_max_iter <= 65472: else
+ * MGRIT_INVALID_ARGUMENT.  The nonlinear model (its Newton workspace does not
+ * fit) and intermediate levels stepped by a stored inverse (a library GEMM):
+ * MGRIT_UNSUPPORTED.  The array is shared by every call on one GPU and keeps
+ * the last call's contents: calls that overlap on one GPU (other threads,
+ * handles or streams) race, so the caller serialises them.  The handle's
+ * device must be current.  Returns after the stream is synchronized. */
+int phi_step_noalloc(void* h, int32_t level, int32_t B, const int64_t* i_from,
+                     const double* u_prev, double* u_next);
+
 /* Sizes of a level: unknowns, steps, stored entries of the operator (fixed
  * row width times n), and kernel_shape[4] of its batched PCG kernels as the
  * autotuner chose them: rows per work-group, columns per lane, kernel family

@@ -26,7 +26,7 @@ EXPORTS = ("mgrit_default_params", "mgrit_setup", "mgrit_solve", "mgrit_seq_solv
            "mgrit_level_info", "mgrit_destroy", "mgrit_strerror", "mgrit_last_error",
            "mgrit_train_coarse", "mgrit_coarse_n_params", "mgrit_set_coarse_weights",
            "mgrit_get_coarse_weights", "mgrit_coarse_apply", "mgrit_coarse_gradient",
-           "mgrit_coarse_adam")
+           "mgrit_coarse_adam", "phi_step_noalloc")
 
 
 class Mesh(C.Structure):
@@ -126,6 +126,8 @@ def lib():
     L.mgrit_seq_solve.restype = C.c_int
     L.phi_step.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.phi_step.restype = C.c_int
+    L.phi_step_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
+    L.phi_step_noalloc.restype = C.c_int
     L.mgrit_level_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_int32 * 4)]
     L.mgrit_level_info.restype = C.c_int

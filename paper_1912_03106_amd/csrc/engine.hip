@@ -108,6 +108,8 @@ struct Handle {
   const double* col_amp = nullptr;   // per-column source amplitude factors / phase
   const double* col_dphi = nullptr;  // shifts of phi_batch (training data only)
   bool verbose = false;      // MGRIT_VERBOSE: one line per MGRIT iteration on stderr
+  int device = 0;           // HIP device the handle was set up on
+  bool noalloc = false;     // inside phi_step_noalloc: no graph capture, no compaction buffers
   double tol_now = 1e-12;   // relative residual of the linear solves
   double eta_now = 0.0;     // > 0: linear solves also stop at eta times their initial residual
   hipStream_t capture_stream = nullptr;
@@ -361,7 +363,7 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
   // arithmetic does not depend on its position, so the iterates are the
   // same).  set = -1: the caller's buffers; 0 / 1: alternate sets.
   const bool fp32 = (kind == IT_LIN32);
-  const bool can_compact = h.par.compact_columns > 0 && kind != IT_JAC;
+  const bool can_compact = h.par.compact_columns > 0 && kind != IT_JAC && !h.noalloc;
   void* ox = fp32 ? static_cast<void*>(w.x32) : static_cast<void*>(w.x);
   void* orr = fp32 ? static_cast<void*>(w.r32) : static_cast<void*>(w.r);
   void* op0 = fp32 ? static_cast<void*>(w.p32[0]) : static_cast<void*>(w.pbuf[0]);
@@ -403,7 +405,8 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
     // (the first carries the `first` iteration and runs eagerly).  HIP events
     // recorded inside a graph do not time its kernels reliably, so profiled
     // solves launch eagerly; compacted column sets change every interval.
-    const bool graph = h.par.use_graphs && !prof && set < 0 && it > 0 && k == chunk && (chunk % 2) == 0;
+    const bool graph = h.par.use_graphs && !prof && !h.noalloc && set < 0 && it > 0 && k == chunk &&
+                       (chunk % 2) == 0;
     if (graph) {
       const Handle::GraphKey key{w.x, &L, w.nl, w.rows_per_block, w.cpl, w.dia ? 1 : 0, w.depth, w.parity,
                                  cur, kind, chunk, tol2};
@@ -993,6 +996,43 @@ static void build_coarse_inverse(Handle& h, LevelState& S) {
 }
 
 // ---------------------------------------------------------------------------
+// Workspace of phi_step_noalloc: one static device array per GPU.  Host code
+// never passes `scratch` itself to a kernel (in host code the name is a
+// host-side stand-in, not a device address): set-up takes the array's device
+// address once per device with hipGetSymbolAddress and the entry point carves
+// every buffer out of that address.
+constexpr int64_t kNoallocVec = int64_t(1) << 21;   // n * round_up(B, 64) at most
+constexpr int64_t kNoallocCols = 32768;             // B at most
+constexpr int64_t kNoallocHist = 65536;             // pcg_max_iter + 64 at most
+constexpr size_t kAlign = 256;
+constexpr size_t align_up(size_t a) { return (a + kAlign - 1) / kAlign * kAlign; }
+// worst case of noalloc_bytes(): 6 FP64 and 4 FP32 vectors, partial sums of
+// 16-row blocks, the per-column scalars, source table, masks, flags, history
+constexpr size_t kScratchBytes =
+    align_up(6 * 8 * kNoallocVec) + align_up(4 * 4 * kNoallocVec) +
+    align_up(3 * 8 * (kNoallocVec / 16 + kNoallocCols)) + align_up(8 * 8 * kNoallocCols) +
+    align_up(3 * 8 * kNoallocCols) + 2 * align_up(kNoallocCols) + align_up(8 * 4) +
+    align_up(4 * kNoallocHist);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (taken once per device).
+static void init_scratch(Handle& h) {
+  MG_HIP(hipGetDevice(&h.device));
+  if (h.device < 0 || h.device >= kMaxDevices) fail(MGRIT_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[h.device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    fail(MGRIT_HIP_ERROR, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[h.device] = ptr;
+}
+
+// ---------------------------------------------------------------------------
 // Setup.
 
 static void setup_gnn(Handle& h, const mgrit_mesh& mesh, const HostPattern& pat, const mgrit_physics& ph);
@@ -1071,6 +1111,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   }
   // device phase
   hipStream_t s = h.stream;
+  init_scratch(h);
   h.lv.resize(L);
   double dt = ph.dt;
   int64_t N = ph.n_steps;
@@ -1402,6 +1443,93 @@ static void phi_step_impl(Handle& h, int level, int B, const int64_t* i_from, co
   }
 }
 
+// phi_step on device arrays with every buffer carved out of the static
+// scratch array of the handle's device: no allocation of any kind.
+static void phi_step_noalloc_impl(Handle& h, int level, int B, const int64_t* i_from,
+                                  const double* u_prev, double* u_next) {
+  h.tol_now = h.par.pcg_tol;
+  h.eta_now = 0.0;
+  if (level < 0 || level >= static_cast<int>(h.lv.size())) fail(MGRIT_INVALID_ARGUMENT, "level");
+  if (B < 0 || (B > 0 && (!i_from || !u_prev || !u_next))) fail(MGRIT_INVALID_ARGUMENT, "phi_step arguments");
+  if (B == 0) return;
+  LevelState& S = h.lv[level];
+  if (S.nl.n_tri > 0)
+    fail(MGRIT_UNSUPPORTED, "phi_step_noalloc: the nonlinear model's Newton workspace does not fit the scratch array");
+  if (S.Ainv && !S.coarsest)
+    fail(MGRIT_UNSUPPORTED, "phi_step_noalloc: this level steps by a library GEMM that may allocate");
+  const int64_t ld = round_up(B, kWave);
+  if (ld > kNoallocCols || static_cast<int64_t>(S.n) * ld > kNoallocVec)
+    fail(MGRIT_INVALID_ARGUMENT, "phi_step_noalloc: n * round_up(B, 64) must be <= 2^21 and B <= 32768 (scratch size)");
+  const int hist_cap = h.par.pcg_max_iter + 64;
+  if (hist_cap > kNoallocHist) fail(MGRIT_INVALID_ARGUMENT, "phi_step_noalloc: pcg_max_iter must be <= 65472");
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_ptr[h.device]);
+  if (!base) fail(MGRIT_HIP_ERROR, "phi_step_noalloc: scratch address not initialised");
+  int cur_dev = -1;
+  MG_HIP(hipGetDevice(&cur_dev));
+  if (cur_dev != h.device) fail(MGRIT_INVALID_ARGUMENT, "phi_step_noalloc: the handle's device is not current");
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    void* p = base + off;
+    off += align_up(bytes);
+    if (off > kScratchBytes) fail(MGRIT_INVALID_ARGUMENT, "phi_step_noalloc: scratch array too small");
+    return p;
+  };
+  const size_t V = static_cast<size_t>(S.n) * ld;
+  PcgWork w;
+  w.n = S.n;
+  w.cap = B;
+  w.ld = ld;
+  w.prec = S.prec;
+  set_rows_per_block(w, S.pcg.rows_per_block);
+  w.cpl = S.pcg.cpl;
+  w.dia = S.pcg.dia;
+  w.depth = S.pcg.depth;
+  w.rpb_narrow = S.pcg.rpb_narrow;
+  w.x = static_cast<double*>(carve(8 * V));
+  w.r = static_cast<double*>(carve(8 * V));
+  w.pbuf[0] = static_cast<double*>(carve(8 * V));
+  w.pbuf[1] = static_cast<double*>(carve(8 * V));
+  double* cols = static_cast<double*>(carve(8 * V));
+  double* outc = static_cast<double*>(carve(8 * V));
+  if (w.prec == MGRIT_FP32_IR) {
+    w.r32 = static_cast<float*>(carve(4 * V));
+    w.x32 = static_cast<float*>(carve(4 * V));
+    w.p32[0] = static_cast<float*>(carve(4 * V));
+    w.p32[1] = static_cast<float*>(carve(4 * V));
+  }
+  const int nrb_max = (S.n + kMinRowsPerBlock - 1) / kMinRowsPerBlock;
+  w.part = static_cast<double*>(carve(8 * 3 * static_cast<size_t>(nrb_max) * ld));
+  w.scal = static_cast<double*>(carve(8 * 8 * static_cast<size_t>(ld)));
+  w.src = static_cast<double*>(carve(8 * 3 * static_cast<size_t>(ld)));
+  w.active = static_cast<uint8_t*>(carve(ld));
+  w.outer = static_cast<uint8_t*>(carve(ld));
+  w.flags = static_cast<int*>(carve(8 * sizeof(int)));
+  w.hist_cap = hist_cap;
+  w.hist = static_cast<int*>(carve(sizeof(int) * hist_cap));
+  // pinned host mirrors: the level's own (one handle per thread)
+  w.host_flags = S.pcg.host_flags;
+  w.host_hist = S.pcg.host_hist;
+  if (S.pcg.hist_cap < hist_cap) fail(MGRIT_INVALID_ARGUMENT, "phi_step_noalloc: history mirror too small");
+  hipStream_t s = h.stream;
+  // the array keeps the previous call's contents: clear what must start at zero
+  MG_HIP(hipMemsetAsync(w.flags, 0, 8 * sizeof(int), s));
+  launch_tm_to_slabs(s, S.n, B, 1, u_prev, cols, ld, 0, S.nat);
+  PhiCall c;
+  c.ncols = B;
+  c.in = CView{cols, ld};
+  c.t_list = i_from;
+  c.ga = c.in;
+  c.out = outc;
+  c.ldo = ld;
+  struct Reset {
+    Handle& h;
+    ~Reset() { h.noalloc = false; }
+  } reset{h};
+  h.noalloc = true;
+  phi_batch(h, level, w, c);
+  launch_slabs_to_tm(s, S.n, B, 1, outc, ld, 0, u_next, S.nat);
+  MG_HIP(hipStreamSynchronize(s));
+}
 
 // ---------------------------------------------------------------------------
 // Learned coarse propagator: model set-up, training data, training.
@@ -1971,6 +2099,13 @@ int phi_step(void* hp, int32_t level, int32_t B, const int64_t* i_from, const do
   auto* h = static_cast<mg::Handle*>(hp);
   if (!h) return MGRIT_INVALID_ARGUMENT;
   return guarded(h, [&] { mg::phi_step_impl(*h, level, B, i_from, u_prev, u_next); });
+}
+
+int phi_step_noalloc(void* hp, int32_t level, int32_t B, const int64_t* i_from, const double* u_prev,
+                     double* u_next) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] { mg::phi_step_noalloc_impl(*h, level, B, i_from, u_prev, u_next); });
 }
 
 int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
