@@ -68,12 +68,15 @@ class ExactCoarse:
 
 class Hierarchy:
     """levels[l] has .phi(u [B, n_l], i_from [B]) and .n; R[l], P[l] map l <-> l+1
-    (None = same mesh, no spatial transfer)."""
+    (None = same mesh, no spatial transfer).  m is the temporal coarsening
+    factor of every level, or a list: m[l] between levels l and l+1 (Sec. 4.2
+    coarsens the first level by a large factor and the others by a small one)."""
 
     def __init__(self, levels, m, R=None, P=None, gamma=1):
         self.levels = levels
-        self.m = m
         L = len(levels)
+        self.ms = list(m) if isinstance(m, (list, tuple)) else [m] * max(L - 1, 1)
+        self.m = self.ms[0]
         self.R = R if R is not None else [None] * (L - 1)
         self.P = P if P is not None else [None] * (L - 1)
         self.gamma = gamma
@@ -92,7 +95,7 @@ class Hierarchy:
 
 
 def f_relax(H, l, u, g):
-    m, N = H.m, u.shape[0] - 1
+    m, N = H.ms[l], u.shape[0] - 1
     for j in range(1, m):
         idx = np.arange(j, N + 1, m)          # F-points k*m + j
         if idx.size == 0:
@@ -101,7 +104,7 @@ def f_relax(H, l, u, g):
 
 
 def c_relax(H, l, u, g):
-    m, N = H.m, u.shape[0] - 1
+    m, N = H.ms[l], u.shape[0] - 1
     idx = np.arange(m, N + 1, m)              # C-points k >= 1
     u[idx] = H.phi(l, u[idx - 1], idx - 1) + g[idx]
 
@@ -115,7 +118,7 @@ def relax(H, l, u, g):
 
 def c_residual(H, l, u, g):
     """r [N_T+1, n]: r_0 = g_0 - u_0, r_k = g_km - u_km + Phi(u_km-1)."""
-    m, N = H.m, u.shape[0] - 1
+    m, N = H.ms[l], u.shape[0] - 1
     idx = np.arange(m, N + 1, m)
     r = np.zeros((idx.size + 1, u.shape[1]))
     r[0] = g[0] - u[0]
@@ -124,7 +127,7 @@ def c_residual(H, l, u, g):
 
 
 def coarse_correct(H, l, u, g, r, kind="V"):
-    m = H.m
+    m = H.ms[l]
     cidx = np.arange(0, u.shape[0], m)
     u2 = Hierarchy._apply(H.R[l], u[cidx])
     rr = Hierarchy._apply(H.R[l], r)
@@ -173,7 +176,7 @@ def joule_losses(level, u_prev, u, dt, l_z=1.0):
 
 def c_point_losses(H, u):
     """Joule losses at the C-points k >= 1 of the finest level (u_km against u_km-1)."""
-    m, N = H.m, u.shape[0] - 1
+    m, N = H.ms[0], u.shape[0] - 1
     idx = np.arange(m, N + 1, m)
     return joule_losses(H.levels[0], u[idx - 1], u[idx], H.levels[0].dt)
 
@@ -202,7 +205,9 @@ def nested_iteration(H, u0, n_steps):
     the returned [(n_steps+1), n0] array is a consistent finest-level
     trajectory of that cycle."""
     L = len(H.levels)
-    Ns = [n_steps // H.m ** l for l in range(L)]
+    Ns = [n_steps]
+    for l in range(L - 1):
+        Ns.append(Ns[-1] // H.ms[l])
     # coarsest problem: g_0 = restricted initial value, g_i = 0
     uc = np.zeros((Ns[-1] + 1, H.levels[-1].n))
     gc = np.zeros_like(uc)
@@ -212,7 +217,7 @@ def nested_iteration(H, u0, n_steps):
         u = np.zeros((Ns[l] + 1, H.levels[l].n))
         g = np.zeros_like(u)
         g[0] = restrict_down(H, u0, l)
-        u[::H.m] = Hierarchy._apply(H.P[l], uc)
+        u[::H.ms[l]] = Hierarchy._apply(H.P[l], uc)
         u[0] = g[0]
         cycle(H, l, u, g, "V")
         uc = u

@@ -35,4 +35,4 @@ def build(cfg, restriction="normalized"):
             P.append(Ps)
             R.append(transfer.restriction(Ps, restriction)
                      if restriction != "injection" else transfer.injection(fine, coarse))
-    return Hierarchy(levels, cfg.m, R=R, P=P, gamma=cfg.gamma), meshes
+    return Hierarchy(levels, cfg.level_factors(), R=R, P=P, gamma=cfg.gamma), meshes

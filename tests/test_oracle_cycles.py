@@ -104,14 +104,17 @@ class DenseLevel:
 class DenseHierarchy:
     def __init__(self, H, n_steps):
         self.H = H
-        self.m = H.m
         self.L = len(H.levels)
-        self.lev = [DenseLevel(H.levels[l], n_steps // H.m ** l) for l in range(self.L)]
+        Ns = [n_steps]
+        for l in range(self.L - 1):
+            Ns.append(Ns[-1] // H.ms[l])
+        self.lev = [DenseLevel(H.levels[l], Ns[l]) for l in range(self.L)]
 
     def _masks(self, l):
         N = self.lev[l].N
         pts = np.arange(N + 1)
-        return pts % self.m == 0, pts % self.m != 0
+        m = self.H.ms[l] if l < self.L - 1 else 1
+        return pts % m == 0, pts % m != 0
 
     def _rows(self, l, mask):
         n = self.lev[l].n
@@ -192,7 +195,7 @@ class DenseHierarchy:
                 u[:] = np.linalg.solve(D.A, (g + D.c).ravel()).reshape(u.shape)
             else:
                 P = self.H.P[l]
-                u[::self.m] = uc if P is None else (P @ uc.T).T
+                u[::self.H.ms[l]] = uc if P is None else (P @ uc.T).T
                 self.cycle(l, u, g, "V")
             uc = u
         return uc
@@ -321,3 +324,67 @@ def test_loss_stop_rule_ends_when_the_losses_settle():
         rel = np.abs(losses[-1][nz] - p_seq[nz]) / p_seq[nz]
         assert rel.max() < 20 * tol, rel.max()
     assert its[1] >= its[0]
+
+
+# --- per-level coarsening factors and delayed spatial coarsening -------------
+
+def test_per_level_factors_match_dense_space_time_block_solves():
+    """Four levels with m = 4 on the first level and 2 below (the paper's
+    pattern of a large first factor and small coarse ones, Sec. 4.1), with
+    spatial coarsening on the last level: V- and F-cycles against the dense
+    block solves."""
+    cfg = _tiny_cfg([(8, 32), (8, 32), (8, 32), (4, 16)], 16, 4, m_coarse=2)
+    assert cfg.level_factors() == [4, 2, 2] and cfg.level_steps(3) == 1
+    for kind in ("V", "F"):
+        H, _ = build(cfg)
+        H.cycle = kind
+        n = H.levels[0].n
+        U, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=0.0, maxit=2)
+        Ud, hd = DenseHierarchy(H, cfg.n_steps).solve(2, kind)
+        for a, b in zip(hist, hd):
+            assert abs(a - b) <= 1e-10 * hd[0], (kind, a, b)
+        assert np.linalg.norm(U - Ud) <= 1e-10 * np.linalg.norm(Ud)
+
+
+def test_five_level_exact_after_nt_over_2m0_fcf():
+    """Five levels, m = 4 then 2, no spatial coarsening: FCF relaxation on the
+    finest level makes two more of its intervals exact per iteration, so the
+    iterate is the sequential solution after N_t / (2 m_0) iterations."""
+    cfg = _tiny_cfg([(4, 16)] * 5, 128, 4, m_coarse=2)
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    U, _, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=0.0, maxit=cfg.n_steps // (2 * cfg.m))
+    assert np.linalg.norm(U - U_seq) <= 1e-12 * np.linalg.norm(U_seq)
+
+
+def test_five_level_spatial_coarsening_strategies():
+    """Five-level V-cycles with FCF relaxation, m = 4 then 2, and three nested
+    meshes 16x64, 8x32, 4x16 (n = 960, 224, 48), with direct spatial
+    coarsening (coarse meshes from level 1 on) or delayed spatial coarsening
+    (the coarser meshes only on the two coarsest levels, Sec. 2.2, Fig. 5).
+    Delayed coarsening converges in about as many iterations as coarsening in
+    time only; direct coarsening onto meshes this coarse degrades the
+    convergence (the effect the delayed strategy is meant to avoid, Sec. 2.2)
+    but, with FCF relaxation, still terminates: the C-relaxation makes one
+    more interval of the finest level exact before every restriction, so the
+    iterate is exact after N_t / m_0 iterations."""
+    fine, mid, coarse = (16, 64), (8, 32), (4, 16)
+    out = {}
+    for strategy, meshes in (("none", [fine] * 5), ("delayed", [fine, fine, fine, mid, coarse]),
+                             ("direct", [fine, mid, coarse, coarse, coarse])):
+        cfg = _tiny_cfg(meshes, 256, 4, m_coarse=2)
+        H, _ = build(cfg)
+        n = H.levels[0].n
+        U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+        maxit = cfg.n_steps // cfg.m if strategy == "direct" else 30
+        U, hist, conv = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=1e-8 if strategy != "direct" else 0.0,
+                                    maxit=maxit)
+        out[strategy] = (hist, np.linalg.norm(U - U_seq) / np.linalg.norm(U_seq))
+    assert out["delayed"][1] <= 1e-7 and out["none"][1] <= 1e-7
+    assert len(out["delayed"][0]) <= len(out["none"][0]) + 2
+    assert out["direct"][1] <= 1e-10
+    # after as many iterations as delayed coarsening needs, direct coarsening
+    # is still far from converged
+    k = len(out["delayed"][0]) - 1
+    assert out["direct"][0][k] / out["direct"][0][0] > 1e3 * out["delayed"][0][k] / out["delayed"][0][0]

@@ -7,7 +7,8 @@ and the initial guess.  Everything here is a setting or a seeded random array;
 none of it is the method's arithmetic.
 
 Time grid: t in [0, 0.02] s (one 50 Hz period), t_i = i * dt.  Level l of an
-MGRIT hierarchy uses dt_l = m**l * dt and N_l = N_t / m**l steps.
+MGRIT hierarchy uses dt_l = m**l * dt and N_l = N_t / m**l steps, or with
+m_coarse > 0 the factor m between levels 0 and 1 and m_coarse below.
 """
 
 from dataclasses import dataclass, field, replace
@@ -41,6 +42,7 @@ class Config:
     newton_maxit: int = 8
     newton_halvings: int = 6    # damping: step lengths 1, 1/2, ..., 2**-newton_halvings
     coarse: str = "implicit_euler"  # or "learned"
+    m_coarse: int = 0           # coarsening factor between levels l >= 1 and l+1 (0 = m)
 
     @property
     def n_levels(self) -> int:
@@ -50,11 +52,16 @@ class Config:
     def dt(self) -> float:
         return self.t_final / self.n_steps
 
+    def level_factors(self) -> list:
+        """Temporal coarsening factor between level l and l+1, for every l."""
+        mc = self.m_coarse if self.m_coarse > 0 else self.m
+        return [self.m] + [mc] * max(self.n_levels - 2, 0)
+
     def level_steps(self, l: int) -> int:
-        return self.n_steps // self.m ** l
+        return self.n_steps // int(np.prod(self.level_factors()[:l], dtype=np.int64))
 
     def level_dt(self, l: int) -> float:
-        return self.dt * self.m ** l
+        return self.dt * int(np.prod(self.level_factors()[:l], dtype=np.int64))
 
     @property
     def spatial_coarsening(self) -> bool:
