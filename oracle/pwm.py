@@ -54,8 +54,9 @@ def pwm(t, src, phase_index):
 
 
 def ramp(t, src):
-    """Start-up factor alpha(t) of the nonlinear model (1 when src.ramp_periods = 0)."""
-    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    """Start-up factor alpha(t) of the nonlinear model (1 when src.ramp_periods = 0),
+    at the shifted time t_start + t."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64)) + getattr(src, "t_start", 0.0)
     if src.ramp_periods <= 0:
         return np.ones_like(t)
     span = src.ramp_periods / src.freq
@@ -65,8 +66,8 @@ def ramp(t, src):
 def phase_signals(t, src):
     """[3, len(t)] array of b_p(t); with src.signal == "sine" the sine
     references r_p(t) themselves (the smooth source that drives the
-    nested-iteration start, Sec. 4.1)."""
-    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    nested-iteration start, Sec. 4.1).  Sampled at the shifted time t_start + t."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64)) + getattr(src, "t_start", 0.0)
     if getattr(src, "signal", "pwm") == "sine":
         return np.stack([reference(t, src, p) for p in range(3)])
     return np.stack([pwm(t, src, p) for p in range(3)])

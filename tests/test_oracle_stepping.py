@@ -150,3 +150,17 @@ def test_damping_does_not_move_the_root():
         if hv:
             assert min(L.newton_lambdas) < 1.0
     assert np.linalg.norm(out[0] - out[1]) <= 1e-9 * np.linalg.norm(out[0])
+
+
+def test_window_with_shifted_time_origin_continues_the_trajectory():
+    """A run of 48 steps whose source starts at t_start = 200 dt, started
+    from the state at step 200, continues the 248-step trajectory."""
+    from dataclasses import replace
+    from workload import config
+    cfg = config("cfg1")
+    mesh = polar_mesh(16, 128)
+    lev = Level(mesh, cfg.dt, cfg.source)
+    U = sequential(lev, np.zeros(lev.n), 248)
+    win = Level(mesh, cfg.dt, replace(cfg.source, t_start=200 * cfg.dt))
+    W = sequential(win, U[200], 48)
+    assert np.linalg.norm(W - U[200:]) <= 1e-12 * np.linalg.norm(U[200:])

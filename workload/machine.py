@@ -164,7 +164,9 @@ class Source:
     source by the smooth start-up factor of the nonlinear model over its first
     `ramp_periods` electric periods (0: no ramp).  `signal` "sine" drives the
     coils with the sine references themselves instead of their PWM signals
-    (the smooth source of the nested-iteration start, Sec. 4.1).
+    (the smooth source of the nested-iteration start, Sec. 4.1).  `t_start`
+    shifts the time origin: step i of a run samples the source at
+    t_start + i*dt (a window of a longer horizon, started from a state of it).
     """
     J0: float = 1.0e7
     freq: float = 50.0
@@ -175,6 +177,7 @@ class Source:
     amplitude: float = 1.0
     ramp_periods: float = 0.0
     signal: str = "pwm"
+    t_start: float = 0.0        # the source is evaluated at t_start + t (a window of the horizon)
 
     @property
     def carrier_code(self) -> int:
