@@ -86,6 +86,10 @@ typedef struct {
   double dt;                  /* finest step; t_i = i * dt */
   int64_t n_steps;            /* N_t on the finest level */
   double ramp_periods;        /* start-up ramp length in electric periods (0 = none) */
+  int32_t signal;             /* 0: the PWM signals b_p; 1: the sine references themselves
+                               * drive the coils (the smooth source of Sec. 4.1) */
+  double t_start;             /* time origin: point i samples the source at t_start + i dt
+                               * (a window of a longer horizon; 0 = the horizon's start) */
 } mgrit_physics;
 
 typedef struct {
@@ -166,6 +170,16 @@ typedef struct {
   int32_t pcg_rows_narrow;    /* rows per work-group of the batched PCG passes once at most 128
                                * columns still iterate (shorter dependent-load walks): 0 = the
                                * autotuner's choice, -1 = never switch, 16/32/64/128/256 = this */
+  int32_t cycle;              /* 0 V-cycles; 1 F-cycles: the coarse problem of a level is
+                               * approximated by an F-cycle and then a V-cycle on the next level
+                               * (Sec. 2.1, Fig. 4) */
+  int32_t nested;             /* 1: start from the nested-iteration guess (Sec. 2.1): the coarsest
+                               * time-stepping problem solved sequentially, then per finer level
+                               * its points interpolated to the C-points and one V-cycle, all with
+                               * the sine references as the source (Sec. 4.1); u_init is ignored */
+  double  loss_tol;           /* > 0: stop once the Joule losses at the C-points change by less than
+                               * loss_tol (relative, every C-point) between two successive
+                               * iterations (Sec. 5.1 uses 1e-2) instead of the residual test */
 } mgrit_params;
 
 typedef struct {
@@ -188,6 +202,11 @@ typedef struct {
   double  time_total_s;
   int32_t coarse_fallback;    /* coarse_model = 1: iteration after which the residual grew and
                                * the coarsest level went back to implicit Euler; -1 = never */
+  double  time_nested_s;      /* nested = 1: time of the nested-iteration start (in time_total_s) */
+  double  loss_change[MGRIT_MAX_HISTORY];  /* loss_tol > 0: largest relative change of the C-point
+                               * Joule losses against the previous iteration (-1 for the first) */
+  double  time_phi_s[MGRIT_MAX_LEVELS];    /* profile_kernels = 1: wall time of each level's Phi
+                               * applications and coarsest solve (stream drained around each) */
 } mgrit_stats;
 
 /* Fill *par with the defaults (m = 16, FCF, FP64, normalized restriction,
@@ -211,6 +230,14 @@ int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par,
  * Returns MGRIT_NOT_CONVERGED (with u_out and *st filled) if max_iter is hit. */
 int mgrit_solve(void* h, const double* u0, const double* u_init, double* u_out,
                 mgrit_stats* st);
+
+/* Joule losses P(t_i) = l_z (du/dt)^T M (du/dt), du/dt = (u_i - u_{i-1}) / dt the
+ * backward difference of the implicit-Euler grid, M the sigma-weighted mass
+ * matrix, l_z = 1 m (Sec. 3.1, the loss integral), at every point of the
+ * iterate the last mgrit_solve on this handle returned: p [N_t + 1], p[0] = 0,
+ * in W per metre of axial length.  A device pointer when device_pointers = 1.
+ * INVALID_ARGUMENT before a completed solve. */
+int mgrit_joule_losses(void* h, double* p);
 
 /* Sequential forward block solve (Sec. 2) on the finest level, on the GPU:
  * u_out [(N_t+1)][n_0] = (u0, Phi_1(u0), ...).  u0 may be NULL (= 0). */

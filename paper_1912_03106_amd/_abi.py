@@ -26,7 +26,7 @@ EXPORTS = ("mgrit_default_params", "mgrit_setup", "mgrit_solve", "mgrit_seq_solv
            "mgrit_level_info", "mgrit_destroy", "mgrit_strerror", "mgrit_last_error",
            "mgrit_train_coarse", "mgrit_coarse_n_params", "mgrit_set_coarse_weights",
            "mgrit_get_coarse_weights", "mgrit_coarse_apply", "mgrit_coarse_gradient",
-           "mgrit_coarse_adam", "phi_step_noalloc")
+           "mgrit_coarse_adam", "phi_step_noalloc", "mgrit_joule_losses")
 
 
 class Mesh(C.Structure):
@@ -46,7 +46,7 @@ class Physics(C.Structure):
         ("J0", C.c_double), ("amplitude", C.c_double), ("freq", C.c_double),
         ("f_carrier", C.c_double), ("phase_offset", C.c_double), ("phases", C.c_double * 3),
         ("carrier", C.c_int32), ("dt", C.c_double), ("n_steps", C.c_int64),
-        ("ramp_periods", C.c_double),
+        ("ramp_periods", C.c_double), ("signal", C.c_int32), ("t_start", C.c_double),
     ]
 
 
@@ -66,6 +66,7 @@ class Params(C.Structure):
         ("pcg_tol_eta", C.c_double), ("precision_coarse", C.c_int32), ("coarse_model", C.c_int32),
         ("compact_columns", C.c_int32), ("compact_fraction", C.c_double),
         ("pcg_prefetch", C.c_int32), ("residual_eta", C.c_double), ("pcg_rows_narrow", C.c_int32),
+        ("cycle", C.c_int32), ("nested", C.c_int32), ("loss_tol", C.c_double),
     ]
 
 
@@ -78,7 +79,8 @@ class Stats(C.Structure):
         ("kernel_launches", (C.c_int64 * MAX_LEVELS) * 2), ("kernel_columns", C.c_int64 * MAX_LEVELS),
         ("kernel_time_s", (C.c_double * MAX_LEVELS) * 2),
         ("time_relax_s", C.c_double), ("time_total_s", C.c_double),
-        ("coarse_fallback", C.c_int32),
+        ("coarse_fallback", C.c_int32), ("time_nested_s", C.c_double),
+        ("loss_change", C.c_double * MAX_HISTORY), ("time_phi_s", C.c_double * MAX_LEVELS),
     ]
 
 
@@ -128,6 +130,8 @@ def lib():
     L.phi_step.restype = C.c_int
     L.phi_step_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.phi_step_noalloc.restype = C.c_int
+    L.mgrit_joule_losses.argtypes = [vp, vp]
+    L.mgrit_joule_losses.restype = C.c_int
     L.mgrit_level_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64), C.POINTER(C.c_int32 * 4)]
     L.mgrit_level_info.restype = C.c_int

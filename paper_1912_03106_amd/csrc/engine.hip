@@ -57,6 +57,7 @@ struct LevelState {
   double* Ainv = nullptr; // coarsest level, linear model: A^{-1} [n][ld_inv]
   int64_t ld_inv = 0;
   double* bvec = nullptr; // [n] right-hand side of one coarse step
+  double* u0r = nullptr;  // [n] initial value restricted to this level's mesh (nested start)
   bool relaxed = false;   // F-points hold a previous iterate (warm starts)
   bool cvalid = false;    // C-points hold a previous iterate
 };
@@ -109,7 +110,9 @@ struct Handle {
   const double* col_dphi = nullptr;  // shifts of phi_batch (training data only)
   bool verbose = false;      // MGRIT_VERBOSE: one line per MGRIT iteration on stderr
   int device = 0;           // HIP device the handle was set up on
+  bool solved = false;      // level 0 holds the iterate of a completed mgrit_solve
   bool noalloc = false;     // inside phi_step_noalloc: no graph capture, no compaction buffers
+  bool timing = false;      // a LevelTimer is running
   double tol_now = 1e-12;   // relative residual of the linear solves
   double eta_now = 0.0;     // > 0: linear solves also stop at eta times their initial residual
   hipStream_t capture_stream = nullptr;
@@ -661,8 +664,32 @@ struct PhiCall {
   double* dout = nullptr;   // if set: dout = x - out (before out is written), ld = ldo
 };
 
+// profile_kernels = 1: wall time of a level's Phi applications (and of the
+// coarsest sequential solve) with the stream drained on entry and exit; the
+// outermost timer of a nest counts.
+struct LevelTimer {
+  Handle& h;
+  int l;
+  bool on;
+  std::chrono::steady_clock::time_point t0;
+  LevelTimer(Handle& hh, int ll)
+      : h(hh), l(ll), on(hh.par.profile_kernels && hh.st && ll < MGRIT_MAX_LEVELS && !hh.timing) {
+    if (!on) return;
+    h.timing = true;
+    MG_HIP(hipStreamSynchronize(h.stream));
+    t0 = std::chrono::steady_clock::now();
+  }
+  ~LevelTimer() {
+    if (!on) return;
+    h.timing = false;
+    if (hipStreamSynchronize(h.stream) != hipSuccess) return;
+    h.st->time_phi_s[l] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
 static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
   if (c.ncols <= 0) return;
+  LevelTimer timer(h, l);
   if (c.ncols > w.cap) fail(MGRIT_INVALID_ARGUMENT, "batched Phi wider than its workspace");
   LevelState& S = h.lv[l];
   hipStream_t s = h.stream;
@@ -806,11 +833,16 @@ static void relax(Handle& h, int l) {
 }
 
 // RES[:, k] = g_km - u_km + Phi(u_km-1) (k >= 1), RES[:, 0] = g_0 - u_0.
+// Level 0 stores no g: g_0 is the initial value, which u_0 holds exactly, so
+// r_0 = 0 there.
 static void c_residual(Handle& h, int l) {
   LevelState& S = h.lv[l];
   hipStream_t s = h.stream;
-  launch_axpby3(s, S.n, 1, S.RES, S.ld, 0.0, CView{}, 1.0, CView{gslab(S, 0), S.ld}, -1.0,
-                CView{slab(S, 0), S.ld});
+  if (S.G)
+    launch_axpby3(s, S.n, 1, S.RES, S.ld, 0.0, CView{}, 1.0, CView{gslab(S, 0), S.ld}, -1.0,
+                  CView{slab(S, 0), S.ld});
+  else
+    launch_axpby3(s, S.n, 1, S.RES, S.ld, 0.0, CView{}, 0.0, CView{}, 0.0, CView{});
   PhiCall c;
   c.ncols = static_cast<int>(S.NT);
   c.in = CView{slab(S, h.m - 1), S.ld};
@@ -846,6 +878,7 @@ static double residual_norm(Handle& h, int l) {
 static void coarsest_solve(Handle& h, int l) {
   LevelState& S = h.lv[l];
   hipStream_t s = h.stream;
+  LevelTimer timer(h, l);
   // u_0 = g_0
   launch_axpby3(s, S.n, 1, S.U, S.ld, 0.0, CView{}, 1.0, CView{S.G, S.ld}, 0.0, CView{});
   if (S.Ainv) {
@@ -897,10 +930,14 @@ static void coarsest_solve(Handle& h, int l) {
   }
 }
 
-static void cycle(Handle& h, int l);
+enum CycleKind { CYCLE_V = 0, CYCLE_F = 1 };
+static void cycle(Handle& h, int l, int kind);
 
 // Algorithm 1, steps 4-9: restrict, FAS right-hand side, coarse solve, correct.
-static void coarse_correct(Handle& h, int l) {
+// The coarse problem is approximated by one V-cycle on level l+1, or for an
+// F-cycle by an F-cycle followed by a V-cycle (Sec. 2.1, Fig. 4); on the
+// coarsest level both are its one exact sequential solve.
+static void coarse_correct(Handle& h, int l, int kind) {
   LevelState& S = h.lv[l];
   LevelState& C = h.lv[l + 1];
   hipStream_t s = h.stream;
@@ -936,7 +973,8 @@ static void coarse_correct(Handle& h, int l) {
     launch_cols_to_slabs(s, C.n, np, h.m, S.G2, S.ld, C.G, C.ld, C.ss);
   }
   C.cvalid = true;
-  cycle(h, l + 1);
+  cycle(h, l + 1, kind);
+  if (kind == CYCLE_F && !C.coarsest) cycle(h, l + 1, CYCLE_V);
   // e = v - u2 (into RR), u_C += P_s e
   if (C.coarsest) {
     launch_axpby3(s, C.n, np, S.RR, S.ld, 1.0, CView{C.U, C.ld}, -1.0, CView{S.U2, S.ld}, 0.0, CView{});
@@ -952,7 +990,7 @@ static void coarse_correct(Handle& h, int l) {
   }
 }
 
-static void cycle(Handle& h, int l) {
+static void cycle(Handle& h, int l, int kind) {
   LevelState& S = h.lv[l];
   if (S.coarsest) {
     coarsest_solve(h, l);
@@ -960,8 +998,103 @@ static void cycle(Handle& h, int l) {
   }
   relax(h, l);
   c_residual(h, l);
-  coarse_correct(h, l);
+  coarse_correct(h, l, kind);
   f_relax(h, l);
+}
+
+// Joule losses (Sec. 3.1) P = (u_a - u_b)^T M (u_a - u_b) / dt^2 (l_z = 1 m)
+// of ncols column pairs of level 0, into host_sums[0 .. ncols).
+static void joule_pairs(Handle& h, int ncols, CView a, CView b) {
+  LevelState& S = h.lv[0];
+  hipStream_t s = h.stream;
+  launch_joule(s, S.pcg, S.op, ncols, a, b);
+  double* sums = S.pcg.scal + 5 * S.pcg.ld;
+  launch_reduce(s, S.pcg, ncols, RED_SUM, 0.0, 1, sums);
+  MG_HIP(hipMemcpyAsync(h.host_sums, sums, sizeof(double) * ncols, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < ncols; ++c) h.host_sums[c] /= S.op.dt;
+}
+
+// Losses at the C-points k >= 1 of level 0 (u_km against u_km-1).
+static void cpoint_losses(Handle& h, std::vector<double>& p) {
+  LevelState& S = h.lv[0];
+  const int nt = static_cast<int>(S.NT);
+  joule_pairs(h, nt, CView{slab(S, 0) + 1, S.ld}, CView{slab(S, h.m - 1), S.ld});
+  p.assign(h.host_sums, h.host_sums + nt);
+  for (double v : p)
+    if (!std::isfinite(v)) fail(MGRIT_NONFINITE, "non-finite Joule loss");
+}
+
+// Largest |p - q| / |p| over the points with p != 0 (Sec. 5.1 stop rule).
+static double max_relative_change(const std::vector<double>& p, const std::vector<double>& q) {
+  double worst = 0.0;
+  bool any = false;
+  for (size_t k = 0; k < p.size(); ++k) {
+    if (p[k] == 0.0) continue;
+    any = true;
+    worst = std::max(worst, std::fabs(p[k] - q[k]) / std::fabs(p[k]));
+  }
+  if (!any) return p == q ? 0.0 : INFINITY;
+  return worst;
+}
+
+// Nested-iteration start (Sec. 2.1; Sec. 4.1 drives it with the sine
+// references): the coarsest level's time-stepping problem (g_0 = the
+// restricted initial value, g_i = 0) is solved sequentially; on every finer
+// level its points become the C-points (P_s in space), one V-cycle is applied
+// to that level's own problem, and so on up to level 0.  On level 0 the
+// V-cycle's last F-relaxation is left to the first MGRIT iteration, whose
+// relaxation starts with it (F-relaxation depends on the C-points only).
+static void nested_start(Handle& h) {
+  const int L = static_cast<int>(h.lv.size());
+  hipStream_t s = h.stream;
+  struct Signal {
+    Handle& h;
+    ~Signal() { h.src.signal = h.phys.signal; }
+  } restore{h};
+  h.src.signal = 1;
+  h.tol_now = h.par.pcg_tol;
+  h.eta_now = 0.0;
+  LevelState& S0 = h.lv[0];
+  // restricted initial values
+  launch_axpby3(s, S0.n, 1, S0.u0r, 1, 1.0, CView{slab(S0, 0), S0.ld}, 0.0, CView{}, 0.0, CView{});
+  for (int l = 0; l + 1 < L; ++l) {
+    LevelState& S = h.lv[l];
+    LevelState& C = h.lv[l + 1];
+    if (S.has_transfer) launch_transfer(s, S.R, 1, CView{S.u0r, 1}, 1.0, C.u0r, 1, 0.0);
+    else launch_axpby3(s, C.n, 1, C.u0r, 1, 1.0, CView{S.u0r, 1}, 0.0, CView{}, 0.0, CView{});
+  }
+  LevelState& C = h.lv[L - 1];
+  MG_HIP(hipMemsetAsync(C.G, 0, sizeof(double) * C.ss, s));
+  launch_axpby3(s, C.n, 1, C.G, C.ld, 1.0, CView{C.u0r, 1}, 0.0, CView{}, 0.0, CView{});
+  coarsest_solve(h, L - 1);
+  for (int l = L - 2; l >= 0; --l) {
+    LevelState& S = h.lv[l];
+    LevelState& Cn = h.lv[l + 1];
+    const int np = static_cast<int>(S.NT + 1);
+    // the coarse level's points in time order, then P_s onto the C-points
+    if (Cn.coarsest)
+      launch_axpby3(s, Cn.n, np, S.RR, S.ld, 1.0, CView{Cn.U, Cn.ld}, 0.0, CView{}, 0.0, CView{});
+    else
+      launch_slabs_to_cols(s, Cn.n, np, h.m, Cn.U, Cn.ld, Cn.ss, S.RR, S.ld);
+    if (S.has_transfer) launch_transfer(s, S.P, np, CView{S.RR, S.ld}, 1.0, slab(S, 0), S.ld, 0.0);
+    else launch_axpby3(s, S.n, np, slab(S, 0), S.ld, 1.0, CView{S.RR, S.ld}, 0.0, CView{}, 0.0, CView{});
+    launch_axpby3(s, S.n, 1, slab(S, 0), S.ld, 1.0, CView{S.u0r, 1}, 0.0, CView{}, 0.0, CView{});
+    S.relaxed = S.cvalid = false;
+    if (l > 0) {
+      MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss * h.m, s));
+      launch_axpby3(s, S.n, 1, S.G, S.ld, 1.0, CView{S.u0r, 1}, 0.0, CView{}, 0.0, CView{});
+      cycle(h, l, CYCLE_V);
+    } else {
+      h.eta_now = h.par.pcg_tol_eta;
+      relax(h, 0);
+      h.eta_now = h.par.residual_eta;
+      c_residual(h, 0);
+      h.eta_now = 0.0;
+      coarse_correct(h, 0, CYCLE_V);
+    }
+  }
+  MG_HIP(hipStreamSynchronize(s));
 }
 
 // A^{-1} of the coarsest level (linear model), by batched CG on the columns
@@ -1067,6 +1200,9 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     if (!(rn == 0 || rn == -1 || rn == 16 || rn == 32 || rn == 64 || rn == 128 || rn == 256))
       fail(MGRIT_INVALID_ARGUMENT, "pcg_rows_narrow must be 0, -1, 16, 32, 64, 128 or 256");
   }
+  if (par->cycle != 0 && par->cycle != 1) fail(MGRIT_INVALID_ARGUMENT, "cycle must be 0 (V) or 1 (F)");
+  if (par->nested != 0 && par->nested != 1) fail(MGRIT_INVALID_ARGUMENT, "nested must be 0 or 1");
+  if (!(par->loss_tol >= 0.0)) fail(MGRIT_INVALID_ARGUMENT, "loss_tol must be >= 0");
   if (par->compact_columns < 0) fail(MGRIT_INVALID_ARGUMENT, "compact_columns must be >= 0");
   if (!(par->compact_fraction > 0.0 && par->compact_fraction < 1.0))
     fail(MGRIT_INVALID_ARGUMENT, "compact_fraction must be in (0, 1)");
@@ -1093,6 +1229,10 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   h.src.carrier = ph.carrier;
   if (!(ph.ramp_periods >= 0.0)) fail(MGRIT_INVALID_ARGUMENT, "ramp_periods must be >= 0");
   h.src.ramp_span = ph.ramp_periods > 0.0 ? ph.ramp_periods / ph.freq : 0.0;
+  if (ph.signal != 0 && ph.signal != 1) fail(MGRIT_INVALID_ARGUMENT, "signal must be 0 (PWM) or 1 (sine)");
+  h.src.signal = ph.signal;
+  if (!std::isfinite(ph.t_start)) fail(MGRIT_INVALID_ARGUMENT, "t_start must be finite");
+  h.src.t0 = ph.t_start;
 
   // host phase: validate every mesh, build patterns and transfers (no HIP call)
   std::vector<HostPattern> pats(L);
@@ -1122,6 +1262,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     S.coarsest = (l == L - 1);
     S.op = assemble_level(h.arena, s, prob->meshes[l], pats[l], ph, dt, &S.elem);
     S.nat = upload_vec(h.arena, s, pats[l].nat);
+    S.u0r = h.arena.alloc<double>(S.n);
     if (ph.nonlinear) {
       S.nl.n_tri = S.elem.n_tri;
       S.nl.tri_u = S.elem.tri_u;
@@ -1260,9 +1401,16 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
   double rho0 = 0.0, rho_prev = 0.0;
   int status = MGRIT_OK;
   h.learned_off = false;
+  h.solved = false;
   st->coarse_fallback = -1;
   if (h.par.coarse_model == 1 && !h.gnn.ready)
     fail(MGRIT_INVALID_ARGUMENT, "coarse_model = 1 needs trained or set coarse weights");
+  if (h.par.nested) {
+    nested_start(h);
+    st->time_nested_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  const bool loss_stop = h.par.loss_tol > 0.0;
+  std::vector<double> p_now, p_prev;
   for (int it = 0;; ++it) {
     // Only the level-0 relaxation stops its solves early (eta times the
     // warm-start residual, which shrinks as MGRIT converges).  Coarse levels
@@ -1299,7 +1447,22 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
       st->coarse_fallback = it;
     }
     rho_prev = rho;
-    if (rho == 0.0 || rho <= h.par.tol * rho0) {
+    if (loss_stop) {
+      // Sec. 5.1: stop once no C-point loss changes by loss_tol or more
+      // (relative) between two successive iterations
+      cpoint_losses(h, p_now);
+      const double ch = p_prev.empty() ? -1.0 : max_relative_change(p_now, p_prev);
+      if (it < MGRIT_MAX_HISTORY) st->loss_change[it] = ch;
+      if (h.verbose) {
+        std::fprintf(stderr, "[mgrit] iteration %d: largest relative C-point loss change %.3e\n", it, ch);
+        std::fflush(stderr);
+      }
+      if (!p_prev.empty() && ch < h.par.loss_tol) {
+        st->converged = 1;
+        break;
+      }
+      std::swap(p_prev, p_now);
+    } else if (rho == 0.0 || rho <= h.par.tol * rho0) {
       st->converged = 1;
       break;
     }
@@ -1307,9 +1470,10 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
       status = MGRIT_NOT_CONVERGED;
       break;
     }
-    coarse_correct(h, 0);
+    coarse_correct(h, 0, h.par.cycle);
     st->iterations = it + 1;
   }
+  h.solved = true;
   double* tm = h.par.device_pointers ? u_out : stage(h);
   launch_slabs_to_tm(s, S0.n, S0.N + 1, h.m, S0.U, S0.ld, S0.ss, tm, S0.nat);
   if (!h.par.device_pointers)
@@ -1317,6 +1481,25 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
   MG_HIP(hipStreamSynchronize(s));
   st->time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (status != MGRIT_OK) fail(status, "MGRIT did not reach tol within max_iter iterations");
+}
+
+// Joule losses at every point of the iterate of the last solve (p[0] = 0).
+static void joule_impl(Handle& h, double* p) {
+  if (!p) fail(MGRIT_INVALID_ARGUMENT, "p is null");
+  if (!h.solved) fail(MGRIT_INVALID_ARGUMENT, "no completed mgrit_solve on this handle");
+  LevelState& S = h.lv[0];
+  const int nt = static_cast<int>(S.NT);
+  std::vector<double> out(static_cast<size_t>(S.N + 1), 0.0);
+  for (int j = 0; j < h.m; ++j) {
+    // points k m + j against k m + j - 1: slab j against slab j-1 (same
+    // column), or for j = 0 slab 0 from column 1 against slab m-1
+    if (j > 0) joule_pairs(h, nt, CView{slab(S, j), S.ld}, CView{slab(S, j - 1), S.ld});
+    else joule_pairs(h, nt, CView{slab(S, 0) + 1, S.ld}, CView{slab(S, h.m - 1), S.ld});
+    for (int k = 0; k < nt; ++k) out[static_cast<size_t>(j > 0 ? k * h.m + j : (k + 1) * h.m)] = h.host_sums[k];
+  }
+  MG_HIP(hipMemcpyAsync(p, out.data(), sizeof(double) * out.size(),
+                        h.par.device_pointers ? hipMemcpyHostToDevice : hipMemcpyHostToHost, h.stream));
+  MG_HIP(hipStreamSynchronize(h.stream));
 }
 
 static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st) {
@@ -2057,6 +2240,9 @@ void mgrit_default_params(mgrit_params* p) {
   p->pcg_prefetch = 0;
   p->residual_eta = 0.0;
   p->pcg_rows_narrow = 0;
+  p->cycle = 0;
+  p->nested = 0;
+  p->loss_tol = 0.0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -2106,6 +2292,12 @@ int phi_step_noalloc(void* hp, int32_t level, int32_t B, const int64_t* i_from, 
   auto* h = static_cast<mg::Handle*>(hp);
   if (!h) return MGRIT_INVALID_ARGUMENT;
   return guarded(h, [&] { mg::phi_step_noalloc_impl(*h, level, B, i_from, u_prev, u_next); });
+}
+
+int mgrit_joule_losses(void* hp, double* p) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] { mg::joule_impl(*h, p); });
 }
 
 int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,

@@ -34,6 +34,8 @@ struct SourceDev {
   double phi[3];       // phases[p] + phase_offset
   int carrier;         // 0 triangle, 1 sawtooth
   double ramp_span;    // start-up ramp length in seconds (0 = none)
+  int signal = 0;      // 0 PWM, 1 the sine references themselves (nested-iteration start)
+  double t0 = 0.0;     // time origin: the source is sampled at t0 + t
 };
 
 // Column-block view: entry (row i, column c) at p[i * ld + c].
@@ -230,6 +232,8 @@ void launch_transfer(hipStream_t s, const DevTransfer& T, int ncols, CView X, do
                      double* Y, int64_t ldy, double beta);
 // Sum of squares of every column: per-column partials into w.part, reduced into sums.
 void launch_colsq(hipStream_t s, PcgWork& w, int n, int ncols, CView X);
+// row-block partials (w.part, quantity 0) of (a - b)^T (M/dt) (a - b) per column
+void launch_joule(hipStream_t s, PcgWork& w, const DevLevel& L, int ncols, CView a, CView b);
 
 // Layout conversions.
 // time-major [npts][n] (user order) <-> slabs (internal order): point t ->

@@ -202,6 +202,40 @@ __global__ __launch_bounds__(kBlock) void k_colsq(int n, int ncols, int nrb, int
   block_partials<1>(acc, part + rb * ldp, static_cast<int64_t>(nrb) * ldp, c, on);
 }
 
+// Joule-loss partial sums (Sec. 3.1): per column c, d = a[:, c] - b[:, c] and
+// the row-block sums of d_i (M/dt d)_i over the rows with a mass entry (the
+// conductor nodes); the caller divides the column total by dt.
+__global__ __launch_bounds__(kBlock) void k_joule(int n, int W, const int* __restrict__ col,
+                                                  const double* __restrict__ mdt,
+                                                  const uint8_t* __restrict__ has_mass, int ncols,
+                                                  int nrb, int ncc, int rpb,
+                                                  const double* __restrict__ a, int64_t lda,
+                                                  const double* __restrict__ b, int64_t ldb,
+                                                  double* __restrict__ part, int64_t ldp) {
+  int rb, cc;
+  tile_decode(blockIdx.x, nrb, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols;
+  double acc[1] = {0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      if (!has_mass[i]) continue;
+      double md = 0.0;
+      for (int t = 0; t < W; ++t) {
+        const int j = col[static_cast<int64_t>(i) * W + t];
+        md += mdt[static_cast<int64_t>(i) * W + t] * (a[j * lda + c] - b[j * ldb + c]);
+      }
+      acc[0] += (a[i * lda + c] - b[i * ldb + c]) * md;
+    }
+  }
+  block_partials<1>(acc, part + rb * ldp, static_cast<int64_t>(nrb) * ldp, c, on);
+}
+
 // Y = alpha * T X + beta * Y for a fixed-width transfer operator.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_transfer(int n_out, const int* __restrict__ col,
@@ -738,6 +772,15 @@ void launch_colsq(hipStream_t s, PcgWork& w, int n, int ncols, CView X) {
   const int nb = grid_tiles(w, ncols, ncc);
   hipLaunchKernelGGL(k_colsq, dim3(nb), dim3(kBlock), 0, s, n, ncols, w.nrb, ncc, w.rows_per_block,
                      X.p, X.ld, w.part, w.ld);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_joule(hipStream_t s, PcgWork& w, const DevLevel& L, int ncols, CView a, CView b) {
+  if (ncols <= 0) return;
+  int ncc;
+  const int nb = grid_tiles(w, ncols, ncc);
+  hipLaunchKernelGGL(k_joule, dim3(nb), dim3(kBlock), 0, s, L.n, L.W, L.col, L.m64, L.has_mass, ncols,
+                     w.nrb, ncc, w.rows_per_block, a.p, a.ld, b.p, b.ld, w.part, w.ld);
   MG_HIP(hipGetLastError());
 }
 

@@ -69,7 +69,7 @@ class Solver:
             _ptr(mats["iron"], C.c_int32), int(bh.nonlinear), bh.k1, bh.k2, bh.k3,
             src.J0, src.amplitude, src.freq, src.f_carrier, src.phase_offset,
             (C.c_double * 3)(*src.phases), src.carrier_code, cfg.dt, cfg.n_steps,
-            src.ramp_periods)
+            src.ramp_periods, {"pwm": 0, "sine": 1}[src.signal], src.t_start)
         self._mesh_arr = mesh_arr
         self._prob = _abi.Problem(len(self.meshes), mesh_arr, phys)
         par = _abi.Params()
@@ -157,6 +157,13 @@ class Solver:
         if rc != 0 and not (rc == -7 and not raise_on_stall):
             _check(self._L, self._h, rc)
         return out, stats_dict(st)
+
+    def joule_losses(self, out=None):
+        """Joule losses P(t_i) of the last solve's iterate at every point (Sec. 3.1)."""
+        N = self.cfg.n_steps
+        out, outp = self._out(out, (N + 1,))
+        _check(self._L, self._h, self._L.mgrit_joule_losses(self._h, outp))
+        return out
 
     def seq_solve(self, u0=None, out=None):
         n0, N = self.n0, self.cfg.n_steps
@@ -277,5 +284,6 @@ def stats_dict(st):
         kernel_launches=[list(st.kernel_launches[0]), list(st.kernel_launches[1])],
         kernel_columns=list(st.kernel_columns),
         kernel_time_s=[list(st.kernel_time_s[0]), list(st.kernel_time_s[1])],
-        coarse_fallback=st.coarse_fallback,
+        coarse_fallback=st.coarse_fallback, time_nested_s=st.time_nested_s,
+        loss_change=list(st.loss_change[:k]), time_phi_s=list(st.time_phi_s),
     )
