@@ -14,7 +14,8 @@
  *  - Unknowns are the non-Dirichlet nodes of a mesh, in increasing node-id
  *    order; n_l is their count on level l.
  *  - Time-major arrays: point t of a trajectory is the contiguous vector
- *    u[t*n .. t*n+n-1].  Level l has N_l = N_t / m^l steps of size m^l dt.
+ *    u[t*n .. t*n+n-1].  Level l has N_l = N_t / (m_0 ... m_{l-1}) steps of
+ *    size m_0 ... m_{l-1} dt, m_0 = m and m_l = m_coarse (or m) for l >= 1.
  *  - Host pointers unless a field says otherwise.  The library copies what it
  *    needs during mgrit_setup; the caller keeps ownership of every array it
  *    passes and may free it after the call returns.
@@ -102,7 +103,7 @@ enum { MGRIT_FP64 = 0, MGRIT_FP32_IR = 1 };
 enum { MGRIT_R_NORMALIZED = 0, MGRIT_R_TRANSPOSE = 1, MGRIT_R_INJECTION = 2 };
 
 typedef struct {
-  int32_t m;                  /* temporal coarsening factor (> 1)               */
+  int32_t m;                  /* temporal coarsening factor between levels 0 and 1 (> 1) */
   int32_t gamma;              /* CF relaxations after the first F (1 = FCF)    */
   int32_t precision;          /* MGRIT_FP64 or MGRIT_FP32_IR                    */
   int32_t restriction;        /* MGRIT_R_*                                      */
@@ -180,6 +181,9 @@ typedef struct {
   double  loss_tol;           /* > 0: stop once the Joule losses at the C-points change by less than
                                * loss_tol (relative, every C-point) between two successive
                                * iterations (Sec. 5.1 uses 1e-2) instead of the residual test */
+  int32_t m_coarse;           /* temporal coarsening factor between levels l >= 1 and l + 1 (Sec. 4.1:
+                               * a large factor m on the first level, a small one below); 0 = m.
+                               * n_steps must be divisible by m * m_coarse^(levels - 2) */
 } mgrit_params;
 
 typedef struct {

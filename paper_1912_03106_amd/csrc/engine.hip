@@ -34,6 +34,7 @@ struct LevelState {
   ElementData elem;
   int n = 0;
   int64_t N = 0;     // steps on this level
+  int m = 0;         // temporal coarsening factor to the next level (non-coarsest levels)
   int64_t NT = 0;    // intervals (N / m) on non-coarsest levels
   bool coarsest = false;
   int prec = 0;      // arithmetic of this level's linear solves (MGRIT_FP64 / MGRIT_FP32_IR)
@@ -777,12 +778,12 @@ static void f_relax(Handle& h, int l) {
                     CView{S.csnap, S.ld});
     launch_axpby3(s, S.n, nt, S.csnap, S.ld, 0.0, CView{}, 1.0, CView{slab(S, 0), S.ld}, 0.0, CView{});
   }
-  for (int j = 1; j < h.m; ++j) {
+  for (int j = 1; j < S.m; ++j) {
     PhiCall c;
     c.ncols = nt;
     c.in = CView{slab(S, j - 1), S.ld};
     c.t_base = j - 1;
-    c.t_stride = h.m;
+    c.t_stride = S.m;
     if (warm && delta) {
       c.ga = CView{slab(S, j), S.ld};
       c.gb = CView{S.dlt, S.ld};
@@ -807,9 +808,9 @@ static void c_relax(Handle& h, int l) {
   LevelState& S = h.lv[l];
   PhiCall c;
   c.ncols = static_cast<int>(S.NT);
-  c.in = CView{slab(S, h.m - 1), S.ld};
-  c.t_base = h.m - 1;
-  c.t_stride = h.m;
+  c.in = CView{slab(S, S.m - 1), S.ld};
+  c.t_base = S.m - 1;
+  c.t_stride = S.m;
   if (S.cvalid && h.par.warm_start) {
     c.ga = CView{slab(S, 0) + 1, S.ld};
     c.gb = CView{S.G ? gslab(S, 0) + 1 : nullptr, S.ld};
@@ -845,9 +846,9 @@ static void c_residual(Handle& h, int l) {
     launch_axpby3(s, S.n, 1, S.RES, S.ld, 0.0, CView{}, 0.0, CView{}, 0.0, CView{});
   PhiCall c;
   c.ncols = static_cast<int>(S.NT);
-  c.in = CView{slab(S, h.m - 1), S.ld};
-  c.t_base = h.m - 1;
-  c.t_stride = h.m;
+  c.in = CView{slab(S, S.m - 1), S.ld};
+  c.t_base = S.m - 1;
+  c.t_stride = S.m;
   c.ga = CView{slab(S, 0) + 1, S.ld};
   c.gb = CView{S.G ? gslab(S, 0) + 1 : nullptr, S.ld};
   c.sgb = -1.0;
@@ -969,8 +970,8 @@ static void coarse_correct(Handle& h, int l, int kind) {
     launch_axpby3(s, C.n, np, C.U, C.ld, 1.0, CView{S.U2, S.ld}, 0.0, CView{}, 0.0, CView{});
     launch_axpby3(s, C.n, np, C.G, C.ld, 1.0, CView{S.G2, S.ld}, 0.0, CView{}, 0.0, CView{});
   } else {
-    launch_cols_to_slabs(s, C.n, np, h.m, S.U2, S.ld, C.U, C.ld, C.ss);
-    launch_cols_to_slabs(s, C.n, np, h.m, S.G2, S.ld, C.G, C.ld, C.ss);
+    launch_cols_to_slabs(s, C.n, np, C.m, S.U2, S.ld, C.U, C.ld, C.ss);
+    launch_cols_to_slabs(s, C.n, np, C.m, S.G2, S.ld, C.G, C.ld, C.ss);
   }
   C.cvalid = true;
   cycle(h, l + 1, kind);
@@ -979,7 +980,7 @@ static void coarse_correct(Handle& h, int l, int kind) {
   if (C.coarsest) {
     launch_axpby3(s, C.n, np, S.RR, S.ld, 1.0, CView{C.U, C.ld}, -1.0, CView{S.U2, S.ld}, 0.0, CView{});
   } else {
-    launch_slabs_to_cols(s, C.n, np, h.m, C.U, C.ld, C.ss, S.RR, S.ld);
+    launch_slabs_to_cols(s, C.n, np, C.m, C.U, C.ld, C.ss, S.RR, S.ld);
     launch_axpby3(s, C.n, np, S.RR, S.ld, 1.0, CView{S.RR, S.ld}, -1.0, CView{S.U2, S.ld}, 0.0, CView{});
   }
   if (S.has_transfer) {
@@ -1076,13 +1077,13 @@ static void nested_start(Handle& h) {
     if (Cn.coarsest)
       launch_axpby3(s, Cn.n, np, S.RR, S.ld, 1.0, CView{Cn.U, Cn.ld}, 0.0, CView{}, 0.0, CView{});
     else
-      launch_slabs_to_cols(s, Cn.n, np, h.m, Cn.U, Cn.ld, Cn.ss, S.RR, S.ld);
+      launch_slabs_to_cols(s, Cn.n, np, Cn.m, Cn.U, Cn.ld, Cn.ss, S.RR, S.ld);
     if (S.has_transfer) launch_transfer(s, S.P, np, CView{S.RR, S.ld}, 1.0, slab(S, 0), S.ld, 0.0);
     else launch_axpby3(s, S.n, np, slab(S, 0), S.ld, 1.0, CView{S.RR, S.ld}, 0.0, CView{}, 0.0, CView{});
     launch_axpby3(s, S.n, 1, slab(S, 0), S.ld, 1.0, CView{S.u0r, 1}, 0.0, CView{}, 0.0, CView{});
     S.relaxed = S.cvalid = false;
     if (l > 0) {
-      MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss * h.m, s));
+      MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss * S.m, s));
       launch_axpby3(s, S.n, 1, S.G, S.ld, 1.0, CView{S.u0r, 1}, 0.0, CView{}, 0.0, CView{});
       cycle(h, l, CYCLE_V);
     } else {
@@ -1216,11 +1217,15 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (ph.n_materials <= 0 || !ph.nu || !ph.sigma) fail(MGRIT_INVALID_ARGUMENT, "material table");
   if (!(ph.dt > 0.0) || ph.n_steps < 1) fail(MGRIT_INVALID_ARGUMENT, "time grid");
   if (ph.carrier != 0 && ph.carrier != 1) fail(MGRIT_INVALID_ARGUMENT, "carrier");
+  if (par->m_coarse != 0 && par->m_coarse < 2) fail(MGRIT_INVALID_ARGUMENT, "m_coarse must be 0 or > 1");
   h.m = par->m;
+  // factor between levels l and l+1: m on level 0, m_coarse (or m) below
+  auto factor = [&](int l) { return (l == 0 || par->m_coarse == 0) ? par->m : par->m_coarse; };
   int64_t mpow = 1;
   for (int l = 0; l + 1 < L; ++l) {
-    mpow *= par->m;
-    if (ph.n_steps % mpow != 0) fail(MGRIT_INVALID_ARGUMENT, "n_steps must be divisible by m^(levels-1)");
+    mpow *= factor(l);
+    if (ph.n_steps % mpow != 0)
+      fail(MGRIT_INVALID_ARGUMENT, "n_steps must be divisible by the product of the coarsening factors");
   }
   h.src.scale = ph.J0 * ph.amplitude;
   h.src.freq = ph.freq;
@@ -1277,8 +1282,11 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
       S.nl.k2 = ph.bh_k2;
       S.nl.k3 = ph.bh_k3;
     }
-    dt *= par->m;
-    N /= par->m;
+    S.m = S.coarsest ? 0 : factor(l);
+    if (!S.coarsest) {
+      dt *= S.m;
+      N /= S.m;
+    }
   }
   for (int l = 0; l < L; ++l) {
     LevelState& S = h.lv[l];
@@ -1292,14 +1300,14 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
       MG_HIP(hipMemsetAsync(S.U, 0, sizeof(double) * S.ss, s));
       MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss, s));
     } else {
-      S.NT = S.N / par->m;
+      S.NT = S.N / S.m;
       S.ld = round_up(S.NT + 1, kWave);
       S.ss = static_cast<int64_t>(S.n) * S.ld;
-      S.U = h.arena.alloc<double>(static_cast<size_t>(S.ss) * par->m);
-      MG_HIP(hipMemsetAsync(S.U, 0, sizeof(double) * S.ss * par->m, s));
+      S.U = h.arena.alloc<double>(static_cast<size_t>(S.ss) * S.m);
+      MG_HIP(hipMemsetAsync(S.U, 0, sizeof(double) * S.ss * S.m, s));
       if (l > 0) {
-        S.G = h.arena.alloc<double>(static_cast<size_t>(S.ss) * par->m);
-        MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss * par->m, s));
+        S.G = h.arena.alloc<double>(static_cast<size_t>(S.ss) * S.m);
+        MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss * S.m, s));
       }
       S.RES = h.arena.alloc<double>(S.ss);
       if (l == 0 && par->warm_start == 2) {
@@ -1732,9 +1740,9 @@ static void setup_gnn(Handle& h, const mgrit_mesh& mesh, const HostPattern& pat,
   LevelState& C = h.lv.back();
   GnnModel& g = h.gnn;
   g.n = C.n;
-  g.m = h.m;
+  g.m = h.lv[h.lv.size() - 2].m;
   g.dT = C.op.dt;
-  g.off = gnn_offsets(h.m);
+  g.off = gnn_offsets(g.m);
   if (g.off.F > 32) return;                  // input features are padded to 32
   hipStream_t s = h.stream;
   const int n = C.n, W = pat.W;
@@ -1931,7 +1939,7 @@ static void train_impl(Handle& h, const mgrit_train_params* tp, mgrit_train_stat
   LevelState& C = h.lv[L - 1];
   LevelState& Gl = h.lv[L - 2];
   GnnModel& g = h.gnn;
-  const int nt = tp->n_traj, m = h.m, n = C.n;
+  const int nt = tp->n_traj, m = Gl.m, n = C.n;
   const int64_t Nc = C.N;
   auto t0 = std::chrono::steady_clock::now();
   GnnStaging st(h);
@@ -2243,6 +2251,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->cycle = 0;
   p->nested = 0;
   p->loss_tol = 0.0;
+  p->m_coarse = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {

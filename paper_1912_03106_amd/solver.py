@@ -75,6 +75,7 @@ class Solver:
         par = _abi.Params()
         self._L.mgrit_default_params(C.byref(par))
         par.m = cfg.m
+        par.m_coarse = cfg.m_coarse
         par.gamma = cfg.gamma
         par.precision = {"fp64": _abi.FP64, "fp32_ir": _abi.FP32_IR}[cfg.precision]
         par.tol = cfg.mgrit_tol
