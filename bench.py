@@ -1,6 +1,6 @@
-"""Benchmark: FAS-MGRIT on the large linear machine workload, one MI355X.
+"""Benchmark: FAS-MGRIT on the eddy-current machine workloads, one MI355X.
 
-Workload: linear eddy-current machine on the 64 x 512 polar mesh (n = 32,256
+Headline (`value`): the linear machine on the 64 x 512 polar mesh (n = 32,256
 unknowns), 16,384 implicit-Euler steps over one 50 Hz period, three-level
 V-cycle (m = 16, FCF, direct spatial coarsening 64x512 -> 32x256 -> 16x128),
 batched FP64 Jacobi-PCG, stop at a 1e-8 relative C-point residual.
@@ -8,7 +8,8 @@ batched FP64 Jacobi-PCG, stop at a 1e-8 relative C-point residual.
 One bench step = one complete MGRIT solve to the tolerance (every part of the
 hot path: F/C relaxation, C-point residual, restriction, FAS right-hand side,
 coarse solves, correction).  `value` is the useful throughput n0 * N_t / T of
-that solve in DOF-steps/s, inputs resident on the GPU.  In the timed solve:
+that solve in DOF-steps/s, inputs resident on the GPU, check intervals of CG
+iterations replayed from captured hipGraphs.  In the timed solve:
   - the level-0 F-relaxation solves start from the previous iterate plus the
     change of their input since it was computed;
   - the level-0 relaxation solves stop at max(1e-12 ||b||, 3e-3 ||r_0||)
@@ -16,18 +17,26 @@ that solve in DOF-steps/s, inputs resident on the GPU.  In the timed solve:
   - the C-point residual solves, which start from the current C-point values,
     stop at max(1e-12 ||b||, 1e-4 ||r_0||), i.e. at a relative accuracy of the
     residual itself;
-  - the coarse levels step with stored inverses (exact implicit Euler: one FP64
-    GEMM per batched step on 32x256).
+  - the coarse levels step with stored inverses (exact implicit Euler).
 
-Also reported (same JSON line):
-  - the same solve with every linear solve to 1e-12 ||b|| ("plain"),
-  - the FP32 + FP64-refinement workload (random initial guess) with early-
-    stopped level-0 relaxation (coarse levels as in the timed solve),
-  - GPU sequential stepping over the whole horizon,
-  - the roofline of the dominant kernel (PCG pass B) from HIP-event timings of
-    every launch in the timed region,
-  - the CPU oracle timed on this host; the states it computes on its sample
-    of the horizon also give each GPU solution's deviation from the oracle.
+Further legs of the same JSON line, run while the time budget (--budget, from
+the start of the process) allows, in this order:
+  - the roofline of the dominant kernel (CG pass B) from one more solve with
+    HIP events around every CG pass;
+  - the nonlinear machine (saturating iron, 32,768 steps, damped Newton per
+    step, FP32 inner CG): time to the 1e-8 residual, and GPU sequential Newton
+    stepping on windows spread over the horizon, each started from the MGRIT
+    state at its first point (time per step -> full-horizon estimate; the
+    deviation of MGRIT from the window's sequential states);
+  - GPU sequential stepping of the linear workload on windows spread over the
+    horizon, the same way;
+  - the CPU oracle timed on this host (its states also give each GPU
+    solution's deviation from the oracle on its sample);
+  - the FP32 + FP64-refinement variant (random initial guess);
+  - the same solve with every linear solve to 1e-12 ||b|| ("plain");
+  - the nonlinear machine with the learned coarsest propagator (training and
+    solve).
+A leg that would not fit the remaining budget is listed under "skipped".
 """
 
 import argparse
@@ -35,6 +44,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -102,7 +113,7 @@ def pass_b_roofline(st, solver, unit):
             "bytes_per_launch": round(bytes_total / launches)}
 
 
-def cpu_baseline(cfg, budget_s=12.0, keep_every=64):
+def cpu_baseline(cfg, budget_s=10.0, keep_every=64):
     """The oracle's sequential stepping (SuperLU factor + one triangular solve
     pair per step, single thread) on a prefix of the same workload.  Returns
     the JSON record and the oracle states at every keep_every-th step."""
@@ -213,76 +224,148 @@ def profile_short(cfg, stream):
                       "copy_bytes": 2 * a.numel() * 8}), flush=True)
 
 
-def nonlinear(N, stream, learned=True, ie=True, strict=True):
-    """Saturating iron (Brauer law, damped Newton per step, FP32 inner CG with
-    FP64 Newton residual), start-up ramp, 3-level V-cycle on the first N steps."""
+T_START = time.perf_counter()
+
+
+class Budget:
+    """Wall-clock budget of the whole run, counted from the start of the process."""
+
+    def __init__(self, seconds):
+        self.seconds = seconds
+        self.skipped = []
+
+    def left(self):
+        return self.seconds - (time.perf_counter() - T_START)
+
+    def fits(self, label, estimate_s):
+        if self.left() >= estimate_s:
+            return True
+        self.skipped.append({"leg": label, "estimate_s": round(estimate_s, 1),
+                             "budget_left_s": round(self.left(), 1)})
+        log(f"skip {label}: needs ~{estimate_s:.0f} s, {self.left():.0f} s left")
+        return False
+
+
+def seq_windows(cfg_name, base, U, starts, width, stream, label):
+    """GPU sequential stepping on windows of `width` steps starting at the
+    points `starts` of the horizon of `base`, each from the MGRIT state U[i0]
+    (U: the MGRIT iterate, a device tensor [(N_t+1), n0]) with the source's
+    time origin moved to i0 * dt.  Returns the record: time per step (mean
+    over the windows), its full-horizon estimate, and the largest relative
+    deviation of the MGRIT states from the sequential ones in the windows."""
     import torch
+    from dataclasses import replace
     from workload import config
-    # these solves run for minutes: one progress line per MGRIT iteration
-    os.environ.setdefault("MGRIT_VERBOSE", "1")
     from paper_1912_03106_amd.solver import Solver
+    per_step, worst, wins = [], 0.0, []
+    for i0 in starts:
+        wcfg = config(cfg_name, n_steps=width, t_final=width * base.dt,
+                      source=replace(base.source, t_start=i0 * base.dt))
+        wcfg.meshes = base.meshes[:1] * 2
+        s = Solver(wcfg, stream=stream.cuda_stream, device_io=True)
+        out = torch.empty((width + 1, s.n0), dtype=torch.float64, device="cuda")
+        u0 = U[i0].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = s.seq_solve(u0=u0, out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        s.close()
+        ref = U[i0:i0 + width + 1]
+        dev = float(((out[1:] - ref[1:]).norm(dim=1) / ref[1:].norm(dim=1).clamp_min(1e-300)).max())
+        worst = max(worst, dev)
+        per_step.append(t / width)
+        wins.append({"start": i0, "steps": width, "time_s": round(t, 3),
+                     "newton_per_step": round(st["newton_sweeps"][0] / width, 2) if st["newton_sweeps"][0] else None,
+                     "pcg_per_step": round(st["pcg_sweeps"][0] / width, 1) if st["pcg_sweeps"][0] else None})
+        log(f"{label}: window at {i0}, {width} steps, {t:.2f} s, deviation {dev:.2e}")
+    ms = sum(per_step) / len(per_step)
+    return {"windows": wins, "ms_per_step": round(1e3 * ms, 3),
+            "time_s_full_horizon_estimate": round(ms * base.n_steps, 1),
+            "mgrit_deviation_in_windows": worst}
+
+
+NL_ETA = 1e-3            # nonlinear level-0 relaxation: stop at eta times the start residual
+NL_ESTIMATE_S = 190.0    # nonlinear 32768-step leg: MGRIT, set-up and the sequential windows
+
+
+def nonlinear_leg(N, stream, budget=None, learned=False, profile=False, seq_width=32, ie=True):
+    """The saturating-iron workload (64x512, dt = 0.02/32768, start-up ramp,
+    damped Newton, FP32 inner CG + FP64 Newton residual, 3-level V-cycle) on
+    its first N steps: MGRIT with implicit Euler on the coarse levels, GPU
+    sequential Newton stepping on four windows spread over the horizon, and
+    optionally the learned coarsest propagator."""
+    from workload import config
     full = config("cfg4")
     cfg = config("cfg4", n_steps=N, t_final=N * full.dt)
-    rec = {"workload": f"nonlinear eddy-current machine 64x512, first {N} of 32768 steps "
-                       f"(dt = {full.dt:.3e} s), 3-level V m=16, FP32 inner CG + FP64 Newton"}
-    out = None
-    runs = (("implicit_euler", {}), ("implicit_euler_eta1e-3", {"pcg_tol_eta": 1e-3}))
-    if N > 4096 or not strict:   # the strict solve takes minutes per 4096 steps
-        runs = runs[1:]
-    if not ie:
-        runs = ()
-    for label, kw in runs:
-        log(f"nonlinear {label}")
-        s = Solver(cfg, stream=stream.cuda_stream, device_io=True, **kw)
-        if out is None:
-            out = torch.empty((N + 1, s.n0), dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, st = s.solve(out=out)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        rec[label] = {"time_s": round(t, 2), "iterations": len(st["rho"]) - 1,
-                      "newton_sweeps": st["newton_sweeps"][:3], "pcg_sweeps": st["pcg_sweeps"][:3],
-                      "dof_steps_per_s": round(s.n0 * N / t, 1)}
-        log(f"nonlinear {label}: {len(st['rho']) - 1} iterations, {t:.1f} s")
-        s.close()
-    if learned:
-        log("nonlinear learned coarse propagator: training")
-        s = Solver(cfg, stream=stream.cuda_stream, device_io=True, coarse_model=1, pcg_tol_eta=1e-3)
-        ts = s.train_coarse(n_traj=128, epochs=8, batch=64, lr=2e-3, seed=5, perturb=0.3)
-        log(f"nonlinear learned: trained ({ts['time_data_s']:.0f} s data, {ts['time_train_s']:.0f} s Adam)")
-        if out is None:
-            out = torch.empty((N + 1, s.n0), dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, st = s.solve(out=out)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        rec["learned_eta1e-3"] = {"time_s": round(t, 2), "iterations": len(st["rho"]) - 1,
-                                  "coarse_fallback": st["coarse_fallback"],
-                                  "training": {k: (round(v, 4) if isinstance(v, float) else v)
-                                               for k, v in ts.items()}}
-        log(f"nonlinear learned: {len(st['rho']) - 1} iterations, {t:.1f} s")
-        s.close()
-    pre = min(N, 512)
-    pcfg = config("cfg4", n_steps=pre, t_final=pre * full.dt)
-    pcfg.meshes = cfg.meshes[:1] * 2
-    ps = Solver(pcfg, stream=stream.cuda_stream, device_io=True)
-    pout = torch.empty((pre + 1, ps.n0), dtype=torch.float64, device="cuda")
-    log(f"nonlinear sequential, {pre} steps")
+    rec = {"workload": f"nonlinear eddy-current machine 64x512 (Brauer iron, ramp over 2 periods), "
+                       f"{N} of 32768 steps (dt = {full.dt:.3e} s), 3-level V m=16 with spatial "
+                       f"coarsening, damped Newton, FP32 inner CG + FP64 Newton residual, level-0 "
+                       f"relaxation stopped at {NL_ETA:g} of the start residual"}
+    t = None
+    if ie:
+        t = _nonlinear_ie(rec, cfg, N, stream, budget, profile, seq_width)
+    if learned and (budget is None or budget.fits("nonlinear learned", 2.2 * (t or 180.0) + 60.0)):
+        _nonlinear_learned(rec, cfg, N, stream)
+    return rec
+
+
+def _nonlinear_ie(rec, cfg, N, stream, budget, profile, seq_width):
+    import torch
+    from paper_1912_03106_amd.solver import Solver
+    log("nonlinear: setup")
+    t_set = time.perf_counter()
+    s = Solver(cfg, stream=stream.cuda_stream, device_io=True, pcg_tol_eta=NL_ETA,
+               profile_kernels=int(profile))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_set
+    out = torch.empty((N + 1, s.n0), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, sst = ps.seq_solve(out=pout)
+    _, st = s.solve(out=out)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    rec["gpu_sequential"] = {"steps_run": pre, "time_s_run": round(t, 2),
-                             "time_s_scaled_to_N": round(t * N / pre, 1),
-                             "newton_per_step": round(sst["newton_sweeps"][0] / pre, 2)}
-    for k in ("implicit_euler", "implicit_euler_eta1e-3", "learned_eta1e-3"):
-        if k not in rec:
-            continue
-        rec[k]["speedup_vs_gpu_sequential"] = round(rec["gpu_sequential"]["time_s_scaled_to_N"] / rec[k]["time_s"], 3)
-    print(json.dumps(rec), flush=True)
+    rho = st["rho"]
+    rec["implicit_euler"] = {"time_to_solution_s": round(t, 2), "iterations": len(rho) - 1,
+                             "rho_rel_final": rho[-1] / rho[0], "setup_s": round(setup_s, 2),
+                             "newton_sweeps": st["newton_sweeps"][:3], "pcg_sweeps": st["pcg_sweeps"][:3],
+                             "dof_steps_per_s": round(s.n0 * N / t, 1)}
+    if profile:
+        rec["implicit_euler"]["time_phi_s"] = [round(x, 2) for x in st["time_phi_s"][:3]]
+    log(f"nonlinear: {len(rho) - 1} iterations, {t:.1f} s")
+    s.close()
+    starts = [N // 8, 3 * N // 8, 5 * N // 8, 7 * N // 8]
+    if budget is None or budget.fits("nonlinear sequential windows", 15.0):
+        rec["gpu_sequential"] = seq_windows("cfg4", cfg, out, starts, seq_width, stream,
+                                            "nonlinear sequential")
+        rec["gpu_sequential"]["kernel"] = "damped Newton on one column, same batched kernels, strict tolerances"
+        rec["implicit_euler"]["speedup_vs_gpu_sequential"] = round(
+            rec["gpu_sequential"]["time_s_full_horizon_estimate"] / t, 3)
+    del out
+    return t
+
+
+def _nonlinear_learned(rec, cfg, N, stream):
+    """The same solve with the learned coarsest propagator (implicit Euler plus
+    the network correction), trained on the GPU first."""
+    import torch
+    from paper_1912_03106_amd.solver import Solver
+    log("nonlinear learned coarse propagator: training")
+    s = Solver(cfg, stream=stream.cuda_stream, device_io=True, coarse_model=1, pcg_tol_eta=NL_ETA)
+    ts = s.train_coarse(n_traj=128, epochs=8, batch=64, lr=2e-3, seed=5, perturb=0.3)
+    log(f"nonlinear learned: trained ({ts['time_data_s']:.0f} s data, {ts['time_train_s']:.0f} s Adam)")
+    out = torch.empty((N + 1, s.n0), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, lst = s.solve(out=out)
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    rec["learned"] = {"time_to_solution_s": round(tl, 2), "iterations": len(lst["rho"]) - 1,
+                      "coarse_fallback": lst["coarse_fallback"],
+                      "training": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in ts.items()}}
+    log(f"nonlinear learned: {len(lst['rho']) - 1} iterations, {tl:.1f} s")
+    s.close()
+    del out
 
 
 HEADLINE_ETA = 3e-3      # level-0 relaxation: stop at max(pcg_tol ||b||, eta ||r_0||)
@@ -298,23 +381,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--seq-prefix", type=int, default=0,
-                    help="run only this many steps of the GPU sequential baseline and scale "
-                         "to N_t (0 = the whole horizon)")
+    ap.add_argument("--budget", type=float, default=555.0,
+                    help="seconds for the whole run (from the start of the process); legs after "
+                         "the headline that would not fit are skipped and listed")
+    ap.add_argument("--seq-width", type=int, default=512,
+                    help="steps per window of the linear GPU sequential baseline (4 windows)")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the plain-tolerance and FP32 + refinement solves")
-    ap.add_argument("--nl-skip-strict", action="store_true",
-                    help="--nonlinear: skip the solve with strict level-0 tolerances")
+    ap.add_argument("--no-nonlinear", action="store_true", help="skip the nonlinear legs")
+    ap.add_argument("--nonlinear", type=int, default=0, metavar="N",
+                    help="instead: only the saturating-iron workload on its first N steps (N "
+                         "divisible by 256), with the learned coarse propagator too")
     ap.add_argument("--nl-skip-learned", action="store_true",
                     help="with --nonlinear: skip the learned coarse propagator run")
-    ap.add_argument("--nl-skip-ie", action="store_true",
-                    help="with --nonlinear: skip the implicit-Euler coarse propagator runs")
-    ap.add_argument("--nonlinear", type=int, default=0, metavar="N",
-                    help="instead: the saturating-iron workload (64x512, dt = 0.02/32768) on its "
-                         "first N steps (N divisible by 256): MGRIT with implicit Euler and with "
-                         "the learned coarse propagator, and sequential stepping on a prefix")
+    ap.add_argument("--nl-profile", action="store_true",
+                    help="with --nonlinear: wall time per level (stream drained around every Phi)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed solve, copy 2^27 doubles (1 GiB read, 1 GiB written) so that "
                          "rocprofv3 byte counters can be calibrated on a kernel of known traffic")
@@ -343,13 +426,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    budget = Budget(args.budget)
     cfg = config("cfg2")
     if args.profile_short:
         profile_short(cfg, stream)
         return
     if args.nonlinear:
-        nonlinear(args.nonlinear, stream, learned=not args.nl_skip_learned, ie=not args.nl_skip_ie,
-                  strict=not args.nl_skip_strict)
+        print(json.dumps(nonlinear_leg(args.nonlinear, stream, learned=not args.nl_skip_learned,
+                                       profile=args.nl_profile)), flush=True)
         return
 
     # headline: timed solves, check intervals of CG iterations replayed from
@@ -383,26 +467,28 @@ def main():
     shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family", "prefetch_rows"), solver.kernel_shape(l)))
               for l in range(cfg.n_levels)]
     solver.close()
-    # the roofline of the dominant kernel comes from one more solve of the
-    # same workload with HIP events around every CG pass (eager launches)
-    log("profiled solve (HIP events around every CG pass)")
-    psolver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1, **HEADLINE)
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    _, pst = psolver.solve(out=out)
-    torch.cuda.synchronize()
-    t_prof = time.perf_counter() - tp0
-    roof = pass_b_roofline(pst, psolver, 8)
-    if roof is not None:
-        roof["traffic"] = measured_traffic()
-        if roof["traffic"] is not None:
-            roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["bytes_per_launch"], 3)
-            roof["traffic_profile"] = TRAFFIC_MEASURED["profile"]
-            roof["traffic_kernel"] = TRAFFIC_MEASURED["kernel"]
-    roof_kernel_shapes = [psolver.kernel_shape(l) for l in range(cfg.n_levels)]
-    psolver.close()
-    U_head = out.cpu().numpy()
-    del out
+
+    # the roofline of the dominant kernel: one more solve of the same
+    # workload with HIP events around every CG pass (eager launches)
+    roof, pst, t_prof = None, None, None
+    if budget.fits("profiled solve", 1.3 * per + 5.0):
+        log("profiled solve (HIP events around every CG pass)")
+        psolver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1, **HEADLINE)
+        pout = torch.empty_like(out)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        _, pst = psolver.solve(out=pout)
+        torch.cuda.synchronize()
+        t_prof = time.perf_counter() - tp0
+        roof = pass_b_roofline(pst, psolver, 8)
+        if roof is not None:
+            roof["traffic"] = measured_traffic()
+            if roof["traffic"] is not None:
+                roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["bytes_per_launch"], 3)
+                roof["traffic_profile"] = TRAFFIC_MEASURED["profile"]
+                roof["traffic_kernel"] = TRAFFIC_MEASURED["kernel"]
+        psolver.close()
+        del pout
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -410,15 +496,29 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # linear GPU sequential stepping on windows of the horizon
+    seq = None
+    if not args.no_seq and budget.fits("linear sequential windows", 4 * args.seq_width * 0.0045 + 8.0):
+        N = cfg.n_steps
+        seq = seq_windows("cfg2", cfg, out, [0, N // 4, N // 2, 3 * N // 4], args.seq_width, stream,
+                          "linear sequential")
+        seq["kernel"] = "cooperative multi-work-group Jacobi-PCG stepper (warm start u_{i-1}, 1e-12)"
+    # the largest workload: the nonlinear machine over its whole horizon
+    nl = None
+    if not args.no_nonlinear and budget.fits("nonlinear 32768 steps", NL_ESTIMATE_S):
+        nl = nonlinear_leg(config("cfg4").n_steps, stream, budget=budget)
+
+    U_head = out.cpu().numpy()
+    del out
+
+    cpu = None
+    if not args.no_cpu and budget.fits("CPU oracle sample", 15.0):
+        log("CPU oracle sample")
+        cpu, kept = cpu_baseline(cfg)
+        cpu["gpu_deviation_on_sample"] = {"timed_solve": oracle_deviation(kept, U_head)}
+
     variants = {}
-    U_var = {}
-    if not args.no_variants:
-        t, vst, vs, vout = timed_solve(cfg, stream, "plain FP64 (every solve to 1e-12)")
-        variants["plain_fp64"] = {"time_to_solution_s": round(t, 3), "iterations": len(vst["rho"]) - 1,
-                                  "pcg_sweeps": vst["pcg_sweeps"][:cfg.n_levels]}
-        U_var["plain_fp64"] = vout.cpu().numpy()
-        vs.close()
-        del vout
+    if not args.no_variants and budget.fits("FP32 + refinement", 0.9 * per + 8.0):
         cfg3 = config("cfg3")
         guess = torch.from_numpy(cfg3.initial_guess(n0)).to("cuda")
         log("setup cfg3 FP32 + refinement")
@@ -437,46 +537,27 @@ def main():
                                "level0_stop": f"max(1e-12 ||b||, {FP32_ETA:g} ||r_0||), F-relaxation "
                                               "from the previous iterate plus its input's change, "
                                               f"C-point residual to {RESIDUAL_ETA:g} relative",
-                               "coarse_levels": "stored inverses (FP64)",
-                               "autotuned_kernels": [dict(zip(("rows_per_block", "cols_per_lane", "family", "prefetch_rows"),
-                                                              vs.kernel_shape(l)))
-                                                     for l in range(cfg.n_levels)]}
-        U_var["fp32_ir"] = vout.cpu().numpy()
+                               "coarse_levels": "stored inverses (FP64)"}
+        U = vout.cpu().numpy()
+        variants["fp32_ir"]["rel_diff_vs_timed_solve"] = float(np.linalg.norm(U - U_head) / np.linalg.norm(U_head))
+        if cpu is not None:
+            cpu["gpu_deviation_on_sample"]["fp32_ir"] = oracle_deviation(kept, U)
         vs.close()
-        del vout, guess
-        import numpy as np
-        for k, U in U_var.items():
-            variants[k]["rel_diff_vs_timed_solve"] = float(np.linalg.norm(U - U_head) / np.linalg.norm(U_head))
+        del vout, guess, U
 
-    seq = None
-    if not args.no_seq:
-        pre = min(args.seq_prefix, cfg.n_steps) if args.seq_prefix > 0 else cfg.n_steps
-        pcfg = config("cfg2", n_steps=pre, t_final=pre * cfg.dt)
-        pcfg.meshes = cfg.meshes[:1] * 2
-        ps = Solver(pcfg, stream=stream.cuda_stream, device_io=True)
-        pout = torch.empty((pre + 1, n0), dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        log(f"GPU sequential stepping, {pre} steps")
-        ts = time.perf_counter()
-        _, sst = ps.seq_solve(out=pout)
-        torch.cuda.synchronize()
-        tseq = time.perf_counter() - ts
-        seq = {"kernel": "cooperative multi-work-group Jacobi-PCG stepper (warm start u_{i-1}, 1e-12)",
-               "steps_run": pre,
-               "time_s_run": round(tseq, 3), "time_s_full_horizon": round(tseq * cfg.n_steps / pre, 2),
-               "dof_steps_per_s": round(n0 * pre / tseq, 1),
-               "pcg_iterations_per_step": round(sst["pcg_sweeps"][0] / pre, 1)}
-        ps.close()
-        del pout
-        log(f"sequential {pre} steps: {tseq:.2f} s")
-
-    cpu = None
-    if not args.no_cpu:
-        log("CPU oracle sample")
-        cpu, kept = cpu_baseline(cfg)
-        cpu["gpu_deviation_on_sample"] = {"timed_solve": oracle_deviation(kept, U_head)}
-        for k, U in U_var.items():
-            cpu["gpu_deviation_on_sample"][k] = oracle_deviation(kept, U)
+    if not args.no_variants and budget.fits("plain FP64", 4.5 * per + 8.0):
+        t, vst, vs, vout = timed_solve(cfg, stream, "plain FP64 (every solve to 1e-12)")
+        variants["plain_fp64"] = {"time_to_solution_s": round(t, 3), "iterations": len(vst["rho"]) - 1,
+                                  "pcg_sweeps": vst["pcg_sweeps"][:cfg.n_levels]}
+        U = vout.cpu().numpy()
+        variants["plain_fp64"]["rel_diff_vs_timed_solve"] = float(np.linalg.norm(U - U_head) / np.linalg.norm(U_head))
+        if cpu is not None:
+            cpu["gpu_deviation_on_sample"]["plain_fp64"] = oracle_deviation(kept, U)
+        vs.close()
+        del vout, U
+    if nl is not None and budget.fits("nonlinear learned", 2.2 * nl["implicit_euler"]["time_to_solution_s"] + 60.0):
+        nl["learned"] = nonlinear_leg(config("cfg5").n_steps, stream, budget=budget, learned=True,
+                                      ie=False).get("learned")
 
     line = {
         "metric": "MGRIT time to 1e-8 rel. resid vs GPU seq. stepping; F-relax DOF-steps/s, GB/s",
@@ -500,18 +581,22 @@ def main():
                   "frelax_dof_steps_per_s": round(n0 * frelax_cols / st["time_relax_s"], 1)
                   if st["time_relax_s"] > 0 else None,
                   "level0_phi": frelax_cols, "pcg_sweeps": st["pcg_sweeps"][:cfg.n_levels],
-                  "setup_s": round(setup_s, 2),
-                  "profiled_solve": {"time_s": round(t_prof, 3), "iterations": len(pst["rho"]) - 1,
-                                     "pass_a_time_s": [round(x, 3) for x in pst["kernel_time_s"][0][:cfg.n_levels]],
-                                     "pass_b_time_s": [round(x, 3) for x in pst["kernel_time_s"][1][:cfg.n_levels]]}},
+                  "setup_s": round(setup_s, 2), "autotuned_kernels": shapes},
+        "nonlinear": nl,
         "variants": variants or None,
         "gpu_sequential": seq,
-        "autotuned_kernels": shapes,
+        "skipped": budget.skipped or None,
+        "wall_s": round(time.perf_counter() - T_START, 1),
     }
+    if pst is not None:
+        line["mgrit"]["profiled_solve"] = {
+            "time_s": round(t_prof, 3), "iterations": len(pst["rho"]) - 1,
+            "pass_a_time_s": [round(x, 3) for x in pst["kernel_time_s"][0][:cfg.n_levels]],
+            "pass_b_time_s": [round(x, 3) for x in pst["kernel_time_s"][1][:cfg.n_levels]]}
     if seq:
-        line["mgrit"]["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon"] / per, 3)
+        line["mgrit"]["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon_estimate"] / per, 3)
         for v in variants.values():
-            v["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon"] / v["time_to_solution_s"], 3)
+            v["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon_estimate"] / v["time_to_solution_s"], 3)
     print(json.dumps(line), flush=True)
 
 
