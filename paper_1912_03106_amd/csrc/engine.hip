@@ -555,9 +555,12 @@ static NlWork& nl_work(Handle& h, LevelState& S, PcgWork& w) {
   auto* nw = new NlWork();
   h.nl_keep.emplace_back(nw);
   nw->fp32 = (w.prec == MGRIT_FP32_IR);
+  // the symmetric Jacobian by offset (upper half, 4 values per row) on the
+  // periodic polar stencil, unless the general sparse-row kernels are forced
+  nw->dia_R = (h.par.pcg_kernel != 1) ? S.op.dia_R : 0;
   const size_t ev = static_cast<size_t>(S.nl.n_tri) * w.ld;
   const size_t vec = static_cast<size_t>(w.n) * w.ld;
-  const size_t mat = vec * S.op.W;
+  const size_t mat = vec * (nw->dia_R > 0 ? 4 : S.op.W);
   nw->nu = h.arena.alloc<double>(ev);
   nw->dnu = h.arena.alloc<double>(ev);
   nw->gx = h.arena.alloc<double>(ev);

@@ -132,6 +132,11 @@ struct PcgWork {
 // Newton workspace of a PcgWork (same n, ld).
 struct NlWork {
   bool fp32 = false;                   // inner solve in FP32
+  // periodic polar stencil (DevLevel::dia_R > 0): the Jacobian is stored as
+  // its upper half by offset, J[i][s][ld] for the offsets 0, +1, +R, +R+1
+  // (mod n) of row i; the lower entries of row i are the upper entries of
+  // the rows i-1, i-R, i-R-1 (J is symmetric)
+  int dia_R = 0;
   double *nu = nullptr, *dnu = nullptr, *gx = nullptr, *gy = nullptr;  // [T][ld]
   double* R = nullptr;                 // [n][ld] Newton residual
   double* dg = nullptr;                // [n][ld] diag(J)

@@ -329,6 +329,190 @@ __global__ __launch_bounds__(kBlock) void k_cgj_pass_b(
   block_partials<2>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
 }
 
+// ---------------------------------------------------------------------------
+// Diagonal-window Jacobian (periodic polar stencil, angle-major numbering,
+// R radial unknowns per ray).  Only the upper half is stored, by offset:
+// Jd[(i*4 + s)*ld + c] for s = 0, 1, 2, 3 <-> offsets 0, +1, +R, +R+1
+// (mod n); an offset without a pattern entry holds 0.  The CG passes walk
+// consecutive rows per wave with sliding register windows of the direction.
+
+__device__ __forceinline__ int wrap_row(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
+
+// Upper-half Jacobian values per column (unscaled) and diag(J).
+template <int W, typename T>
+__global__ __launch_bounds__(kBlock) void k_nl_jacobian_dia(
+    int n, int R, const int* __restrict__ col, const double* __restrict__ mm,
+    const int* __restrict__ cptr, const int* __restrict__ contrib,
+    const int* __restrict__ diag_slot, const double* __restrict__ area,
+    const double* __restrict__ grad, int ncols, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ outer, const double* __restrict__ nu_e,
+    const double* __restrict__ dnu_e, const double* __restrict__ gx, const double* __restrict__ gy,
+    T* __restrict__ Jd, double* __restrict__ dg) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && outer[c])) return;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  const int offs[4] = {0, 1, R, R + 1};
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      // the pattern pads short rows with zero entries in the diagonal
+      // column: the diagonal is the row's diagonal slot, every other offset
+      // appears at most once
+      const int j = wrap_row(i + offs[sl], n);
+      int t = -1;
+      if (sl == 0) {
+        t = diag_slot[i];
+      } else {
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+          if (t < 0 && col[static_cast<int64_t>(i) * W + q] == j) t = q;
+      }
+      double v = 0.0;
+      if (t >= 0) {
+        const int64_t slot = static_cast<int64_t>(i) * W + t;
+        v = mm[slot];
+        for (int q = cptr[slot]; q < cptr[slot + 1]; ++q) {
+          const int code = contrib[q];
+          const int e = code / 9, a = (code % 9) / 3, b = code % 3;
+          const int64_t o = static_cast<int64_t>(e) * ld + c;
+          const double* g = grad + 6 * e;
+          const double gag = g[2 * a] * gx[o] + g[2 * a + 1] * gy[o];
+          const double gbg = g[2 * b] * gx[o] + g[2 * b + 1] * gy[o];
+          v += area[e] * (nu_e[o] * (g[2 * a] * g[2 * b] + g[2 * a + 1] * g[2 * b + 1]) +
+                          2.0 * dnu_e[o] * gag * gbg);
+        }
+      }
+      Jd[(static_cast<int64_t>(i) * 4 + sl) * ld + c] = static_cast<T>(v);
+      if (sl == 0) dg[i * ld + c] = v;
+    }
+  }
+}
+
+// J^ = S J S on the upper half, S = diag(J)^{-1/2}; stores S.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_nl_scale_dia(int n, int R, int ncols, int ncc, int rpb,
+                                                         int64_t ld, const uint8_t* __restrict__ outer,
+                                                         const double* __restrict__ dg,
+                                                         T* __restrict__ Jd, T* __restrict__ sc) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  if (!(c < ncols && outer[c])) return;
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  const int offs[4] = {0, 1, R, R + 1};
+  for (int k = 0; k < rpw; ++k) {
+    const int i = i0 + k;
+    if (i >= n) break;
+    const double si = 1.0 / sqrt(dg[i * ld + c]);
+    sc[i * ld + c] = static_cast<T>(si);
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      const double sj = 1.0 / sqrt(dg[wrap_row(i + offs[sl], n) * ld + c]);
+      const int64_t o = (static_cast<int64_t>(i) * 4 + sl) * ld + c;
+      Jd[o] = static_cast<T>(si * static_cast<double>(Jd[o]) * sj);
+    }
+  }
+}
+
+// Pass A: p^ = r^ + beta p^_old (row i stored), partials of p^.J^p^ from the
+// upper half: p_i (J_ii p_i + 2 (J_i,i+1 p_i+1 + J_i,i+R p_i+R + J_i,i+R+1 p_i+R+1)).
+// Window rows i, i+1, i+R, i+R+1: two new direction rows per row.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cgj_pass_a_dia(
+    int n, int R, const T* __restrict__ Jd, int ncols, int ncc, int rpb, int64_t ld,
+    const uint8_t* __restrict__ active, const double* __restrict__ beta, int first,
+    const T* __restrict__ r, const T* __restrict__ pold, T* __restrict__ pnew,
+    double* __restrict__ part, int nrb, int* __restrict__ flags, int* __restrict__ hist) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int it = flags[4];
+    hist[it] = flags[0];
+    flags[4] = it + 1;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && active[c];
+  double acc[1] = {0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on && i0 < n) {
+    const int iend = (i0 + rpw < n) ? i0 + rpw : n;
+    const T be = first ? T(0) : static_cast<T>(beta[c]);
+    auto dir = [&](int row) {
+      const int64_t o = static_cast<int64_t>(row) * ld + c;
+      return first ? r[o] : fma(be, pold[o], r[o]);
+    };
+    T m1 = dir(i0), hi0 = dir(wrap_row(i0 + R, n));
+    for (int i = i0; i < iend; ++i) {
+      const T m2 = dir(wrap_row(i + 1, n)), hi1 = dir(wrap_row(i + R + 1, n));
+      const T* a = Jd + static_cast<int64_t>(i) * 4 * ld + c;
+      const T up = a[ld] * m2 + a[2 * ld] * hi0 + a[3 * ld] * hi1;
+      const T s = a[0] * m1 + T(2) * up;
+      acc[0] += static_cast<double>(m1) * static_cast<double>(s);
+      pnew[static_cast<int64_t>(i) * ld + c] = m1;
+      m1 = m2;
+      hi0 = hi1;
+    }
+  }
+  block_partials<1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
+// Pass B: q^ = J^ p^ from the upper half of row i and the upper entries of
+// the rows i-1 (offset +1), i-R (+R) and i-R-1 (+R+1) that reach row i;
+// x += alpha S p^, r^ -= alpha q^, partials of r^.r^ and diag(J) r^.r^.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cgj_pass_b_dia(
+    int n, int R, const T* __restrict__ Jd, const T* __restrict__ sc, const double* __restrict__ dg,
+    int ncols, int ncc, int rpb, int64_t ld, const uint8_t* __restrict__ active,
+    const double* __restrict__ alpha, const T* __restrict__ p, T* __restrict__ x,
+    T* __restrict__ r, double* __restrict__ part, int nrb) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  const bool on = c < ncols && active[c];
+  double acc[2] = {0.0, 0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on && i0 < n) {
+    const int iend = (i0 + rpw < n) ? i0 + rpw : n;
+    const T al = static_cast<T>(alpha[c]);
+    auto pv = [&](int row) { return p[static_cast<int64_t>(row) * ld + c]; };
+    auto jv = [&](int row, int sl) { return Jd[(static_cast<int64_t>(row) * 4 + sl) * ld + c]; };
+    T lo0 = pv(wrap_row(i0 - R - 1, n)), m0 = pv(wrap_row(i0 - 1, n));
+    T m1 = pv(i0), hi0 = pv(wrap_row(i0 + R, n));
+    T jm = jv(wrap_row(i0 - 1, n), 1);   // J_{i-1,i}
+    for (int i = i0; i < iend; ++i) {
+      const T lo1 = pv(wrap_row(i - R, n)), m2 = pv(wrap_row(i + 1, n)), hi1 = pv(wrap_row(i + R + 1, n));
+      const T j0 = jv(i, 0), j1 = jv(i, 1), j2 = jv(i, 2), j3 = jv(i, 3);
+      const T jl = jv(wrap_row(i - R, n), 2), jll = jv(wrap_row(i - R - 1, n), 3);
+      const T q = jll * lo0 + jl * lo1 + jm * m0 + j0 * m1 + j1 * m2 + j2 * hi0 + j3 * hi1;
+      const int64_t o = static_cast<int64_t>(i) * ld + c;
+      x[o] = fma(al * sc[o], m1, x[o]);
+      const T rv = r[o] - al * q;
+      r[o] = rv;
+      const double rd = static_cast<double>(rv);
+      acc[0] += rd * rd;
+      acc[1] += dg[o] * (rd * rd);
+      lo0 = lo1;
+      m0 = m1;
+      m1 = m2;
+      hi0 = hi1;
+      jm = j1;
+    }
+  }
+  block_partials<2>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
 // u += d for the columns still refining.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_nl_update(int n, int ncols, int ncc, int rpb, int64_t ld,
@@ -513,8 +697,27 @@ static void jac_impl(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork
   MG_HIP(hipGetLastError());
 }
 
+template <typename T>
+static void jac_dia_impl(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
+                         int ncols, T* Jd, T* sc) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  auto k = (L.W == 8) ? k_nl_jacobian_dia<8, T> : k_nl_jacobian_dia<16, T>;
+  hipLaunchKernelGGL(k, dim3(nb), dim3(kBlock), 0, s, L.n, nw.dia_R, L.col, L.m64, N.cptr, N.contrib,
+                     N.diag, N.area, N.grad, ncols, ncc, w.rows_per_block, w.ld, w.outer, nw.nu, nw.dnu, nw.gx,
+                     nw.gy, Jd, nw.dg);
+  hipLaunchKernelGGL(k_nl_scale_dia<T>, dim3(nb), dim3(kBlock), 0, s, L.n, nw.dia_R, ncols, ncc,
+                     w.rows_per_block, w.ld, w.outer, nw.dg, Jd, sc);
+  MG_HIP(hipGetLastError());
+}
+
 void launch_nl_jacobian(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgWork& w, NlWork& nw,
                         int ncols) {
+  if (nw.dia_R > 0) {
+    if (nw.fp32) jac_dia_impl<float>(s, L, N, w, nw, ncols, nw.J32, nw.s32);
+    else jac_dia_impl<double>(s, L, N, w, nw, ncols, nw.J64, nw.s64);
+    return;
+  }
   if (nw.fp32) jac_impl<float>(s, L, N, w, nw, ncols, nw.J32, nw.s32);
   else jac_impl<double>(s, L, N, w, nw, ncols, nw.J64, nw.s64);
 }
@@ -553,8 +756,37 @@ static void cgj_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int 
                      w.part, w.nrb);
 }
 
+template <typename T>
+static void cgj_a_dia(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols, int first,
+                      const T* J, const T* r, T* pold, T* pnew) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  hipLaunchKernelGGL(k_cgj_pass_a_dia<T>, dim3(nb), dim3(kBlock), 0, s, L.n, nw.dia_R, J, ncols, ncc,
+                     w.rows_per_block, w.ld, w.active, w.scal + 4 * w.ld, first, r, pold, pnew, w.part,
+                     w.nrb, w.flags, w.hist);
+}
+
+template <typename T>
+static void cgj_b_dia(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols, const T* J,
+                      const T* sc, const T* p, T* x, T* r) {
+  int ncc;
+  const int nb = tiles(w, ncols, ncc);
+  hipLaunchKernelGGL(k_cgj_pass_b_dia<T>, dim3(nb), dim3(kBlock), 0, s, L.n, nw.dia_R, J, sc, nw.dg,
+                     ncols, ncc, w.rows_per_block, w.ld, w.active, w.scal + 3 * w.ld, p, x, r, w.part,
+                     w.nrb);
+}
+
 void launch_nl_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols,
                       int first) {
+  if (nw.dia_R > 0) {
+    if (nw.fp32) cgj_a_dia<float>(s, L, w, nw, ncols, first, nw.J32, w.r32, w.p32[w.parity],
+                                  w.p32[w.parity ^ 1]);
+    else cgj_a_dia<double>(s, L, w, nw, ncols, first, nw.J64, nw.r64, nw.p64[w.parity],
+                           nw.p64[w.parity ^ 1]);
+    w.parity ^= 1;
+    MG_HIP(hipGetLastError());
+    return;
+  }
   if (nw.fp32) {
     float* po = w.p32[w.parity];
     float* pn = w.p32[w.parity ^ 1];
@@ -571,6 +803,12 @@ void launch_nl_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, 
 }
 
 void launch_nl_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols) {
+  if (nw.dia_R > 0) {
+    if (nw.fp32) cgj_b_dia<float>(s, L, w, nw, ncols, nw.J32, nw.s32, w.p32[w.parity], w.x32, w.r32);
+    else cgj_b_dia<double>(s, L, w, nw, ncols, nw.J64, nw.s64, nw.p64[w.parity], nw.d64, nw.r64);
+    MG_HIP(hipGetLastError());
+    return;
+  }
   if (nw.fp32) {
     const float* p = w.p32[w.parity];
     if (L.W == 8) cgj_b<float, 8>(s, L, w, nw, ncols, nw.J32, nw.s32, p, w.x32, w.r32);

@@ -192,3 +192,27 @@ def test_newton_early_stopped_relaxation_reaches_the_same_solution():
     U, st = s.solve()
     assert st["converged"]
     assert _rel(U, U_seq) <= 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_newton_jacobian_layouts_agree(nl_pair, precision):
+    """The Jacobian stored by stencil offset (upper half of the symmetric
+    matrix, diagonal-window CG passes) and on the general sparse rows
+    (pcg_kernel = 1): both reach the oracle's Newton solution."""
+    print(f"newton jacobian layouts {precision}", flush=True)
+    cfg, lev, U = nl_pair
+    from paper_1912_03106_amd import _abi
+    prec = _abi.FP64 if precision == "fp64" else _abi.FP32_IR
+    rng = np.random.default_rng(17)
+    B = 70
+    i_from = rng.integers(0, cfg.n_steps - 1, size=B)
+    u_prev = U[rng.integers(5, U.shape[0], size=B)]
+    ref = lev.phi(u_prev, i_from)
+    outs = []
+    for kernel in (0, 1):
+        s = _solver(cfg, precision=prec, ir_inner_tol=1e-6, newton_tol=1e-12, newton_max_iter=GPU_MAXIT,
+                    pcg_kernel=kernel)
+        outs.append(s.phi(0, u_prev, i_from))
+        s.close()
+    for out in outs:
+        assert _col_err(out, ref).max() <= PHI_TOL
