@@ -135,7 +135,9 @@ typedef struct {
                                * a stored A^{-1} (exact implicit Euler) instead of PCG; 2 = also
                                * every intermediate level <= 16384 unknowns (batched steps become
                                * one FP64 GEMM each); 0 = PCG everywhere */
-  int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one work-group, 2 cooperative grid */
+  int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one persistent work-group (linear
+                               * PCG or, nonlinear, the whole Newton sweep), 2 cooperative grid
+                               * (linear) / batched Newton kernels step by step (nonlinear) */
   int32_t use_graphs;         /* 1: replay each check interval of CG iterations from a captured
                                * hipGraph (not while profile_kernels = 1: launches stay eager so
                                * that HIP events time each pass) */
@@ -184,6 +186,11 @@ typedef struct {
   int32_t m_coarse;           /* temporal coarsening factor between levels l >= 1 and l + 1 (Sec. 4.1:
                                * a large factor m on the first level, a small one below); 0 = m.
                                * n_steps must be divisible by m * m_coarse^(levels - 2) */
+  int32_t coarse_persistent;  /* nonlinear model, coarsest level's sequential solve: 0 = one
+                               * persistent work-group runs the whole Newton sweep (every Newton,
+                               * CG and step-length iteration on the device) when the level has
+                               * at most 16384 unknowns, 1 = always, -1 = never (batched kernels
+                               * step by step) */
 } mgrit_params;
 
 typedef struct {

@@ -59,6 +59,7 @@ struct LevelState {
   int64_t ld_inv = 0;
   double* bvec = nullptr; // [n] right-hand side of one coarse step
   double* u0r = nullptr;  // [n] initial value restricted to this level's mesh (nested start)
+  double* nl_ws = nullptr; // persistent Newton stepper workspace (coarsest nonlinear level)
   bool relaxed = false;   // F-points hold a previous iterate (warm starts)
   bool cvalid = false;    // C-points hold a previous iterate
 };
@@ -77,6 +78,7 @@ struct Handle {
   double* u0_dev = nullptr;       // [n0]
   double* seq_U = nullptr;        // sequential trajectory [n0][ld] (lazy)
   double* seq_ws = nullptr;
+  double* seq_nl_ws = nullptr;    // persistent Newton stepper of the sequential solve (lazy)
   int coop_blocks = 0;            // cooperative stepper (lazy)
   double* coop_ws = nullptr;
   double* coop_part = nullptr;
@@ -125,6 +127,7 @@ constexpr int kMinRowsPerBlock = 16;
 constexpr size_t kMaxGraphs = 256;       // cached CG-interval graphs per handle
 constexpr int kMaxInverseN = 8192;        // largest coarsest level given a stored inverse
 constexpr int kMaxInverseNCoarse = 16384; // largest intermediate level given one (coarse_inverse = 2)
+constexpr int kMaxPersistentN = 16384;    // largest level given the persistent one-work-group Newton sweep
 static const int kRowsPerBlockCandidates[] = {16, 32, 64, 128, 256};
 
 static void alloc_pcg(Handle& h, PcgWork& w, int n, int cap, int rows_per_block, int prec) {
@@ -904,6 +907,25 @@ static void coarsest_solve(Handle& h, int l) {
     if (h.st && l < MGRIT_MAX_LEVELS) h.st->phi_columns[l] += S.N;
     return;
   }
+  if (S.nl.n_tri > 0 && !learned_active(h, l) && S.nl_ws) {
+    // the whole sequential Newton sweep in one persistent work-group
+    MG_HIP(hipMemsetAsync(S.pcg.flags, 0, 8 * sizeof(int), s));
+    launch_seq_newton(s, S.op, S.nl, h.src, static_cast<int>(S.N), 0, S.U, S.ld, S.G, S.ld, 1,
+                      h.par.newton_tol, h.par.newton_max_iter, std::ldexp(1.0, -h.par.newton_halvings),
+                      h.par.ir_inner_tol, h.par.pcg_max_iter, S.nl_ws, S.pcg.flags);
+    MG_HIP(hipMemcpyAsync(S.pcg.host_flags, S.pcg.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    const int bits = S.pcg.host_flags[1];
+    if (bits & 1) fail(MGRIT_NONFINITE, "non-finite value in the coarsest Newton solve");
+    if (bits & 8) fail(MGRIT_NEWTON_NOT_CONVERGED, "Newton did not converge in newton_max_iter iterations on the coarsest level");
+    if (bits & 2) fail(MGRIT_PCG_NOT_CONVERGED, "inner CG did not converge on the coarsest level");
+    if (h.st && l < MGRIT_MAX_LEVELS) {
+      h.st->phi_columns[l] += S.N;
+      h.st->pcg_sweeps[l] += S.pcg.host_flags[2];
+      h.st->newton_sweeps[l] += S.pcg.host_flags[3];
+    }
+    return;
+  }
   if (S.nl.n_tri > 0 || learned_active(h, l)) {
     // one step at a time, u_s = Psi(u_{s-1}) + g_s (Newton for the nonlinear model)
     for (int64_t st = 1; st <= S.N; ++st) {
@@ -1221,6 +1243,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (!(ph.dt > 0.0) || ph.n_steps < 1) fail(MGRIT_INVALID_ARGUMENT, "time grid");
   if (ph.carrier != 0 && ph.carrier != 1) fail(MGRIT_INVALID_ARGUMENT, "carrier");
   if (par->m_coarse != 0 && par->m_coarse < 2) fail(MGRIT_INVALID_ARGUMENT, "m_coarse must be 0 or > 1");
+  if (par->coarse_persistent < -1 || par->coarse_persistent > 1)
+    fail(MGRIT_INVALID_ARGUMENT, "coarse_persistent must be -1, 0 or 1");
   h.m = par->m;
   // factor between levels l and l+1: m on level 0, m_coarse (or m) below
   auto factor = [&](int l) { return (l == 0 || par->m_coarse == 0) ? par->m : par->m_coarse; };
@@ -1300,6 +1324,13 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
       S.U = h.arena.alloc<double>(S.ss);
       S.G = h.arena.alloc<double>(S.ss);
       S.seq_ws = h.arena.alloc<double>(4 * static_cast<size_t>(S.n));
+      // nonlinear coarsest level: one persistent work-group runs the whole
+      // sequential Newton sweep (latency-bound otherwise)
+      const bool persistent = par->coarse_persistent == 1 ||
+                              (par->coarse_persistent == 0 && S.n <= kMaxPersistentN);
+      if (ph.nonlinear && L > 1 && persistent)
+        S.nl_ws = h.arena.alloc<double>(
+            static_cast<size_t>(seq_newton_ws_doubles(S.n, S.op.W, S.nl.n_tri)));
       MG_HIP(hipMemsetAsync(S.U, 0, sizeof(double) * S.ss, s));
       MG_HIP(hipMemsetAsync(S.G, 0, sizeof(double) * S.ss, s));
     } else {
@@ -1534,7 +1565,25 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   MG_HIP(hipMemsetAsync(flags, 0, 8 * sizeof(int), s));
   const bool coop = h.par.seq_kernel == 2 || (h.par.seq_kernel == 0 && S0.n >= 4096 && S0.op.W == 8);
   auto t0 = std::chrono::steady_clock::now();
-  if (S0.nl.n_tri > 0) {
+  const bool nl_persistent = S0.nl.n_tri > 0 &&
+                             (h.par.seq_kernel == 1 || (h.par.seq_kernel == 0 && S0.n <= 4096));
+  if (nl_persistent) {
+    // nonlinear, small level: the whole sweep in one persistent work-group
+    if (!h.seq_nl_ws)
+      h.seq_nl_ws = h.arena.alloc<double>(
+          static_cast<size_t>(seq_newton_ws_doubles(S0.n, S0.op.W, S0.nl.n_tri)));
+    launch_seq_newton(s, S0.op, S0.nl, h.src, static_cast<int>(S0.N), 0, U, ld, nullptr, 0, 0,
+                      h.par.newton_tol, h.par.newton_max_iter, std::ldexp(1.0, -h.par.newton_halvings),
+                      h.par.ir_inner_tol, h.par.pcg_max_iter, h.seq_nl_ws, flags);
+    MG_HIP(hipMemcpyAsync(S0.pcg.host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    const int bits = S0.pcg.host_flags[1];
+    st->newton_sweeps[0] += S0.pcg.host_flags[3];
+    st->pcg_sweeps[0] += S0.pcg.host_flags[2];
+    if (bits & 8) fail(MGRIT_NEWTON_NOT_CONVERGED, "Newton did not converge in newton_max_iter iterations");
+    S0.pcg.host_flags[1] = bits & 3;
+    S0.pcg.host_flags[2] = 0;
+  } else if (S0.nl.n_tri > 0) {
     // nonlinear: batched Newton on one column, step after step
     for (int64_t st = 1; st <= S0.N; ++st) {
       PhiCall c;
@@ -2255,6 +2304,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->nested = 0;
   p->loss_tol = 0.0;
   p->m_coarse = 0;
+  p->coarse_persistent = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {

@@ -167,6 +167,16 @@ void launch_nl_jacobian(hipStream_t s, const DevLevel& L, const NlLevel& N, PcgW
                         int ncols);
 void launch_nl_cg_init(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);
 void launch_nl_pass_a(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols, int first);
+// Persistent one-work-group damped-Newton stepper: nsteps sequential steps
+// u_s = Phi(u_{s-1}) + g_s on the column block U (column s = point s), the
+// whole Newton / CG / step-length loop on the device.  ws: seq_newton_ws_doubles.
+// flags[1] bits: 1 non-finite, 2 inner CG cap, 8 Newton cap; flags[2] += CG
+// iterations, flags[3] += Newton iterations.
+int64_t seq_newton_ws_doubles(int n, int W, int n_tri);
+void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
+                       int nsteps, int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
+                       int warm, double newton_tol, int newton_max, double lam_min, double inner_tol,
+                       int cg_max, double* ws, int* flags);
 void launch_nl_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols);
 // u += fac[c] d on the columns with ls[c] set
 void launch_nl_update(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);

@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "source_dev.h"
 
 namespace mg {
 namespace {
@@ -638,9 +639,333 @@ __global__ __launch_bounds__(kBlock) void k_nl_test(int ncols, int nrb, int64_t 
 
 __global__ void k_zero_flag0(int* flags) { flags[0] = 0; }
 
+// ---------------------------------------------------------------------------
+// Persistent single-work-group damped-Newton stepper for small levels (the
+// coarsest level's sequential solve u_s = Phi(u_{s-1}) + g_s, and small
+// sequential baselines).  One work-group runs every step, every Newton
+// iteration, every inner CG iteration and every step-length trial of the
+// whole sweep without returning to the host: the same arithmetic as the
+// batched Newton (element fields, FP64 residual, Jacobian on the shared
+// pattern, symmetric Jacobi scaling, CG to the inner tolerance, Armijo step
+// lengths), with the vectors in global memory (L2-resident at these sizes)
+// and block reductions in a fixed order.
+
+__device__ double nl_block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) t += sh[k];
+  return t;
+}
+
+struct SeqNewtonArgs {
+  int n, W, n_tri;
+  const int* col;
+  const double* mm;          // M/dt on the pattern
+  const uint8_t* has_mass;
+  const double* F;           // [3][n]
+  const int* tri_u;
+  const double* grad;
+  const double* area;
+  const double* nu_lin;
+  const uint8_t* iron;
+  const int* cptr;
+  const int* contrib;
+  const int* diag_slot;
+  double k1, k2, k3;
+  double dt;
+  int nsteps;
+  int64_t t0;                // step offset: step s samples the source at (t0 + s) dt
+  double* U;                 // column s = point s
+  int64_t ldu;
+  const double* G;           // FAS right-hand side (or null)
+  int64_t ldg;
+  int warm;                  // start from U[:, s] - G[:, s] instead of U[:, s-1]
+  double tol2;               // (Newton tolerance)^2, relative to ||R(u_prev)||^2
+  int newton_max;
+  double lam_min;
+  double tin2;               // (inner CG tolerance)^2
+  int cg_max;
+  double* ws;                // workspace, see seq_newton_ws_doubles
+  int* flags;                // [1] bits: 1 non-finite, 2 inner CG cap, 8 Newton cap; [2] CG its; [3] Newton its
+};
+
+// Element fields of u: gradient, nu, d nu / d B^2.
+__device__ void sn_elem(const SeqNewtonArgs& a, const double* u, double* gx, double* gy, double* nu,
+                        double* dnu) {
+  for (int e = threadIdx.x; e < a.n_tri; e += blockDim.x) {
+    const int* v = a.tri_u + 3 * e;
+    const double* gr = a.grad + 6 * e;
+    double ux = 0.0, uy = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double uk = v[k] >= 0 ? u[v[k]] : 0.0;
+      ux += uk * gr[2 * k];
+      uy += uk * gr[2 * k + 1];
+    }
+    double nv = a.nu_lin[e], dv = 0.0;
+    if (a.iron[e]) {
+      const double ex = exp(a.k2 * (ux * ux + uy * uy));
+      nv = a.k1 * ex + a.k3;
+      dv = a.k1 * a.k2 * ex;
+    }
+    gx[e] = ux;
+    gy[e] = uy;
+    nu[e] = nv;
+    dnu[e] = dv;
+  }
+  __syncthreads();
+}
+
+// R = (M/dt)(u - u_prev) + K(u) u - f; returns ||R||^2.
+__device__ double sn_residual(const SeqNewtonArgs& a, const double* u, const double* up, double s0,
+                              double s1, double s2, const double* gx, const double* gy,
+                              const double* nu, double* R, double* sh) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
+    double rv = 0.0;
+    if (a.has_mass[i]) {
+      for (int t = 0; t < a.W; ++t) {
+        const int64_t sl = static_cast<int64_t>(i) * a.W + t;
+        const int j = a.col[sl];
+        rv += a.mm[sl] * (u[j] - up[j]);
+      }
+    }
+    const int64_t slot = static_cast<int64_t>(i) * a.W + a.diag_slot[i];
+    for (int q = a.cptr[slot]; q < a.cptr[slot + 1]; ++q) {
+      const int code = a.contrib[q];
+      const int e = code / 9, al = (code % 9) / 3;
+      rv += nu[e] * a.area[e] * (a.grad[6 * e + 2 * al] * gx[e] + a.grad[6 * e + 2 * al + 1] * gy[e]);
+    }
+    rv -= (s0 * a.F[i] + s1 * a.F[a.n + i]) + s2 * a.F[2 * a.n + i];
+    R[i] = rv;
+    acc += rv * rv;
+  }
+  return nl_block_sum(acc, sh);
+}
+
+__global__ __launch_bounds__(kSeqThreads) void k_seq_newton(SeqNewtonArgs a, SourceDev src) {
+  __shared__ double sh[32];
+  __shared__ double sgn[3];
+  __shared__ int stop;
+  if (threadIdx.x == 0) stop = 0;
+  const int n = a.n, W = a.W, T = a.n_tri;
+  double* x = a.ws;
+  double* xt = x + n;
+  double* up = xt + n;                       // u_prev of the step
+  double* R = up + n;
+  double* r = R + n;
+  double* p = r + n;
+  double* q = p + n;
+  double* y = q + n;
+  double* sc = y + n;
+  double* J = sc + n;                        // [n*W] scaled Jacobian
+  double* gx = J + static_cast<int64_t>(n) * W;
+  double* gy = gx + T;
+  double* nu = gy + T;
+  double* dnu = nu + T;
+  int cg_total = 0, newton_total = 0;
+  for (int s = 1; s <= a.nsteps; ++s) {
+    if (threadIdx.x == 0) {
+      const double t = static_cast<double>(a.t0 + s) * a.dt;
+      const double amp = source_scale(t, src);
+      for (int k = 0; k < 3; ++k) sgn[k] = amp * pwm(t, src, k);
+    }
+    __syncthreads();
+    const double s0 = sgn[0], s1 = sgn[1], s2 = sgn[2];
+    // u_prev and the start as contiguous vectors
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double g = a.warm ? a.U[i * a.ldu + s] : a.U[i * a.ldu + s - 1];
+      if (a.warm && a.G) g -= a.G[i * a.ldg + s];
+      x[i] = g;
+      up[i] = a.U[i * a.ldu + s - 1];
+    }
+    __syncthreads();
+    // reference ||R(u_prev)||^2, then the residual of the start
+    sn_elem(a, up, gx, gy, nu, dnu);
+    const double ref = sn_residual(a, up, up, s0, s1, s2, gx, gy, nu, R, sh);
+    sn_elem(a, x, gx, gy, nu, dnu);
+    double rcur = sn_residual(a, x, up, s0, s1, s2, gx, gy, nu, R, sh);
+    if (!isfinite(rcur) || !isfinite(ref)) {
+      if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); stop = 1; }
+    }
+    __syncthreads();
+    if (stop) break;
+    int k = 0;
+    while (rcur > a.tol2 * ref) {
+      if (k >= a.newton_max) {
+        if (threadIdx.x == 0) { atomicOr(a.flags + 1, 8); stop = 1; }
+        break;
+      }
+      ++k;
+      // Jacobian at x (element fields of x are current), diag, scaling
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        for (int t = 0; t < W; ++t) {
+          const int64_t slot = static_cast<int64_t>(i) * W + t;
+          double v = a.mm[slot];
+          for (int qq = a.cptr[slot]; qq < a.cptr[slot + 1]; ++qq) {
+            const int code = a.contrib[qq];
+            const int e = code / 9, al = (code % 9) / 3, bl = code % 3;
+            const double* g = a.grad + 6 * e;
+            const double gag = g[2 * al] * gx[e] + g[2 * al + 1] * gy[e];
+            const double gbg = g[2 * bl] * gx[e] + g[2 * bl + 1] * gy[e];
+            v += a.area[e] * (nu[e] * (g[2 * al] * g[2 * bl] + g[2 * al + 1] * g[2 * bl + 1]) +
+                              2.0 * dnu[e] * gag * gbg);
+          }
+          J[slot] = v;
+          if (t == a.diag_slot[i]) sc[i] = 1.0 / sqrt(v);
+        }
+      }
+      __syncthreads();
+      // J^ = S J S; CG on J^ y = S (-R), y = 0
+      double lrr = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double si = sc[i];
+        for (int t = 0; t < W; ++t) {
+          const int64_t slot = static_cast<int64_t>(i) * W + t;
+          J[slot] = si * J[slot] * sc[a.col[slot]];
+        }
+        const double rv = -si * R[i];
+        r[i] = rv;
+        p[i] = rv;
+        y[i] = 0.0;
+        lrr += rv * rv;
+      }
+      double rr = nl_block_sum(lrr, sh);
+      const double rr0 = rr;
+      int it = 0;
+      while (rr > a.tin2 * rr0) {
+        if (it >= a.cg_max) {
+          if (threadIdx.x == 0) { atomicOr(a.flags + 1, 2); stop = 1; }
+          break;
+        }
+        double lpq = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+          double sq = 0.0;
+          for (int t = 0; t < W; ++t) {
+            const int64_t slot = static_cast<int64_t>(i) * W + t;
+            sq += J[slot] * p[a.col[slot]];
+          }
+          q[i] = sq;
+          lpq += p[i] * sq;
+        }
+        const double pq = nl_block_sum(lpq, sh);
+        const double al = rr / pq;
+        double lr = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+          y[i] += al * p[i];
+          const double rv = r[i] - al * q[i];
+          r[i] = rv;
+          lr += rv * rv;
+        }
+        const double rrn = nl_block_sum(lr, sh);
+        if (!isfinite(rrn)) {
+          if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); stop = 1; }
+          break;
+        }
+        const double be = rrn / rr;
+        rr = rrn;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = r[i] + be * p[i];
+        __syncthreads();
+        ++it;
+      }
+      cg_total += it;
+      __syncthreads();
+      if (stop) break;
+      // damped update: the first lambda in 1, 1/2, ... with
+      // ||R(x + lambda d)|| < (1 - 1e-4 lambda) ||R(x)||, else lam_min
+      double lam = 1.0;
+      while (true) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) xt[i] = x[i] + lam * (sc[i] * y[i]);
+        __syncthreads();
+        sn_elem(a, xt, gx, gy, nu, dnu);
+        const double t = sn_residual(a, xt, up, s0, s1, s2, gx, gy, nu, R, sh);
+        const double shrink = 1.0 - 1e-4 * lam;
+        const bool ok = isfinite(t) && t < shrink * shrink * rcur;
+        if (ok || lam <= a.lam_min) {
+          if (!isfinite(t)) {
+            if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); stop = 1; }
+          }
+          rcur = t;
+          break;
+        }
+        lam *= 0.5;
+      }
+      __syncthreads();
+      if (stop) break;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = xt[i];
+      __syncthreads();
+      // the element fields and R now belong to x
+    }
+    newton_total += k;
+    __syncthreads();
+    if (stop) break;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double v = x[i];
+      if (a.G) v += a.G[i * a.ldg + s];
+      a.U[i * a.ldu + s] = v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(a.flags + 2, cg_total);
+    atomicAdd(a.flags + 3, newton_total);
+  }
+}
+
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 }  // namespace
+
+int64_t seq_newton_ws_doubles(int n, int W, int n_tri) {
+  return 9LL * n + static_cast<int64_t>(n) * W + 4LL * n_tri;
+}
+
+void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
+                       int nsteps, int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
+                       int warm, double newton_tol, int newton_max, double lam_min, double inner_tol,
+                       int cg_max, double* ws, int* flags) {
+  if (nsteps <= 0) return;
+  SeqNewtonArgs a;
+  a.n = L.n;
+  a.W = L.W;
+  a.n_tri = N.n_tri;
+  a.col = L.col;
+  a.mm = L.m64;
+  a.has_mass = L.has_mass;
+  a.F = L.F;
+  a.tri_u = N.tri_u;
+  a.grad = N.grad;
+  a.area = N.area;
+  a.nu_lin = N.nu_lin;
+  a.iron = N.iron;
+  a.cptr = N.cptr;
+  a.contrib = N.contrib;
+  a.diag_slot = N.diag;
+  a.k1 = N.k1;
+  a.k2 = N.k2;
+  a.k3 = N.k3;
+  a.dt = L.dt;
+  a.nsteps = nsteps;
+  a.t0 = t0;
+  a.U = U;
+  a.ldu = ldu;
+  a.G = G;
+  a.ldg = ldg;
+  a.warm = warm;
+  a.tol2 = newton_tol * newton_tol;
+  a.newton_max = newton_max;
+  a.lam_min = lam_min;
+  a.tin2 = inner_tol * inner_tol;
+  a.cg_max = cg_max;
+  a.ws = ws;
+  a.flags = flags;
+  hipLaunchKernelGGL(k_seq_newton, dim3(1), dim3(kSeqThreads), 0, s, a, src);
+  MG_HIP(hipGetLastError());
+}
 
 // ----------------------------------------------------------------------------
 

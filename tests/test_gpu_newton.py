@@ -103,14 +103,19 @@ def test_newton_phi_full_size_sampled_columns():
     assert err.max() <= PHI_TOL, err
 
 
-def test_newton_seq_solve_matches_oracle(nl_pair):
-    print("newton seq", flush=True)
+@pytest.mark.parametrize("seq_kernel", [1, 2])
+def test_newton_seq_solve_matches_oracle(nl_pair, seq_kernel):
+    """Sequential damped-Newton stepping in one persistent work-group (the
+    whole sweep on the device, seq_kernel = 1) and with the batched kernels
+    step by step (seq_kernel = 2) against the oracle."""
+    print(f"newton seq kernel {seq_kernel}", flush=True)
     cfg, lev, _ = nl_pair
     cfg = _small_cfg(n_steps=64, t_final=64 * cfg.dt)
     from paper_1912_03106_amd import _abi
     s = _solver(cfg, precision=_abi.FP64, ir_inner_tol=1e-6, newton_tol=1e-12,
-                newton_max_iter=GPU_MAXIT)
-    U, _ = s.seq_solve()
+                newton_max_iter=GPU_MAXIT, seq_kernel=seq_kernel)
+    U, st = s.seq_solve()
+    assert st["newton_sweeps"][0] > 64
     U_ref = sequential(lev, np.zeros(lev.n), 64)
     err = np.linalg.norm(U - U_ref, axis=1)[1:] / np.linalg.norm(U_ref, axis=1)[1:]
     assert err.max() <= PHI_TOL * 10, err.max()
@@ -216,3 +221,25 @@ def test_newton_jacobian_layouts_agree(nl_pair, precision):
         s.close()
     for out in outs:
         assert _col_err(out, ref).max() <= PHI_TOL
+
+
+@pytest.mark.parametrize("persistent", [-1, 1])
+def test_newton_mgrit_coarsest_persistent_and_batched_agree(persistent):
+    """The coarsest level's sequential Newton sweep in one persistent
+    work-group or with the batched kernels step by step: the same history
+    (to the Newton tolerance) and the sequential solution."""
+    print(f"newton mgrit coarsest persistent {persistent}", flush=True)
+    cfg = _small_cfg()
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=2)
+    from paper_1912_03106_amd import _abi
+    s = _solver(cfg, precision=_abi.FP32_IR, ir_inner_tol=1e-5, newton_tol=1e-11,
+                newton_max_iter=GPU_MAXIT, pcg_tol=1e-12, coarse_persistent=persistent)
+    U, st = s.solve()
+    assert st["converged"]
+    for a, b in zip(st["rho"][:3], hist[:3]):
+        assert abs(a - b) <= 1e-8 * hist[0], (a, b)
+    assert _rel(U, U_seq) <= 1e-7
+    assert st["newton_sweeps"][1] > 0
