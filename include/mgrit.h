@@ -134,7 +134,7 @@ typedef struct {
   int32_t coarse_inverse;     /* linear model: 1 = the coarsest level (<= 8192 unknowns) steps with
                                * a stored A^{-1} (exact implicit Euler) instead of PCG; 2 = also
                                * every intermediate level <= 16384 unknowns (batched steps become
-                               * one FP64 GEMM each); 0 = PCG everywhere */
+                               * one FP64 matrix-core product each); 0 = PCG everywhere */
   int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one persistent work-group (linear
                                * PCG or, nonlinear, the whole Newton sweep), 2 cooperative grid
                                * (linear) / batched Newton kernels step by step (nonlinear) */
@@ -273,8 +273,7 @@ int phi_step(void* h, int32_t level, int32_t B, const int64_t* i_from,
  * Limits: n_level * round_up(B, 64) <= 2^21 (e.g. B <= 64 on the 64 x 512
  * mesh, B <= 1024 on 16 x 128), B <= 32768, pcg_max_iter <= 65472: else
  * MGRIT_INVALID_ARGUMENT.  The nonlinear model (its Newton workspace does not
- * fit) and intermediate levels stepped by a stored inverse (a library GEMM):
- * MGRIT_UNSUPPORTED.  The array is shared by every call on one GPU and keeps
+ * fit): MGRIT_UNSUPPORTED.  The array is shared by every call on one GPU and keeps
  * the last call's contents: calls that overlap on one GPU (other threads,
  * handles or streams) race, so the caller serialises them.  The handle's
  * device must be current.  Returns after the stream is synchronized. */

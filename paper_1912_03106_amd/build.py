@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libmgrit.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "pcg.hip", "newton.hip", "gnn.hip", "setup.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "pcg.hip", "newton.hip", "gnn.hip", "gemm.hip", "setup.hip", "engine.hip"]
 HEADERS = ["internal.h", "setup.h", "source_dev.h"]
 
 CFLAGS = [
@@ -48,7 +48,7 @@ def build(verbose=False):
         list(ex.map(lambda c: _run(c, verbose), jobs))
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-          "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"], verbose)
+          "-Wl,-rpath,/opt/rocm/lib"], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -7,7 +7,6 @@
 // C-points are slab 0 (columns 0..N/m).  The coarsest level is one column
 // block [n][ld] with column t = point t.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -60,6 +59,8 @@ struct LevelState {
   double* bvec = nullptr; // [n] right-hand side of one coarse step
   double* u0r = nullptr;  // [n] initial value restricted to this level's mesh (nested start)
   double* nl_ws = nullptr; // persistent Newton stepper workspace (coarsest nonlinear level)
+  double* gemm_part = nullptr;   // partial sums of the stored-inverse product (intermediate levels)
+  int64_t gemm_part_size = 0;
   bool relaxed = false;   // F-points hold a previous iterate (warm starts)
   bool cvalid = false;    // C-points hold a previous iterate
 };
@@ -103,7 +104,6 @@ struct Handle {
     bool operator<(const GraphKey& o) const { return tie() < o.tie(); }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
-  rocblas_handle blas = nullptr;   // FP64 GEMMs with stored inverses of intermediate levels
   // learned coarse propagator on the coarsest level
   GnnModel gnn;
   bool has_gnn = false;
@@ -708,15 +708,11 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
     // as its sequential solve
     launch_ie_inverse_batch(s, S.op, c.ncols, w.src, w.ld, c.in, S.Ainv, S.ld_inv, w.r, w.x, w.ld);
   } else if (S.Ainv) {
-    // intermediate linear level: right-hand sides, then one FP64 GEMM
-    // X = Ainv B.  In column-major terms the [n][ld] blocks are ld x n
-    // matrices (columns of the block are rows), so X_cm = B_cm * Ainv_cm.
+    // intermediate linear level: right-hand sides, then X = Ainv B on the
+    // FP64 matrix cores
     launch_ie_rhs_batch(s, S.op, c.ncols, w.src, w.ld, c.in, w.r, w.ld);
-    const double one = 1.0, zero = 0.0;
-    if (rocblas_dgemm(h.blas, rocblas_operation_none, rocblas_operation_none, c.ncols, S.n, S.n, &one,
-                      w.r, static_cast<rocblas_int>(w.ld), S.Ainv, static_cast<rocblas_int>(S.ld_inv), &zero,
-                      w.x, static_cast<rocblas_int>(w.ld)) != rocblas_status_success)
-      fail(MGRIT_HIP_ERROR, "rocblas_dgemm failed");
+    launch_inv_gemm(s, c.ncols, S.n, w.r, w.ld, S.Ainv, S.ld_inv, w.x, w.ld, S.gemm_part,
+                    S.gemm_part_size);
   } else {
     launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
     it = S.nl.n_tri > 0
@@ -1384,13 +1380,13 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (!ph.nonlinear && par->coarse_inverse == 2) {
     for (int l = 1; l + 1 < L; ++l)
       if (h.lv[l].n <= kMaxInverseNCoarse) {
-        if (!h.blas) {
-          if (rocblas_create_handle(&h.blas) != rocblas_status_success)
-            fail(MGRIT_HIP_ERROR, "rocblas_create_handle failed");
-          if (rocblas_set_stream(h.blas, s) != rocblas_status_success)
-            fail(MGRIT_HIP_ERROR, "rocblas_set_stream failed");
-        }
-        build_coarse_inverse(h, h.lv[l]);
+        LevelState& S = h.lv[l];
+        build_coarse_inverse(h, S);
+        // partial sums of the k slices of narrow batches (phi_step_noalloc
+        // may pass up to 2^21 / n columns)
+        const int max_cols = std::max<int>(S.pcg.cap, static_cast<int>(kNoallocVec / S.n));
+        S.gemm_part_size = inv_gemm_part_doubles(max_cols, S.n);
+        if (S.gemm_part_size > 0) S.gemm_part = h.arena.alloc<double>(static_cast<size_t>(S.gemm_part_size));
       }
   }
   if (L > 1) setup_gnn(h, prob->meshes[L - 1], pats[L - 1], ph);
@@ -1698,8 +1694,6 @@ static void phi_step_noalloc_impl(Handle& h, int level, int B, const int64_t* i_
   LevelState& S = h.lv[level];
   if (S.nl.n_tri > 0)
     fail(MGRIT_UNSUPPORTED, "phi_step_noalloc: the nonlinear model's Newton workspace does not fit the scratch array");
-  if (S.Ainv && !S.coarsest)
-    fail(MGRIT_UNSUPPORTED, "phi_step_noalloc: this level steps by a library GEMM that may allocate");
   const int64_t ld = round_up(B, kWave);
   if (ld > kNoallocCols || static_cast<int64_t>(S.n) * ld > kNoallocVec)
     fail(MGRIT_INVALID_ARGUMENT, "phi_step_noalloc: n * round_up(B, 64) must be <= 2^21 and B <= 32768 (scratch size)");
@@ -2072,6 +2066,13 @@ static void train_impl(Handle& h, const mgrit_train_params* tp, mgrit_train_stat
       std::swap(X, Xn);
     }
     restrict_to(X, Y + k * nt);
+    if (h.verbose && ((k + 1) % 16 == 0 || k + 1 == Nc)) {
+      MG_HIP(hipStreamSynchronize(s));
+      std::fprintf(stderr, "[mgrit train] trajectories: %lld of %lld coarse steps, %.1f s\n",
+                   static_cast<long long>(k + 1), static_cast<long long>(Nc),
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+      std::fflush(stderr);
+    }
   }
   for (int64_t k = 0; k < Nc; ++k) {
     PhiCall c;
@@ -2190,6 +2191,15 @@ static void train_impl(Handle& h, const mgrit_train_params* tp, mgrit_train_stat
       MG_HIP(hipMemsetAsync(g.grad, 0, sizeof(float) * g.off.n_params, s));
       gnn_backward(s, g, S, Psib, Yb, loss_d + e);
       gnn_adam(s, g, lr, ++g.adam_step);
+    }
+    if (h.verbose) {
+      double le = 0.0;
+      MG_HIP(hipMemcpyAsync(&le, loss_d + e, sizeof(double), hipMemcpyDeviceToHost, s));
+      MG_HIP(hipStreamSynchronize(s));
+      std::fprintf(stderr, "[mgrit train] epoch %d of %d: loss %.4e, %.1f s\n", e + 1, tp->epochs,
+                   le / (static_cast<double>(spe) * S * n),
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count());
+      std::fflush(stderr);
     }
   }
   std::vector<double> losses(tp->epochs);
@@ -2442,7 +2452,6 @@ void mgrit_destroy(void* hp) {
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   for (auto e : h->ev) (void)hipEventDestroy(e);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
-  if (h->blas) (void)rocblas_destroy_handle(h->blas);
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   delete h;
 }

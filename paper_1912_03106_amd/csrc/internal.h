@@ -355,6 +355,12 @@ void launch_ie_rhs_batch(hipStream_t s, const DevLevel& L, int ncols, const doub
 void launch_ie_inverse_batch(hipStream_t s, const DevLevel& L, int ncols, const double* src, int64_t lds,
                              CView u, const double* Ainv, int64_t lda, double* B, double* X,
                              int64_t ld);
+// X = Ainv B for M columns of [N][ld] blocks (FP64 MFMA): X[j*ldx + c] =
+// sum_k Ainv[k*lda + j] B[k*ldb + c]; part: partial sums of the k slices
+// (inv_gemm_part_doubles(max columns, N) doubles), unused for wide batches.
+int64_t inv_gemm_part_doubles(int max_cols, int N);
+void launch_inv_gemm(hipStream_t s, int M, int N, const double* B, int64_t ldb, const double* A,
+                     int64_t lda, double* X, int64_t ldx, double* part, int64_t part_size);
 // Y[:, b] = X[:, b] + alpha[b] (X[:, perm[b]] - X[:, b]), b < nt (Y != X)
 void gnn_mix(hipStream_t s, int n, int nt, const double* X, int64_t ld, const int* perm,
              const double* alpha, double* Y);

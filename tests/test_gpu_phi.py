@@ -154,3 +154,22 @@ def test_phi_full_size_compaction_identical():
     pick = [0, 299, 599]
     err = _col_err(outs[1][pick], lev.phi(u_prev[pick], i_from[pick]))
     assert err.max() <= PHI_TOL, err
+
+
+@pytest.mark.parametrize("B", [1, 64, 100, 1030])
+def test_phi_intermediate_level_stored_inverse(B):
+    """An intermediate level that steps by its stored inverse (the product
+    X = A^{-1} B on the FP64 matrix cores, k split over work-groups for narrow
+    batches): the 32x256 level 1 of the large workload against the direct
+    solve, batches of 1, 64 (the relaxation sweeps), 100 and 1030 (ragged
+    tiles) columns."""
+    print(f"phi stored inverse 32x256 B={B}", flush=True)
+    cfg = config("cfg2")
+    s = _solver(cfg, pcg_tol=1e-13, coarse_inverse=2)
+    lev = Level(polar_mesh(32, 256), cfg.level_dt(1), cfg.source)
+    U = sequential(lev, np.zeros(lev.n), 30)
+    rng = np.random.default_rng(B)
+    i_from = rng.integers(0, cfg.level_steps(1) - 1, size=B)
+    u_prev = U[rng.integers(1, 31, size=B)] * rng.uniform(0.5, 1.5, size=(B, 1))
+    err = _col_err(s.phi(1, u_prev, i_from), lev.phi(u_prev, i_from))
+    assert err.max() <= PHI_TOL, err.max()

@@ -95,7 +95,8 @@ def test_noalloc_matches_phi_step_two_calls(level, precision):
 
 def test_noalloc_full_size_level_at_the_limit():
     """The 64x512 level at the largest batch the scratch array holds
-    (B = 64: n * 64 <= 2^21), then a smaller ragged one; B = 65 is rejected."""
+    (B = 64: n * 64 <= 2^21), then a smaller ragged one; B = 65 is rejected;
+    the intermediate 32x256 level of the same hierarchy, two calls."""
     print("noalloc 64x512 B=64", flush=True)
     from paper_1912_03106_amd import MgritError
     from paper_1912_03106_amd.solver import Solver
@@ -115,10 +116,16 @@ def test_noalloc_full_size_level_at_the_limit():
     with pytest.raises(MgritError) as e:
         _noalloc(s, 0, np.zeros((65, lev.n)), np.zeros(65, dtype=np.int64))
     assert e.value.name == "INVALID_ARGUMENT"
-    # the intermediate level steps by a library GEMM
-    with pytest.raises(MgritError) as e:
-        _noalloc(s, 1, np.zeros((4, s.level_info(1)[0])), np.zeros(4, dtype=np.int64))
-    assert e.value.name == "UNSUPPORTED"
+    # the intermediate 32x256 level steps by its stored inverse (the FP64
+    # matrix-core product with k split over work-groups for narrow batches)
+    lev1 = Level(polar_mesh(32, 256), cfg.level_dt(1), cfg.source)
+    U1 = sequential(lev1, np.zeros(lev1.n), 20)
+    for B in (64, 5):
+        u_prev = U1[rng.integers(2, 21, size=B)] * rng.uniform(0.5, 1.5, size=(B, 1))
+        i_from = rng.integers(0, cfg.level_steps(1) - 1, size=B)
+        got = _noalloc(s, 1, u_prev, i_from)
+        assert _rel_cols(got, lev1.phi(u_prev, i_from)) <= PHI_TOL
+        assert _rel_cols(got, s.phi(1, u_prev, i_from)) <= 1e-12
     # an empty batch is a no-op
     assert _noalloc(s, 0, np.zeros((0, lev.n)), np.zeros(0, dtype=np.int64)).shape == (0, lev.n)
     s.close()
