@@ -285,6 +285,34 @@ def seq_windows(cfg_name, base, U, starts, width, stream, label):
             "mgrit_deviation_in_windows": worst}
 
 
+def seq_inverse(base, U, width, stream):
+    """GPU sequential stepping of the linear workload with the finest level's
+    stored inverse (seq_kernel = 3) on the first `width` steps: build time,
+    time per step (the same for every step) and its full-horizon estimate."""
+    import torch
+    from workload import config
+    from paper_1912_03106_amd.solver import Solver
+    wcfg = config("cfg2", n_steps=width, t_final=width * base.dt)
+    wcfg.meshes = base.meshes[:1] * 2
+    s = Solver(wcfg, stream=stream.cuda_stream, device_io=True, seq_kernel=3)
+    out = torch.empty((width + 1, s.n0), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = s.seq_solve(out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.close()
+    build = st["time_nested_s"]
+    step = (t - build) / width
+    dev = float(((out[1:] - U[1:width + 1]).norm(dim=1) / U[1:width + 1].norm(dim=1).clamp_min(1e-300)).max())
+    log(f"linear sequential, stored inverse: build {build:.1f} s, {1e3 * step:.3f} ms per step")
+    del out
+    return {"kernel": "exact implicit-Euler steps by the stored FP64 inverse (n^2 = 8.3 GB streamed per step)",
+            "steps_run": width, "inverse_build_s": round(build, 2), "ms_per_step": round(1e3 * step, 3),
+            "time_s_full_horizon_estimate": round(build + step * base.n_steps, 1),
+            "mgrit_deviation": dev}
+
+
 NL_ETA = 1e-3            # nonlinear level-0 relaxation: stop at eta times the start residual
 NL_ESTIMATE_S = 190.0    # nonlinear 32768-step leg: MGRIT, set-up and the sequential windows
 
@@ -503,6 +531,13 @@ def main():
         seq = seq_windows("cfg2", cfg, out, [0, N // 4, N // 2, 3 * N // 4], args.seq_width, stream,
                           "linear sequential")
         seq["kernel"] = "cooperative multi-work-group Jacobi-PCG stepper (warm start u_{i-1}, 1e-12)"
+    # the same stepping with the level's stored inverse (exact steps, one
+    # stream of the 8.3 GB inverse per step; cost independent of the state)
+    if not args.no_seq and budget.fits("linear sequential, stored inverse", 45.0):
+        seq_inv = seq_inverse(cfg, out, args.seq_width * 2, stream)
+        if seq is None:
+            seq = {}
+        seq["stored_inverse"] = seq_inv
     # the largest workload: the nonlinear machine over its whole horizon
     nl = None
     if not args.no_nonlinear and budget.fits("nonlinear 32768 steps", NL_ESTIMATE_S):
@@ -594,9 +629,14 @@ def main():
             "pass_a_time_s": [round(x, 3) for x in pst["kernel_time_s"][0][:cfg.n_levels]],
             "pass_b_time_s": [round(x, 3) for x in pst["kernel_time_s"][1][:cfg.n_levels]]}
     if seq:
-        line["mgrit"]["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon_estimate"] / per, 3)
+        # the fastest GPU sequential method is the reference
+        cands = [x["time_s_full_horizon_estimate"] for x in (seq, seq.get("stored_inverse") or {})
+                 if "time_s_full_horizon_estimate" in x]
+        ref = min(cands)
+        seq["fastest_full_horizon_s"] = ref
+        line["mgrit"]["speedup_vs_gpu_sequential"] = round(ref / per, 3)
         for v in variants.values():
-            v["speedup_vs_gpu_sequential"] = round(seq["time_s_full_horizon_estimate"] / v["time_to_solution_s"], 3)
+            v["speedup_vs_gpu_sequential"] = round(ref / v["time_to_solution_s"], 3)
     print(json.dumps(line), flush=True)
 
 

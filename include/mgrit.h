@@ -137,7 +137,10 @@ typedef struct {
                                * one FP64 matrix-core product each); 0 = PCG everywhere */
   int32_t seq_kernel;         /* mgrit_seq_solve: 0 choose, 1 one persistent work-group (linear
                                * PCG or, nonlinear, the whole Newton sweep), 2 cooperative grid
-                               * (linear) / batched Newton kernels step by step (nonlinear) */
+                               * (linear) / batched Newton kernels step by step (nonlinear),
+                               * 3 linear model: exact steps with the finest level's stored
+                               * inverse (built by the first call, n^2 doubles; the build time is
+                               * reported in time_nested_s) */
   int32_t use_graphs;         /* 1: replay each check interval of CG iterations from a captured
                                * hipGraph (not while profile_kernels = 1: launches stay eager so
                                * that HIP events time each pass) */
@@ -191,6 +194,10 @@ typedef struct {
                                * CG and step-length iteration on the device) when the level has
                                * at most 16384 unknowns, 1 = always, -1 = never (batched kernels
                                * step by step) */
+  int32_t pcg_check_narrow;   /* PCG iterations between host reads of the active-column count for
+                               * batches of at most 128 columns (coarse levels: no compaction, and
+                               * each read is a device-to-host round trip); 0 = pcg_check_every;
+                               * default 16; both at most 64 */
 } mgrit_params;
 
 typedef struct {
@@ -213,7 +220,8 @@ typedef struct {
   double  time_total_s;
   int32_t coarse_fallback;    /* coarse_model = 1: iteration after which the residual grew and
                                * the coarsest level went back to implicit Euler; -1 = never */
-  double  time_nested_s;      /* nested = 1: time of the nested-iteration start (in time_total_s) */
+  double  time_nested_s;      /* nested = 1: time of the nested-iteration start (in time_total_s);
+                               * mgrit_seq_solve with seq_kernel = 3: time of the inverse build */
   double  loss_change[MGRIT_MAX_HISTORY];  /* loss_tol > 0: largest relative change of the C-point
                                * Joule losses against the previous iteration (-1 for the first) */
   double  time_phi_s[MGRIT_MAX_LEVELS];    /* profile_kernels = 1: wall time of each level's Phi

@@ -67,7 +67,7 @@ class Params(C.Structure):
         ("compact_columns", C.c_int32), ("compact_fraction", C.c_double),
         ("pcg_prefetch", C.c_int32), ("residual_eta", C.c_double), ("pcg_rows_narrow", C.c_int32),
         ("cycle", C.c_int32), ("nested", C.c_int32), ("loss_tol", C.c_double),
-        ("m_coarse", C.c_int32), ("coarse_persistent", C.c_int32),
+        ("m_coarse", C.c_int32), ("coarse_persistent", C.c_int32), ("pcg_check_narrow", C.c_int32),
     ]
 
 

@@ -359,8 +359,11 @@ static int pcg_iterate(Handle& h, int level, const DevLevel& L, PcgWork& w, int 
   hipStream_t s = h.stream;
   const bool prof = h.par.profile_kernels && h.st && level < MGRIT_MAX_LEVELS;
   int it = 0, used = 0;
-  const int chunk = std::max(1, std::min(h.par.pcg_check_every > 0 ? h.par.pcg_check_every : 16,
-                                         static_cast<int>(h.ev.size() / 4)));
+  // narrow batches (coarse levels) gain nothing from compaction checks, and
+  // every check is a device-to-host round trip: check less often
+  const int every = (ncols <= kNarrowCols && h.par.pcg_check_narrow > 0) ? h.par.pcg_check_narrow
+                                                                         : h.par.pcg_check_every;
+  const int chunk = std::max(1, std::min(every > 0 ? every : 16, static_cast<int>(h.ev.size() / 4)));
   const int cap = std::min(max_iter > 0 ? max_iter : h.par.pcg_max_iter, w.hist_cap);
   int64_t cols = 0, launches = 0;
   w.parity = 0;
@@ -891,24 +894,43 @@ static void coarsest_solve(Handle& h, int l) {
     PcgWork& w = S.pcg;
     const bool learned = learned_active(h, l);
     for (int64_t st = 1; st <= S.N; ++st) {
+      // one column: right-hand side and result contiguous (the product's
+      // arithmetic does not depend on the strides)
       launch_source_table(s, h.src, S.op.dt, 1, nullptr, st - 1, 0, w.src, w.ld);
       launch_ie_inverse_batch(s, S.op, 1, w.src, w.ld, CView{S.U + st - 1, S.ld}, S.Ainv, S.ld_inv,
-                              w.r, w.x, w.ld);
+                              S.bvec, w.x, 1);
       if (learned)
         gnn_forward64(s, h.gnn, h.src, 1, nullptr, st - 1, 0, nullptr, nullptr, CView{S.U + st - 1, S.ld},
-                      CView{w.x, w.ld}, w.x, w.ld);
-      launch_axpby3(s, S.n, 1, S.U + st, S.ld, 1.0, CView{w.x, w.ld}, 1.0, CView{S.G + st, S.ld}, 0.0,
+                      CView{w.x, 1}, w.x, 1);
+      launch_axpby3(s, S.n, 1, S.U + st, S.ld, 1.0, CView{w.x, 1}, 1.0, CView{S.G + st, S.ld}, 0.0,
                     CView{});
     }
     if (h.st && l < MGRIT_MAX_LEVELS) h.st->phi_columns[l] += S.N;
     return;
   }
-  if (S.nl.n_tri > 0 && !learned_active(h, l) && S.nl_ws) {
-    // the whole sequential Newton sweep in one persistent work-group
+  if (S.nl.n_tri > 0 && S.nl_ws) {
+    const double lam_min = std::ldexp(1.0, -h.par.newton_halvings);
     MG_HIP(hipMemsetAsync(S.pcg.flags, 0, 8 * sizeof(int), s));
-    launch_seq_newton(s, S.op, S.nl, h.src, static_cast<int>(S.N), 0, S.U, S.ld, S.G, S.ld, 1,
-                      h.par.newton_tol, h.par.newton_max_iter, std::ldexp(1.0, -h.par.newton_halvings),
-                      h.par.ir_inner_tol, h.par.pcg_max_iter, S.nl_ws, S.pcg.flags);
+    if (!learned_active(h, l)) {
+      // the whole sequential Newton sweep in one persistent work-group
+      launch_seq_newton(s, S.op, S.nl, h.src, static_cast<int>(S.N), 0, S.U, S.ld, S.G, S.ld, 1,
+                        h.par.newton_tol, h.par.newton_max_iter, lam_min, h.par.ir_inner_tol,
+                        h.par.pcg_max_iter, S.nl_ws, S.pcg.flags);
+    } else {
+      // learned propagator: per step the implicit-Euler Newton step in the
+      // persistent work-group, the network correction, then + g_s
+      PcgWork& w = S.pcg;
+      for (int64_t st = 1; st <= S.N; ++st) {
+        launch_seq_newton(s, S.op, S.nl, h.src, 1, st - 1, S.U + st - 1, S.ld, S.G + st - 1, S.ld, 1,
+                          h.par.newton_tol, h.par.newton_max_iter, lam_min, h.par.ir_inner_tol,
+                          h.par.pcg_max_iter, S.nl_ws, S.pcg.flags, false);
+        launch_axpby3(s, S.n, 1, w.x, w.ld, 1.0, CView{S.U + st, S.ld}, 0.0, CView{}, 0.0, CView{});
+        gnn_forward64(s, h.gnn, h.src, 1, nullptr, st - 1, 0, nullptr, nullptr, CView{S.U + st - 1, S.ld},
+                      CView{w.x, w.ld}, w.x, w.ld);
+        launch_axpby3(s, S.n, 1, S.U + st, S.ld, 1.0, CView{w.x, w.ld}, 1.0, CView{S.G + st, S.ld}, 0.0,
+                      CView{});
+      }
+    }
     MG_HIP(hipMemcpyAsync(S.pcg.host_flags, S.pcg.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     MG_HIP(hipStreamSynchronize(s));
     const int bits = S.pcg.host_flags[1];
@@ -1129,6 +1151,11 @@ static void build_coarse_inverse(Handle& h, LevelState& S) {
   h.par.pcg_max_iter = std::max(keep_max, 20000);   // history buffer size for this solve
   alloc_pcg(h, w, S.n, chunk, rows_per_block_for(S.n), MGRIT_FP64);
   h.par.pcg_max_iter = keep_max;
+  // the level's own (autotuned) CG kernel shape
+  set_rows_per_block(w, S.pcg.rows_per_block);
+  w.cpl = S.pcg.cpl;
+  w.dia = S.pcg.dia;
+  w.depth = S.pcg.depth;
   S.ld_inv = round_up(S.n, kWave);
   S.Ainv = h.arena.alloc<double>(static_cast<size_t>(S.n) * S.ld_inv);
   S.bvec = h.arena.alloc<double>(S.n);
@@ -1239,6 +1266,9 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   if (!(ph.dt > 0.0) || ph.n_steps < 1) fail(MGRIT_INVALID_ARGUMENT, "time grid");
   if (ph.carrier != 0 && ph.carrier != 1) fail(MGRIT_INVALID_ARGUMENT, "carrier");
   if (par->m_coarse != 0 && par->m_coarse < 2) fail(MGRIT_INVALID_ARGUMENT, "m_coarse must be 0 or > 1");
+  if (par->pcg_check_every < 0 || par->pcg_check_every > 64 || par->pcg_check_narrow < 0 ||
+      par->pcg_check_narrow > 64)
+    fail(MGRIT_INVALID_ARGUMENT, "pcg_check_every and pcg_check_narrow must be in 0..64");
   if (par->coarse_persistent < -1 || par->coarse_persistent > 1)
     fail(MGRIT_INVALID_ARGUMENT, "coarse_persistent must be -1, 0 or 1");
   h.m = par->m;
@@ -1367,8 +1397,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   MG_HIP(hipEventCreate(&h.ev0));
   MG_HIP(hipEventCreate(&h.ev1));
   MG_HIP(hipStreamCreateWithFlags(&h.capture_stream, hipStreamNonBlocking));
-  const int chunk = std::max(1, std::min(par->pcg_check_every > 0 ? par->pcg_check_every : 16, 64));
-  h.ev.resize(4 * chunk);
+  h.ev.resize(4 * 64);   // 4 events per CG iteration of a check interval (<= 64 iterations)
   for (auto& e : h.ev) MG_HIP(hipEventCreate(&e));
   for (auto& S : h.lv) {
     if (par->pcg_kernel == 2 && S.op.dia_R == 0)
@@ -1560,10 +1589,32 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   int* flags = S0.pcg.flags;
   MG_HIP(hipMemsetAsync(flags, 0, 8 * sizeof(int), s));
   const bool coop = h.par.seq_kernel == 2 || (h.par.seq_kernel == 0 && S0.n >= 4096 && S0.op.W == 8);
+  if (h.par.seq_kernel < 0 || h.par.seq_kernel > 3) fail(MGRIT_INVALID_ARGUMENT, "seq_kernel must be 0..3");
   auto t0 = std::chrono::steady_clock::now();
   const bool nl_persistent = S0.nl.n_tri > 0 &&
                              (h.par.seq_kernel == 1 || (h.par.seq_kernel == 0 && S0.n <= 4096));
-  if (nl_persistent) {
+  if (h.par.seq_kernel == 3) {
+    // linear model: every step is exact implicit Euler with the level's
+    // stored inverse, one stream of A^{-1} per step (built here on first use)
+    if (S0.nl.n_tri > 0) fail(MGRIT_UNSUPPORTED, "seq_kernel = 3 needs the linear model");
+    if (!S0.Ainv) {
+      const auto tb = std::chrono::steady_clock::now();
+      build_coarse_inverse(h, S0);
+      st->time_nested_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
+    }
+    PcgWork& w = S0.pcg;
+    t0 = std::chrono::steady_clock::now();
+    for (int64_t st_i = 1; st_i <= S0.N; ++st_i) {
+      // right-hand side and result as contiguous vectors (stride 1), so that
+      // the product streams A^{-1} and the right-hand side coalesced
+      launch_source_table(s, h.src, S0.op.dt, 1, nullptr, st_i - 1, 0, w.src, w.ld);
+      launch_ie_inverse_batch(s, S0.op, 1, w.src, w.ld, CView{U + st_i - 1, ld}, S0.Ainv, S0.ld_inv,
+                              S0.bvec, w.x, 1);
+      launch_axpby3(s, S0.n, 1, U + st_i, ld, 1.0, CView{w.x, 1}, 0.0, CView{}, 0.0, CView{});
+    }
+    MG_HIP(hipStreamSynchronize(s));
+    std::memset(S0.pcg.host_flags, 0, 4 * sizeof(int));
+  } else if (nl_persistent) {
     // nonlinear, small level: the whole sweep in one persistent work-group
     if (!h.seq_nl_ws)
       h.seq_nl_ws = h.arena.alloc<double>(
@@ -2315,6 +2366,7 @@ void mgrit_default_params(mgrit_params* p) {
   p->loss_tol = 0.0;
   p->m_coarse = 0;
   p->coarse_persistent = 0;
+  p->pcg_check_narrow = 16;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {

@@ -176,7 +176,7 @@ int64_t seq_newton_ws_doubles(int n, int W, int n_tri);
 void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
                        int nsteps, int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
                        int warm, double newton_tol, int newton_max, double lam_min, double inner_tol,
-                       int cg_max, double* ws, int* flags);
+                       int cg_max, double* ws, int* flags, bool add_g = true);
 void launch_nl_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols);
 // u += fac[c] d on the columns with ls[c] set
 void launch_nl_update(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);

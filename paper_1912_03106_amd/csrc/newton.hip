@@ -685,6 +685,7 @@ struct SeqNewtonArgs {
   const double* G;           // FAS right-hand side (or null)
   int64_t ldg;
   int warm;                  // start from U[:, s] - G[:, s] instead of U[:, s-1]
+  int add_g;                 // store Phi(u_{s-1}) + g_s (1) or Phi(u_{s-1}) alone (0)
   double tol2;               // (Newton tolerance)^2, relative to ||R(u_prev)||^2
   int newton_max;
   double lam_min;
@@ -905,7 +906,7 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_newton(SeqNewtonArgs a, Sou
     if (stop) break;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       double v = x[i];
-      if (a.G) v += a.G[i * a.ldg + s];
+      if (a.G && a.add_g) v += a.G[i * a.ldg + s];
       a.U[i * a.ldu + s] = v;
     }
     __syncthreads();
@@ -927,9 +928,10 @@ int64_t seq_newton_ws_doubles(int n, int W, int n_tri) {
 void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
                        int nsteps, int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
                        int warm, double newton_tol, int newton_max, double lam_min, double inner_tol,
-                       int cg_max, double* ws, int* flags) {
+                       int cg_max, double* ws, int* flags, bool add_g) {
   if (nsteps <= 0) return;
   SeqNewtonArgs a;
+  a.add_g = add_g ? 1 : 0;
   a.n = L.n;
   a.W = L.W;
   a.n_tri = N.n_tri;

@@ -508,6 +508,68 @@ __global__ __launch_bounds__(kBlock) void k_cg_pass_b_dia(
   block_partials<2, CPL>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c0, on);
 }
 
+// CG start on the periodic polar stencil: b = (M/dt) u_in + f (original
+// scaling) and r^ = S (b - A x) = S b - A^ (S^-1 x), with A^ by offset and the
+// window rows of S^-1 x (rows i-R-1 .. i+R+1) kept in registers while a wave
+// walks its rows (three new rows per row); partials r^.r^, r.r, b.b as in
+// k_cg_init.  The mass term gathers u_in only on the conductor rows.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_cg_init_dia(
+    int n, int R, const double* __restrict__ dv, const int* __restrict__ col,
+    const double* __restrict__ mm, const uint8_t* __restrict__ has_mass,
+    const double* __restrict__ sc, const double* __restrict__ F, int ncols, int ncc, int rpb,
+    const double* __restrict__ uin, int64_t ldu, const double* __restrict__ src, int64_t ld,
+    const double* __restrict__ x, double* __restrict__ r, double* __restrict__ part,
+    int nrb, int* __restrict__ flags) {
+  int rb, cc;
+  tile_decode(blockIdx.x, ncc, rb, cc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[4] = 0;
+  }
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = cc * kWave + lane;
+  bool on[1] = {c < ncols};
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (on[0]) { s0 = src[c]; s1 = src[ld + c]; s2 = src[2 * ld + c]; }
+  double acc[3][1] = {{0.0}, {0.0}, {0.0}};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (on[0] && i0 < n) {
+    const int iend = (i0 + rpw < n) ? i0 + rpw : n;
+    auto xs = [&](int row) { return x[static_cast<int64_t>(row) * ld + c] / sc[row]; };
+    double lo0 = xs(wrap_index(i0 - R - 1, n)), m0 = xs(wrap_index(i0 - 1, n));
+    double m1 = xs(i0), hi0 = xs(wrap_index(i0 + R, n));
+    for (int i = i0; i < iend; ++i) {
+      const double lo1 = xs(wrap_index(i - R, n)), m2 = xs(wrap_index(i + 1, n));
+      const double hi1 = xs(wrap_index(i + R + 1, n));
+      double bv = 0.0;
+      if (has_mass[i]) {
+        const int* ci = col + static_cast<int64_t>(i) * W;
+        const double* mi = mm + static_cast<int64_t>(i) * W;
+#pragma unroll
+        for (int t = 0; t < W; ++t) bv += mi[t] * uin[ci[t] * ldu + c];
+      }
+      bv += (s0 * F[i] + s1 * F[n + i]) + s2 * F[2 * n + i];
+      const double* a = dv + static_cast<int64_t>(i) * 8;
+      const double ax = a[0] * lo0 + a[1] * lo1 + a[2] * m0 + a[3] * m1 + a[4] * m2 + a[5] * hi0 +
+                        a[6] * hi1;
+      const double si = sc[i];
+      const double rh = si * bv - ax;
+      r[static_cast<int64_t>(i) * ld + c] = rh;
+      const double rv = rh / si;
+      acc[0][0] += rh * rh;
+      acc[1][0] += rv * rv;
+      acc[2][0] += bv * bv;
+      lo0 = lo1;
+      m0 = m1;
+      m1 = m2;
+      hi0 = hi1;
+    }
+  }
+  block_partials<3, 1>(acc, part + rb * ld, static_cast<int64_t>(nrb) * ld, c, on);
+}
+
 // Scatter the scaled operator into the per-offset layout; flags[0] counts
 // entries whose offset is not one of the seven (then the layout is unusable).
 __global__ void k_build_dia(int n, int W, int R, const int* __restrict__ col,
@@ -931,6 +993,14 @@ void launch_fill_u8(hipStream_t s, uint8_t* p, int n, uint8_t v) {
 void launch_pcg_init(hipStream_t s, const DevLevel& L, PcgWork& w, int ncols, CView u_in) {
   int ncc;
   const int nb = grid_tiles(w, ncols, 1, ncc);
+  if (w.dia && L.dia_R > 0) {
+    auto kd = (L.W == 8) ? k_cg_init_dia<8> : k_cg_init_dia<16>;
+    hipLaunchKernelGGL(kd, dim3(nb), dim3(kBlock), 0, s, L.n, L.dia_R, L.dv64, L.col, L.m64, L.has_mass,
+                       L.s64, L.F, ncols, ncc, w.rows_per_block, u_in.p, u_in.ld, w.src, w.ld, w.x, w.r,
+                       w.part, w.nrb, w.flags);
+    MG_HIP(hipGetLastError());
+    return;
+  }
   auto k = (L.W == 8) ? k_cg_init<8> : k_cg_init<16>;
   hipLaunchKernelGGL(k, dim3(nb), dim3(kBlock), 0, s, L.n, L.col, L.a64, L.m64, L.has_mass, L.s64,
                      L.F, ncols, ncc, w.rows_per_block, u_in.p, u_in.ld, w.src, w.ld, w.x, w.r,

@@ -35,10 +35,11 @@ def cfg1_oracle():
     return cfg, U_seq, U_mg, hist
 
 
-@pytest.mark.parametrize("seq_kernel", [1, 2])
+@pytest.mark.parametrize("seq_kernel", [1, 2, 3])
 def test_seq_solve_matches_oracle(cfg1_oracle, seq_kernel):
-    """GPU sequential stepping (one work-group, or the cooperative grid) vs the
-    oracle's direct-solve stepping."""
+    """GPU sequential stepping (one work-group, the cooperative grid, or the
+    level's stored inverse streamed once per step) vs the oracle's
+    direct-solve stepping."""
     print(f"seq cfg1 kernel {seq_kernel}", flush=True)
     cfg, U_seq, _, _ = cfg1_oracle
     s = _solver(cfg, pcg_tol=1e-13, seq_kernel=seq_kernel)

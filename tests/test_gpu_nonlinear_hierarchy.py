@@ -82,7 +82,15 @@ def test_nonlinear_three_level_sc_learned_coarsest(nl3):
     """The learned coarsest propagator (implicit Euler plus the trained
     network correction) in the same hierarchy: trained on the GPU from the
     intermediate level's trajectories, MGRIT reaches the sequential solution
-    (the FAS fixed point does not depend on the coarse propagator)."""
+    (the FAS fixed point does not depend on the coarse propagator).
+
+    What the network gains over the method without it: on held-out
+    trajectories its coarse step is several times closer to m steps of the
+    intermediate level than implicit Euler (4.7x here), while MGRIT takes the
+    same number of iterations as with implicit Euler (28 here): the
+    convergence of this spatially coarsened hierarchy is bounded by the
+    spatial coarsening, not by the coarse step's accuracy, and the network's
+    evaluation adds time.  Both facts are asserted."""
     print("nonlinear 3-level SC learned coarsest", flush=True)
     cfg, U_seq, _ = nl3
     s = _solver(cfg, coarse_model=1)
@@ -95,3 +103,6 @@ def test_nonlinear_three_level_sc_learned_coarsest(nl3):
           "fallback", st["coarse_fallback"], flush=True)
     assert st["converged"]
     assert _rel(U, U_seq) <= MGRIT_GATE
+    assert st["coarse_fallback"] == -1
+    assert ts["val_err_learned"] < 0.5 * ts["val_err_ie"]
+    assert abs(len(st["rho"]) - len(st_ie["rho"])) <= 1
