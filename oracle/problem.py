@@ -3,7 +3,9 @@
 Level l uses the mesh of the configuration's l-th entry and the step
 dt_l = m**l * dt (coarse propagators are re-discretisations with the coarse
 step, Sec. 2.1).  Spatial transfers between differing meshes are P_s and
-R_s = D^{-1} P_s^T from `transfer.py`; equal meshes use none.
+R_s = D^{-1} P_s^T from `transfer.py`; equal meshes use none.  With a
+field-circuit configuration every level is the coupled model of
+`circuit.py`; MGRIT's state stays the vector potential.
 """
 
 from workload import hierarchy as mesh_hierarchy
@@ -11,6 +13,7 @@ from workload import hierarchy as mesh_hierarchy
 from .fe import MachineFE
 from .mgrit import Hierarchy
 from .stepping import Level
+from .circuit import CircuitLevel
 from . import transfer
 
 
@@ -22,6 +25,11 @@ def build(cfg, restriction="normalized"):
         key = (mesh.n_r, mesh.n_theta)
         if key not in fes:
             fes[key] = MachineFE(mesh)
+        if cfg.circuit is not None:
+            if cfg.bh.nonlinear:
+                raise NotImplementedError("the field-circuit model is linear here")
+            levels.append(CircuitLevel(mesh, cfg.level_dt(l), cfg.source, cfg.circuit, fe=fes[key]))
+            continue
         levels.append(Level(mesh, cfg.level_dt(l), cfg.source, cfg.bh, fe=fes[key],
                             newton_tol=cfg.newton_tol, newton_maxit=cfg.newton_maxit,
                             newton_halvings=cfg.newton_halvings))

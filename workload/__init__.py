@@ -9,6 +9,6 @@ on its own.
 
 from .machine import (  # noqa: F401
     R_IN, R_OUT, MU0, MATERIALS, MAT_ROTOR_IRON, MAT_BAR, MAT_AIR, MAT_SLOT,
-    MAT_STATOR_IRON, PolarMesh, polar_mesh, Source, BHLaw,
+    MAT_STATOR_IRON, N_BARS, PolarMesh, polar_mesh, Source, BHLaw, Circuit,
 )
 from .configs import Config, LevelSpec, config, CONFIG_NAMES, hierarchy  # noqa: F401

@@ -12,9 +12,11 @@ m_coarse > 0 the factor m between levels 0 and 1 and m_coarse below.
 """
 
 from dataclasses import dataclass, field, replace
+from typing import Optional
+
 import numpy as np
 
-from .machine import Source, BHLaw
+from .machine import Source, BHLaw, Circuit
 
 
 @dataclass
@@ -43,6 +45,7 @@ class Config:
     newton_halvings: int = 6    # damping: step lengths 1, 1/2, ..., 2**-newton_halvings
     coarse: str = "implicit_euler"  # or "learned"
     m_coarse: int = 0           # coarsening factor between levels l >= 1 and l+1 (0 = m)
+    circuit: Optional[Circuit] = None   # field-circuit coupling (linear model); None = current-driven coils
 
     @property
     def n_levels(self) -> int:

@@ -62,6 +62,7 @@ class PolarMesh:
     cell_phase: np.ndarray  # [T] int32, -1 = no source, else 0/1/2
     cell_sign: np.ndarray   # [T] int32, winding direction (0 where no source)
     dirichlet: np.ndarray   # [N] uint8, 1 = A fixed to 0
+    cell_bar: np.ndarray = None  # [T] int32, rotor bar index 0..N_BARS-1, -1 elsewhere
 
     @property
     def n_nodes(self) -> int:
@@ -115,7 +116,10 @@ def _cell_material(n_r: int, n_theta: int):
     coil = mat == MAT_SLOT
     phase[coil] = belt_phase[grp[coil]]
     sign[coil] = belt_sign[grp[coil]]
-    return mat, phase, sign
+    bar = np.full((n_r, n_theta), -1, dtype=np.int32)
+    is_bar = mat == MAT_BAR
+    bar[is_bar] = (np.floor(thc / bar_pitch).astype(np.int64) % N_BARS)[is_bar]
+    return mat, phase, sign, bar
 
 
 def polar_mesh(n_r: int, n_theta: int) -> PolarMesh:
@@ -140,16 +144,17 @@ def polar_mesh(n_r: int, n_theta: int) -> PolarMesh:
     t2 = np.stack([a, c, d], axis=-1)
     tri = np.stack([t1, t2], axis=2).reshape(-1, 3).astype(np.int32)
 
-    mat, phase, sign = _cell_material(n_r, n_theta)
+    mat, phase, sign, bar = _cell_material(n_r, n_theta)
     cell_mat = np.repeat(mat.ravel(), 2).astype(np.int32)
     cell_phase = np.repeat(phase.ravel(), 2).astype(np.int32)
     cell_sign = np.repeat(sign.ravel(), 2).astype(np.int32)
+    cell_bar = np.repeat(bar.ravel(), 2).astype(np.int32)
 
     dirichlet = np.zeros((n_r + 1) * n_theta, dtype=np.uint8)
     dirichlet[:n_theta] = 1
     dirichlet[n_r * n_theta:] = 1
     return PolarMesh(n_r, n_theta, xy, tri, cell_mat, cell_phase, cell_sign,
-                     dirichlet)
+                     dirichlet, cell_bar)
 
 
 @dataclass
@@ -182,6 +187,32 @@ class Source:
     @property
     def carrier_code(self) -> int:
         return {"triangle": 0, "sawtooth": 1}[self.carrier]
+
+
+@dataclass
+class Circuit:
+    """Field-circuit coupling (Sec. 3.1): the stator coils are stranded
+    conductors fed by three phase voltages, the rotor bars solid conductors
+    joined at both ends by resistive end rings.
+
+    Stator: the winding function of phase s is turns_density * sign on the
+    cells of phase s (turns per m^2 of slot); its current i_s is unknown and
+    obeys l_z d/dt(flux integral) + r_phase i_s = v_s(t), with
+    v_s(t) = v0 * amplitude * b_s(t) (times the start-up ramp when set): the
+    source's PWM signals drive voltages, and Source.J0 is unused.
+    Rotor (`rotor` True): bar k carries the voltage v_k and current
+    i_k = G_k v_k - d/dt(integral of sigma A over bar k), G_k = sigma area_k / l_z;
+    two end rings with resistance ring_r between neighbouring bars give
+    i = -(1 / (2 ring_r)) L v, L the periodic path Laplacian over the bars.
+    `rotor` False keeps the bars as plain conductors (v = 0).
+    """
+    turns_density: float = 60.0 / 8.84e-5   # 60 turns in a slot of 8.84e-5 m^2
+    l_z: float = 0.1            # axial length, m
+    r_phase: float = 1.5        # stator phase resistance, ohm
+    v0: float = 325.0           # phase-voltage amplitude, V
+    ring_r: float = 5.0e-6      # end-ring resistance between neighbouring bars, ohm
+    rotor: bool = True
+    n_bars: int = N_BARS
 
 
 @dataclass
