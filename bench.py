@@ -53,27 +53,29 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the timed solve's pass-B launches, from the two rocprofv3
-# --pmc runs summarised in profiles/cg_pass_b_64x512_hbm_traffic.md (each
-# counter scaled by a 1 GiB copy).  Valid only for the CG kernel sources
-# (pcg.hip, internal.h) they were taken with: reported as null once those change.
+# HBM traffic of the timed solve's pass-B and pass-A launches, from the two
+# rocprofv3 --pmc runs summarised in the profile named below (each counter
+# scaled by a 1 GiB copy).  Valid only for the CG kernel source (pcg.hip)
+# they were taken with: reported as null once it changes.
 TRAFFIC_MEASURED = {
-    "sources_sha256": "2f376c647d9a9d0389c0d9b6a10d82335c4fbb7c6109a77a29dcd2a1510baea8",
-    "bytes_per_launch": 761692161,
-    "kernel": "k_cg_pass_b_dia<double, 1, 1> (the autotuner's level-0 choice in the profiled run)",
-    "profile": "profiles/cg_pass_b_64x512_hbm_traffic.md",
+    "sources_sha256": "f69e1baa4c52f632445b443ffea9d9d2bae6a213a22fb226e73cf9903d519227",
+    "shape": [128, 1, 2, 1, 0],   # level-0 kernel shape as mgrit_level_info reports it
+    "pass_b": {"bytes_per_launch": 753919749, "kernel": "k_cg_pass_b_dia<double, 1, 1>"},
+    "pass_a": {"bytes_per_launch": 493644127, "kernel": "k_cg_pass_a_dia<double, 1, 1>"},
+    "profile": "profiles/cg_passes_64x512_hbm_traffic.md",
 }
 
 
 def measured_traffic():
+    """The counters' bytes per launch of passes B and A, or None once the CG
+    kernel source (pcg.hip) differs from the one the counters were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("pcg.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_1912_03106_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1912_03106_amd", "csrc", "pcg.hip"), "rb") as fh:
+        h.update(fh.read())
     if h.hexdigest() != TRAFFIC_MEASURED["sources_sha256"]:
         return None
-    return TRAFFIC_MEASURED["bytes_per_launch"]
+    return TRAFFIC_MEASURED
 
 
 def log(msg):
@@ -89,28 +91,46 @@ def pass_b_bytes(n, W, family, unit, cols, launches):
     return 5 * unit * n * cols + launches * (matrix + n * (unit + 8))
 
 
+def pass_a_bytes(n, W, family, unit, cols, launches):
+    """Algorithmic bytes of CG pass A: per unconverged column of one row, read
+    r^ and the old direction and write the new one (3 values; a solve's first
+    launch reads no old direction, counted as 3 all the same: about 2 % of the
+    launches); per launch, the operator's diagonal and upper offsets (family
+    2: 4 values per row; family 1: W values + W column indices)."""
+    matrix = n * 4 * unit if family == 2 else n * W * (unit + 4)
+    return 3 * unit * n * cols + launches * matrix
+
+
 def pass_b_roofline(st, solver, unit):
     """Pass B over the whole timed region: algorithmic bytes / device time
-    (HIP events around every launch, every level)."""
-    bytes_total, launches, t = 0.0, 0, 0.0
-    names = set()
-    for l in range(solver.cfg.n_levels):
-        n, _, nnz = solver.level_info(l)
-        rpb, cpl, fam, depth = solver.kernel_shape(l)
-        lau = st["kernel_launches"][1][l]
-        bytes_total += pass_b_bytes(n, nnz // n, fam, unit, st["kernel_columns"][l], lau)
-        launches += lau
-        t += st["kernel_time_s"][1][l]
-        T = "double" if unit == 8 else "float"
-        names.add(f"k_cg_pass_b_dia<{T}, {cpl}, {depth}>" if fam == 2 else f"k_cg_pass_b<{T}, {nnz // n}, {cpl}>")
-    if launches == 0 or t <= 0:
-        return None
-    achieved = bytes_total / t / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": " + ".join(sorted(names)), "launches": launches,
-            "avg_launch_us": round(1e6 * t / launches, 2),
-            "bytes_per_launch": round(bytes_total / launches)}
+    (HIP events around every launch, every level); pass A alongside."""
+    T = "double" if unit == 8 else "float"
+    rec = {}
+    for key, pas, fbytes, tag in (("b", 1, pass_b_bytes, "b"), ("a", 0, pass_a_bytes, "a")):
+        bytes_total, launches, t, cols = 0.0, 0, 0.0, 0
+        names = set()
+        for l in range(solver.cfg.n_levels):
+            n, _, nnz = solver.level_info(l)
+            rpb, cpl, fam, depth, _ = solver.kernel_shape(l)
+            lau = st["kernel_launches"][pas][l]
+            bytes_total += fbytes(n, nnz // n, fam, unit, st["kernel_columns"][l], lau)
+            launches += lau
+            cols += st["kernel_columns"][l]
+            t += st["kernel_time_s"][pas][l]
+            names.add(f"k_cg_pass_{tag}_dia<{T}, {cpl}, {depth}>" if fam == 2
+                      else f"k_cg_pass_{tag}<{T}, {nnz // n}, {cpl}>")
+        if launches == 0 or t <= 0:
+            return None
+        achieved = bytes_total / t / 1e9
+        rec[key] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": " + ".join(sorted(names)), "launches": launches,
+                    "avg_launch_us": round(1e6 * t / launches, 2),
+                    "bytes_per_launch": round(bytes_total / launches),
+                    "columns_per_launch": round(cols / launches, 1)}
+    out = rec["b"]
+    out["pass_a"] = rec["a"]
+    return out
 
 
 def cpu_baseline(cfg, budget_s=10.0, keep_every=64):
@@ -171,31 +191,38 @@ def timed_solve(cfg, stream, label, **kw):
 
 def summarize_pmc(fetch_csv, write_csv, bench_json):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the timed solve's CG
-    pass-B launches (the last `launches` pass-B dispatches of the run; the
-    earlier ones belong to the set-up), each scaled by true / counted bytes of
-    the 1 GiB calibration copy."""
+    pass-B and pass-A launches (the last `launches` dispatches of each pass in
+    the run; the earlier ones belong to the set-up), each scaled by true /
+    counted bytes of the 1 GiB calibration copy, and the ratio of the traffic
+    to the algorithmic bytes of the same launches."""
     import csv
     with open(bench_json) as f:
-        launches = json.loads(f.readline())["roofline"]["launches"]
-    out = {"timed_launches": launches}
-    for key, path, ctr in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
-        pb, cp = [], []
-        with open(path) as f:
-            for r in csv.DictReader(f):
-                if r["Counter_Name"] != ctr:
-                    continue
-                if "k_cg_pass_b" in r["Kernel_Name"]:
-                    pb.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
-                elif r["Kernel_Name"] == "__amd_rocclr_copyBuffer" and int(r["Grid_Size"]) >= 131072:
-                    cp.append(float(r["Counter_Value"]))
-        if len(pb) < launches or not cp:
-            raise SystemExit(f"{path}: too few pass-B or no calibration-copy dispatches")
-        pb = [v for _, v in sorted(pb)[-launches:]]
-        scale = (2 ** 30 / 1024) / cp[-1]
-        out[key] = {"dispatches": len(pb), "raw_kib_per_launch": sum(pb) / len(pb),
-                    "calibration_copy_kib": cp[-1], "scale": scale,
-                    "bytes_per_launch": 1024 * scale * sum(pb) / len(pb)}
-    out["traffic_bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+        roof = json.loads(f.readline())["roofline"]
+    passes = {"k_cg_pass_b": roof, "k_cg_pass_a": roof["pass_a"]}
+    out = {}
+    for tag, rec in passes.items():
+        launches = rec["launches"]
+        res = {"timed_launches": launches, "algorithmic_bytes_per_launch": rec["bytes_per_launch"]}
+        for key, path, ctr in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+            pb, cp = [], []
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    if r["Counter_Name"] != ctr:
+                        continue
+                    if tag in r["Kernel_Name"]:
+                        pb.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+                    elif r["Kernel_Name"] == "__amd_rocclr_copyBuffer" and int(r["Grid_Size"]) >= 131072:
+                        cp.append(float(r["Counter_Value"]))
+            if len(pb) < launches or not cp:
+                raise SystemExit(f"{path}: too few {tag} or no calibration-copy dispatches")
+            pb = [v for _, v in sorted(pb)[-launches:]]
+            scale = (2 ** 30 / 1024) / cp[-1]
+            res[key] = {"dispatches": len(pb), "raw_kib_per_launch": sum(pb) / len(pb),
+                        "calibration_copy_kib": cp[-1], "scale": scale,
+                        "bytes_per_launch": 1024 * scale * sum(pb) / len(pb)}
+        res["traffic_bytes_per_launch"] = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+        res["traffic_over_algorithmic"] = res["traffic_bytes_per_launch"] / rec["bytes_per_launch"]
+        out[tag] = res
     return out
 
 
@@ -210,7 +237,7 @@ def profile_short(cfg, stream):
     out = torch.empty((cfg.n_steps + 1, solver.n0), dtype=torch.float64, device="cuda")
     _, st = solver.solve(out=out, raise_on_stall=False)
     torch.cuda.synchronize()
-    rpb, cpl, fam, depth = solver.kernel_shape(0)
+    rpb, cpl, fam, depth, _ = solver.kernel_shape(0)
     n, _, nnz = solver.level_info(0)
     lau = st["kernel_launches"][1][0]
     byts = pass_b_bytes(n, nnz // n, fam, 8, st["kernel_columns"][0], lau)
@@ -404,6 +431,24 @@ RESIDUAL_ETA = 1e-4      # C-point residual solves: relative accuracy of the res
 HEADLINE = dict(pcg_tol_eta=HEADLINE_ETA, warm_start=2, residual_eta=RESIDUAL_ETA)
 
 
+def pinned(shape):
+    """Solver settings that fix the level-0 batched-CG kernel shape (as
+    mgrit_level_info reports it) instead of autotuning it."""
+    rpb, cpl, fam, depth, narrow = shape
+    return dict(pcg_kernel=fam, pcg_rows_per_block=rpb, pcg_cols_per_lane=cpl, pcg_prefetch=depth,
+                pcg_rows_narrow=narrow if narrow > 0 else -1)
+
+
+def profiled_settings(args):
+    """The profiled (roofline) solve: the headline settings, with the kernel
+    shape the HBM counters were taken with, so that the measured traffic
+    belongs to the kernel whose time is measured."""
+    kw = dict(HEADLINE)
+    if TRAFFIC_MEASURED["shape"] and not args.pin_shape:
+        kw.update(pinned(TRAFFIC_MEASURED["shape"]))
+    return kw
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,6 +479,10 @@ def main():
                          "counter_collection.csv files (FETCH_SIZE, WRITE_SIZE), calibrated by the copy; "
                          "the last `launches` pass-B dispatches (from the bench line of the same run) "
                          "are the timed solve's")
+    ap.add_argument("--pin-shape", metavar="RPB,CPL,DEPTH,NARROW",
+                    help="pin the level-0 batched-CG kernel shape (rows per work-group, columns per "
+                         "lane, prefetch depth, narrow-set rows per work-group, 0 = none) instead of "
+                         "autotuning it: hardware-counter runs distort the autotuner's timings")
     ap.add_argument("--profile-short", action="store_true",
                     help="for hardware-counter runs: one level-0 relaxation and C-point residual "
                          "of the 64x512 workload, then a 1 GiB device copy of known size")
@@ -441,6 +490,9 @@ def main():
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(*args.summarize_pmc)))
         return
+    if args.pin_shape:
+        rpb, cpl, depth, narrow = (int(v) for v in args.pin_shape.split(","))
+        HEADLINE.update(pinned((rpb, cpl, 2, depth, narrow)))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-parallel "
               "decomposition over several GPUs is not part of this build.", file=sys.stderr)
@@ -492,7 +544,8 @@ def main():
     rho = st["rho"]
     n_t = cfg.level_steps(1)                     # intervals = C-point residual columns per iteration
     frelax_cols = st["phi_columns"][0] - len(rho) * n_t
-    shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family", "prefetch_rows"), solver.kernel_shape(l)))
+    shapes = [dict(zip(("rows_per_block", "cols_per_lane", "family", "prefetch_rows", "rows_per_block_narrow"),
+                       solver.kernel_shape(l)))
               for l in range(cfg.n_levels)]
     solver.close()
 
@@ -501,7 +554,8 @@ def main():
     roof, pst, t_prof = None, None, None
     if budget.fits("profiled solve", 1.3 * per + 5.0):
         log("profiled solve (HIP events around every CG pass)")
-        psolver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1, **HEADLINE)
+        psolver = Solver(cfg, stream=stream.cuda_stream, device_io=True, profile_kernels=1,
+                         **profiled_settings(args))
         pout = torch.empty_like(out)
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
@@ -510,11 +564,19 @@ def main():
         t_prof = time.perf_counter() - tp0
         roof = pass_b_roofline(pst, psolver, 8)
         if roof is not None:
-            roof["traffic"] = measured_traffic()
-            if roof["traffic"] is not None:
-                roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["bytes_per_launch"], 3)
-                roof["traffic_profile"] = TRAFFIC_MEASURED["profile"]
-                roof["traffic_kernel"] = TRAFFIC_MEASURED["kernel"]
+            tm = measured_traffic()
+            shape0 = list(psolver.kernel_shape(0))
+            roof["shape"] = shape0
+            if tm is not None and shape0 != tm["shape"]:
+                roof["traffic_note"] = (f"counters were taken with level-0 kernel shape {tm['shape']}; "
+                                        f"this run's autotuner chose {shape0}")
+                tm = None
+            if tm is not None:
+                for rec, key in ((roof, "pass_b"), (roof["pass_a"], "pass_a")):
+                    rec["traffic"] = tm[key]["bytes_per_launch"]
+                    rec["traffic_over_algorithmic"] = round(rec["traffic"] / rec["bytes_per_launch"], 3)
+                    rec["traffic_kernel"] = tm[key]["kernel"]
+                roof["traffic_profile"] = tm["profile"]
         psolver.close()
         del pout
     if args.copy_calibration:

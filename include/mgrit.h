@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define MGRIT_ABI_VERSION 1
+#define MGRIT_ABI_VERSION 2
 #define MGRIT_MAX_LEVELS 8
 #define MGRIT_MAX_HISTORY 128
 
@@ -64,6 +64,8 @@ typedef struct {
   const int32_t* cell_phase;  /* [n_tri] -1 = no source, else phase 0, 1 or 2   */
   const int32_t* cell_sign;   /* [n_tri] winding direction (+1 / -1 / 0)        */
   const uint8_t* dirichlet;   /* [n_nodes] 1 = A fixed to 0                     */
+  const int32_t* cell_bar;    /* [n_tri] rotor bar 0 .. n_bars-1, -1 elsewhere; read only
+                               * with circuit = 1 and n_bars > 0 (may be NULL otherwise) */
 } mgrit_mesh;
 
 /* Materials, source and time grid (Sec. 3.1-3.3).
@@ -91,6 +93,28 @@ typedef struct {
                                * drive the coils (the smooth source of Sec. 4.1) */
   double t_start;             /* time origin: point i samples the source at t_start + i dt
                                * (a window of a longer horizon; 0 = the horizon's start) */
+  /* Field-circuit coupling (Sec. 3.1, the stator coil and rotor bar circuit
+   * equations), linear model only.  circuit = 1: the coils are stranded
+   * conductors with winding function turns_density * cell_sign on the cells
+   * of each phase, fed by the phase voltages v_s(t) = v0 * amplitude * b_s(t)
+   * (times the start-up ramp) through the phase resistance r_phase:
+   *   l_z d/dt (X_s^T a) + r_phase i_s = v_s(t),  X_s = turns_density F_s;
+   * J0 is unused.  With n_bars > 0 the cells of bar k (cell_bar) are a solid
+   * conductor with voltage distribution 1 / l_z carrying the voltage v_k and
+   * the current i_k = G_k v_k - d/dt(integral of sigma A over bar k),
+   * G_k = sigma area_k / l_z; two end rings with resistance ring_r between
+   * neighbouring bars close the cage: i = -(1 / (2 ring_r)) L v, L the
+   * periodic path Laplacian over the bars.  No circuit inductance: the
+   * currents and voltages are algebraic, fixed by two consecutive states, so
+   * MGRIT's state stays the vector potential.  With n_bars = 0 the bar cells
+   * are plain conductors (bar voltages 0), as with circuit = 0. */
+  int32_t circuit;            /* 0: current-driven coils (sign * J0 * amplitude * b_p); 1: coupled */
+  double turns_density;       /* turns per m^2 of slot (> 0 with circuit = 1) */
+  double l_z;                 /* axial length, m (> 0) */
+  double r_phase;             /* stator phase resistance, ohm (> 0) */
+  double v0;                  /* phase-voltage amplitude, V */
+  int32_t n_bars;             /* rotor bars with circuit equations, 0 .. 32 */
+  double ring_r;              /* end-ring resistance between neighbouring bars, ohm (> 0 with bars) */
 } mgrit_physics;
 
 typedef struct {
@@ -198,6 +222,13 @@ typedef struct {
                                * batches of at most 128 columns (coarse levels: no compaction, and
                                * each read is a device-to-host round trip); 0 = pcg_check_every;
                                * default 16; both at most 64 */
+  int32_t pcg_rows_per_block; /* rows per work-group of the batched PCG passes: 0 = the
+                               * autotuner's choice, else 16, 32, 64, 128 or 256 */
+  int32_t pcg_cols_per_lane;  /* columns per lane of the batched PCG passes: 0 = the autotuner's
+                               * choice, else 1 or 2.  With pcg_kernel, pcg_prefetch and
+                               * pcg_rows_narrow these pin the whole kernel shape (hardware-counter
+                               * runs, where timings would steer the autotuner); results do not
+                               * depend on the shape. */
 } mgrit_params;
 
 typedef struct {
@@ -258,6 +289,18 @@ int mgrit_solve(void* h, const double* u0, const double* u_init, double* u_out,
  * INVALID_ARGUMENT before a completed solve. */
 int mgrit_joule_losses(void* h, double* p);
 
+/* Circuit quantities of a level-0 trajectory (circuit = 1; Sec. 3.1, the
+ * stator coil and rotor bar circuit equations).  u: [(N_t+1)][n_0] time-major
+ * (a device pointer when device_pointers = 1), e.g. the output of
+ * mgrit_solve or mgrit_seq_solve.  out (host): [N_t][3 + 2 n_bars]; row i-1
+ * holds for the step t_{i-1} -> t_i the stator phase currents i_1..3 (A),
+ * the bar voltages v_1..nb (V) and the bar currents (A), each from the
+ * circuit equations of that step alone:
+ *   i_s = (v_s(t_i) - l_z X_s^T (u_i - u_{i-1}) / dt) / r_phase,
+ *   C v = Y'^T (u_i - u_{i-1}) / dt,   i_bar = -L v / (2 ring_r).
+ * UNSUPPORTED without a circuit. */
+int mgrit_circuit_values(void* h, const double* u, double* out);
+
 /* Sequential forward block solve (Sec. 2) on the finest level, on the GPU:
  * u_out [(N_t+1)][n_0] = (u0, Phi_1(u0), ...).  u0 may be NULL (= 0). */
 int mgrit_seq_solve(void* h, const double* u0, double* u_out, mgrit_stats* st);
@@ -289,11 +332,12 @@ int phi_step_noalloc(void* h, int32_t level, int32_t B, const int64_t* i_from,
                      const double* u_prev, double* u_next);
 
 /* Sizes of a level: unknowns, steps, stored entries of the operator (fixed
- * row width times n), and kernel_shape[4] of its batched PCG kernels as the
+ * row width times n), and kernel_shape[5] of its batched PCG kernels as the
  * autotuner chose them: rows per work-group, columns per lane, kernel family
- * (1 general sparse rows, 2 diagonal window) and rows of loads in flight per
- * wave (1, 2 or 4; diagonal window only, else 1).  Any output pointer may be
- * NULL. */
+ * (1 general sparse rows, 2 diagonal window), rows of loads in flight per
+ * wave (1, 2 or 4; diagonal window only, else 1) and rows per work-group once
+ * at most 128 columns still iterate (0 = unchanged).  Any output pointer may
+ * be NULL. */
 int mgrit_level_info(void* h, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
                      int32_t* kernel_shape);
 

@@ -26,7 +26,7 @@ EXPORTS = ("mgrit_default_params", "mgrit_setup", "mgrit_solve", "mgrit_seq_solv
            "mgrit_level_info", "mgrit_destroy", "mgrit_strerror", "mgrit_last_error",
            "mgrit_train_coarse", "mgrit_coarse_n_params", "mgrit_set_coarse_weights",
            "mgrit_get_coarse_weights", "mgrit_coarse_apply", "mgrit_coarse_gradient",
-           "mgrit_coarse_adam", "phi_step_noalloc", "mgrit_joule_losses")
+           "mgrit_coarse_adam", "phi_step_noalloc", "mgrit_joule_losses", "mgrit_circuit_values")
 
 
 class Mesh(C.Structure):
@@ -35,6 +35,7 @@ class Mesh(C.Structure):
         ("xy", C.POINTER(C.c_double)), ("tri", C.POINTER(C.c_int32)),
         ("cell_mat", C.POINTER(C.c_int32)), ("cell_phase", C.POINTER(C.c_int32)),
         ("cell_sign", C.POINTER(C.c_int32)), ("dirichlet", C.POINTER(C.c_uint8)),
+        ("cell_bar", C.POINTER(C.c_int32)),
     ]
 
 
@@ -47,6 +48,8 @@ class Physics(C.Structure):
         ("f_carrier", C.c_double), ("phase_offset", C.c_double), ("phases", C.c_double * 3),
         ("carrier", C.c_int32), ("dt", C.c_double), ("n_steps", C.c_int64),
         ("ramp_periods", C.c_double), ("signal", C.c_int32), ("t_start", C.c_double),
+        ("circuit", C.c_int32), ("turns_density", C.c_double), ("l_z", C.c_double),
+        ("r_phase", C.c_double), ("v0", C.c_double), ("n_bars", C.c_int32), ("ring_r", C.c_double),
     ]
 
 
@@ -68,6 +71,7 @@ class Params(C.Structure):
         ("pcg_prefetch", C.c_int32), ("residual_eta", C.c_double), ("pcg_rows_narrow", C.c_int32),
         ("cycle", C.c_int32), ("nested", C.c_int32), ("loss_tol", C.c_double),
         ("m_coarse", C.c_int32), ("coarse_persistent", C.c_int32), ("pcg_check_narrow", C.c_int32),
+        ("pcg_rows_per_block", C.c_int32), ("pcg_cols_per_lane", C.c_int32),
     ]
 
 
@@ -133,8 +137,10 @@ def lib():
     L.phi_step_noalloc.restype = C.c_int
     L.mgrit_joule_losses.argtypes = [vp, vp]
     L.mgrit_joule_losses.restype = C.c_int
+    L.mgrit_circuit_values.argtypes = [vp, vp, vp]
+    L.mgrit_circuit_values.restype = C.c_int
     L.mgrit_level_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
-                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32 * 4)]
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32 * 5)]
     L.mgrit_level_info.restype = C.c_int
     L.mgrit_destroy.argtypes = [vp]
     L.mgrit_destroy.restype = None

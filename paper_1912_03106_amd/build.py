@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libmgrit.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "pcg.hip", "newton.hip", "gnn.hip", "gemm.hip", "setup.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "pcg.hip", "newton.hip", "gnn.hip", "gemm.hip", "circuit.hip", "setup.hip", "engine.hip"]
 HEADERS = ["internal.h", "setup.h", "source_dev.h"]
 
 CFLAGS = [

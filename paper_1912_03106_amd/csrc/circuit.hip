@@ -1,0 +1,192 @@
+// Kernels of the field-circuit coupled step (Sec. 3.1): the dense
+// right-hand-side CG start of the set-up solves Z = A^-1 B^T, and the
+// per-column elimination of the circuit unknowns after a step's linear solve.
+// Every sum runs in a fixed order, so a column's result does not depend on
+// the batch it is computed in.
+#include <hip/hip_runtime.h>
+
+#include "circuit.h"
+
+namespace mg {
+namespace {
+
+__device__ __forceinline__ int wave_index() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+}
+
+inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// x = 0, r^ = S b; partials r^.r^, r.r (= b.b) and b.b per row block, summed
+// over the block's four waves in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_circ_rhs_init(int n, const double* __restrict__ sc,
+                                                          const double* __restrict__ B, int64_t ldb,
+                                                          int ncols, int rpb, int64_t ld,
+                                                          double* __restrict__ x, double* __restrict__ r,
+                                                          double* __restrict__ part, int nrb,
+                                                          int* __restrict__ flags) {
+  __shared__ double red[3][4][kWave];
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = blockIdx.x * kWave + lane;
+  const int rb = blockIdx.y;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    flags[0] = 0;
+    flags[4] = 0;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int rpw = rpb >> 2;
+  const int i0 = rb * rpb + wv * rpw;
+  if (c < ncols) {
+    for (int k = 0; k < rpw; ++k) {
+      const int i = i0 + k;
+      if (i >= n) break;
+      const double b = B[static_cast<int64_t>(i) * ldb + c];
+      const double rh = sc[i] * b;
+      x[static_cast<int64_t>(i) * ld + c] = 0.0;
+      r[static_cast<int64_t>(i) * ld + c] = rh;
+      acc[0] += rh * rh;
+      acc[1] += b * b;
+      acc[2] += b * b;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) red[q][wv][lane] = acc[q];
+  __syncthreads();
+  if (wv == 0 && c < ncols) {
+    const int64_t qs = static_cast<int64_t>(nrb) * ld;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      part[q * qs + static_cast<int64_t>(rb) * ld + c] =
+          ((red[q][0][lane] + red[q][1][lane]) + red[q][2][lane]) + red[q][3][lane];
+  }
+}
+
+// One wave per partial p (kCircRowsPerWave consecutive rows), one lane per
+// column: part[p][j][c] = sum_i Bt[i][j] (y[i][c] - a[i][c]), rows in order.
+__global__ __launch_bounds__(kBlock) void k_circ_dots(int n, int k, int ncols,
+                                                      const double* __restrict__ Bt,
+                                                      const double* __restrict__ y, int64_t ldy,
+                                                      const double* __restrict__ a, int64_t lda,
+                                                      double* __restrict__ part, int64_t ldp,
+                                                      int nparts) {
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = blockIdx.x * kWave + lane;
+  const int p = blockIdx.y * 4 + wv;
+  if (p >= nparts || c >= ncols) return;
+  double acc[kCircMax];
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j) acc[j] = 0.0;
+  const int i0 = p * kCircRowsPerWave;
+  const int i1 = (i0 + kCircRowsPerWave < n) ? i0 + kCircRowsPerWave : n;
+  for (int i = i0; i < i1; ++i) {
+    const double d = y[static_cast<int64_t>(i) * ldy + c] - a[static_cast<int64_t>(i) * lda + c];
+    const double* b = Bt + static_cast<int64_t>(i) * k;
+#pragma unroll
+    for (int j = 0; j < kCircMax; ++j)
+      if (j < k) acc[j] = fma(b[j], d, acc[j]);
+  }
+  double* o = part + static_cast<int64_t>(p) * k * ldp + c;
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j)
+    if (j < k) o[static_cast<int64_t>(j) * ldp] = acc[j];
+}
+
+__global__ void k_circ_sum(int k, int ncols, int nparts, const double* __restrict__ part, int64_t ldp,
+                           double* __restrict__ d, int64_t ldd) {
+  const int c = blockIdx.x * kWave + static_cast<int>(threadIdx.x);
+  const int j = blockIdx.y;
+  if (c >= ncols || j >= k) return;
+  double t = 0.0;
+  for (int p = 0; p < nparts; ++p) t += part[(static_cast<int64_t>(p) * k + j) * ldp + c];
+  d[static_cast<int64_t>(j) * ldd + c] = t;
+}
+
+__global__ void k_circ_solve(int k, int ncols, const double* __restrict__ d, int64_t ldd,
+                             const double* __restrict__ src, int64_t lds,
+                             const double* __restrict__ cS, double* __restrict__ w, int64_t ldw) {
+  const int c = blockIdx.x * kWave + static_cast<int>(threadIdx.x);
+  if (c >= ncols) return;
+  double dv[kCircMax];
+#pragma unroll
+  for (int l = 0; l < kCircMax; ++l) dv[l] = (l < k) ? d[static_cast<int64_t>(l) * ldd + c] : 0.0;
+  const double v0 = src[c], v1 = src[lds + c], v2 = src[2 * lds + c];
+  for (int j = 0; j < k; ++j) {
+    const double* row = cS + static_cast<int64_t>(j) * (3 + k);
+    double t = (row[0] * v0 + row[1] * v1) + row[2] * v2;
+#pragma unroll
+    for (int l = 0; l < kCircMax; ++l)
+      if (l < k) t = fma(-row[3 + l], dv[l], t);
+    w[static_cast<int64_t>(j) * ldw + c] = t;
+  }
+}
+
+// x[i][c] += sum_j Z[i][j] w[j][c]: one lane per column, a wave walks 64 rows.
+__global__ __launch_bounds__(kBlock) void k_circ_apply(int n, int k, int ncols,
+                                                       const double* __restrict__ Z,
+                                                       const double* __restrict__ w, int64_t ldw,
+                                                       double* __restrict__ x, int64_t ldx) {
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = blockIdx.x * kWave + lane;
+  if (c >= ncols) return;
+  double wc[kCircMax];
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j) wc[j] = (j < k) ? w[static_cast<int64_t>(j) * ldw + c] : 0.0;
+  const int i0 = (blockIdx.y * 4 + wv) * kWave;
+  const int i1 = (i0 + kWave < n) ? i0 + kWave : n;
+  for (int i = i0; i < i1; ++i) {
+    const double* z = Z + static_cast<int64_t>(i) * k;
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < kCircMax; ++j)
+      if (j < k) t = fma(z[j], wc[j], t);
+    x[static_cast<int64_t>(i) * ldx + c] += t;
+  }
+}
+
+}  // namespace
+
+void launch_circ_rhs_init(hipStream_t s, const DevLevel& L, PcgWork& w, const double* B, int64_t ldb,
+                          int ncols) {
+  if (ncols <= 0) return;
+  if (ncols > w.cap) fail(MGRIT_INVALID_ARGUMENT, "circuit set-up solve wider than its workspace");
+  hipLaunchKernelGGL(k_circ_rhs_init, dim3(cdiv(ncols, kWave), w.nrb), dim3(kBlock), 0, s, L.n, L.s64, B,
+                     ldb, ncols, w.rows_per_block, w.ld, w.x, w.r, w.part, w.nrb, w.flags);
+  MG_HIP(hipGetLastError());
+}
+
+int circ_parts(int n) { return cdiv(n, kCircRowsPerWave); }
+
+void launch_circ_dots(hipStream_t s, int n, int k, int ncols, const double* Bt, CView y, CView a,
+                      double* part, int64_t ldp) {
+  if (ncols <= 0 || n <= 0) return;
+  if (k < 1 || k > kCircMax || ldp < ncols) fail(MGRIT_INVALID_ARGUMENT, "circuit dots: bad sizes");
+  const int np = circ_parts(n);
+  hipLaunchKernelGGL(k_circ_dots, dim3(cdiv(ncols, kWave), cdiv(np, 4)), dim3(kBlock), 0, s, n, k, ncols,
+                     Bt, y.p, y.ld, a.p, a.ld, part, ldp, np);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_circ_sum(hipStream_t s, int k, int ncols, int nparts, const double* part, int64_t ldp,
+                     double* d, int64_t ldd) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_circ_sum, dim3(cdiv(ncols, kWave), k), dim3(kWave), 0, s, k, ncols, nparts, part,
+                     ldp, d, ldd);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_circ_solve(hipStream_t s, int k, int ncols, const double* d, int64_t ldd,
+                       const double* src, int64_t lds, const double* cS, double* w, int64_t ldw) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_circ_solve, dim3(cdiv(ncols, kWave)), dim3(kWave), 0, s, k, ncols, d, ldd, src, lds,
+                     cS, w, ldw);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_circ_apply(hipStream_t s, int n, int k, int ncols, const double* Z, const double* w,
+                       int64_t ldw, double* x, int64_t ldx) {
+  if (ncols <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_circ_apply, dim3(cdiv(ncols, kWave), cdiv(n, 4 * kWave)), dim3(kBlock), 0, s, n, k,
+                     ncols, Z, w, ldw, x, ldx);
+  MG_HIP(hipGetLastError());
+}
+
+}  // namespace mg

@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "circuit.h"
 #include "internal.h"
 #include "setup.h"
 
@@ -61,6 +62,16 @@ struct LevelState {
   double* nl_ws = nullptr; // persistent Newton stepper workspace (coarsest nonlinear level)
   double* gemm_part = nullptr;   // partial sums of the stored-inverse product (intermediate levels)
   int64_t gemm_part_size = 0;
+  // field-circuit coupling: coupling rows B^T and Z = A^-1 B^T ([n][k] each),
+  // the eliminated circuit system [k][3 + k], and per-column work buffers
+  // ([parts][k][c_ld] partial dots, [k][c_ld] dots and circuit unknowns)
+  double* cBt = nullptr;
+  double* cZ = nullptr;
+  double* cS = nullptr;
+  double* cpart = nullptr;
+  double* cd = nullptr;
+  double* cw = nullptr;
+  int64_t c_ld = 0;
   bool relaxed = false;   // F-points hold a previous iterate (warm starts)
   bool cvalid = false;    // C-points hold a previous iterate
 };
@@ -111,6 +122,10 @@ struct Handle {
   double* gnn_tmp = nullptr; // [n_c][ld_c] implicit-Euler part of a coarse step
   const double* col_amp = nullptr;   // per-column source amplitude factors / phase
   const double* col_dphi = nullptr;  // shifts of phi_batch (training data only)
+  bool circ = false;         // field-circuit coupling (phys.circuit = 1)
+  int circ_k = 0;            // circuit unknowns: 3 phase currents + bar voltages
+  std::vector<double> circ_Cinv;  // level 0: inverse of the cage matrix C (host, nb x nb)
+  double* circ_stage = nullptr;   // mgrit_circuit_values staging (lazy)
   bool verbose = false;      // MGRIT_VERBOSE: one line per MGRIT iteration on stderr
   int device = 0;           // HIP device the handle was set up on
   bool solved = false;      // level 0 holds the iterate of a completed mgrit_solve
@@ -179,10 +194,10 @@ static void set_rows_per_block(PcgWork& w, int rpb) {
 // and keep the fastest.  Results are cached per (n, W, columns, precision)
 // for the life of the process.
 struct TuneKey {
-  int n, W, cols, prec, dia, depth, narrow;
+  int n, W, cols, prec, dia, depth, narrow, rpb, cpl;
   bool operator<(const TuneKey& o) const {
-    return std::tie(n, W, cols, prec, dia, depth, narrow) <
-           std::tie(o.n, o.W, o.cols, o.prec, o.dia, o.depth, o.narrow);
+    return std::tie(n, W, cols, prec, dia, depth, narrow, rpb, cpl) <
+           std::tie(o.n, o.W, o.cols, o.prec, o.dia, o.depth, o.narrow, o.rpb, o.cpl);
   }
 };
 struct TuneChoice {
@@ -206,10 +221,17 @@ static void autotune(Handle& h, LevelState& S) {
   w.depth = forced_depth > 0 ? forced_depth : 1;
   const int forced_narrow = h.par.pcg_rows_narrow;
   w.rpb_narrow = forced_narrow > 0 ? forced_narrow : 0;
-  if (!h.par.autotune || S.n < 4096 || ncols < kWave) return;
+  const int forced_rpb = h.par.pcg_rows_per_block, forced_cpl = h.par.pcg_cols_per_lane;
+  if (forced_rpb > 0) set_rows_per_block(w, forced_rpb);
+  if (forced_cpl > 0) w.cpl = forced_cpl;
+  if (!h.par.autotune || S.n < 4096 || ncols < kWave) {
+    if (w.cpl == 2 && !w.dia && S.op.W != 8)
+      fail(MGRIT_INVALID_ARGUMENT, "two columns per lane need the 8-wide row family or the diagonal window");
+    return;
+  }
   const bool fp32 = w.prec == MGRIT_FP32_IR;
   const TuneKey key{S.n, S.op.W, ncols, w.prec, S.op.dia_R * 4 + h.par.pcg_kernel, forced_depth,
-                    forced_narrow};
+                    forced_narrow, forced_rpb, forced_cpl};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -254,6 +276,7 @@ static void autotune(Handle& h, LevelState& S) {
     // depth applies to the diagonal-window family and needs rows to walk
     if ((!dia || depth > rpb / 4) && depth != 1) continue;
     if (forced_depth > 0 && dia && depth != forced_depth) continue;
+    if ((forced_rpb > 0 && rpb != forced_rpb) || (forced_cpl > 0 && cpl != forced_cpl)) continue;
     set_rows_per_block(w, rpb);
     w.cpl = cpl;
     w.dia = dia;
@@ -697,6 +720,28 @@ struct LevelTimer {
   }
 };
 
+static void circuit_buffers(Handle& h, LevelState& S, int ncols) {
+  if (S.c_ld >= ncols) return;
+  const int64_t ld = round_up(std::max<int64_t>(ncols, S.pcg.cap), kWave);
+  const size_t k = static_cast<size_t>(h.circ_k);
+  S.cpart = h.arena.alloc<double>(static_cast<size_t>(circ_parts(S.n)) * k * ld);
+  S.cd = h.arena.alloc<double>(k * ld);
+  S.cw = h.arena.alloc<double>(k * ld);
+  S.c_ld = ld;
+}
+
+// a' = y + Z w, w = S^-1 (v(t'); 0) - S^-1 (l_z/dt) E B^T' (y - u_in) per column
+// (y in w.x on entry, a' on exit; the phase voltages are the source table).
+static void circuit_step(Handle& h, LevelState& S, PcgWork& w, const PhiCall& c) {
+  hipStream_t s = h.stream;
+  circuit_buffers(h, S, c.ncols);
+  const int k = h.circ_k;
+  launch_circ_dots(s, S.n, k, c.ncols, S.cBt, CView{w.x, w.ld}, c.in, S.cpart, S.c_ld);
+  launch_circ_sum(s, k, c.ncols, circ_parts(S.n), S.cpart, S.c_ld, S.cd, S.c_ld);
+  launch_circ_solve(s, k, c.ncols, S.cd, S.c_ld, w.src, w.ld, S.cS, S.cw, S.c_ld);
+  launch_circ_apply(s, S.n, k, c.ncols, S.cZ, S.cw, S.c_ld, w.x, w.ld);
+}
+
 static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
   if (c.ncols <= 0) return;
   LevelTimer timer(h, l);
@@ -722,6 +767,9 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
              ? newton_solve(h, l, S, w, c.ncols, c.in, c.ga.p == c.in.p && c.gb.p == nullptr)
              : pcg_solve(h, l, S.op, w, c.ncols, c.in);
   }
+  // field-circuit coupling: the solve gave y = A^-1 (M/dt) u_in; eliminate
+  // the circuit unknowns and add Z w
+  if (h.circ) circuit_step(h, S, w, c);
   if (c.dout)
     launch_axpby3(s, S.n, c.ncols, c.dout, c.ldo, 1.0, CView{w.x, w.ld}, -1.0, CView{c.out, c.ldo},
                   0.0, CView{});
@@ -887,7 +935,7 @@ static void coarsest_solve(Handle& h, int l) {
   LevelTimer timer(h, l);
   // u_0 = g_0
   launch_axpby3(s, S.n, 1, S.U, S.ld, 0.0, CView{}, 1.0, CView{S.G, S.ld}, 0.0, CView{});
-  if (S.Ainv) {
+  if (S.Ainv && !h.circ) {
     // implicit Euler with the stored inverse (the same kernels as the batched
     // coarse steps of the FAS right-hand side, so both evaluate the same
     // propagator), the learned correction in place if active, then + g_s
@@ -944,8 +992,9 @@ static void coarsest_solve(Handle& h, int l) {
     }
     return;
   }
-  if (S.nl.n_tri > 0 || learned_active(h, l)) {
-    // one step at a time, u_s = Psi(u_{s-1}) + g_s (Newton for the nonlinear model)
+  if (S.nl.n_tri > 0 || learned_active(h, l) || h.circ) {
+    // one step at a time, u_s = Psi(u_{s-1}) + g_s (Newton for the nonlinear
+    // model; the circuit elimination after each step of the coupled model)
     for (int64_t st = 1; st <= S.N; ++st) {
       PhiCall c;
       c.ncols = 1;
@@ -1178,6 +1227,149 @@ static void build_coarse_inverse(Handle& h, LevelState& S) {
 }
 
 // ---------------------------------------------------------------------------
+// Field-circuit coupling set-up (Sec. 3.1): per level the coupling rows
+// B = [X; Y'/l_z] (X_s = turns_density * integral of sign phi over the cells
+// of phase s, Y'_k = integral of sigma phi over bar k), Z = A^-1 B^T by
+// batched CG to 1e-14 relative residual, and the eliminated circuit system
+// S = (l_z/dt) E B Z + diag(r_phase I_3, C), C = diag(G) + L / (2 ring_r),
+// stored as [S^-1 columns 0..2 | S^-1 (l_z/dt) E] per row.
+
+// Inverse of a small dense matrix (row-major k x k) by Gauss-Jordan
+// elimination with partial pivoting.
+static std::vector<double> small_inverse(std::vector<double> a, int k) {
+  std::vector<double> inv(static_cast<size_t>(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) inv[static_cast<size_t>(i) * k + i] = 1.0;
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (std::fabs(a[static_cast<size_t>(r) * k + c]) > std::fabs(a[static_cast<size_t>(piv) * k + c])) piv = r;
+    if (!(std::fabs(a[static_cast<size_t>(piv) * k + c]) > 0.0))
+      fail(MGRIT_INVALID_ARGUMENT, "field-circuit system is singular");
+    if (piv != c)
+      for (int j = 0; j < k; ++j) {
+        std::swap(a[static_cast<size_t>(piv) * k + j], a[static_cast<size_t>(c) * k + j]);
+        std::swap(inv[static_cast<size_t>(piv) * k + j], inv[static_cast<size_t>(c) * k + j]);
+      }
+    const double d = a[static_cast<size_t>(c) * k + c];
+    for (int j = 0; j < k; ++j) {
+      a[static_cast<size_t>(c) * k + j] /= d;
+      inv[static_cast<size_t>(c) * k + j] /= d;
+    }
+    for (int r = 0; r < k; ++r) {
+      if (r == c) continue;
+      const double f = a[static_cast<size_t>(r) * k + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < k; ++j) {
+        a[static_cast<size_t>(r) * k + j] -= f * a[static_cast<size_t>(c) * k + j];
+        inv[static_cast<size_t>(r) * k + j] -= f * inv[static_cast<size_t>(c) * k + j];
+      }
+    }
+  }
+  return inv;
+}
+
+static void setup_circuit(Handle& h, const mgrit_problem* prob, const std::vector<HostPattern>& pats) {
+  const mgrit_physics& ph = prob->phys;
+  hipStream_t s = h.stream;
+  const int nb = ph.n_bars, k = 3 + nb;
+  h.circ_k = k;
+  for (size_t l = 0; l < h.lv.size(); ++l) {
+    LevelState& S = h.lv[l];
+    const mgrit_mesh& m = prob->meshes[l];
+    const HostPattern& P = pats[l];
+    const int n = S.n;
+    // coupling rows by unknown (device order), and the bars' conductances
+    std::vector<double> Bt(static_cast<size_t>(n) * k, 0.0);
+    std::vector<double> G(nb, 0.0);
+    for (int e = 0; e < m.n_tri; ++e) {
+      const int* v = m.tri + 3 * e;
+      const double* p0 = m.xy + 2 * v[0];
+      const double* p1 = m.xy + 2 * v[1];
+      const double* p2 = m.xy + 2 * v[2];
+      const double area = 0.5 * ((p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]));
+      const int ph_e = m.cell_phase[e];
+      const double sig = ph.sigma[m.cell_mat[e]];
+      const int bar = (nb > 0) ? m.cell_bar[e] : -1;
+      if (bar >= 0) G[bar] += sig * area / ph.l_z;
+      for (int a = 0; a < 3; ++a) {
+        const int i = P.index[v[a]];
+        if (i < 0) continue;
+        if (ph_e >= 0) Bt[static_cast<size_t>(i) * k + ph_e] += ph.turns_density * m.cell_sign[e] * area / 3.0;
+        if (bar >= 0) Bt[static_cast<size_t>(i) * k + 3 + bar] += sig * area / 3.0 / ph.l_z;
+      }
+    }
+    for (int b = 0; b < nb; ++b)
+      if (!(G[b] > 0.0)) fail(MGRIT_INVALID_ARGUMENT, "a rotor bar has no conducting cells on some level");
+    S.cBt = h.arena.alloc<double>(Bt.size());
+    MG_HIP(hipMemcpyAsync(S.cBt, Bt.data(), sizeof(double) * Bt.size(), hipMemcpyHostToDevice, s));
+    // Z = A^-1 B^T: k columns of batched FP64 CG (the level's kernel shape)
+    PcgWork w;
+    const int keep_max = h.par.pcg_max_iter;
+    h.par.pcg_max_iter = std::max(keep_max, 20000);
+    alloc_pcg(h, w, n, k, rows_per_block_for(n), MGRIT_FP64);
+    h.par.pcg_max_iter = keep_max;
+    set_rows_per_block(w, S.pcg.rows_per_block);
+    w.cpl = S.pcg.cpl;
+    w.dia = S.pcg.dia;
+    w.depth = S.pcg.depth;
+    const double tol2 = 1e-28;
+    launch_circ_rhs_init(s, S.op, w, S.cBt, k, k);
+    launch_reduce(s, w, k, RED_INIT, tol2, 3, nullptr);
+    MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    mgrit_stats* keep = h.st;
+    h.st = nullptr;
+    pcg_iterate(h, 0, S.op, w, k, tol2, IT_LIN64, w.host_flags[0], true, w.hist_cap);
+    h.st = keep;
+    S.cZ = h.arena.alloc<double>(static_cast<size_t>(n) * k);
+    launch_axpby3(s, n, k, S.cZ, k, 1.0, CView{w.x, w.ld}, 0.0, CView{}, 0.0, CView{});
+    std::vector<double> Z(static_cast<size_t>(n) * k);
+    MG_HIP(hipMemcpyAsync(Z.data(), S.cZ, sizeof(double) * Z.size(), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    // S = (l_z/dt) E B Z + diag(r_phase I_3, C)
+    const double f = ph.l_z / S.op.dt;
+    std::vector<double> Sm(static_cast<size_t>(k) * k, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < k; ++a) {
+        const double ba = Bt[static_cast<size_t>(i) * k + a];
+        if (ba == 0.0) continue;
+        for (int b = 0; b < k; ++b) Sm[static_cast<size_t>(a) * k + b] += ba * Z[static_cast<size_t>(i) * k + b];
+      }
+    for (int a = 0; a < k; ++a) {
+      const double e = a < 3 ? f : -f;
+      for (int b = 0; b < k; ++b) Sm[static_cast<size_t>(a) * k + b] *= e;
+    }
+    for (int a = 0; a < 3; ++a) Sm[static_cast<size_t>(a) * k + a] += ph.r_phase;
+    for (int b = 0; b < nb; ++b) {
+      const int r = 3 + b;
+      Sm[static_cast<size_t>(r) * k + r] += G[b] + 2.0 / (2.0 * ph.ring_r);
+      Sm[static_cast<size_t>(r) * k + 3 + (b + 1) % nb] -= 1.0 / (2.0 * ph.ring_r);
+      Sm[static_cast<size_t>(r) * k + 3 + (b + nb - 1) % nb] -= 1.0 / (2.0 * ph.ring_r);
+    }
+    if (l == 0 && nb > 0) {
+      std::vector<double> Cm(static_cast<size_t>(nb) * nb, 0.0);
+      for (int b = 0; b < nb; ++b) {
+        Cm[static_cast<size_t>(b) * nb + b] += G[b] + 2.0 / (2.0 * ph.ring_r);
+        Cm[static_cast<size_t>(b) * nb + (b + 1) % nb] -= 1.0 / (2.0 * ph.ring_r);
+        Cm[static_cast<size_t>(b) * nb + (b + nb - 1) % nb] -= 1.0 / (2.0 * ph.ring_r);
+      }
+      h.circ_Cinv = small_inverse(Cm, nb);
+    }
+    const std::vector<double> Si = small_inverse(Sm, k);
+    std::vector<double> cS(static_cast<size_t>(k) * (3 + k));
+    for (int j = 0; j < k; ++j) {
+      for (int q = 0; q < 3; ++q) cS[static_cast<size_t>(j) * (3 + k) + q] = Si[static_cast<size_t>(j) * k + q];
+      for (int a = 0; a < k; ++a)
+        cS[static_cast<size_t>(j) * (3 + k) + 3 + a] = Si[static_cast<size_t>(j) * k + a] * (a < 3 ? f : -f);
+    }
+    S.cS = h.arena.alloc<double>(cS.size());
+    MG_HIP(hipMemcpyAsync(S.cS, cS.data(), sizeof(double) * cS.size(), hipMemcpyHostToDevice, s));
+    MG_HIP(hipStreamSynchronize(s));
+    circuit_buffers(h, S, S.pcg.cap);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Workspace of phi_step_noalloc: one static device array per GPU.  Host code
 // never passes `scratch` itself to a kernel (in host code the name is a
 // host-side stand-in, not a device address): set-up takes the array's device
@@ -1271,6 +1463,13 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     fail(MGRIT_INVALID_ARGUMENT, "pcg_check_every and pcg_check_narrow must be in 0..64");
   if (par->coarse_persistent < -1 || par->coarse_persistent > 1)
     fail(MGRIT_INVALID_ARGUMENT, "coarse_persistent must be -1, 0 or 1");
+  {
+    const int rb = par->pcg_rows_per_block;
+    if (!(rb == 0 || rb == 16 || rb == 32 || rb == 64 || rb == 128 || rb == 256))
+      fail(MGRIT_INVALID_ARGUMENT, "pcg_rows_per_block must be 0, 16, 32, 64, 128 or 256");
+    if (par->pcg_cols_per_lane < 0 || par->pcg_cols_per_lane > 2)
+      fail(MGRIT_INVALID_ARGUMENT, "pcg_cols_per_lane must be 0, 1 or 2");
+  }
   h.m = par->m;
   // factor between levels l and l+1: m on level 0, m_coarse (or m) below
   auto factor = [&](int l) { return (l == 0 || par->m_coarse == 0) ? par->m : par->m_coarse; };
@@ -1291,6 +1490,25 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
   h.src.signal = ph.signal;
   if (!std::isfinite(ph.t_start)) fail(MGRIT_INVALID_ARGUMENT, "t_start must be finite");
   h.src.t0 = ph.t_start;
+  if (ph.circuit != 0 && ph.circuit != 1) fail(MGRIT_INVALID_ARGUMENT, "circuit must be 0 or 1");
+  h.circ = ph.circuit == 1;
+  if (h.circ) {
+    if (ph.nonlinear) fail(MGRIT_UNSUPPORTED, "the field-circuit coupling needs the linear model");
+    if (par->coarse_model != 0) fail(MGRIT_UNSUPPORTED, "the learned coarse propagator does not model the circuit");
+    if (!(ph.turns_density > 0.0) || !(ph.l_z > 0.0) || !(ph.r_phase > 0.0) || !std::isfinite(ph.v0))
+      fail(MGRIT_INVALID_ARGUMENT, "circuit: turns_density, l_z and r_phase must be > 0, v0 finite");
+    if (ph.n_bars < 0 || ph.n_bars > kCircMax - 3) fail(MGRIT_INVALID_ARGUMENT, "circuit: n_bars must be 0..32");
+    if (ph.n_bars > 0 && !(ph.ring_r > 0.0)) fail(MGRIT_INVALID_ARGUMENT, "circuit: ring_r must be > 0");
+    for (int l = 0; l < L && ph.n_bars > 0; ++l) {
+      const mgrit_mesh& mm = prob->meshes[l];
+      if (!mm.cell_bar) fail(MGRIT_INVALID_ARGUMENT, "circuit: cell_bar is required with n_bars > 0");
+      for (int e = 0; e < mm.n_tri; ++e)
+        if (mm.cell_bar[e] < -1 || mm.cell_bar[e] >= ph.n_bars)
+          fail(MGRIT_INVALID_ARGUMENT, "circuit: cell_bar out of range");
+    }
+    // the source table then holds the phase voltages v_s(t)
+    h.src.scale = ph.v0 * ph.amplitude;
+  }
 
   // host phase: validate every mesh, build patterns and transfers (no HIP call)
   std::vector<HostPattern> pats(L);
@@ -1319,6 +1537,8 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
     S.N = N;
     S.coarsest = (l == L - 1);
     S.op = assemble_level(h.arena, s, prob->meshes[l], pats[l], ph, dt, &S.elem);
+    // coupled model: the coils carry the circuit currents, not a source term
+    if (h.circ) MG_HIP(hipMemsetAsync(S.op.F, 0, sizeof(double) * 3 * static_cast<size_t>(S.n), s));
     S.nat = upload_vec(h.arena, s, pats[l].nat);
     S.u0r = h.arena.alloc<double>(S.n);
     if (ph.nonlinear) {
@@ -1418,6 +1638,7 @@ static void setup_impl(Handle& h, const mgrit_problem* prob, const mgrit_params*
         if (S.gemm_part_size > 0) S.gemm_part = h.arena.alloc<double>(static_cast<size_t>(S.gemm_part_size));
       }
   }
+  if (h.circ) setup_circuit(h, prob, pats);
   if (L > 1) setup_gnn(h, prob->meshes[L - 1], pats[L - 1], ph);
   if (par->coarse_model != 0 && par->coarse_model != 1)
     fail(MGRIT_INVALID_ARGUMENT, "coarse_model must be 0 or 1");
@@ -1569,6 +1790,58 @@ static void joule_impl(Handle& h, double* p) {
   MG_HIP(hipStreamSynchronize(h.stream));
 }
 
+// Circuit quantities of the steps of a level-0 trajectory (time-major
+// [(N+1)][n0], host or device): per step the k dot products with the
+// coupling rows of u_i - u_{i-1} on the GPU, then on the host
+//   i_s = (v_s(t_i) - (l_z/dt) d_s) / r_phase,  v_bar = C^-1 (l_z/dt) d_bar,
+//   i_bar = -L v_bar / (2 ring_r).
+static void circuit_values_impl(Handle& h, const double* u, double* out) {
+  if (!h.circ) fail(MGRIT_UNSUPPORTED, "the problem has no circuit (circuit = 0)");
+  if (!u || !out) fail(MGRIT_INVALID_ARGUMENT, "null trajectory or output");
+  hipStream_t s = h.stream;
+  LevelState& S = h.lv[0];
+  const mgrit_physics& ph = h.phys;
+  const int k = h.circ_k, nb = ph.n_bars, n = S.n;
+  const int64_t N = S.N;
+  const int chunk = 1024;                    // steps per pass
+  const int64_t ldc = round_up(chunk + 1, kWave);
+  if (!h.circ_stage)
+    h.circ_stage = h.arena.alloc<double>(static_cast<size_t>(n) * (chunk + 1) + static_cast<size_t>(n) * ldc +
+                                         3 * static_cast<size_t>(ldc));
+  double* tm = h.circ_stage;
+  double* cols = tm + static_cast<size_t>(n) * (chunk + 1);
+  double* vtab = cols + static_cast<size_t>(n) * ldc;
+  circuit_buffers(h, S, chunk);
+  const double f = ph.l_z / S.op.dt;
+  const int kout = 3 + 2 * nb;
+  std::vector<double> d(static_cast<size_t>(k) * S.c_ld), v(3 * static_cast<size_t>(ldc));
+  for (int64_t i0 = 0; i0 < N; i0 += chunk) {
+    const int P = static_cast<int>(std::min<int64_t>(chunk, N - i0));   // steps i0+1 .. i0+P
+    MG_HIP(hipMemcpyAsync(tm, u + static_cast<size_t>(i0) * n, sizeof(double) * static_cast<size_t>(P + 1) * n,
+                          h.par.device_pointers ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    launch_tm_to_slabs(s, n, P + 1, 1, tm, cols, ldc, 0, S.nat);
+    launch_circ_dots(s, n, k, P, S.cBt, CView{cols + 1, ldc}, CView{cols, ldc}, S.cpart, S.c_ld);
+    launch_circ_sum(s, k, P, circ_parts(n), S.cpart, S.c_ld, S.cd, S.c_ld);
+    launch_source_table(s, h.src, S.op.dt, P, nullptr, i0, 1, vtab, ldc);
+    MG_HIP(hipMemcpyAsync(d.data(), S.cd, sizeof(double) * d.size(), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipMemcpyAsync(v.data(), vtab, sizeof(double) * v.size(), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < P; ++c) {
+      double* o = out + static_cast<size_t>(i0 + c) * kout;
+      for (int q = 0; q < 3; ++q)
+        o[q] = (v[static_cast<size_t>(q) * ldc + c] - f * d[static_cast<size_t>(q) * S.c_ld + c]) / ph.r_phase;
+      for (int b = 0; b < nb; ++b) {
+        double t = 0.0;
+        for (int a = 0; a < nb; ++a)
+          t += h.circ_Cinv[static_cast<size_t>(b) * nb + a] * f * d[static_cast<size_t>(3 + a) * S.c_ld + c];
+        o[3 + b] = t;
+      }
+      for (int b = 0; b < nb; ++b)
+        o[3 + nb + b] = -(2.0 * o[3 + b] - o[3 + (b + 1) % nb] - o[3 + (b + nb - 1) % nb]) / (2.0 * ph.ring_r);
+    }
+  }
+}
+
 static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st) {
   hipStream_t s = h.stream;
   h.tol_now = h.par.pcg_tol;
@@ -1593,7 +1866,7 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   auto t0 = std::chrono::steady_clock::now();
   const bool nl_persistent = S0.nl.n_tri > 0 &&
                              (h.par.seq_kernel == 1 || (h.par.seq_kernel == 0 && S0.n <= 4096));
-  if (h.par.seq_kernel == 3) {
+  if (h.par.seq_kernel == 3 && !h.circ) {
     // linear model: every step is exact implicit Euler with the level's
     // stored inverse, one stream of A^{-1} per step (built here on first use)
     if (S0.nl.n_tri > 0) fail(MGRIT_UNSUPPORTED, "seq_kernel = 3 needs the linear model");
@@ -1608,8 +1881,8 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
       // right-hand side and result as contiguous vectors (stride 1), so that
       // the product streams A^{-1} and the right-hand side coalesced
       launch_source_table(s, h.src, S0.op.dt, 1, nullptr, st_i - 1, 0, w.src, w.ld);
-      launch_ie_inverse_batch(s, S0.op, 1, w.src, w.ld, CView{U + st_i - 1, ld}, S0.Ainv, S0.ld_inv,
-                              S0.bvec, w.x, 1);
+      launch_ie_rhs_batch(s, S0.op, 1, w.src, w.ld, CView{U + st_i - 1, ld}, S0.bvec, 1);
+      launch_inv_gemv(s, S0.n, S0.Ainv, S0.ld_inv, S0.bvec, w.x);
       launch_axpby3(s, S0.n, 1, U + st_i, ld, 1.0, CView{w.x, 1}, 0.0, CView{}, 0.0, CView{});
     }
     MG_HIP(hipStreamSynchronize(s));
@@ -1630,8 +1903,9 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
     if (bits & 8) fail(MGRIT_NEWTON_NOT_CONVERGED, "Newton did not converge in newton_max_iter iterations");
     S0.pcg.host_flags[1] = bits & 3;
     S0.pcg.host_flags[2] = 0;
-  } else if (S0.nl.n_tri > 0) {
-    // nonlinear: batched Newton on one column, step after step
+  } else if (S0.nl.n_tri > 0 || h.circ) {
+    // nonlinear: batched Newton on one column, step after step; coupled
+    // model: the batched step and its circuit elimination
     for (int64_t st = 1; st <= S0.N; ++st) {
       PhiCall c;
       c.ncols = 1;
@@ -1669,7 +1943,7 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
     MG_HIP(hipStreamSynchronize(s));
   }
   st->time_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (S0.nl.n_tri == 0) {
+  if (S0.nl.n_tri == 0 && !h.circ) {
     st->phi_columns[0] += S0.N;
     st->pcg_sweeps[0] += S0.pcg.host_flags[2];
   }
@@ -1739,6 +2013,7 @@ static void phi_step_noalloc_impl(Handle& h, int level, int B, const int64_t* i_
                                   const double* u_prev, double* u_next) {
   h.tol_now = h.par.pcg_tol;
   h.eta_now = 0.0;
+  if (h.circ) fail(MGRIT_UNSUPPORTED, "phi_step_noalloc does not step the field-circuit model");
   if (level < 0 || level >= static_cast<int>(h.lv.size())) fail(MGRIT_INVALID_ARGUMENT, "level");
   if (B < 0 || (B > 0 && (!i_from || !u_prev || !u_next))) fail(MGRIT_INVALID_ARGUMENT, "phi_step arguments");
   if (B == 0) return;
@@ -2022,6 +2297,7 @@ static double uniform01(uint64_t& x) { return static_cast<double>(splitmix64(x) 
 static void train_impl(Handle& h, const mgrit_train_params* tp, mgrit_train_stats* ts) {
   if (!tp || !ts) fail(MGRIT_INVALID_ARGUMENT, "null training parameters or statistics");
   if (h.lv.size() < 2 || !h.has_gnn) fail(MGRIT_UNSUPPORTED, "no learned coarse propagator on this hierarchy");
+  if (h.circ) fail(MGRIT_UNSUPPORTED, "the learned coarse propagator does not model the circuit");
   if (tp->n_traj < 2 || tp->epochs < 1 || tp->batch < 1 || !(tp->lr > 0.0) ||
       !(tp->perturb >= 0.0 && tp->perturb <= 1.0) ||
       !(tp->amp_spread >= 0.0 && tp->amp_spread < 1.0) ||
@@ -2367,6 +2643,8 @@ void mgrit_default_params(mgrit_params* p) {
   p->m_coarse = 0;
   p->coarse_persistent = 0;
   p->pcg_check_narrow = 16;
+  p->pcg_rows_per_block = 0;
+  p->pcg_cols_per_lane = 0;
 }
 
 int mgrit_setup(const mgrit_problem* prob, const mgrit_params* par, void* hip_stream, void** out) {
@@ -2424,6 +2702,12 @@ int mgrit_joule_losses(void* hp, double* p) {
   return guarded(h, [&] { mg::joule_impl(*h, p); });
 }
 
+int mgrit_circuit_values(void* hp, const double* u, double* out) {
+  auto* h = static_cast<mg::Handle*>(hp);
+  if (!h) return MGRIT_INVALID_ARGUMENT;
+  return guarded(h, [&] { mg::circuit_values_impl(*h, u, out); });
+}
+
 int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int64_t* nnz,
                      int32_t* kernel_shape) {
   auto* h = static_cast<mg::Handle*>(hp);
@@ -2437,6 +2721,7 @@ int mgrit_level_info(void* hp, int32_t level, int64_t* n, int64_t* n_steps, int6
     kernel_shape[1] = S.pcg.cpl;
     kernel_shape[2] = S.pcg.dia ? 2 : 1;
     kernel_shape[3] = S.pcg.dia ? S.pcg.depth : 1;
+    kernel_shape[4] = S.pcg.rpb_narrow;
   }
   return MGRIT_OK;
 }

@@ -117,9 +117,73 @@ __global__ void k_inv_gemm_sum(int M, int N, int splits, const double* __restric
   X[static_cast<int64_t>(j) * ldx + c] = v;
 }
 
+// y = A x for one contiguous column (the stored-inverse sequential stepper):
+// a wave owns 4 rows, its lanes read 16-byte pairs of each row and of x
+// (x once for the 4 rows), two pairs in flight per row, then a fixed-order
+// shuffle reduction.  A streams from HBM once; x stays in the caches.
+constexpr int kGemvRows = 4;
+
+__global__ __launch_bounds__(256) void k_inv_gemv(int n, const double* __restrict__ A, int64_t lda,
+                                                  const double* __restrict__ x, double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int r0 = (blockIdx.x * 4 + wv) * kGemvRows;
+  if (r0 >= n) return;
+  double acc[kGemvRows][2];
+#pragma unroll
+  for (int r = 0; r < kGemvRows; ++r) acc[r][0] = acc[r][1] = 0.0;
+  const int npair = n >> 1;                 // full 16-byte pairs of a row
+  int p = lane;
+  for (; p + 64 < npair; p += 128) {
+    const double2 xa = reinterpret_cast<const double2*>(x)[p];
+    const double2 xb = reinterpret_cast<const double2*>(x)[p + 64];
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) {
+      const int row = (r0 + r < n) ? r0 + r : n - 1;
+      const double2* ar = reinterpret_cast<const double2*>(A + static_cast<int64_t>(row) * lda);
+      const double2 a0 = ar[p], a1 = ar[p + 64];
+      acc[r][0] = fma(a0.x, xa.x, acc[r][0]);
+      acc[r][1] = fma(a0.y, xa.y, acc[r][1]);
+      acc[r][0] = fma(a1.x, xb.x, acc[r][0]);
+      acc[r][1] = fma(a1.y, xb.y, acc[r][1]);
+    }
+  }
+  for (; p < npair; p += 64) {
+    const double2 xa = reinterpret_cast<const double2*>(x)[p];
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) {
+      const int row = (r0 + r < n) ? r0 + r : n - 1;
+      const double2 a0 = reinterpret_cast<const double2*>(A + static_cast<int64_t>(row) * lda)[p];
+      acc[r][0] = fma(a0.x, xa.x, acc[r][0]);
+      acc[r][1] = fma(a0.y, xa.y, acc[r][1]);
+    }
+  }
+  if ((n & 1) && lane == 0) {
+#pragma unroll
+    for (int r = 0; r < kGemvRows; ++r) {
+      const int row = (r0 + r < n) ? r0 + r : n - 1;
+      acc[r][0] = fma(A[static_cast<int64_t>(row) * lda + n - 1], x[n - 1], acc[r][0]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kGemvRows; ++r) {
+    double t = acc[r][0] + acc[r][1];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (lane == 0 && r0 + r < n) y[r0 + r] = t;
+  }
+}
+
 inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 }  // namespace
+
+void launch_inv_gemv(hipStream_t s, int n, const double* A, int64_t lda, const double* x, double* y) {
+  if (n <= 0) return;
+  if ((lda & 1) || (reinterpret_cast<uintptr_t>(A) & 15) || (reinterpret_cast<uintptr_t>(x) & 15))
+    fail(MGRIT_INVALID_ARGUMENT, "inverse GEMV: A, its stride and x must be 16-byte aligned");
+  hipLaunchKernelGGL(k_inv_gemv, dim3(cdiv(n, 4 * kGemvRows)), dim3(256), 0, s, n, A, lda, x, y);
+  MG_HIP(hipGetLastError());
+}
 
 // Slices of k for M columns: enough work-groups for two per compute unit.
 static int inv_gemm_slices(int M, int N, int& kslice) {

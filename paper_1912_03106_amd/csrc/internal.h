@@ -361,6 +361,9 @@ void launch_ie_inverse_batch(hipStream_t s, const DevLevel& L, int ncols, const 
 int64_t inv_gemm_part_doubles(int max_cols, int N);
 void launch_inv_gemm(hipStream_t s, int M, int N, const double* B, int64_t ldb, const double* A,
                      int64_t lda, double* X, int64_t ldx, double* part, int64_t part_size);
+// y = A x for one contiguous column, A row-major [n][lda] (stored-inverse
+// sequential stepping); A, lda and x 16-byte aligned.
+void launch_inv_gemv(hipStream_t s, int n, const double* A, int64_t lda, const double* x, double* y);
 // Y[:, b] = X[:, b] + alpha[b] (X[:, perm[b]] - X[:, b]), b < nt (Y != X)
 void gnn_mix(hipStream_t s, int n, int nt, const double* X, int64_t ld, const int* perm,
              const double* alpha, double* Y);

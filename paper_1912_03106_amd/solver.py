@@ -52,13 +52,16 @@ class Solver:
                 cell_phase=np.ascontiguousarray(m.cell_phase, dtype=np.int32),
                 cell_sign=np.ascontiguousarray(m.cell_sign, dtype=np.int32),
                 dirichlet=np.ascontiguousarray(m.dirichlet, dtype=np.uint8),
+                cell_bar=np.ascontiguousarray(m.cell_bar if m.cell_bar is not None
+                                              else np.full(m.n_tri, -1), dtype=np.int32),
             )
             self._keep.append(arrs)
             mesh_arr[k] = _abi.Mesh(
                 m.n_r, m.n_theta, m.n_nodes, m.n_tri,
                 _ptr(arrs["xy"], C.c_double), _ptr(arrs["tri"], C.c_int32),
                 _ptr(arrs["cell_mat"], C.c_int32), _ptr(arrs["cell_phase"], C.c_int32),
-                _ptr(arrs["cell_sign"], C.c_int32), _ptr(arrs["dirichlet"], C.c_uint8))
+                _ptr(arrs["cell_sign"], C.c_int32), _ptr(arrs["dirichlet"], C.c_uint8),
+                _ptr(arrs["cell_bar"], C.c_int32))
         nu, sigma, iron = material_arrays()
         mats = dict(nu=np.ascontiguousarray(nu), sigma=np.ascontiguousarray(sigma),
                     iron=np.ascontiguousarray(iron, dtype=np.int32))
@@ -70,6 +73,15 @@ class Solver:
             src.J0, src.amplitude, src.freq, src.f_carrier, src.phase_offset,
             (C.c_double * 3)(*src.phases), src.carrier_code, cfg.dt, cfg.n_steps,
             src.ramp_periods, {"pwm": 0, "sine": 1}[src.signal], src.t_start)
+        ct = cfg.circuit
+        if ct is not None:
+            phys.circuit = 1
+            phys.turns_density = ct.turns_density
+            phys.l_z = ct.l_z
+            phys.r_phase = ct.r_phase
+            phys.v0 = ct.v0
+            phys.n_bars = ct.n_bars if ct.rotor else 0
+            phys.ring_r = ct.ring_r
         self._mesh_arr = mesh_arr
         self._prob = _abi.Problem(len(self.meshes), mesh_arr, phys)
         par = _abi.Params()
@@ -106,11 +118,12 @@ class Solver:
         return n.value, N.value, nnz.value
 
     def kernel_shape(self, level):
-        """(rows per work-group, columns per lane, family, prefetch depth) of the
-        level's batched PCG kernels as the autotuner chose them; family 1 =
-        general sparse rows, 2 = diagonal window; depth = rows of loads in
-        flight per wave."""
-        shape = (C.c_int32 * 4)()
+        """(rows per work-group, columns per lane, family, prefetch depth, rows
+        per work-group of narrow column sets) of the level's batched PCG
+        kernels as the autotuner chose them; family 1 = general sparse rows,
+        2 = diagonal window; depth = rows of loads in flight per wave; the last
+        is 0 when narrow sets keep the first."""
+        shape = (C.c_int32 * 5)()
         _check(self._L, self._h, self._L.mgrit_level_info(self._h, level, None, None, None,
                                                           C.byref(shape)))
         return tuple(shape)
@@ -165,6 +178,17 @@ class Solver:
         out, outp = self._out(out, (N + 1,))
         _check(self._L, self._h, self._L.mgrit_joule_losses(self._h, outp))
         return out
+
+    def circuit_values(self, U):
+        """Stator currents [N, 3], bar voltages [N, nb] and bar currents [N, nb]
+        of the steps of a level-0 trajectory U [(N+1), n0] (Sec. 3.1)."""
+        ct = self.cfg.circuit
+        nb = (ct.n_bars if ct.rotor else 0) if ct is not None else 0
+        N, n0 = self.cfg.n_steps, self.n0
+        _, up = self._io(U, (N + 1, n0))
+        out = np.empty((N, 3 + 2 * nb))
+        _check(self._L, self._h, self._L.mgrit_circuit_values(self._h, up, out.ctypes.data_as(C.c_void_p)))
+        return out[:, :3], out[:, 3:3 + nb], out[:, 3 + nb:]
 
     def seq_solve(self, u0=None, out=None):
         n0, N = self.n0, self.cfg.n_steps

@@ -63,6 +63,11 @@ def test_mgrit_two_level_matches_oracle(cfg1_oracle):
         assert abs(a - b) <= 1e-9 * hist[0], (a, b)
     assert _rel(U, U_seq) <= MGRIT_GATE
     assert _rel(U, U_mg) <= MGRIT_GATE
+    # and at every time point (the oracle's own MGRIT iterate is within
+    # 8e-10 of sequential stepping at every point)
+    for ref in (U_seq, U_mg):
+        err = np.linalg.norm(U - ref, axis=1)[1:] / np.linalg.norm(ref, axis=1)[1:]
+        assert err.max() <= 1e-8, (int(np.argmax(err)), err.max())
     assert st["rho"][-1] <= cfg.mgrit_tol * st["rho"][0]
 
 
@@ -270,7 +275,7 @@ def test_prefetch_depth_gives_identical_iterates(precision):
     for depth in (1, 2, 4):
         s = _solver(cfg, pcg_tol=1e-12, precision=prec, pcg_kernel=2, pcg_prefetch=depth,
                     compact_columns=1, pcg_tol_eta=1e-3)
-        assert s.kernel_shape(0)[2:] == (2, depth)
+        assert s.kernel_shape(0)[2:4] == (2, depth)
         out.append(s.solve())
         s.close()
     for U, st in out[1:]:
@@ -280,8 +285,26 @@ def test_prefetch_depth_gives_identical_iterates(precision):
     assert _rel(out[0][0], U_seq) <= MGRIT_GATE
 
 
+def test_pinned_kernel_shape_is_used_and_matches_oracle():
+    """Rows per work-group, columns per lane, prefetch depth and narrow-set
+    rows pinned instead of autotuned (the hardware-counter runs): the level
+    reports exactly that shape and MGRIT still reaches the sequential solution."""
+    print("pinned kernel shape", flush=True)
+    cfg = config("cfg1", meshes=[LevelSpec(16, 126), LevelSpec(16, 126)])
+    H, _ = build(cfg)
+    U_seq = stepping.sequential(H.levels[0], np.zeros(H.levels[0].n), cfg.n_steps)
+    s = _solver(cfg, pcg_tol=1e-12, pcg_kernel=2, pcg_rows_per_block=32, pcg_cols_per_lane=2,
+                pcg_prefetch=2, pcg_rows_narrow=16)
+    assert s.kernel_shape(0) == (32, 2, 2, 2, 16)
+    U, st = s.solve()
+    s.close()
+    assert st["converged"]
+    assert _rel(U, U_seq) <= MGRIT_GATE
+
+
 @pytest.mark.parametrize("bad", [dict(pcg_prefetch=3), dict(warm_start=3), dict(residual_eta=1.0),
-                                 dict(residual_eta=-1e-3), dict(pcg_rows_narrow=48)])
+                                 dict(residual_eta=-1e-3), dict(pcg_rows_narrow=48),
+                                 dict(pcg_rows_per_block=48), dict(pcg_cols_per_lane=3)])
 def test_solver_parameters_are_validated(cfg1_oracle, bad):
     from paper_1912_03106_amd._abi import MgritError
     cfg = cfg1_oracle[0]
