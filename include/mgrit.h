@@ -213,11 +213,14 @@ typedef struct {
   int32_t m_coarse;           /* temporal coarsening factor between levels l >= 1 and l + 1 (Sec. 4.1:
                                * a large factor m on the first level, a small one below); 0 = m.
                                * n_steps must be divisible by m * m_coarse^(levels - 2) */
-  int32_t coarse_persistent;  /* nonlinear model, coarsest level's sequential solve: 0 = one
-                               * persistent work-group runs the whole Newton sweep (every Newton,
-                               * CG and step-length iteration on the device) when the level has
-                               * at most 16384 unknowns, 1 = always, -1 = never (batched kernels
-                               * step by step) */
+  int32_t coarse_persistent;  /* nonlinear model, coarse levels.  0 = one persistent work-group
+                               * runs the coarsest level's whole sequential Newton sweep (every
+                               * Newton, CG and step-length iteration on the device) when the
+                               * level has at most 16384 unknowns; 1 = that at any size, and in
+                               * addition one persistent work-group per column for batches of at
+                               * most 256 columns on levels >= 1 (FP64 inner CG; Newton and CG
+                               * iterations then counted per column; slower than the batched
+                               * kernels on the 32x256 level); -1 = never (batched kernels) */
   int32_t pcg_check_narrow;   /* PCG iterations between host reads of the active-column count for
                                * batches of at most 128 columns (coarse levels: no compaction, and
                                * each read is a device-to-host round trip); 0 = pcg_check_every;

@@ -60,6 +60,7 @@ struct LevelState {
   double* bvec = nullptr; // [n] right-hand side of one coarse step
   double* u0r = nullptr;  // [n] initial value restricted to this level's mesh (nested start)
   double* nl_ws = nullptr; // persistent Newton stepper workspace (coarsest nonlinear level)
+  double* nl_batch_ws = nullptr; // per-column persistent Newton workspaces of narrow batches (lazy)
   double* gemm_part = nullptr;   // partial sums of the stored-inverse product (intermediate levels)
   int64_t gemm_part_size = 0;
   // field-circuit coupling: coupling rows B^T and Z = A^-1 B^T ([n][k] each),
@@ -678,6 +679,43 @@ static int newton_solve(Handle& h, int level, LevelState& S, PcgWork& w, int nco
   return inner;
 }
 
+// Narrow batches on the coarse levels of the nonlinear model, on request
+// (coarse_persistent = 1): one persistent work-group per column runs the
+// column's whole damped Newton solve (every Newton, CG and step-length
+// iteration on the device), the same per-column solver as the coarsest
+// level's sequential sweep.  Measured on the nonlinear 64x512 workload
+// (8192 steps, 16-column batches on 32x256) it is slower than the batched
+// kernels (16.9 s against 11.0 s on that level): a column's CG then streams
+// through one compute unit, and 16 columns leave most of the chip idle.
+constexpr int kNarrowPersistentCols = 256;
+
+static bool narrow_persistent(const Handle& h, int l, const LevelState& S, int ncols) {
+  return S.nl.n_tri > 0 && l > 0 && ncols <= kNarrowPersistentCols && !h.noalloc && !h.col_amp &&
+         !h.col_dphi && h.eta_now == 0.0 && h.par.coarse_persistent == 1;
+}
+
+// x[:, c] (start on entry, result on exit) = Phi(u_in[:, c]); returns the CG
+// iterations summed over the columns.
+static int newton_narrow(Handle& h, int l, LevelState& S, PcgWork& w, int ncols, CView in,
+                         const int64_t* t_list, int64_t t_base, int64_t t_stride) {
+  hipStream_t s = h.stream;
+  const int64_t per = seq_newton_ws_doubles(S.n, S.op.W, S.nl.n_tri);
+  if (!S.nl_batch_ws)
+    S.nl_batch_ws = h.arena.alloc<double>(static_cast<size_t>(per) * kNarrowPersistentCols);
+  MG_HIP(hipMemsetAsync(w.flags, 0, 4 * sizeof(int), s));
+  launch_seq_newton_batch(s, S.op, S.nl, h.src, ncols, in, w.x, w.ld, t_list, t_base, t_stride,
+                          h.par.newton_tol, h.par.newton_max_iter, std::ldexp(1.0, -h.par.newton_halvings),
+                          h.par.ir_inner_tol, h.par.pcg_max_iter, S.nl_batch_ws, w.flags);
+  MG_HIP(hipMemcpyAsync(w.host_flags, w.flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  const int bits = w.host_flags[1];
+  if (bits & 1) fail(MGRIT_NONFINITE, "non-finite value in a Newton step");
+  if (bits & 8) fail(MGRIT_NEWTON_NOT_CONVERGED, "Newton did not converge in newton_max_iter iterations");
+  if (bits & 2) fail(MGRIT_PCG_NOT_CONVERGED, "an inner CG of a Newton step hit pcg_max_iter");
+  if (h.st && l < MGRIT_MAX_LEVELS) h.st->newton_sweeps[l] += w.host_flags[3];
+  return w.host_flags[2];
+}
+
 // One batched application of Phi on level l:
 //   x = Phi(u_in[:, c]) for c < ncols, input time index t_base + c*t_stride
 //   (or t_list[c]), initial guess x0 = ga + sgb * gb,
@@ -763,9 +801,12 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
                     S.gemm_part_size);
   } else {
     launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
-    it = S.nl.n_tri > 0
-             ? newton_solve(h, l, S, w, c.ncols, c.in, c.ga.p == c.in.p && c.gb.p == nullptr)
-             : pcg_solve(h, l, S.op, w, c.ncols, c.in);
+    if (S.nl.n_tri > 0 && narrow_persistent(h, l, S, c.ncols))
+      it = newton_narrow(h, l, S, w, c.ncols, c.in, c.t_list, c.t_base, c.t_stride);
+    else
+      it = S.nl.n_tri > 0
+               ? newton_solve(h, l, S, w, c.ncols, c.in, c.ga.p == c.in.p && c.gb.p == nullptr)
+               : pcg_solve(h, l, S.op, w, c.ncols, c.in);
   }
   // field-circuit coupling: the solve gave y = A^-1 (M/dt) u_in; eliminate
   // the circuit unknowns and add Z w

@@ -177,6 +177,14 @@ void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const
                        int nsteps, int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
                        int warm, double newton_tol, int newton_max, double lam_min, double inner_tol,
                        int cg_max, double* ws, int* flags, bool add_g = true);
+// The same per-column Newton for a narrow batch of independent steps, one
+// work-group per column: u_prev = uin[:, c], start and result in x[:, c], the
+// step from t_i to t_{i+1} with i = t_list[c] (or t_base + c t_stride); ws
+// holds ncols workspaces of seq_newton_ws_doubles each.
+void launch_seq_newton_batch(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
+                             int ncols, CView uin, double* x, int64_t ldx, const int64_t* t_list,
+                             int64_t t_base, int64_t t_stride, double newton_tol, int newton_max,
+                             double lam_min, double inner_tol, int cg_max, double* ws, int* flags);
 void launch_nl_pass_b(hipStream_t s, const DevLevel& L, PcgWork& w, NlWork& nw, int ncols);
 // u += fac[c] d on the columns with ls[c] set
 void launch_nl_update(hipStream_t s, PcgWork& w, NlWork& nw, int ncols);

@@ -748,26 +748,177 @@ __device__ double sn_residual(const SeqNewtonArgs& a, const double* u, const dou
   return nl_block_sum(acc, sh);
 }
 
+// Workspace of one column: x, xt, u_prev, R, r, p, q, y, S (n each), the
+// scaled Jacobian (n W), element fields (4 T).
+struct SnBufs {
+  double *x, *xt, *up, *R, *r, *p, *q, *y, *sc, *J, *gx, *gy, *nu, *dnu;
+};
+
+__device__ SnBufs sn_bufs(const SeqNewtonArgs& a, double* ws) {
+  const int n = a.n, T = a.n_tri;
+  SnBufs b;
+  b.x = ws;
+  b.xt = b.x + n;
+  b.up = b.xt + n;
+  b.R = b.up + n;
+  b.r = b.R + n;
+  b.p = b.r + n;
+  b.q = b.p + n;
+  b.y = b.q + n;
+  b.sc = b.y + n;
+  b.J = b.sc + n;
+  b.gx = b.J + static_cast<int64_t>(n) * a.W;
+  b.gy = b.gx + T;
+  b.nu = b.gy + T;
+  b.dnu = b.nu + T;
+  return b;
+}
+
+// One damped-Newton step of one column by the calling work-group: b.x holds
+// the start on entry and the solution on exit, b.up = u_prev, s0..s2 the
+// source values at the new time.  Returns the Newton iterations; on failure
+// sets the bits of a.flags[1] and *stop (shared).
+__device__ int sn_newton(const SeqNewtonArgs& a, const SnBufs& b, double s0, double s1, double s2,
+                         double* sh, int* stop, int* cg_its) {
+  const int n = a.n, W = a.W;
+  double* x = b.x;
+  double* xt = b.xt;
+  double* up = b.up;
+  double* R = b.R;
+  double* r = b.r;
+  double* p = b.p;
+  double* q = b.q;
+  double* y = b.y;
+  double* sc = b.sc;
+  double* J = b.J;
+  double *gx = b.gx, *gy = b.gy, *nu = b.nu, *dnu = b.dnu;
+  // reference ||R(u_prev)||^2, then the residual of the start
+  sn_elem(a, up, gx, gy, nu, dnu);
+  const double ref = sn_residual(a, up, up, s0, s1, s2, gx, gy, nu, R, sh);
+  sn_elem(a, x, gx, gy, nu, dnu);
+  double rcur = sn_residual(a, x, up, s0, s1, s2, gx, gy, nu, R, sh);
+  if (!isfinite(rcur) || !isfinite(ref)) {
+    if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); *stop = 1; }
+  }
+  __syncthreads();
+  if (*stop) return 0;
+  int k = 0;
+  while (rcur > a.tol2 * ref) {
+    if (k >= a.newton_max) {
+      if (threadIdx.x == 0) { atomicOr(a.flags + 1, 8); *stop = 1; }
+      break;
+    }
+    ++k;
+    // Jacobian at x (element fields of x are current), diag, scaling
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      for (int t = 0; t < W; ++t) {
+        const int64_t slot = static_cast<int64_t>(i) * W + t;
+        double v = a.mm[slot];
+        for (int qq = a.cptr[slot]; qq < a.cptr[slot + 1]; ++qq) {
+          const int code = a.contrib[qq];
+          const int e = code / 9, al = (code % 9) / 3, bl = code % 3;
+          const double* g = a.grad + 6 * e;
+          const double gag = g[2 * al] * gx[e] + g[2 * al + 1] * gy[e];
+          const double gbg = g[2 * bl] * gx[e] + g[2 * bl + 1] * gy[e];
+          v += a.area[e] * (nu[e] * (g[2 * al] * g[2 * bl] + g[2 * al + 1] * g[2 * bl + 1]) +
+                            2.0 * dnu[e] * gag * gbg);
+        }
+        J[slot] = v;
+        if (t == a.diag_slot[i]) sc[i] = 1.0 / sqrt(v);
+      }
+    }
+    __syncthreads();
+    // J^ = S J S; CG on J^ y = S (-R), y = 0
+    double lrr = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double si = sc[i];
+      for (int t = 0; t < W; ++t) {
+        const int64_t slot = static_cast<int64_t>(i) * W + t;
+        J[slot] = si * J[slot] * sc[a.col[slot]];
+      }
+      const double rv = -si * R[i];
+      r[i] = rv;
+      p[i] = rv;
+      y[i] = 0.0;
+      lrr += rv * rv;
+    }
+    double rr = nl_block_sum(lrr, sh);
+    const double rr0 = rr;
+    int it = 0;
+    while (rr > a.tin2 * rr0) {
+      if (it >= a.cg_max) {
+        if (threadIdx.x == 0) { atomicOr(a.flags + 1, 2); *stop = 1; }
+        break;
+      }
+      double lpq = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double sq = 0.0;
+        for (int t = 0; t < W; ++t) {
+          const int64_t slot = static_cast<int64_t>(i) * W + t;
+          sq += J[slot] * p[a.col[slot]];
+        }
+        q[i] = sq;
+        lpq += p[i] * sq;
+      }
+      const double pq = nl_block_sum(lpq, sh);
+      const double al = rr / pq;
+      double lr = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        y[i] += al * p[i];
+        const double rv = r[i] - al * q[i];
+        r[i] = rv;
+        lr += rv * rv;
+      }
+      const double rrn = nl_block_sum(lr, sh);
+      if (!isfinite(rrn)) {
+        if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); *stop = 1; }
+        break;
+      }
+      const double be = rrn / rr;
+      rr = rrn;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = r[i] + be * p[i];
+      __syncthreads();
+      ++it;
+    }
+    *cg_its += it;
+    __syncthreads();
+    if (*stop) break;
+    // damped update: the first lambda in 1, 1/2, ... with
+    // ||R(x + lambda d)|| < (1 - 1e-4 lambda) ||R(x)||, else lam_min
+    double lam = 1.0;
+    while (true) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) xt[i] = x[i] + lam * (sc[i] * y[i]);
+      __syncthreads();
+      sn_elem(a, xt, gx, gy, nu, dnu);
+      const double t = sn_residual(a, xt, up, s0, s1, s2, gx, gy, nu, R, sh);
+      const double shrink = 1.0 - 1e-4 * lam;
+      const bool ok = isfinite(t) && t < shrink * shrink * rcur;
+      if (ok || lam <= a.lam_min) {
+        if (!isfinite(t)) {
+          if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); *stop = 1; }
+        }
+        rcur = t;
+        break;
+      }
+      lam *= 0.5;
+    }
+    __syncthreads();
+    if (*stop) break;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = xt[i];
+    __syncthreads();
+    // the element fields and R now belong to x
+  }
+  __syncthreads();
+  return k;
+}
+
 __global__ __launch_bounds__(kSeqThreads) void k_seq_newton(SeqNewtonArgs a, SourceDev src) {
   __shared__ double sh[32];
   __shared__ double sgn[3];
   __shared__ int stop;
   if (threadIdx.x == 0) stop = 0;
-  const int n = a.n, W = a.W, T = a.n_tri;
-  double* x = a.ws;
-  double* xt = x + n;
-  double* up = xt + n;                       // u_prev of the step
-  double* R = up + n;
-  double* r = R + n;
-  double* p = r + n;
-  double* q = p + n;
-  double* y = q + n;
-  double* sc = y + n;
-  double* J = sc + n;                        // [n*W] scaled Jacobian
-  double* gx = J + static_cast<int64_t>(n) * W;
-  double* gy = gx + T;
-  double* nu = gy + T;
-  double* dnu = nu + T;
+  const int n = a.n;
+  const SnBufs b = sn_bufs(a, a.ws);
   int cg_total = 0, newton_total = 0;
   for (int s = 1; s <= a.nsteps; ++s) {
     if (threadIdx.x == 0) {
@@ -781,131 +932,14 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_newton(SeqNewtonArgs a, Sou
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       double g = a.warm ? a.U[i * a.ldu + s] : a.U[i * a.ldu + s - 1];
       if (a.warm && a.G) g -= a.G[i * a.ldg + s];
-      x[i] = g;
-      up[i] = a.U[i * a.ldu + s - 1];
+      b.x[i] = g;
+      b.up[i] = a.U[i * a.ldu + s - 1];
     }
     __syncthreads();
-    // reference ||R(u_prev)||^2, then the residual of the start
-    sn_elem(a, up, gx, gy, nu, dnu);
-    const double ref = sn_residual(a, up, up, s0, s1, s2, gx, gy, nu, R, sh);
-    sn_elem(a, x, gx, gy, nu, dnu);
-    double rcur = sn_residual(a, x, up, s0, s1, s2, gx, gy, nu, R, sh);
-    if (!isfinite(rcur) || !isfinite(ref)) {
-      if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); stop = 1; }
-    }
-    __syncthreads();
-    if (stop) break;
-    int k = 0;
-    while (rcur > a.tol2 * ref) {
-      if (k >= a.newton_max) {
-        if (threadIdx.x == 0) { atomicOr(a.flags + 1, 8); stop = 1; }
-        break;
-      }
-      ++k;
-      // Jacobian at x (element fields of x are current), diag, scaling
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        for (int t = 0; t < W; ++t) {
-          const int64_t slot = static_cast<int64_t>(i) * W + t;
-          double v = a.mm[slot];
-          for (int qq = a.cptr[slot]; qq < a.cptr[slot + 1]; ++qq) {
-            const int code = a.contrib[qq];
-            const int e = code / 9, al = (code % 9) / 3, bl = code % 3;
-            const double* g = a.grad + 6 * e;
-            const double gag = g[2 * al] * gx[e] + g[2 * al + 1] * gy[e];
-            const double gbg = g[2 * bl] * gx[e] + g[2 * bl + 1] * gy[e];
-            v += a.area[e] * (nu[e] * (g[2 * al] * g[2 * bl] + g[2 * al + 1] * g[2 * bl + 1]) +
-                              2.0 * dnu[e] * gag * gbg);
-          }
-          J[slot] = v;
-          if (t == a.diag_slot[i]) sc[i] = 1.0 / sqrt(v);
-        }
-      }
-      __syncthreads();
-      // J^ = S J S; CG on J^ y = S (-R), y = 0
-      double lrr = 0.0;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const double si = sc[i];
-        for (int t = 0; t < W; ++t) {
-          const int64_t slot = static_cast<int64_t>(i) * W + t;
-          J[slot] = si * J[slot] * sc[a.col[slot]];
-        }
-        const double rv = -si * R[i];
-        r[i] = rv;
-        p[i] = rv;
-        y[i] = 0.0;
-        lrr += rv * rv;
-      }
-      double rr = nl_block_sum(lrr, sh);
-      const double rr0 = rr;
-      int it = 0;
-      while (rr > a.tin2 * rr0) {
-        if (it >= a.cg_max) {
-          if (threadIdx.x == 0) { atomicOr(a.flags + 1, 2); stop = 1; }
-          break;
-        }
-        double lpq = 0.0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-          double sq = 0.0;
-          for (int t = 0; t < W; ++t) {
-            const int64_t slot = static_cast<int64_t>(i) * W + t;
-            sq += J[slot] * p[a.col[slot]];
-          }
-          q[i] = sq;
-          lpq += p[i] * sq;
-        }
-        const double pq = nl_block_sum(lpq, sh);
-        const double al = rr / pq;
-        double lr = 0.0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-          y[i] += al * p[i];
-          const double rv = r[i] - al * q[i];
-          r[i] = rv;
-          lr += rv * rv;
-        }
-        const double rrn = nl_block_sum(lr, sh);
-        if (!isfinite(rrn)) {
-          if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); stop = 1; }
-          break;
-        }
-        const double be = rrn / rr;
-        rr = rrn;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = r[i] + be * p[i];
-        __syncthreads();
-        ++it;
-      }
-      cg_total += it;
-      __syncthreads();
-      if (stop) break;
-      // damped update: the first lambda in 1, 1/2, ... with
-      // ||R(x + lambda d)|| < (1 - 1e-4 lambda) ||R(x)||, else lam_min
-      double lam = 1.0;
-      while (true) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) xt[i] = x[i] + lam * (sc[i] * y[i]);
-        __syncthreads();
-        sn_elem(a, xt, gx, gy, nu, dnu);
-        const double t = sn_residual(a, xt, up, s0, s1, s2, gx, gy, nu, R, sh);
-        const double shrink = 1.0 - 1e-4 * lam;
-        const bool ok = isfinite(t) && t < shrink * shrink * rcur;
-        if (ok || lam <= a.lam_min) {
-          if (!isfinite(t)) {
-            if (threadIdx.x == 0) { atomicOr(a.flags + 1, 1); stop = 1; }
-          }
-          rcur = t;
-          break;
-        }
-        lam *= 0.5;
-      }
-      __syncthreads();
-      if (stop) break;
-      for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = xt[i];
-      __syncthreads();
-      // the element fields and R now belong to x
-    }
-    newton_total += k;
-    __syncthreads();
+    newton_total += sn_newton(a, b, s0, s1, s2, sh, &stop, &cg_total);
     if (stop) break;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      double v = x[i];
+      double v = b.x[i];
       if (a.G && a.add_g) v += a.G[i * a.ldg + s];
       a.U[i * a.ldu + s] = v;
     }
@@ -917,6 +951,44 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_newton(SeqNewtonArgs a, Sou
   }
 }
 
+// Narrow batches of independent steps: work-group c takes column c,
+// u_prev = uin[:, c], the start and the result in x[:, c], the step from
+// t_{i_c} to t_{i_c + 1} with i_c = t_list[c] (or t_base + c t_stride).
+__global__ __launch_bounds__(kSeqThreads) void k_seq_newton_batch(SeqNewtonArgs a, SourceDev src,
+                                                                  const double* __restrict__ uin,
+                                                                  int64_t ldin, double* __restrict__ xio,
+                                                                  int64_t ldx,
+                                                                  const int64_t* __restrict__ t_list,
+                                                                  int64_t t_base, int64_t t_stride,
+                                                                  int64_t ws_stride) {
+  __shared__ double sh[32];
+  __shared__ double sgn[3];
+  __shared__ int stop;
+  const int c = blockIdx.x;
+  if (threadIdx.x == 0) {
+    stop = 0;
+    const int64_t i_from = t_list ? t_list[c] : t_base + static_cast<int64_t>(c) * t_stride;
+    const double t = static_cast<double>(i_from + 1) * a.dt;
+    const double amp = source_scale(t, src);
+    for (int k = 0; k < 3; ++k) sgn[k] = amp * pwm(t, src, k);
+  }
+  const int n = a.n;
+  const SnBufs b = sn_bufs(a, a.ws + static_cast<int64_t>(c) * ws_stride);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    b.x[i] = xio[static_cast<int64_t>(i) * ldx + c];
+    b.up[i] = uin[static_cast<int64_t>(i) * ldin + c];
+  }
+  __syncthreads();
+  int cg = 0;
+  const int nk = sn_newton(a, b, sgn[0], sgn[1], sgn[2], sh, &stop, &cg);
+  if (!stop)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) xio[static_cast<int64_t>(i) * ldx + c] = b.x[i];
+  if (threadIdx.x == 0) {
+    atomicAdd(a.flags + 2, cg);
+    atomicAdd(a.flags + 3, nk);
+  }
+}
+
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 }  // namespace
@@ -925,13 +997,10 @@ int64_t seq_newton_ws_doubles(int n, int W, int n_tri) {
   return 9LL * n + static_cast<int64_t>(n) * W + 4LL * n_tri;
 }
 
-void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
-                       int nsteps, int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
-                       int warm, double newton_tol, int newton_max, double lam_min, double inner_tol,
-                       int cg_max, double* ws, int* flags, bool add_g) {
-  if (nsteps <= 0) return;
-  SeqNewtonArgs a;
-  a.add_g = add_g ? 1 : 0;
+static SeqNewtonArgs seq_newton_args(const DevLevel& L, const NlLevel& N, double newton_tol,
+                                     int newton_max, double lam_min, double inner_tol, int cg_max,
+                                     double* ws, int* flags) {
+  SeqNewtonArgs a{};
   a.n = L.n;
   a.W = L.W;
   a.n_tri = N.n_tri;
@@ -951,13 +1020,6 @@ void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const
   a.k2 = N.k2;
   a.k3 = N.k3;
   a.dt = L.dt;
-  a.nsteps = nsteps;
-  a.t0 = t0;
-  a.U = U;
-  a.ldu = ldu;
-  a.G = G;
-  a.ldg = ldg;
-  a.warm = warm;
   a.tol2 = newton_tol * newton_tol;
   a.newton_max = newton_max;
   a.lam_min = lam_min;
@@ -965,6 +1027,34 @@ void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const
   a.cg_max = cg_max;
   a.ws = ws;
   a.flags = flags;
+  return a;
+}
+
+void launch_seq_newton_batch(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
+                             int ncols, CView uin, double* x, int64_t ldx, const int64_t* t_list,
+                             int64_t t_base, int64_t t_stride, double newton_tol, int newton_max,
+                             double lam_min, double inner_tol, int cg_max, double* ws, int* flags) {
+  if (ncols <= 0) return;
+  const SeqNewtonArgs a = seq_newton_args(L, N, newton_tol, newton_max, lam_min, inner_tol, cg_max, ws, flags);
+  hipLaunchKernelGGL(k_seq_newton_batch, dim3(ncols), dim3(kSeqThreads), 0, s, a, src, uin.p, uin.ld, x, ldx,
+                     t_list, t_base, t_stride, seq_newton_ws_doubles(L.n, L.W, N.n_tri));
+  MG_HIP(hipGetLastError());
+}
+
+void launch_seq_newton(hipStream_t s, const DevLevel& L, const NlLevel& N, const SourceDev& src,
+                       int nsteps, int64_t t0, double* U, int64_t ldu, const double* G, int64_t ldg,
+                       int warm, double newton_tol, int newton_max, double lam_min, double inner_tol,
+                       int cg_max, double* ws, int* flags, bool add_g) {
+  if (nsteps <= 0) return;
+  SeqNewtonArgs a = seq_newton_args(L, N, newton_tol, newton_max, lam_min, inner_tol, cg_max, ws, flags);
+  a.add_g = add_g ? 1 : 0;
+  a.nsteps = nsteps;
+  a.t0 = t0;
+  a.U = U;
+  a.ldu = ldu;
+  a.G = G;
+  a.ldg = ldg;
+  a.warm = warm;
   hipLaunchKernelGGL(k_seq_newton, dim3(1), dim3(kSeqThreads), 0, s, a, src);
   MG_HIP(hipGetLastError());
 }

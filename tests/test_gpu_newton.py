@@ -243,3 +243,26 @@ def test_newton_mgrit_coarsest_persistent_and_batched_agree(persistent):
         assert abs(a - b) <= 1e-8 * hist[0], (a, b)
     assert _rel(U, U_seq) <= 1e-7
     assert st["newton_sweeps"][1] > 0
+
+
+@pytest.mark.parametrize("B", [1, 17, 200])
+def test_newton_coarse_level_narrow_persistent_matches_oracle(nl_pair, B):
+    """Narrow batches on a coarse level (dt_1 = m dt): one persistent
+    work-group per column runs the whole damped Newton solve
+    (coarse_persistent = 1) or the batched kernels do (the default); both
+    reach the oracle's Newton solution."""
+    print(f"newton level-1 narrow persistent B={B}", flush=True)
+    cfg, _, U = nl_pair
+    lev1 = Level(polar_mesh(16, 128), cfg.level_dt(1), cfg.source, bh=cfg.bh, newton_maxit=MAXIT,
+                 newton_tol=ORACLE_TOL)
+    rng = np.random.default_rng(100 + B)
+    i_from = rng.integers(0, cfg.level_steps(1) - 1, size=B)
+    u_prev = U[rng.integers(5, U.shape[0], size=B)]
+    ref = lev1.phi(u_prev, i_from)
+    from paper_1912_03106_amd import _abi
+    for persistent in (1, 0):
+        s = _solver(cfg, precision=_abi.FP64, ir_inner_tol=1e-6, newton_tol=1e-12,
+                    newton_max_iter=GPU_MAXIT, coarse_persistent=persistent)
+        err = _col_err(s.phi(1, u_prev, i_from), ref)
+        s.close()
+        assert err.max() <= PHI_TOL, (persistent, err.max())
