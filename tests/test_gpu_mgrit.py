@@ -352,8 +352,9 @@ def full_horizon_oracle():
 
 @pytest.mark.parametrize("variant", ["fp64_timed", "fp32_ir"])
 def test_full_size_mgrit_whole_horizon_against_oracle(full_horizon_oracle, variant):
-    """The 64x512 / 16384-step / 3-level workload in the launch configuration
-    bench.py times (graph replay, no kernel timing), and its FP32 +
+    """The 64x512 / 16384-step / 3-level workload in the configuration
+    bench.py times (F-cycles from the nested-iteration start, graph replay, no
+    kernel timing), and its FP32 +
     refinement variant with the random guess: every C-point (and one F-point
     in every 64th interval) of the whole horizon against the oracle's
     sequential stepping, per time point."""
@@ -362,8 +363,9 @@ def test_full_size_mgrit_whole_horizon_against_oracle(full_horizon_oracle, varia
     idx, ref = full_horizon_oracle
     timed = dict(pcg_tol_eta=3e-3, warm_start=2, residual_eta=1e-4)
     if variant == "fp64_timed":
+        # F-cycles from the nested-iteration start, as timed
         cfg = config("cfg2")
-        s = _solver(cfg, **timed)
+        s = _solver(cfg, cycle=1, nested=1, **timed)
         assert s.params.use_graphs == 1 and s.params.profile_kernels == 0
         U, st = s.solve()
     else:
