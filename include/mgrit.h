@@ -164,7 +164,9 @@ typedef struct {
                                * (linear) / batched Newton kernels step by step (nonlinear),
                                * 3 linear model: exact steps with the finest level's stored
                                * inverse (built by the first call, n^2 doubles; the build time is
-                               * reported in time_nested_s) */
+                               * reported in time_nested_s).  With circuit = 1 every choice steps
+                               * with the batched step and its circuit elimination, one column at
+                               * a time. */
   int32_t use_graphs;         /* 1: replay each check interval of CG iterations from a captured
                                * hipGraph (not while profile_kernels = 1: launches stay eager so
                                * that HIP events time each pass) */

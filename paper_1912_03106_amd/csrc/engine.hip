@@ -1182,11 +1182,18 @@ static double max_relative_change(const std::vector<double>& p, const std::vecto
 static void nested_start(Handle& h) {
   const int L = static_cast<int>(h.lv.size());
   hipStream_t s = h.stream;
-  struct Signal {
+  struct Restore {
     Handle& h;
-    ~Signal() { h.src.signal = h.phys.signal; }
-  } restore{h};
+    bool learned_off;
+    ~Restore() {
+      h.src.signal = h.phys.signal;
+      h.learned_off = learned_off;
+    }
+  } restore{h, h.learned_off};
   h.src.signal = 1;
+  // the learned correction was trained on PWM-driven steps: the sine-driven
+  // start steps the coarsest level by implicit Euler
+  h.learned_off = true;
   h.tol_now = h.par.pcg_tol;
   h.eta_now = 0.0;
   LevelState& S0 = h.lv[0];

@@ -69,6 +69,30 @@ def test_nonlinear_three_level_sc_matches_oracle(nl3):
     assert min(st["newton_sweeps"][:3]) > 0
 
 
+def test_nonlinear_three_level_sc_nested_start(nl3):
+    """The nested-iteration start (Sec. 2.1, 4.1: the coarse problems driven by
+    the sine references, one V-cycle per level on the way up) in the nonlinear
+    hierarchy, as the nonlinear workloads are timed: the oracle's residual
+    history from its own nested guess, on the scale of the zero-start rho_0,
+    and the sequential solution."""
+    print("nonlinear 3-level SC nested start", flush=True)
+    from dataclasses import replace
+    cfg, U_seq, hist0 = nl3
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    Hs, _ = build(replace(cfg, source=replace(cfg.source, signal="sine")))
+    guess = mgrit.nested_iteration(Hs, np.zeros(n), cfg.n_steps)
+    _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=2, guess=guess)
+    U, st = _solver(cfg, nested=1, pcg_tol_eta=1e-3).solve()
+    assert st["converged"] and st["time_nested_s"] > 0
+    U2, st2 = _solver(cfg, nested=1).solve()
+    for a, b in zip(st2["rho"][:3], hist[:3]):
+        assert abs(a - b) <= 1e-8 * hist0[0], (a, b)
+    assert st2["rho"][0] < hist0[0]
+    assert _rel(U, U_seq) <= MGRIT_GATE
+    assert _rel(U2, U_seq) <= MGRIT_GATE
+
+
 def test_nonlinear_three_level_sc_early_stop(nl3):
     """The nonlinear workloads' level-0 early stop (eta = 1e-3): same fixed point."""
     print("nonlinear 3-level SC early stop", flush=True)
