@@ -273,7 +273,7 @@ class Budget:
         return False
 
 
-def seq_windows(cfg_name, base, U, starts, width, stream, label):
+def seq_windows(cfg_name, base, U, starts, width, stream, label, circuit=None):
     """GPU sequential stepping on windows of `width` steps starting at the
     points `starts` of the horizon of `base`, each from the MGRIT state U[i0]
     (U: the MGRIT iterate, a device tensor [(N_t+1), n0]) with the source's
@@ -287,7 +287,7 @@ def seq_windows(cfg_name, base, U, starts, width, stream, label):
     per_step, worst, wins = [], 0.0, []
     for i0 in starts:
         wcfg = config(cfg_name, n_steps=width, t_final=width * base.dt,
-                      source=replace(base.source, t_start=i0 * base.dt))
+                      source=replace(base.source, t_start=i0 * base.dt), circuit=circuit)
         wcfg.meshes = base.meshes[:1] * 2
         s = Solver(wcfg, stream=stream.cuda_stream, device_io=True)
         out = torch.empty((width + 1, s.n0), dtype=torch.float64, device="cuda")
@@ -312,14 +312,14 @@ def seq_windows(cfg_name, base, U, starts, width, stream, label):
             "mgrit_deviation_in_windows": worst}
 
 
-def seq_inverse(base, U, width, stream):
+def seq_inverse(base, U, width, stream, circuit=None):
     """GPU sequential stepping of the linear workload with the finest level's
     stored inverse (seq_kernel = 3) on the first `width` steps: build time,
     time per step (the same for every step) and its full-horizon estimate."""
     import torch
     from workload import config
     from paper_1912_03106_amd.solver import Solver
-    wcfg = config("cfg2", n_steps=width, t_final=width * base.dt)
+    wcfg = config("cfg2", n_steps=width, t_final=width * base.dt, circuit=circuit)
     wcfg.meshes = base.meshes[:1] * 2
     s = Solver(wcfg, stream=stream.cuda_stream, device_io=True, seq_kernel=3)
     out = torch.empty((width + 1, s.n0), dtype=torch.float64, device="cuda")
@@ -338,6 +338,61 @@ def seq_inverse(base, U, width, stream):
             "steps_run": width, "inverse_build_s": round(build, 2), "ms_per_step": round(1e3 * step, 3),
             "time_s_full_horizon_estimate": round(build + step * base.n_steps, 1),
             "mgrit_deviation": dev}
+
+
+CIRCUIT_STEPS = 4096      # the field-circuit leg: the first quarter of the 16384-step horizon
+
+
+def circuit_leg(stream, seq_width=32):
+    """The linear workload with the field-circuit coupling (voltage-driven
+    stranded stator coils, rotor bars joined by resistive end rings) on the
+    first CIRCUIT_STEPS steps: MGRIT with F-cycles from the nested start and
+    every solve to 1e-12 (coupled steps take no early stop), the set-up
+    (coupling solves Z = A^-1 B^T per level), the peak currents, and the
+    deviation from GPU sequential stepping of the coupled model on four
+    windows spread over the horizon."""
+    import torch
+    from workload import config, Circuit
+    from paper_1912_03106_amd.solver import Solver
+    full = config("cfg2")
+    cfg = config("cfg2", circuit=Circuit(), n_steps=CIRCUIT_STEPS, t_final=CIRCUIT_STEPS * full.dt)
+    log("field-circuit: setup")
+    t_set = time.perf_counter()
+    s = Solver(cfg, stream=stream.cuda_stream, device_io=True, warm_start=2, cycle=1, nested=1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_set
+    out = torch.empty((cfg.n_steps + 1, s.n0), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = s.solve(out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    i1, v2, i2 = s.circuit_values(out)
+    s.close()
+    rho = st["rho"]
+    log(f"field-circuit: {len(rho) - 1} iterations, {t:.2f} s")
+    N = cfg.n_steps
+    rec = {"workload": f"the linear 64x512 workload, first {N} of 16384 steps, with voltage-driven "
+                       "stranded stator coils (325 V PWM, 1.5 ohm) and 28 rotor bars joined by resistive "
+                       "end rings; 3-level F-cycles from the nested start, every solve to 1e-12",
+           "time_to_solution_s": round(t, 3), "iterations": len(rho) - 1, "rho_rel_final": rho[-1] / rho[0],
+           "setup_s": round(setup_s, 2), "dof_steps_per_s": round(32256 * N / t, 1),
+           "stator_current_peak_a": round(float(abs(i1).max()), 2),
+           "bar_current_peak_a": round(float(abs(i2).max()), 1)}
+    rec["gpu_sequential"] = seq_windows("cfg2", cfg, out, [N // 8, 3 * N // 8, 5 * N // 8, 7 * N // 8],
+                                        seq_width, stream, "field-circuit sequential", circuit=cfg.circuit)
+    rec["gpu_sequential"]["kernel"] = "the batched step and its circuit elimination on one column (1e-12)"
+    # the same stepping with the level's stored inverse (exact steps) and the
+    # circuit elimination after each
+    inv = seq_inverse(cfg, out, 1024, stream, circuit=cfg.circuit)
+    inv["kernel"] = ("exact implicit-Euler steps by the stored FP64 inverse, then the circuit "
+                     "elimination")
+    rec["gpu_sequential"]["stored_inverse"] = inv
+    ref = min(rec["gpu_sequential"]["time_s_full_horizon_estimate"], inv["time_s_full_horizon_estimate"])
+    rec["gpu_sequential"]["fastest_full_horizon_s"] = ref
+    rec["speedup_vs_gpu_sequential"] = round(ref / t, 3)
+    del out
+    return rec
 
 
 NL_ETA = 1e-3            # nonlinear level-0 relaxation: stop at eta times the start residual
@@ -474,6 +529,10 @@ def main():
     ap.add_argument("--nonlinear", type=int, default=0, metavar="N",
                     help="instead: only the saturating-iron workload on its first N steps (N "
                          "divisible by 256), with the learned coarse propagator too")
+    ap.add_argument("--no-circuit", action="store_true", help="skip the field-circuit leg")
+    ap.add_argument("--circuit", action="store_true",
+                    help="instead: only the field-circuit leg (the timed linear workload with "
+                         "voltage-driven coils and the rotor cage)")
     ap.add_argument("--nl-skip-learned", action="store_true",
                     help="with --nonlinear: skip the learned coarse propagator run")
     ap.add_argument("--nl-profile", action="store_true",
@@ -521,6 +580,9 @@ def main():
     if args.nonlinear:
         print(json.dumps(nonlinear_leg(args.nonlinear, stream, learned=not args.nl_skip_learned,
                                        profile=args.nl_profile)), flush=True)
+        return
+    if args.circuit:
+        print(json.dumps(circuit_leg(stream)), flush=True)
         return
 
     # headline: timed solves, check intervals of CG iterations replayed from
@@ -659,6 +721,9 @@ def main():
             cpu["gpu_deviation_on_sample"]["plain_fp64"] = oracle_deviation(kept, U)
         vs.close()
         del vout, U
+    circ = None
+    if not args.no_circuit and budget.fits("field-circuit", 55.0):
+        circ = circuit_leg(stream)
     if nl is not None and budget.fits("nonlinear learned", 2.2 * nl["implicit_euler"]["time_to_solution_s"] + 60.0):
         nl["learned"] = nonlinear_leg(config("cfg5").n_steps, stream, budget=budget, learned=True,
                                       ie=False).get("learned")
@@ -691,6 +756,7 @@ def main():
                   "autotuned_kernels": shapes},
         "nonlinear": nl,
         "variants": variants or None,
+        "field_circuit": circ,
         "gpu_sequential": seq,
         "skipped": budget.skipped or None,
         "wall_s": round(time.perf_counter() - T_START, 1),

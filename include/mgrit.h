@@ -107,7 +107,9 @@ typedef struct {
    * periodic path Laplacian over the bars.  No circuit inductance: the
    * currents and voltages are algebraic, fixed by two consecutive states, so
    * MGRIT's state stays the vector potential.  With n_bars = 0 the bar cells
-   * are plain conductors (bar voltages 0), as with circuit = 0. */
+   * are plain conductors (bar voltages 0), as with circuit = 0.  Coupled steps
+   * ignore pcg_tol_eta and residual_eta: the elimination multiplies the error
+   * of an early-stopped solve and the relaxation diverges. */
   int32_t circuit;            /* 0: current-driven coils (sign * J0 * amplitude * b_p); 1: coupled */
   double turns_density;       /* turns per m^2 of slot (> 0 with circuit = 1) */
   double l_z;                 /* axial length, m (> 0) */
@@ -164,9 +166,9 @@ typedef struct {
                                * (linear) / batched Newton kernels step by step (nonlinear),
                                * 3 linear model: exact steps with the finest level's stored
                                * inverse (built by the first call, n^2 doubles; the build time is
-                               * reported in time_nested_s).  With circuit = 1 every choice steps
-                               * with the batched step and its circuit elimination, one column at
-                               * a time. */
+                               * reported in time_nested_s).  With circuit = 1 the choices 0-2 step
+                               * with the batched step and its circuit elimination one column at a
+                               * time; 3 eliminates the circuit unknowns after each inverse step. */
   int32_t use_graphs;         /* 1: replay each check interval of CG iterations from a captured
                                * hipGraph (not while profile_kernels = 1: launches stay eager so
                                * that HIP events time each pass) */

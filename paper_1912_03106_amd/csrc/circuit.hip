@@ -77,6 +77,10 @@ __global__ __launch_bounds__(kBlock) void k_circ_dots(int n, int k, int ncols,
   for (int j = 0; j < kCircMax; ++j) acc[j] = 0.0;
   const int i0 = p * kCircRowsPerWave;
   const int i1 = (i0 + kCircRowsPerWave < n) ? i0 + kCircRowsPerWave : n;
+  // unrolled so that several rows' loads are in flight (narrow batches, one
+  // column in sequential stepping, are latency-bound); the order of the sums
+  // is unchanged
+#pragma unroll 8
   for (int i = i0; i < i1; ++i) {
     const double d = y[static_cast<int64_t>(i) * ldy + c] - a[static_cast<int64_t>(i) * lda + c];
     const double* b = Bt + static_cast<int64_t>(i) * k;
@@ -96,6 +100,7 @@ __global__ void k_circ_sum(int k, int ncols, int nparts, const double* __restric
   const int j = blockIdx.y;
   if (c >= ncols || j >= k) return;
   double t = 0.0;
+#pragma unroll 8
   for (int p = 0; p < nparts; ++p) t += part[(static_cast<int64_t>(p) * k + j) * ldp + c];
   d[static_cast<int64_t>(j) * ldd + c] = t;
 }
@@ -132,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_circ_apply(int n, int k, int ncols,
   for (int j = 0; j < kCircMax; ++j) wc[j] = (j < k) ? w[static_cast<int64_t>(j) * ldw + c] : 0.0;
   const int i0 = (blockIdx.y * 4 + wv) * kWave;
   const int i1 = (i0 + kWave < n) ? i0 + kWave : n;
+#pragma unroll 4
   for (int i = i0; i < i1; ++i) {
     const double* z = Z + static_cast<int64_t>(i) * k;
     double t = 0.0;

@@ -768,16 +768,22 @@ static void circuit_buffers(Handle& h, LevelState& S, int ncols) {
   S.c_ld = ld;
 }
 
-// a' = y + Z w, w = S^-1 (v(t'); 0) - S^-1 (l_z/dt) E B^T' (y - u_in) per column
-// (y in w.x on entry, a' on exit; the phase voltages are the source table).
-static void circuit_step(Handle& h, LevelState& S, PcgWork& w, const PhiCall& c) {
+// a' = y + Z w, w = S^-1 (v(t'); 0) - S^-1 (l_z/dt) E B (y - u_in) per column
+// (y[:, c] at y[i * ldy + c] on entry, a' on exit; the phase voltages are the
+// source table src[q * lds + c]).
+static void circuit_eliminate(Handle& h, LevelState& S, int ncols, double* y, int64_t ldy, CView in,
+                              const double* src, int64_t lds) {
   hipStream_t s = h.stream;
-  circuit_buffers(h, S, c.ncols);
+  circuit_buffers(h, S, ncols);
   const int k = h.circ_k;
-  launch_circ_dots(s, S.n, k, c.ncols, S.cBt, CView{w.x, w.ld}, c.in, S.cpart, S.c_ld);
-  launch_circ_sum(s, k, c.ncols, circ_parts(S.n), S.cpart, S.c_ld, S.cd, S.c_ld);
-  launch_circ_solve(s, k, c.ncols, S.cd, S.c_ld, w.src, w.ld, S.cS, S.cw, S.c_ld);
-  launch_circ_apply(s, S.n, k, c.ncols, S.cZ, S.cw, S.c_ld, w.x, w.ld);
+  launch_circ_dots(s, S.n, k, ncols, S.cBt, CView{y, ldy}, in, S.cpart, S.c_ld);
+  launch_circ_sum(s, k, ncols, circ_parts(S.n), S.cpart, S.c_ld, S.cd, S.c_ld);
+  launch_circ_solve(s, k, ncols, S.cd, S.c_ld, src, lds, S.cS, S.cw, S.c_ld);
+  launch_circ_apply(s, S.n, k, ncols, S.cZ, S.cw, S.c_ld, y, ldy);
+}
+
+static void circuit_step(Handle& h, LevelState& S, PcgWork& w, const PhiCall& c) {
+  circuit_eliminate(h, S, c.ncols, w.x, w.ld, c.in, w.src, w.ld);
 }
 
 static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
@@ -801,6 +807,16 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
                     S.gemm_part_size);
   } else {
     launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
+    // field-circuit coupling: the elimination multiplies the error of the
+    // solve (the circuit rows weigh B (a' - a) with l_z / dt), so an
+    // early-stopped relaxation solve diverges over an F-sweep; coupled steps
+    // always solve to pcg_tol
+    struct EtaOff {
+      Handle& h;
+      double keep;
+      ~EtaOff() { h.eta_now = keep; }
+    } eta_off{h, h.eta_now};
+    if (h.circ) h.eta_now = 0.0;
     if (S.nl.n_tri > 0 && narrow_persistent(h, l, S, c.ncols))
       it = newton_narrow(h, l, S, w, c.ncols, c.in, c.t_list, c.t_base, c.t_stride);
     else
@@ -1914,7 +1930,7 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
   auto t0 = std::chrono::steady_clock::now();
   const bool nl_persistent = S0.nl.n_tri > 0 &&
                              (h.par.seq_kernel == 1 || (h.par.seq_kernel == 0 && S0.n <= 4096));
-  if (h.par.seq_kernel == 3 && !h.circ) {
+  if (h.par.seq_kernel == 3) {
     // linear model: every step is exact implicit Euler with the level's
     // stored inverse, one stream of A^{-1} per step (built here on first use)
     if (S0.nl.n_tri > 0) fail(MGRIT_UNSUPPORTED, "seq_kernel = 3 needs the linear model");
@@ -1931,6 +1947,8 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
       launch_source_table(s, h.src, S0.op.dt, 1, nullptr, st_i - 1, 0, w.src, w.ld);
       launch_ie_rhs_batch(s, S0.op, 1, w.src, w.ld, CView{U + st_i - 1, ld}, S0.bvec, 1);
       launch_inv_gemv(s, S0.n, S0.Ainv, S0.ld_inv, S0.bvec, w.x);
+      // field-circuit coupling: eliminate the circuit unknowns of the step
+      if (h.circ) circuit_eliminate(h, S0, 1, w.x, 1, CView{U + st_i - 1, ld}, w.src, w.ld);
       launch_axpby3(s, S0.n, 1, U + st_i, ld, 1.0, CView{w.x, 1}, 0.0, CView{}, 0.0, CView{});
     }
     MG_HIP(hipStreamSynchronize(s));

@@ -95,10 +95,14 @@ def test_coupled_step_without_rotor_circuit():
     assert err.max() <= PHI_TOL, err.max()
 
 
-def test_sequential_solve_with_circuit(two_level):
-    print("circuit seq solve", flush=True)
+@pytest.mark.parametrize("seq_kernel", [0, 3])
+def test_sequential_solve_with_circuit(two_level, seq_kernel):
+    """Sequential stepping of the coupled model: the batched step one column
+    at a time, or exact steps by the level's stored inverse, each followed by
+    the circuit elimination."""
+    print(f"circuit seq solve kernel {seq_kernel}", flush=True)
     cfg, _, U_seq, _ = two_level
-    s = _solver(cfg, pcg_tol=PCG_TOL)
+    s = _solver(cfg, pcg_tol=PCG_TOL, seq_kernel=seq_kernel)
     U, _ = s.seq_solve()
     s.close()
     err = np.linalg.norm(U - U_seq, axis=1)[1:] / np.linalg.norm(U_seq, axis=1)[1:]
@@ -177,3 +181,31 @@ def test_circuit_settings_are_validated(two_level):
     with pytest.raises(MgritError, match="UNSUPPORTED"):
         plain.circuit_values(np.zeros((plain.cfg.n_steps + 1, plain.n0)))
     plain.close()
+
+
+def test_mgrit_circuit_f_cycle_nested_matches_oracle():
+    """Three levels with spatial coarsening, F-cycles from the nested-iteration
+    start (the sine references as the phase voltages, Sec. 4.1), as the
+    field-circuit leg of the benchmark runs: the oracle's residual history
+    from its own nested guess on the scale of the zero-start rho_0, and the
+    sequential solution at every time point."""
+    print("circuit mgrit F-cycle nested", flush=True)
+    from dataclasses import replace
+    cfg = _sc_cfg()
+    H, _ = build(cfg)
+    n = H.levels[0].n
+    U_seq = stepping.sequential(H.levels[0], np.zeros(n), cfg.n_steps)
+    Hs, _ = build(replace(cfg, source=replace(cfg.source, signal="sine")))
+    guess = mgrit.nested_iteration(Hs, np.zeros(n), cfg.n_steps)
+    H.cycle = "F"
+    _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=3, guess=guess)
+    _, hist0, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=0)
+    # the timed solver settings: the early stops are not applied to coupled
+    # steps, so the history still follows the oracle's
+    U, st = _solver(cfg, pcg_tol=PCG_TOL, cycle=1, nested=1, warm_start=2, pcg_tol_eta=3e-3,
+                    residual_eta=1e-4).solve()
+    assert st["converged"] and st["time_nested_s"] > 0
+    for a, b in zip(st["rho"][:4], hist[:4]):
+        assert abs(a - b) <= 2e-9 * hist0[0], (a, b)
+    err = np.linalg.norm(U - U_seq, axis=1)[1:] / np.linalg.norm(U_seq, axis=1)[1:]
+    assert err.max() <= MGRIT_GATE, err.max()
