@@ -92,6 +92,9 @@ struct Handle {
   double* seq_U = nullptr;        // sequential trajectory [n0][ld] (lazy)
   double* seq_ws = nullptr;
   double* seq_nl_ws = nullptr;    // persistent Newton stepper of the sequential solve (lazy)
+  double* seq_inv = nullptr;      // finest level's A^-1 of the stored-inverse sequential solve (lazy)
+  int64_t seq_ld_inv = 0;
+  double* seq_bvec = nullptr;
   int coop_blocks = 0;            // cooperative stepper (lazy)
   double* coop_ws = nullptr;
   double* coop_part = nullptr;
@@ -1934,9 +1937,16 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
     // linear model: every step is exact implicit Euler with the level's
     // stored inverse, one stream of A^{-1} per step (built here on first use)
     if (S0.nl.n_tri > 0) fail(MGRIT_UNSUPPORTED, "seq_kernel = 3 needs the linear model");
-    if (!S0.Ainv) {
+    if (!h.seq_inv) {
       const auto tb = std::chrono::steady_clock::now();
       build_coarse_inverse(h, S0);
+      // kept apart from the level: the MGRIT solve of this handle still
+      // steps level 0 by its batched solves
+      h.seq_inv = S0.Ainv;
+      h.seq_ld_inv = S0.ld_inv;
+      h.seq_bvec = S0.bvec;
+      S0.Ainv = nullptr;
+      S0.bvec = nullptr;
       st->time_nested_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
     }
     PcgWork& w = S0.pcg;
@@ -1945,8 +1955,8 @@ static void seq_impl(Handle& h, const double* u0, double* u_out, mgrit_stats* st
       // right-hand side and result as contiguous vectors (stride 1), so that
       // the product streams A^{-1} and the right-hand side coalesced
       launch_source_table(s, h.src, S0.op.dt, 1, nullptr, st_i - 1, 0, w.src, w.ld);
-      launch_ie_rhs_batch(s, S0.op, 1, w.src, w.ld, CView{U + st_i - 1, ld}, S0.bvec, 1);
-      launch_inv_gemv(s, S0.n, S0.Ainv, S0.ld_inv, S0.bvec, w.x);
+      launch_ie_rhs_batch(s, S0.op, 1, w.src, w.ld, CView{U + st_i - 1, ld}, h.seq_bvec, 1);
+      launch_inv_gemv(s, S0.n, h.seq_inv, h.seq_ld_inv, h.seq_bvec, w.x);
       // field-circuit coupling: eliminate the circuit unknowns of the step
       if (h.circ) circuit_eliminate(h, S0, 1, w.x, 1, CView{U + st_i - 1, ld}, w.src, w.ld);
       launch_axpby3(s, S0.n, 1, U + st_i, ld, 1.0, CView{w.x, 1}, 0.0, CView{}, 0.0, CView{});

@@ -47,6 +47,12 @@ def test_seq_solve_matches_oracle(cfg1_oracle, seq_kernel):
     assert U.shape == U_seq.shape
     err = np.linalg.norm(U - U_seq, axis=1)[1:] / np.linalg.norm(U_seq, axis=1)[1:]
     assert err.max() <= SEQ_TOL, err.max()
+    if seq_kernel == 3:
+        # the inverse built for the sequential solve leaves the handle's MGRIT
+        # solve on its batched level-0 solves
+        U2, st2 = s.solve()
+        assert st2["converged"] and st2["pcg_sweeps"][0] > 0
+        assert _rel(U2, U_seq) <= MGRIT_GATE
 
 
 def test_mgrit_two_level_matches_oracle(cfg1_oracle):
