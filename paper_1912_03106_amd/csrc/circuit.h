@@ -35,6 +35,11 @@ int circ_parts(int n);
 // Bt row-major [n][k]; ldp >= ncols.
 void launch_circ_dots(hipStream_t s, int n, int k, int ncols, const double* Bt, CView y, CView a,
                       double* part, int64_t ldp);
+// The same partials plus those of Z^T r, r = (M/dt) a - A y the residual of an
+// inexact solve for y (L's rows, Z row-major [n][k]): the circuit rows of the
+// exact step, whatever the solve left.
+void launch_circ_dots_res(hipStream_t s, const DevLevel& L, int k, int ncols, const double* Bt,
+                          const double* Z, CView y, CView a, double* part, int64_t ldp);
 // d[j][c] = sum over p in order of part[p][j][c].
 void launch_circ_sum(hipStream_t s, int k, int ncols, int nparts, const double* part, int64_t ldp,
                      double* d, int64_t ldd);

@@ -94,6 +94,55 @@ __global__ __launch_bounds__(kBlock) void k_circ_dots(int n, int k, int ncols,
     if (j < k) o[static_cast<int64_t>(j) * ldp] = acc[j];
 }
 
+// As k_circ_dots, with the residual of the step's inexact solve folded in.
+// The solve left y with A y = (M/dt) a - r, r its residual (recomputed here
+// row by row); A is symmetric, so the error of y seen by the circuit rows is
+// B A^-1 r = Z^T r, and the exact B (y* - a) is B (y - a) + Z^T r:
+//   part[p][j][c] = sum_i Bt[i][j] (y - a)[i][c] + Z[i][j] r[i][c], rows in order.
+// The circuit unknowns then carry no error of the solve, and a' = y + Z w
+// differs from the exact step by the solve's own error only.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_circ_dots_res(
+    int n, int k, int ncols, const double* __restrict__ Bt, const double* __restrict__ Z,
+    const int* __restrict__ col, const double* __restrict__ av, const double* __restrict__ mm,
+    const uint8_t* __restrict__ has_mass, const double* __restrict__ y, int64_t ldy,
+    const double* __restrict__ a, int64_t lda, double* __restrict__ part, int64_t ldp, int nparts) {
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int c = blockIdx.x * kWave + lane;
+  const int p = blockIdx.y * 4 + wv;
+  if (p >= nparts || c >= ncols) return;
+  double acc[kCircMax];
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j) acc[j] = 0.0;
+  const int i0 = p * kCircRowsPerWave;
+  const int i1 = (i0 + kCircRowsPerWave < n) ? i0 + kCircRowsPerWave : n;
+#pragma unroll 2
+  for (int i = i0; i < i1; ++i) {
+    const int* ci = col + static_cast<int64_t>(i) * W;
+    double bv = 0.0;
+    if (has_mass[i]) {
+      const double* mi = mm + static_cast<int64_t>(i) * W;
+#pragma unroll
+      for (int t = 0; t < W; ++t) bv += mi[t] * a[static_cast<int64_t>(ci[t]) * lda + c];
+    }
+    const double* ai = av + static_cast<int64_t>(i) * W;
+    double ax = 0.0;
+#pragma unroll
+    for (int t = 0; t < W; ++t) ax += ai[t] * y[static_cast<int64_t>(ci[t]) * ldy + c];
+    const double r = bv - ax;
+    const double d = y[static_cast<int64_t>(i) * ldy + c] - a[static_cast<int64_t>(i) * lda + c];
+    const double* b = Bt + static_cast<int64_t>(i) * k;
+    const double* z = Z + static_cast<int64_t>(i) * k;
+#pragma unroll
+    for (int j = 0; j < kCircMax; ++j)
+      if (j < k) acc[j] = fma(z[j], r, fma(b[j], d, acc[j]));
+  }
+  double* o = part + static_cast<int64_t>(p) * k * ldp + c;
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j)
+    if (j < k) o[static_cast<int64_t>(j) * ldp] = acc[j];
+}
+
 __global__ void k_circ_sum(int k, int ncols, int nparts, const double* __restrict__ part, int64_t ldp,
                            double* __restrict__ d, int64_t ldd) {
   const int c = blockIdx.x * kWave + static_cast<int>(threadIdx.x);
@@ -168,6 +217,18 @@ void launch_circ_dots(hipStream_t s, int n, int k, int ncols, const double* Bt, 
   const int np = circ_parts(n);
   hipLaunchKernelGGL(k_circ_dots, dim3(cdiv(ncols, kWave), cdiv(np, 4)), dim3(kBlock), 0, s, n, k, ncols,
                      Bt, y.p, y.ld, a.p, a.ld, part, ldp, np);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_circ_dots_res(hipStream_t s, const DevLevel& L, int k, int ncols, const double* Bt,
+                          const double* Z, CView y, CView a, double* part, int64_t ldp) {
+  if (ncols <= 0 || L.n <= 0) return;
+  if (k < 1 || k > kCircMax || ldp < ncols) fail(MGRIT_INVALID_ARGUMENT, "circuit dots: bad sizes");
+  if (L.W != 8 && L.W != 16) fail(MGRIT_INVALID_ARGUMENT, "circuit dots: unsupported row width");
+  const int np = circ_parts(L.n);
+  auto kern = (L.W == 8) ? k_circ_dots_res<8> : k_circ_dots_res<16>;
+  hipLaunchKernelGGL(kern, dim3(cdiv(ncols, kWave), cdiv(np, 4)), dim3(kBlock), 0, s, L.n, k, ncols, Bt, Z,
+                     L.col, L.a64, L.m64, L.has_mass, y.p, y.ld, a.p, a.ld, part, ldp, np);
   MG_HIP(hipGetLastError());
 }
 

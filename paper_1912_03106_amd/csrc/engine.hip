@@ -774,19 +774,25 @@ static void circuit_buffers(Handle& h, LevelState& S, int ncols) {
 // a' = y + Z w, w = S^-1 (v(t'); 0) - S^-1 (l_z/dt) E B (y - u_in) per column
 // (y[:, c] at y[i * ldy + c] on entry, a' on exit; the phase voltages are the
 // source table src[q * lds + c]).
+// inexact = true: y comes from an iterative solve, and the dots take its
+// residual into account (Z^T r), so that the error of the solve is not
+// multiplied by the elimination.
 static void circuit_eliminate(Handle& h, LevelState& S, int ncols, double* y, int64_t ldy, CView in,
-                              const double* src, int64_t lds) {
+                              const double* src, int64_t lds, bool inexact = false) {
   hipStream_t s = h.stream;
   circuit_buffers(h, S, ncols);
   const int k = h.circ_k;
-  launch_circ_dots(s, S.n, k, ncols, S.cBt, CView{y, ldy}, in, S.cpart, S.c_ld);
+  if (inexact)
+    launch_circ_dots_res(s, S.op, k, ncols, S.cBt, S.cZ, CView{y, ldy}, in, S.cpart, S.c_ld);
+  else
+    launch_circ_dots(s, S.n, k, ncols, S.cBt, CView{y, ldy}, in, S.cpart, S.c_ld);
   launch_circ_sum(s, k, ncols, circ_parts(S.n), S.cpart, S.c_ld, S.cd, S.c_ld);
   launch_circ_solve(s, k, ncols, S.cd, S.c_ld, src, lds, S.cS, S.cw, S.c_ld);
   launch_circ_apply(s, S.n, k, ncols, S.cZ, S.cw, S.c_ld, y, ldy);
 }
 
 static void circuit_step(Handle& h, LevelState& S, PcgWork& w, const PhiCall& c) {
-  circuit_eliminate(h, S, c.ncols, w.x, w.ld, c.in, w.src, w.ld);
+  circuit_eliminate(h, S, c.ncols, w.x, w.ld, c.in, w.src, w.ld, S.Ainv == nullptr);
 }
 
 static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
@@ -810,10 +816,11 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
                     S.gemm_part_size);
   } else {
     launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
-    // field-circuit coupling: the elimination multiplies the error of the
-    // solve (the circuit rows weigh B (a' - a) with l_z / dt), so an
-    // early-stopped relaxation solve diverges over an F-sweep; coupled steps
-    // always solve to pcg_tol
+    // field-circuit coupling: coupled steps always solve to pcg_tol.  The
+    // stop test sees the residual of y = a' - Z w, and a start from a guess
+    // of a' holds the circuits' field B^T w in it: a stop at eta times that
+    // residual does not tighten as MGRIT converges (the F-relaxation of the
+    // 64x512 model diverged at eta = 3e-3)
     struct EtaOff {
       Handle& h;
       double keep;

@@ -14,17 +14,15 @@ from oracle import mgrit, stepping
 pytestmark = pytest.mark.gpu
 
 MGRIT_GATE = 1e-7    # ||U - U_seq|| / ||U_seq|| after MGRIT stops at rho <= 1e-8 rho_0
-# The elimination of the circuit unknowns multiplies the error of the step's
-# linear solve: the circuit rows weigh B (a' - a) with l_z / dt = 8.2e4, so a
-# solve error in y moves w and hence a' = y + Z w by the oblique projection
-# I - Z S^-1 (l_z/dt) E B.  An emulation on the CPU (SciPy CG on the same
-# scaled system, the oracle's inputs) gives for a perturbed trajectory state a
-# relative error of y of 2.5e-11 at a 1e-13 residual and of a' 2.8e-10 (11x);
-# at 1e-14 they are 1.3e-12 and 9e-12.  The coupled tests solve to a 1e-14
-# relative residual.  Trajectory states are held to the 1e-10 of an FP64 step;
-# with the perturbed inputs of the uncoupled Phi tests (noise of 1e-4 on
-# trajectory states) the GPU's y errors reach ~1e-11 on some columns, and
-# those steps are held to 5e-10.
+# After an iterative solve the elimination of the circuit unknowns uses the
+# exact circuit rows of the step: it adds Z^T r (r the solve's residual) to
+# B (y - a), so a' = y + Z w carries the solve's own error only.  Without that
+# term the elimination multiplied it by the oblique projection
+# I - Z S^-1 (l_z/dt) E B (an emulation with SciPy CG on the oracle's inputs:
+# 11x at a 1e-13 residual).  The coupled parity tests solve to a 1e-14
+# relative residual and hold trajectory states to the 1e-10 of an FP64 step,
+# steps from the perturbed inputs of the uncoupled Phi tests (noise of 1e-4
+# on trajectory states) to 5e-10.
 PCG_TOL = 1e-14
 PHI_TOL = 1e-10          # relative 2-norm error per column, trajectory states
 PHI_TOL_PERTURBED = 5e-10
