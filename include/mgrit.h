@@ -108,8 +108,10 @@ typedef struct {
    * currents and voltages are algebraic, fixed by two consecutive states, so
    * MGRIT's state stays the vector potential.  With n_bars = 0 the bar cells
    * are plain conductors (bar voltages 0), as with circuit = 0.  Coupled steps
-   * ignore pcg_tol_eta and residual_eta: the elimination multiplies the error
-   * of an early-stopped solve and the relaxation diverges. */
+   * ignore pcg_tol_eta and residual_eta: their linear solve is for
+   * a' - Z w (Z = A^-1 B^T), a start from a guess of a' holds the circuits'
+   * field in its residual, and a stop relative to that residual does not
+   * tighten as MGRIT converges. */
   int32_t circuit;            /* 0: current-driven coils (sign * J0 * amplitude * b_p); 1: coupled */
   double turns_density;       /* turns per m^2 of slot (> 0 with circuit = 1) */
   double l_z;                 /* axial length, m (> 0) */
