@@ -563,7 +563,7 @@ def main():
         HEADLINE.update(pinned((rpb, cpl, 2, depth, narrow)))
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the time-parallel "
-              "decomposition over several GPUs is not part of this build.", file=sys.stderr)
+              "decomposition over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
