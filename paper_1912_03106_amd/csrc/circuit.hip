@@ -2,7 +2,9 @@
 // right-hand-side CG start of the set-up solves Z = A^-1 B^T, and the
 // per-column elimination of the circuit unknowns after a step's linear solve.
 // Every sum runs in a fixed order, so a column's result does not depend on
-// the batch it is computed in.
+// the batch it is computed in, except that a one-column batch (the
+// sequential steppers, the coarsest level's steps) spreads the rows of each
+// partial dot over the lanes of its wave.
 #include <hip/hip_runtime.h>
 
 #include "circuit.h"
@@ -154,23 +156,61 @@ __global__ void k_circ_sum(int k, int ncols, int nparts, const double* __restric
   d[static_cast<int64_t>(j) * ldd + c] = t;
 }
 
+// One column of the dots on one column: wave p sums the rows of partial p,
+// row i0 + q * 64 + lane on lane `lane`, then reduces over its lanes by a
+// butterfly (the same order on every call).
+__global__ __launch_bounds__(kBlock) void k_circ_dots1(int n, int k, const double* __restrict__ Bt,
+                                                       const double* __restrict__ y, int64_t ldy,
+                                                       const double* __restrict__ a, int64_t lda,
+                                                       double* __restrict__ part, int64_t ldp, int nparts) {
+  const int lane = threadIdx.x & 63, wv = wave_index();
+  const int p = blockIdx.x * 4 + wv;
+  if (p >= nparts) return;   // wave-uniform
+  double acc[kCircMax];
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j) acc[j] = 0.0;
+  const int i0 = p * kCircRowsPerWave;
+#pragma unroll
+  for (int q = 0; q < kCircRowsPerWave / kWave; ++q) {
+    const int i = i0 + q * kWave + lane;
+    if (i < n) {
+      const double d = y[static_cast<int64_t>(i) * ldy] - a[static_cast<int64_t>(i) * lda];
+      const double* b = Bt + static_cast<int64_t>(i) * k;
+#pragma unroll
+      for (int j = 0; j < kCircMax; ++j)
+        if (j < k) acc[j] = fma(b[j], d, acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j) {
+    if (j < k) {
+      double v = acc[j];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[j] = v;
+    }
+  }
+  if (lane == 0) {
+    double* o = part + static_cast<int64_t>(p) * k * ldp;
+#pragma unroll
+    for (int j = 0; j < kCircMax; ++j)
+      if (j < k) o[static_cast<int64_t>(j) * ldp] = acc[j];
+  }
+}
+
+// One thread per column and circuit unknown j.
 __global__ void k_circ_solve(int k, int ncols, const double* __restrict__ d, int64_t ldd,
                              const double* __restrict__ src, int64_t lds,
                              const double* __restrict__ cS, double* __restrict__ w, int64_t ldw) {
   const int c = blockIdx.x * kWave + static_cast<int>(threadIdx.x);
-  if (c >= ncols) return;
-  double dv[kCircMax];
-#pragma unroll
-  for (int l = 0; l < kCircMax; ++l) dv[l] = (l < k) ? d[static_cast<int64_t>(l) * ldd + c] : 0.0;
+  const int j = blockIdx.y;
+  if (c >= ncols || j >= k) return;
   const double v0 = src[c], v1 = src[lds + c], v2 = src[2 * lds + c];
-  for (int j = 0; j < k; ++j) {
-    const double* row = cS + static_cast<int64_t>(j) * (3 + k);
-    double t = (row[0] * v0 + row[1] * v1) + row[2] * v2;
+  const double* row = cS + static_cast<int64_t>(j) * (3 + k);
+  double t = (row[0] * v0 + row[1] * v1) + row[2] * v2;
 #pragma unroll
-    for (int l = 0; l < kCircMax; ++l)
-      if (l < k) t = fma(-row[3 + l], dv[l], t);
-    w[static_cast<int64_t>(j) * ldw + c] = t;
-  }
+  for (int l = 0; l < kCircMax; ++l)
+    if (l < k) t = fma(-row[3 + l], d[static_cast<int64_t>(l) * ldd + c], t);
+  w[static_cast<int64_t>(j) * ldw + c] = t;
 }
 
 // x[i][c] += sum_j Z[i][j] w[j][c]: one lane per column, a wave walks 64 rows.
@@ -197,6 +237,20 @@ __global__ __launch_bounds__(kBlock) void k_circ_apply(int n, int k, int ncols,
   }
 }
 
+// x[i] += sum_j Z[i][j] w[j] for one column: one thread per row (the sum in
+// the order of k_circ_apply).
+__global__ void k_circ_apply1(int n, int k, const double* __restrict__ Z, const double* __restrict__ w,
+                              int64_t ldw, double* __restrict__ x, int64_t ldx) {
+  const int i = blockIdx.x * blockDim.x + static_cast<int>(threadIdx.x);
+  if (i >= n) return;
+  const double* z = Z + static_cast<int64_t>(i) * k;
+  double t = 0.0;
+#pragma unroll
+  for (int j = 0; j < kCircMax; ++j)
+    if (j < k) t = fma(z[j], w[static_cast<int64_t>(j) * ldw], t);
+  x[static_cast<int64_t>(i) * ldx] += t;
+}
+
 }  // namespace
 
 void launch_circ_rhs_init(hipStream_t s, const DevLevel& L, PcgWork& w, const double* B, int64_t ldb,
@@ -215,8 +269,12 @@ void launch_circ_dots(hipStream_t s, int n, int k, int ncols, const double* Bt, 
   if (ncols <= 0 || n <= 0) return;
   if (k < 1 || k > kCircMax || ldp < ncols) fail(MGRIT_INVALID_ARGUMENT, "circuit dots: bad sizes");
   const int np = circ_parts(n);
-  hipLaunchKernelGGL(k_circ_dots, dim3(cdiv(ncols, kWave), cdiv(np, 4)), dim3(kBlock), 0, s, n, k, ncols,
-                     Bt, y.p, y.ld, a.p, a.ld, part, ldp, np);
+  if (ncols == 1)
+    hipLaunchKernelGGL(k_circ_dots1, dim3(cdiv(np, 4)), dim3(kBlock), 0, s, n, k, Bt, y.p, y.ld, a.p, a.ld,
+                       part, ldp, np);
+  else
+    hipLaunchKernelGGL(k_circ_dots, dim3(cdiv(ncols, kWave), cdiv(np, 4)), dim3(kBlock), 0, s, n, k, ncols,
+                       Bt, y.p, y.ld, a.p, a.ld, part, ldp, np);
   MG_HIP(hipGetLastError());
 }
 
@@ -243,7 +301,8 @@ void launch_circ_sum(hipStream_t s, int k, int ncols, int nparts, const double* 
 void launch_circ_solve(hipStream_t s, int k, int ncols, const double* d, int64_t ldd,
                        const double* src, int64_t lds, const double* cS, double* w, int64_t ldw) {
   if (ncols <= 0) return;
-  hipLaunchKernelGGL(k_circ_solve, dim3(cdiv(ncols, kWave)), dim3(kWave), 0, s, k, ncols, d, ldd, src, lds,
+  if (k < 1 || k > kCircMax) fail(MGRIT_INVALID_ARGUMENT, "circuit solve: bad sizes");
+  hipLaunchKernelGGL(k_circ_solve, dim3(cdiv(ncols, kWave), k), dim3(kWave), 0, s, k, ncols, d, ldd, src, lds,
                      cS, w, ldw);
   MG_HIP(hipGetLastError());
 }
@@ -251,8 +310,12 @@ void launch_circ_solve(hipStream_t s, int k, int ncols, const double* d, int64_t
 void launch_circ_apply(hipStream_t s, int n, int k, int ncols, const double* Z, const double* w,
                        int64_t ldw, double* x, int64_t ldx) {
   if (ncols <= 0 || n <= 0) return;
-  hipLaunchKernelGGL(k_circ_apply, dim3(cdiv(ncols, kWave), cdiv(n, 4 * kWave)), dim3(kBlock), 0, s, n, k,
-                     ncols, Z, w, ldw, x, ldx);
+  if (k < 1 || k > kCircMax) fail(MGRIT_INVALID_ARGUMENT, "circuit apply: bad sizes");
+  if (ncols == 1)
+    hipLaunchKernelGGL(k_circ_apply1, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, s, n, k, Z, w, ldw, x, ldx);
+  else
+    hipLaunchKernelGGL(k_circ_apply, dim3(cdiv(ncols, kWave), cdiv(n, 4 * kWave)), dim3(kBlock), 0, s, n, k,
+                       ncols, Z, w, ldw, x, ldx);
   MG_HIP(hipGetLastError());
 }
 
