@@ -107,11 +107,13 @@ typedef struct {
    * periodic path Laplacian over the bars.  No circuit inductance: the
    * currents and voltages are algebraic, fixed by two consecutive states, so
    * MGRIT's state stays the vector potential.  With n_bars = 0 the bar cells
-   * are plain conductors (bar voltages 0), as with circuit = 0.  Coupled steps
-   * ignore pcg_tol_eta and residual_eta: their linear solve is for
-   * a' - Z w (Z = A^-1 B^T), a start from a guess of a' holds the circuits'
-   * field in its residual, and a stop relative to that residual does not
-   * tighten as MGRIT converges. */
+   * are plain conductors (bar voltages 0), as with circuit = 0.  Inside
+   * mgrit_solve a coupled step's linear solve (for a' - Z w, Z = A^-1 B^T)
+   * starts from its guess of a' less Z times the circuit unknowns of the
+   * latest step from the same time point, and pcg_tol_eta / residual_eta
+   * apply as in the uncoupled model.  With them, pcg_tol <= 1e-14 is
+   * advised: the right-hand side (M/dt) a is dominated by the bars' sigma/dt
+   * rows, and with 1e-12 the iteration levels off near 1e-8 of rho_0. */
   int32_t circuit;            /* 0: current-driven coils (sign * J0 * amplitude * b_p); 1: coupled */
   double turns_density;       /* turns per m^2 of slot (> 0 with circuit = 1) */
   double l_z;                 /* axial length, m (> 0) */

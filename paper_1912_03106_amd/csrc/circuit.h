@@ -50,5 +50,13 @@ void launch_circ_solve(hipStream_t s, int k, int ncols, const double* d, int64_t
 // x[i][c] += sum_j Z[i][j] w[j][c], Z row-major [n][k].
 void launch_circ_apply(hipStream_t s, int n, int k, int ncols, const double* Z, const double* w,
                        int64_t ldw, double* x, int64_t ldx);
+// Per-time-point store wt [k][nt] of the circuit unknowns (i = t_list[c], or
+// t_base + c t_stride without a list; points outside [0, nt) are skipped):
+// recall writes w[j][c] = -wt[j][i] (so that launch_circ_apply subtracts
+// Z w), keep writes wt[j][i] = w[j][c].
+void launch_circ_recall(hipStream_t s, int k, int ncols, const int64_t* t_list, int64_t t_base,
+                        int64_t t_stride, const double* wt, int64_t nt, double* w, int64_t ldw);
+void launch_circ_keep(hipStream_t s, int k, int ncols, const int64_t* t_list, int64_t t_base,
+                      int64_t t_stride, const double* w, int64_t ldw, double* wt, int64_t nt);
 
 }  // namespace mg

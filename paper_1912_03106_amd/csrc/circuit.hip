@@ -251,6 +251,28 @@ __global__ void k_circ_apply1(int n, int k, const double* __restrict__ Z, const 
   x[static_cast<int64_t>(i) * ldx] += t;
 }
 
+// w[j][c] = -wt[j][i], i the column's time point (0 outside [0, nt)).
+__global__ void k_circ_recall(int k, int ncols, const int64_t* __restrict__ t_list, int64_t t_base,
+                              int64_t t_stride, const double* __restrict__ wt, int64_t nt,
+                              double* __restrict__ w, int64_t ldw) {
+  const int c = blockIdx.x * kWave + static_cast<int>(threadIdx.x);
+  const int j = blockIdx.y;
+  if (c >= ncols || j >= k) return;
+  const int64_t i = t_list ? t_list[c] : t_base + static_cast<int64_t>(c) * t_stride;
+  w[static_cast<int64_t>(j) * ldw + c] = (i >= 0 && i < nt) ? -wt[static_cast<int64_t>(j) * nt + i] : 0.0;
+}
+
+// wt[j][i] = w[j][c], i the column's time point (skipped outside [0, nt)).
+__global__ void k_circ_keep(int k, int ncols, const int64_t* __restrict__ t_list, int64_t t_base,
+                            int64_t t_stride, const double* __restrict__ w, int64_t ldw,
+                            double* __restrict__ wt, int64_t nt) {
+  const int c = blockIdx.x * kWave + static_cast<int>(threadIdx.x);
+  const int j = blockIdx.y;
+  if (c >= ncols || j >= k) return;
+  const int64_t i = t_list ? t_list[c] : t_base + static_cast<int64_t>(c) * t_stride;
+  if (i >= 0 && i < nt) wt[static_cast<int64_t>(j) * nt + i] = w[static_cast<int64_t>(j) * ldw + c];
+}
+
 }  // namespace
 
 void launch_circ_rhs_init(hipStream_t s, const DevLevel& L, PcgWork& w, const double* B, int64_t ldb,
@@ -316,6 +338,24 @@ void launch_circ_apply(hipStream_t s, int n, int k, int ncols, const double* Z, 
   else
     hipLaunchKernelGGL(k_circ_apply, dim3(cdiv(ncols, kWave), cdiv(n, 4 * kWave)), dim3(kBlock), 0, s, n, k,
                        ncols, Z, w, ldw, x, ldx);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_circ_recall(hipStream_t s, int k, int ncols, const int64_t* t_list, int64_t t_base,
+                        int64_t t_stride, const double* wt, int64_t nt, double* w, int64_t ldw) {
+  if (ncols <= 0) return;
+  if (k < 1 || k > kCircMax || ldw < ncols) fail(MGRIT_INVALID_ARGUMENT, "circuit recall: bad sizes");
+  hipLaunchKernelGGL(k_circ_recall, dim3(cdiv(ncols, kWave), k), dim3(kWave), 0, s, k, ncols, t_list, t_base,
+                     t_stride, wt, nt, w, ldw);
+  MG_HIP(hipGetLastError());
+}
+
+void launch_circ_keep(hipStream_t s, int k, int ncols, const int64_t* t_list, int64_t t_base,
+                      int64_t t_stride, const double* w, int64_t ldw, double* wt, int64_t nt) {
+  if (ncols <= 0) return;
+  if (k < 1 || k > kCircMax || ldw < ncols) fail(MGRIT_INVALID_ARGUMENT, "circuit keep: bad sizes");
+  hipLaunchKernelGGL(k_circ_keep, dim3(cdiv(ncols, kWave), k), dim3(kWave), 0, s, k, ncols, t_list, t_base,
+                     t_stride, w, ldw, wt, nt);
   MG_HIP(hipGetLastError());
 }
 

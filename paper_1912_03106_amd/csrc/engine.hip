@@ -73,6 +73,8 @@ struct LevelState {
   double* cd = nullptr;
   double* cw = nullptr;
   int64_t c_ld = 0;
+  double* cwt = nullptr;  // [k][c_nt]: circuit unknowns of the latest step from each time point
+  int64_t c_nt = 0;
   bool relaxed = false;   // F-points hold a previous iterate (warm starts)
   bool cvalid = false;    // C-points hold a previous iterate
 };
@@ -92,6 +94,7 @@ struct Handle {
   double* seq_U = nullptr;        // sequential trajectory [n0][ld] (lazy)
   double* seq_ws = nullptr;
   double* seq_nl_ws = nullptr;    // persistent Newton stepper of the sequential solve (lazy)
+  bool circ_guess = false;        // coupled solves start from the stored circuit unknowns
   double* seq_inv = nullptr;      // finest level's A^-1 of the stored-inverse sequential solve (lazy)
   int64_t seq_ld_inv = 0;
   double* seq_bvec = nullptr;
@@ -793,6 +796,24 @@ static void circuit_eliminate(Handle& h, LevelState& S, int ncols, double* y, in
 
 static void circuit_step(Handle& h, LevelState& S, PcgWork& w, const PhiCall& c) {
   circuit_eliminate(h, S, c.ncols, w.x, w.ld, c.in, w.src, w.ld, S.Ainv == nullptr);
+  if (h.circ_guess)
+    launch_circ_keep(h.stream, h.circ_k, c.ncols, c.t_list, c.t_base, c.t_stride, S.cw, S.c_ld, S.cwt,
+                     S.c_nt);
+}
+
+// Start of a coupled step's linear solve inside an MGRIT solve.  The solve
+// is for y = a' - Z w, and its guess x0 is one of a' (the previous iterate at
+// the same time point, plus the change of its input).  With the circuit
+// unknowns w0 of the latest step from that point, y starts from x0 - Z w0:
+// its start residual then shrinks as MGRIT converges, as in the uncoupled
+// model, instead of holding the circuits' field A Z w0 = B^T w0, so a stop
+// at eta times the start residual tightens with the iterations.
+static void circuit_guess(Handle& h, LevelState& S, PcgWork& w, const PhiCall& c) {
+  if (!h.circ_guess) return;
+  circuit_buffers(h, S, c.ncols);
+  launch_circ_recall(h.stream, h.circ_k, c.ncols, c.t_list, c.t_base, c.t_stride, S.cwt, S.c_nt, S.cw,
+                     S.c_ld);
+  launch_circ_apply(h.stream, S.n, h.circ_k, c.ncols, S.cZ, S.cw, S.c_ld, w.x, w.ld);
 }
 
 static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
@@ -816,17 +837,7 @@ static void phi_batch(Handle& h, int l, PcgWork& w, const PhiCall& c) {
                     S.gemm_part_size);
   } else {
     launch_axpby3(s, S.n, c.ncols, w.x, w.ld, 0.0, CView{}, 1.0, c.ga, c.sgb, c.gb);
-    // field-circuit coupling: coupled steps always solve to pcg_tol.  The
-    // stop test sees the residual of y = a' - Z w, and a start from a guess
-    // of a' holds the circuits' field B^T w in it: a stop at eta times that
-    // residual does not tighten as MGRIT converges (the F-relaxation of the
-    // 64x512 model diverged at eta = 3e-3)
-    struct EtaOff {
-      Handle& h;
-      double keep;
-      ~EtaOff() { h.eta_now = keep; }
-    } eta_off{h, h.eta_now};
-    if (h.circ) h.eta_now = 0.0;
+    if (h.circ) circuit_guess(h, S, w, c);
     if (S.nl.n_tri > 0 && narrow_persistent(h, l, S, c.ncols))
       it = newton_narrow(h, l, S, w, c.ncols, c.in, c.t_list, c.t_base, c.t_stride);
     else
@@ -1438,6 +1449,10 @@ static void setup_circuit(Handle& h, const mgrit_problem* prob, const std::vecto
     }
     S.cS = h.arena.alloc<double>(cS.size());
     MG_HIP(hipMemcpyAsync(S.cS, cS.data(), sizeof(double) * cS.size(), hipMemcpyHostToDevice, s));
+    // circuit unknowns of the latest coupled step from every time point (the
+    // start of the next solve from the same point)
+    S.c_nt = std::max<int64_t>(S.N, 1);
+    S.cwt = h.arena.alloc<double>(static_cast<size_t>(k) * S.c_nt);
     MG_HIP(hipStreamSynchronize(s));
     circuit_buffers(h, S, S.pcg.cap);
   }
@@ -1765,6 +1780,19 @@ static void solve_impl(Handle& h, const double* u0, const double* u_init, double
   h.learned_off = false;
   h.solved = false;
   st->coarse_fallback = -1;
+  // coupled steps start from the circuit unknowns of the previous step from
+  // the same time point (zero before the first)
+  struct GuessOff {
+    Handle& h;
+    ~GuessOff() { h.circ_guess = false; }
+  } guess_off{h};
+  if (h.circ) {
+    for (auto& S : h.lv)
+      if (S.cwt)
+        launch_axpby3(s, h.circ_k, static_cast<int>(S.c_nt), S.cwt, S.c_nt, 0.0, CView{}, 0.0, CView{}, 0.0,
+                      CView{});
+    h.circ_guess = true;
+  }
   if (h.par.coarse_model == 1 && !h.gnn.ready)
     fail(MGRIT_INVALID_ARGUMENT, "coarse_model = 1 needs trained or set coarse weights");
   if (h.par.nested) {

@@ -198,12 +198,19 @@ def test_mgrit_circuit_f_cycle_nested_matches_oracle():
     H.cycle = "F"
     _, hist, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=3, guess=guess)
     _, hist0, _ = mgrit.solve(H, np.zeros(n), cfg.n_steps, tol=cfg.mgrit_tol, maxit=0)
-    # the timed solver settings: the early stops are not applied to coupled
-    # steps, so the history still follows the oracle's
-    U, st = _solver(cfg, pcg_tol=PCG_TOL, cycle=1, nested=1, warm_start=2, pcg_tol_eta=3e-3,
-                    residual_eta=1e-4).solve()
+    # strict solves: the oracle's history
+    U, st = _solver(cfg, pcg_tol=PCG_TOL, cycle=1, nested=1, warm_start=2).solve()
     assert st["converged"] and st["time_nested_s"] > 0
     for a, b in zip(st["rho"][:4], hist[:4]):
         assert abs(a - b) <= 2e-9 * hist0[0], (a, b)
     err = np.linalg.norm(U - U_seq, axis=1)[1:] / np.linalg.norm(U_seq, axis=1)[1:]
+    assert err.max() <= MGRIT_GATE, err.max()
+    # the timed settings (level-0 relaxation solves stopped at 3e-3 of their
+    # start residual, C-point residual solves at 1e-4): the same solution in
+    # a few more iterations
+    U2, st2 = _solver(cfg, pcg_tol=PCG_TOL, cycle=1, nested=1, warm_start=2, pcg_tol_eta=3e-3,
+                      residual_eta=1e-4).solve()
+    print("circuit timed settings", len(st2["rho"]) - 1, "iterations, strict", len(st["rho"]) - 1, flush=True)
+    assert st2["converged"] and len(st2["rho"]) <= len(st["rho"]) + 4, (st2["rho"], st["rho"])
+    err = np.linalg.norm(U2 - U_seq, axis=1)[1:] / np.linalg.norm(U_seq, axis=1)[1:]
     assert err.max() <= MGRIT_GATE, err.max()
