@@ -2,8 +2,10 @@
 
 Headline (`value`): the linear machine on the 64 x 512 polar mesh (n = 32,256
 unknowns), 16,384 implicit-Euler steps over one 50 Hz period, three-level
-V-cycle (m = 16, FCF, direct spatial coarsening 64x512 -> 32x256 -> 16x128),
-batched FP64 Jacobi-PCG, stop at a 1e-8 relative C-point residual.
+F-cycles (m = 16, FCF, direct spatial coarsening 64x512 -> 32x256 -> 16x128)
+from the nested-iteration start (coarse problems driven by the sine
+references; rho_0 is the residual of that start), batched FP64 Jacobi-PCG,
+stop at a 1e-8 relative C-point residual.
 
 One bench step = one complete MGRIT solve to the tolerance (every part of the
 hot path: F/C relaxation, C-point residual, restriction, FAS right-hand side,
@@ -34,6 +36,9 @@ the start of the process) allows, in this order:
     solution's deviation from the oracle on its sample);
   - the FP32 + FP64-refinement variant (random initial guess);
   - the same solve with every linear solve to 1e-12 ||b|| ("plain");
+  - the linear machine with the field-circuit coupling (first 4,096 steps,
+    the timed solve's settings with pcg_tol 1e-14) against sequential
+    stepping of the coupled model (batched CG and the stored inverse);
   - the nonlinear machine with the learned coarsest propagator (training and
     solve).
 A leg that would not fit the remaining budget is listed under "skipped".
