@@ -25,13 +25,13 @@ Further legs of the same JSON line, run while the time budget (--budget, from
 the start of the process) allows, in this order:
   - the roofline of the dominant kernel (CG pass B) from one more solve with
     HIP events around every CG pass;
+  - GPU sequential stepping of the linear workload on windows spread over the
+    horizon, each started from the MGRIT state at its first point (time per
+    step -> full-horizon estimate; the deviation of MGRIT from the window's
+    sequential states), and by the finest level's stored inverse;
   - the nonlinear machine (saturating iron, 32,768 steps, damped Newton per
     step, FP32 inner CG): time to the 1e-8 residual, and GPU sequential Newton
-    stepping on windows spread over the horizon, each started from the MGRIT
-    state at its first point (time per step -> full-horizon estimate; the
-    deviation of MGRIT from the window's sequential states);
-  - GPU sequential stepping of the linear workload on windows spread over the
-    horizon, the same way;
+    stepping on windows spread over the horizon, the same way;
   - the CPU oracle timed on this host (its states also give each GPU
     solution's deviation from the oracle on its sample);
   - the FP32 + FP64-refinement variant (random initial guess);
