@@ -737,7 +737,13 @@ def main():
         del vout, U
     circ = None
     if not args.no_circuit and budget.fits("field-circuit", 55.0):
-        circ = circuit_leg(stream)
+        from paper_1912_03106_amd._abi import MgritError
+        try:
+            circ = circuit_leg(stream)
+        except MgritError as e:
+            # a solver error of this leg goes into the line; it does not end the run
+            log(f"field-circuit leg failed: {e}")
+            circ = {"error": str(e)}
     if nl is not None and budget.fits("nonlinear learned", 2.2 * nl["implicit_euler"]["time_to_solution_s"] + 60.0):
         nl["learned"] = nonlinear_leg(config("cfg5").n_steps, stream, budget=budget, learned=True,
                                       ie=False).get("learned")
